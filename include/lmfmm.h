@@ -1,0 +1,148 @@
+/*
+ * lmfmm.h -- C ABI of the MI355X layered-media FMM for the reflected field g_2^t.
+ *
+ * The operator (Cho & Huang, arXiv 1902.08250, Section 1; Section 3 Example 4):
+ *
+ *   u_i = sum_j g_2^t(x_i, x_j) q_j,
+ *   g_2^t(x1,y1; x0,y0) = Int_R e^{s2 y1 + i lam x1} e^{-s1 y0 - i lam x0} sigma_2^t(lam)/(4 pi s2) d lam,
+ *   s_m = sqrt(lam^2 - k_m^2) (principal branch),
+ *
+ * for sources x_j in the top layer (y > 0) and targets x_i in the middle layer
+ * (-d < y < 0) of a three-layer medium with wave numbers k1, k2, k3 (Im k >= 0)
+ * and interfaces y = 0 and y = -d.  The apply is the adapted free-space FMM of
+ * Section 2 (Algorithm 1): quadtree, source-to-multipole and multipole-to-
+ * multipole with the free-space Helmholtz operators for k1, multipole-to-local
+ * by Sommerfeld-integral translation matrices (Lemma M2L), local-to-local and
+ * local evaluation with the free-space operators for k2, and the near field by
+ * direct Sommerfeld quadrature on deformed contours (Section 4.2).
+ *
+ * Conventions shared by every entry point:
+ *   - All point and density arrays are DEVICE pointers owned by the caller and
+ *     must stay valid until the work queued on the given stream completes.
+ *   - Coordinates are float64, structure of arrays [2][n]: x[0..n), y[0..n).
+ *   - Densities are interleaved complex, [nrhs][n]: complex128 (re, im float64)
+ *     for LMFMM_C128, complex64 (re, im float32) for LMFMM_C64_MIXED.
+ *   - stream is a hipStream_t (NULL = the default stream).  Entry points queue
+ *     work asynchronously except where noted; argument errors are returned
+ *     synchronously and nothing is queued.
+ *   - A plan is not thread-safe; use one plan per host thread.
+ *   - Status codes are returned, never thrown; lmfmm_last_error() gives the
+ *     thread-local message of the last failure.
+ */
+#ifndef LMFMM_H
+#define LMFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lmfmm_plan_s *lmfmm_plan;
+
+enum {
+    LMFMM_OK = 0,
+    LMFMM_EINVAL = -1,  /* bad argument (null pointer, size, option)            */
+    LMFMM_EDOMAIN = -2, /* a point lies outside its layer or is not finite      */
+    LMFMM_ENOMEM = -3,  /* device or host allocation failed                     */
+    LMFMM_EHIP = -4,    /* a HIP runtime call failed                            */
+    LMFMM_ETOL = -5,    /* the requested tolerance cannot be met                */
+    LMFMM_ENODEV = -6   /* no usable GPU                                        */
+};
+
+enum {
+    LMFMM_C128 = 0,       /* FP64 throughout                                      */
+    LMFMM_C64_MIXED = 1   /* FP32 expansions and translations; sigma, quadrature
+                             weights and the near field stay FP64                */
+};
+
+/* Create a plan for the medium (Section 3 Example 4).
+ *   k:     {Re k1, Im k1, Re k2, Im k2, Re k3, Im k3}, Re k > 0, Im k >= 0.
+ *   d:     thickness of the middle layer, d > 0.
+ *   order: expansion order p of the multipole/local series (truncation of
+ *          the sums over p in Section 2), 1 <= order <= 256; the order used at
+ *          a level is max(order, the order that tol requires there).
+ *   tol:   target relative accuracy, 0 < tol < 1.
+ * Queues the sigma_2^t quadrature tables on the null stream and synchronizes.
+ * On success *out receives the plan (destroy with lmfmm_destroy). */
+int lmfmm_create(const double k[6], double d, int order, double tol, lmfmm_plan *out);
+
+/* Release a plan and its device memory (synchronizes the device). */
+int lmfmm_destroy(lmfmm_plan plan);
+
+/* Set an option (string key/value).  Keys:
+ *   "levels"      quadtree depth L >= 1, or "auto" (default, ~40 points/leaf)
+ *   "fixed_order" "1": use exactly `order` at every level, ignoring tol
+ *   "domain"      "x_lo,width": fix the root square [x_lo, x_lo+width] x
+ *                 [-width/2, width/2] (skips the bounding-box readback, so
+ *                 an apply queues no host synchronisation); "auto" to clear
+ *   "near"        "1" (default) / "0": include / skip the near field
+ *   "far"         "1" (default) / "0": include / skip the far field
+ * Returns LMFMM_EINVAL for an unknown key or malformed value. */
+int lmfmm_set_option(lmfmm_plan plan, const char *key, const char *value);
+
+/* Forward apply (Algorithm 1, Steps 1-4): u[r][i] = sum_j g_2^t(tgt_i, src_j) q[r][j].
+ *   n_src, src_xy: source count and coordinates [2][n_src] (y > 0).
+ *   q:     densities [nrhs][n_src].
+ *   n_tgt, tgt_xy: target count and coordinates [2][n_tgt] (-d < y < 0).
+ *   u:     output [nrhs][n_tgt], overwritten.
+ *   nrhs:  number of right-hand sides, 1 <= nrhs <= 64.
+ *   precision: LMFMM_C128 or LMFMM_C64_MIXED (selects the dtype of q and u).
+ * Unless the "domain" option is set, the call reads the points' bounding box
+ * back to the host (one stream synchronisation).  Points outside their layer
+ * are reported as LMFMM_EDOMAIN by the host check of that bounding box, or by
+ * lmfmm_sync_status when a fixed domain is used. */
+int lmfmm_apply(lmfmm_plan plan, int64_t n_src, const double *src_xy, const void *q, int64_t n_tgt,
+                const double *tgt_xy, void *u, int nrhs, int precision, void *stream);
+
+/* Transposed operator, no conjugation: v[r][j] = sum_i g_2^t(tgt_i, src_j) w[r][i].
+ * Same arguments as lmfmm_apply with w: [nrhs][n_tgt] in, v: [nrhs][n_src] out. */
+int lmfmm_apply_adjoint(lmfmm_plan plan, int64_t n_src, const double *src_xy, int64_t n_tgt,
+                        const double *tgt_xy, const void *w, void *v, int nrhs, int precision,
+                        void *stream);
+
+/* Coordinate gradients of L = Re sum_r sum_i w[r][i] u[r][i], u = G q:
+ *   dsrc: [2][n_src] float64 (dL/dx_j, dL/dy_j), dtgt: [2][n_tgt] float64.
+ * The kernel's derivatives multiply the Sommerfeld integrand by i lam (x1),
+ * s2 (y1), -i lam (x0), -s1 (y0).  Tree and expansions are recomputed. */
+int lmfmm_grad_coords(lmfmm_plan plan, int64_t n_src, const double *src_xy, const void *q, int64_t n_tgt,
+                      const double *tgt_xy, const void *w, double *dsrc, double *dtgt, int nrhs,
+                      int precision, void *stream);
+
+/* Brute-force direct sum on the GPU (every pair by contour quadrature, FP64
+ * arithmetic, no tree); same arguments and result as lmfmm_apply. */
+int lmfmm_direct(lmfmm_plan plan, int64_t n_src, const double *src_xy, const void *q, int64_t n_tgt,
+                 const double *tgt_xy, void *u, int nrhs, int precision, void *stream);
+
+/* Statistics of the last apply. */
+typedef struct {
+    int levels;            /* quadtree depth L                               */
+    int order[32];         /* expansion order used at levels 0..L            */
+    double root_x_lo;      /* root square [x_lo, x_lo+width] x [-w/2, w/2]    */
+    double root_width;
+    int64_t near_pairs;    /* source-target pairs evaluated by quadrature    */
+    int64_t m2l_pairs;     /* box pairs translated by M2L                    */
+    int64_t leaves_src;    /* leaf boxes covering the sources' bounding box   */
+    int64_t leaves_tgt;
+    int near_nodes_mid;    /* near-field quadrature nodes on the finite piece */
+    int near_nodes_ray;    /* ... on each of the two rays                     */
+    int m2l_classes;       /* translation classes with a table               */
+    int64_t m2l_nodes;     /* quadrature nodes summed over all classes       */
+    double table_seconds;  /* host wall time of the last M2L table rebuild   */
+} lmfmm_stats;
+
+int lmfmm_get_stats(lmfmm_plan plan, lmfmm_stats *stats);
+
+/* Synchronize the stream and report a device-detected error of the plan's
+ * last apply (points outside the fixed domain or their layer). */
+int lmfmm_sync_status(lmfmm_plan plan, void *stream);
+
+const char *lmfmm_status_string(int status);
+const char *lmfmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMFMM_H */

@@ -1,0 +1,259 @@
+// Internal declarations of the MI355X layered-media FMM library.
+//
+// Shared by the host plan code and the HIP kernels: a small complex type,
+// the principal-branch square root, sigma_2^t, the scaled Bessel bases of the
+// multipole and local expansions, and the launch wrappers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+namespace lmfmm {
+
+// ---------------------------------------------------------------------------
+// Complex arithmetic (device and host)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ inline cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator*(cx<T> a, T s) { return {s * a.re, s * a.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> &operator+=(cx<T> &a, cx<T> b)
+{
+    a.re += b.re;
+    a.im += b.im;
+    return a;
+}
+// a += b * c
+template <typename T>
+__host__ __device__ inline void cfma(cx<T> &a, cx<T> b, cx<T> c)
+{
+    a.re = fma(b.re, c.re, fma(-b.im, c.im, a.re));
+    a.im = fma(b.re, c.im, fma(b.im, c.re, a.im));
+}
+template <typename T>
+__host__ __device__ inline cx<T> cinv(cx<T> a)
+{
+    T s = T(1) / (a.re * a.re + a.im * a.im);
+    return {a.re * s, -a.im * s};
+}
+template <typename T>
+__host__ __device__ inline cx<T> cdiv(cx<T> a, cx<T> b) { return a * cinv(b); }
+template <typename T>
+__host__ __device__ inline T cabs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// exp(z) in FP64
+__host__ __device__ inline cx<double> cexp_d(cx<double> z)
+{
+    double e = exp(z.re), s, c;
+    sincos(z.im, &s, &c);
+    return {e * c, e * s};
+}
+
+// Principal square root: branch cut on the negative real axis, Re >= 0.
+__host__ __device__ inline cx<double> csqrt_d(cx<double> z)
+{
+    double r = hypot(z.re, z.im);
+    if (r == 0.0) return {0.0, 0.0};
+    if (z.re >= 0.0) {
+        double t = sqrt(0.5 * (r + z.re));
+        return {t, z.im / (2.0 * t)};
+    }
+    double t = sqrt(0.5 * (r - z.re));
+    return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+// s_m(lam) = sqrt(lam^2 - k^2), principal branch.
+__host__ __device__ inline cx<double> sroot_d(cx<double> lam, cx<double> k) { return csqrt_d(lam * lam - k * k); }
+
+struct Medium {
+    cx<double> k1, k2, k3;
+    double d;
+};
+
+// sigma_2^t(lam) of the three-layer medium (Section 1; Section 3 Example 4),
+// with numerator and denominator divided by exp(d s2) so that every factor
+// stays bounded (Re s2 >= 0).
+__host__ __device__ inline cx<double> sigma2t_d(cx<double> lam, const Medium &m, cx<double> s1, cx<double> s2)
+{
+    cx<double> s3 = sroot_d(lam, m.k3);
+    cx<double> e = cexp_d(mk(-2.0 * m.d * s2.re, -2.0 * m.d * s2.im));
+    cx<double> l2 = lam * lam, kk = m.k2 * m.k2;
+    cx<double> num = l2 + s2 * s3 - kk;
+    cx<double> one = mk(1.0, 0.0);
+    cx<double> den = 0.5 * ((one - e) * (l2 + s1 * s3 - kk)) + 0.5 * (s2 * (s1 + s3) * (one + e));
+    return cdiv(num, den);
+}
+
+// ---------------------------------------------------------------------------
+// Scaled Bessel bases of the expansions.
+//
+// Multipole basis (sign = -1) at offset (X, Y) from the box centre, wave
+// number k, scale radius R:   B_q = s_q J_q(k r) e^{-i q theta},
+// local basis (sign = +1):    B_p = s_p J_p(k r) e^{+i p theta},
+// with s_q = |q|! (2/(kR))^|q| so that |B_q| <= ~(r/R)^|q| at low frequency.
+// J_{-q} = (-1)^q J_q.  Computed by Miller's backward recurrence on the ratios
+// t_m = J_m / (z J_{m-1}) = 1/(2m - z^2 t_{m+1}), z = k r, which needs only
+// z^2 = k^2 (X^2 + Y^2) (no square root or angle), and the normalisation
+// 1 = J_0 + 2 sum_m J_{2m}.  Then J_q e^{i sign q theta} s_q / (J_{q-1} ...) =
+// 2 q t_q (X + i sign Y) / R.
+// ---------------------------------------------------------------------------
+template <typename T, int PMAX>
+__host__ __device__ inline void bessel_ratios(cx<T> k, T X, T Y, int P, cx<T> *tm, cx<T> &J0)
+{
+    cx<T> z2 = (k * k) * (X * X + Y * Y);
+    T az = sqrt(sqrt(cabs2(z2)));
+    int N = P + 16 + (int)(az * T(1.2));
+    cx<T> t = mk<T>(0, 0), tprev = mk<T>(0, 0);
+    // U = 2 sum_{even j >= max(m,2)} J_j / J_m, updated at every odd m:
+    // U_{m-1} = 2 [m-1 >= 2] + U_{m+1} z^2 t_{m+1} t_m.
+    cx<T> U = mk<T>(0, 0);
+    for (int m = N; m > P; --m) {
+        t = cinv(mk<T>(T(2 * m), T(0)) - z2 * t);
+        if (m & 1) {
+            U = U * (z2 * (tprev * t));
+            if (m - 1 >= 2) U.re += T(2);
+        }
+        tprev = t;
+    }
+#pragma unroll
+    for (int m = PMAX; m >= 1; --m) {
+        if (m <= P) {
+            t = cinv(mk<T>(T(2 * m), T(0)) - z2 * t);
+            tm[m] = t;
+            if (m & 1) {
+                U = U * (z2 * (tprev * t));
+                if (m - 1 >= 2) U.re += T(2);
+            }
+            tprev = t;
+        }
+    }
+    J0 = cinv(mk<T>(T(1), T(0)) + U);
+}
+
+// Scaled basis values written to out[(P+q)*stride], q = -P..P.
+template <typename T, int PMAX>
+__host__ __device__ inline void bessel_basis(cx<T> k, T X, T Y, T invR, int P, int sign, cx<T> *out, int stride)
+{
+    cx<T> tm[PMAX + 1];
+    cx<T> J0;
+    bessel_ratios<T, PMAX>(k, X, Y, P, tm, J0);
+    out[P * stride] = J0;
+    cx<T> up = mk<T>(X * invR, T(sign) * Y * invR);   // (X + i sign Y)/R
+    cx<T> dn = mk<T>(-X * invR, T(sign) * Y * invR);  // -(X - i sign Y)/R
+    cx<T> vp = J0, vm = J0;
+#pragma unroll
+    for (int q = 1; q <= PMAX; ++q) {
+        if (q <= P) {
+            cx<T> f = T(2 * q) * tm[q];
+            vp = vp * (f * up);
+            vm = vm * (f * dn);
+            out[(P + q) * stride] = vp;
+            out[(P - q) * stride] = vm;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tree geometry
+// ---------------------------------------------------------------------------
+constexpr int MAXLEV = 24;
+
+struct Level {
+    int P;           // expansion order at this level
+    int nc;          // 2P + 1
+    int col_lo;      // first column (global index) covered at this level
+    int ncol;        // columns covered
+    int rows_s;      // rows of source boxes (above y = 0)
+    int rows_t;      // rows of target boxes (below y = 0)
+    double w;        // box width
+    int64_t off_s;   // offset (in complex elements) of this level's multipole block
+    int64_t off_t;   // offset of this level's local block
+};
+
+struct Geometry {
+    double x_lo, W;
+    int L;
+    Level lev[MAXLEV + 1];
+    int64_t ncoef_s, ncoef_t;  // total complex coefficients (times nrhs)
+};
+
+// Near-field node record (FP64): lambda, s1, s2 and the weighted density D =
+// dlam-weight * sigma_2^t / (4 pi s2).
+struct Node {
+    double lr, li, s1r, s1i, s2r, s2i, dr, di;
+};
+
+constexpr int NGL = 16;  // Gauss-Legendre points per panel
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+// tree.hip
+void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double d, double *partial,
+                 int nblk, double *out, hipStream_t st);
+int bbox_blocks(int64_t n);
+struct SortBufs {
+    uint32_t *key_a, *key_b;
+    int32_t *idx_a, *idx_b;
+    uint32_t *hist;  // 256 * nblk
+    int nblk;
+};
+int sort_blocks(int64_t n);
+// returns 0 if the result ends in key_a/idx_a, 1 if in key_b/idx_b
+int launch_radix_sort(SortBufs &b, int64_t n, int bits, hipStream_t st);
+void launch_leaf_ranges(const uint32_t *key, const int32_t *idx, int64_t n, int64_t nbox, int32_t *start,
+                        int32_t *end, const double *src, int64_t ns, const double *tgt, int64_t nt, double *xs,
+                        double *ys, hipStream_t st);
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
+void launch_keys(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
+                 int ncol, int rows_s, int rows_t, double d, uint32_t *key, int32_t *idx, int32_t *err,
+                 hipStream_t st);
+
+// expand.hip (T = double or float)
+template <typename T>
+void launch_p2m(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
+                const void *q, int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st);
+template <typename T>
+void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int nrhs, hipStream_t st);
+template <typename T>
+void launch_m2l(const Geometry &g, int l, const cx<T> *atab, const int *cls_index, const cx<T> *M, cx<T> *Lc,
+                int nrhs, const cx<T> *l2l_tab, int do_m2l, hipStream_t st);
+template <typename T>
+void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
+                     const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
+                     Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far,
+                     int do_near, void *u, hipStream_t st);
+void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, int nrhs, int prec,
+                   const Node *nodes, int nmid, int npan, double t0, void *u, hipStream_t st);
+
+// tables.hip
+void launch_node_table(const double *lamw, int n, Medium med, Node *out, hipStream_t st);
+void launch_m2l_tables(const double *lamw, const int *node_cls, const int *node_local, int ntot,
+                       const double *cls_geo, Medium med, const int *cls_P, const int *cls_Q,
+                       const int64_t *cls_toff, const int64_t *cls_aoff, int ncls, int ncmax, cx<double> *Tm,
+                       cx<double> *Sm, cx<double> *A, cx<float> *A32, hipStream_t st);
+
+}  // namespace lmfmm

@@ -1,0 +1,896 @@
+// Host side of the library: plan state, tree geometry, table construction and
+// the apply sequence of Algorithm 1, behind the C ABI of include/lmfmm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lmfmm.h"
+#include "lmfmm_internal.h"
+
+using namespace lmfmm;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                                            \
+    do {                                                                                                     \
+        hipError_t e_ = (x);                                                                                 \
+        if (e_ != hipSuccess) return fail(LMFMM_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device buffer
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    int ensure(size_t bytes)
+    {
+        if (bytes <= n && p) return LMFMM_OK;
+        if (p) {
+            hipDeviceSynchronize();
+            hipFree(p);
+            p = nullptr;
+            n = 0;
+        }
+        size_t want = bytes < 256 ? 256 : bytes;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            return fail(LMFMM_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+        }
+        n = want;
+        return LMFMM_OK;
+    }
+    void release()
+    {
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// Bump allocator over one device arena.
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *r = reinterpret_cast<T *>(base + off);
+        off += count * sizeof(T);
+        return r;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre rule (Newton on the Legendre polynomial, three-term recurrence)
+// ---------------------------------------------------------------------------
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            double dz = p1 / pp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p1 = 1.0, p2 = 0.0;
+        for (int j = 1; j <= n; ++j) {
+            double p3 = p2;
+            p2 = p1;
+            p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+        }
+        pp = n * (z * p1 - p2) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+typedef std::complex<double> zc;
+
+// Nodes of one contour piece: appends (lam, weight) pairs.
+struct NodeList {
+    std::vector<double> lw;  // [n][4]: lam re, lam im, w re, w im
+    int count() const { return (int)(lw.size() / 4); }
+    void add(zc lam, zc w)
+    {
+        lw.push_back(lam.real());
+        lw.push_back(lam.imag());
+        lw.push_back(w.real());
+        lw.push_back(w.imag());
+    }
+};
+
+static const std::vector<double> &gl_x()
+{
+    static std::vector<double> x, w;
+    if (x.empty()) gauss_legendre(NGL, x, w);
+    return x;
+}
+static const std::vector<double> &gl_w()
+{
+    static std::vector<double> x, w;
+    if (w.empty()) gauss_legendre(NGL, x, w);
+    return w;
+}
+
+// Finite piece of the contour: lam(t) = t - i h sin(pi t / c), t in [-c, c],
+// below the real axis for Re lam > 0 and above it for Re lam < 0, where the
+// integrand has no singularity (Section 4.2, Fig. 1 argument).
+static void add_bump(NodeList &nl, double c, double h, int npan)
+{
+    const auto &X = gl_x();
+    const auto &W = gl_w();
+    for (int p = 0; p < npan; ++p) {
+        double a = -c + 2.0 * c * p / npan, b = -c + 2.0 * c * (p + 1) / npan;
+        double hw = 0.5 * (b - a), m = 0.5 * (a + b);
+        for (int i = 0; i < NGL; ++i) {
+            double t = m + hw * X[i];
+            zc lam(t, -h * std::sin(M_PI * t / c));
+            zc dl(1.0, -h * M_PI / c * std::cos(M_PI * t / c));
+            nl.add(lam, W[i] * hw * dl);
+        }
+    }
+}
+
+// Ray panel [ta, tb] of both rays: right lam = c + t e^{i s psi}, left
+// lam = -c - t e^{-i s psi} (traversed towards -c); weights include dlam/dt.
+static void add_ray_panel(NodeList &nl, double c, double psi, double sgn, double ta, double tb)
+{
+    const auto &X = gl_x();
+    const auto &W = gl_w();
+    zc er = std::polar(1.0, sgn * psi), el = std::polar(1.0, -sgn * psi);
+    double hw = 0.5 * (tb - ta), m = 0.5 * (ta + tb);
+    for (int i = 0; i < NGL; ++i) {
+        double t = m + hw * X[i];
+        nl.add(zc(c, 0) + t * er, W[i] * hw * er);
+    }
+    for (int i = 0; i < NGL; ++i) {
+        double t = m + hw * X[i];
+        nl.add(zc(-c, 0) - t * el, W[i] * hw * el);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct LevelTables {
+    int P = 0, Pp = 0;
+    DevBuf m2m64, m2m32, l2l64, l2l32;  // [4][nc_in][nc_out]
+    DevBuf a64, a32;                    // M2L tables [slot][nc][nc]
+    DevBuf cls;                         // int[28]
+    int nslots = 0;
+    int64_t nodes = 0;
+};
+
+struct lmfmm_plan_s {
+    Medium med;
+    int order = 16;
+    double tol = 1e-6;
+    int levels_opt = 0;
+    int fixed_order = 0;
+    bool have_domain = false;
+    double dom[4] = {0, 0, 0, 0};  // xmin, xmax, ys_max, yt_min
+    bool do_near = true, do_far = true;
+
+    DevBuf ws;
+    double *h_bbox = nullptr;  // pinned
+    DevBuf bbox_dev;
+
+    // cached far-field tables
+    int t_L = -1;
+    double t_W = -1;
+    int t_P[MAXLEV + 1] = {0};
+    LevelTables lt[MAXLEV + 1];
+    double table_seconds = 0;
+
+    // near-field node table
+    DevBuf near_nodes;
+    double n_c = 0, n_h = -1, n_t0 = 0;
+    int n_nmid = 0, n_npan = 0;
+    int64_t n_count = 0;
+
+    // direct-sum node table
+    DevBuf dir_nodes;
+    double d_h = -1;
+    int d_nmid = 0, d_npan = 0;
+    double d_t0 = 0;
+
+    Geometry geo;
+    lmfmm_stats stats;
+    int32_t *d_err = nullptr;  // device error flag of the last apply (in the workspace)
+};
+
+static double kmax_re(const Medium &m) { return std::max(m.k1.re, std::max(m.k2.re, m.k3.re)); }
+static double contour_c(const Medium &m) { return std::max(1.0, 1.25 * kmax_re(m)); }
+
+// Expansion order at a level: max(order, the order the tolerance needs for the
+// worst one-box-separated pair (ratio ~0.4 per term, Theorem 1), the order
+// the box size needs at the largest wave number).
+static int order_for_level(const lmfmm_plan_s *p, double w)
+{
+    if (p->fixed_order) return p->order;
+    double R = w / std::sqrt(2.0);
+    double kabs = std::max(std::abs(zc(p->med.k1.re, p->med.k1.im)), std::abs(zc(p->med.k2.re, p->med.k2.im)));
+    int ptol = (int)std::ceil(std::log(p->tol) / std::log(0.4));
+    int phf = (int)std::ceil(1.2 * kabs * R + 10.0);
+    int P = std::max(p->order, std::max(ptol, phf));
+    return std::min(P, 480);
+}
+
+// Build the geometry from a bounding box {xmin, xmax, ys_min, ys_max, yt_min, yt_max}.
+static int make_geometry(lmfmm_plan_s *p, const double *bb, int64_t ns, int nrhs, Geometry &g)
+{
+    double xmin = bb[0], xmax = bb[1], ysmax = bb[3], ytmin = bb[4];
+    if (!(xmax >= xmin)) xmin = xmax = 0.0;
+    if (!(ysmax > 0)) ysmax = 0.0;
+    if (!(ytmin < 0)) ytmin = 0.0;
+    double ext = std::max(xmax - xmin, 2.0 * std::max(ysmax, -ytmin));
+    if (!(ext > 0)) ext = 1.0;
+    double W = ext * (1.0 + 1e-9) + 1e-300;
+    g.W = W;
+    g.x_lo = 0.5 * (xmin + xmax) - 0.5 * W;
+    int L = p->levels_opt;
+    if (L <= 0) {
+        L = 1;
+        for (int l = 2; l <= 20; ++l) {
+            double w = W / std::ldexp(1.0, l);
+            double ncol = std::floor((xmax - g.x_lo) / w) - std::floor((xmin - g.x_lo) / w) + 1;
+            double rows = std::floor(std::max(ysmax, 0.0) / w) + 1;
+            rows = std::min(rows, std::ldexp(1.0, l - 1));
+            if ((double)ns / (ncol * rows) >= 24.0)
+                L = l;
+            else
+                break;
+        }
+    }
+    if (L > MAXLEV) return fail(LMFMM_EINVAL, "too many levels");
+    g.L = L;
+    double wL = W / std::ldexp(1.0, L);
+    long maxcol = (1L << L) - 1, maxrow = (1L << (L - 1)) - 1;
+    long clo = (long)std::floor((xmin - g.x_lo) / wL), chi = (long)std::floor((xmax - g.x_lo) / wL);
+    clo = std::max(0L, std::min(clo, maxcol));
+    chi = std::max(clo, std::min(chi, maxcol));
+    long rs = std::min((long)std::floor(ysmax / wL), maxrow) + 1;
+    long rt = std::min((long)std::floor(-ytmin / wL), maxrow) + 1;
+    int64_t offs = 0, offt = 0;
+    for (int l = L; l >= 1; --l) {
+        Level &lv = g.lev[l];
+        int sh = L - l;
+        lv.w = W / std::ldexp(1.0, l);
+        lv.col_lo = (int)(clo >> sh);
+        lv.ncol = (int)((chi >> sh) - (clo >> sh) + 1);
+        lv.rows_s = (int)(((rs - 1) >> sh) + 1);
+        lv.rows_t = (int)(((rt - 1) >> sh) + 1);
+        lv.P = order_for_level(p, lv.w);
+        lv.nc = 2 * lv.P + 1;
+    }
+    g.lev[0] = g.lev[1];
+    for (int l = 1; l <= L; ++l) {
+        Level &lv = g.lev[l];
+        lv.off_s = offs;
+        lv.off_t = offt;
+        offs += (int64_t)lv.rows_s * lv.ncol * lv.nc * nrhs;
+        offt += (int64_t)lv.rows_t * lv.ncol * lv.nc * nrhs;
+    }
+    g.ncoef_s = offs;
+    g.ncoef_t = offt;
+    return LMFMM_OK;
+}
+
+// Free-space shift tables (Lemma M2M with k1, Lemma L2L with k2), scaled.
+// g_m = J_m(k rho) e^{sign i m phi} for |m| <= M, from the Bessel ratios.
+static void shift_coeffs(zc k, double X, double Y, int M, int sign, std::vector<zc> &g)
+{
+    std::vector<cx<double>> tm(M + 1);
+    cx<double> J0;
+    cx<double> kk = {k.real(), k.imag()};
+    // bessel_ratios is instantiated with a large static bound on the host
+    std::vector<cx<double>> buf(1025);
+    bessel_ratios<double, 1024>(kk, X, Y, M, buf.data(), J0);
+    g.assign(2 * M + 1, zc(0, 0));
+    zc j0(J0.re, J0.im);
+    g[M] = j0;
+    zc up = k * zc(X, sign * Y), dn = -k * zc(X, -sign * Y);
+    zc vp = j0, vm = j0;
+    for (int m = 1; m <= M; ++m) {
+        zc t(buf[m].re, buf[m].im);
+        vp *= t * up;
+        vm *= t * dn;
+        g[M + m] = vp;
+        g[M - m] = vm;
+    }
+}
+
+// log of the scale factor s_n = |n|! (2/(kR))^|n| as a complex number
+static zc log_scale(int n, zc k, double R)
+{
+    int a = std::abs(n);
+    return zc(std::lgamma(a + 1.0), 0.0) + (double)a * std::log(zc(2.0, 0.0) / (k * R));
+}
+
+static int upload(DevBuf &b, const void *h, size_t bytes)
+{
+    int rc = b.ensure(bytes);
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(b.p, h, bytes, hipMemcpyHostToDevice));
+    return LMFMM_OK;
+}
+
+static int build_shift_tables(lmfmm_plan_s *p, const Geometry &g, int l)
+{
+    // children at level l, parents at level l - 1
+    LevelTables &T = p->lt[l];
+    const Level &c = g.lev[l], &pa = g.lev[l - 1];
+    int ncc = c.nc, ncp = pa.nc, Pc = c.P, Pp = pa.P;
+    double Rc = c.w / std::sqrt(2.0), Rp = pa.w / std::sqrt(2.0);
+    zc k1(p->med.k1.re, p->med.k1.im), k2(p->med.k2.re, p->med.k2.im);
+    std::vector<cx<double>> m2m((size_t)4 * ncc * ncp), l2l((size_t)4 * ncp * ncc);
+    std::vector<zc> gm;
+    for (int pos = 0; pos < 4; ++pos) {
+        int dx = pos & 1, dy = pos >> 1;
+        double X = (dx - 0.5) * c.w;
+        // sources: child centre minus parent centre, multipole shift with k1
+        double Ys = (dy - 0.5) * c.w;
+        shift_coeffs(k1, X, Ys, Pc + Pp, -1, gm);
+        for (int a = 0; a < ncc; ++a)
+            for (int b = 0; b < ncp; ++b) {
+                int np_ = b - Pp, nc_ = a - Pc;  // parent index n, child index n'
+                zc sc = std::exp(log_scale(np_, k1, Rp) - log_scale(nc_, k1, Rc));
+                zc v = sc * gm[(Pc + Pp) + (np_ - nc_)];
+                m2m[((size_t)pos * ncc + a) * ncp + b] = {v.real(), v.imag()};
+            }
+        // targets: child centre minus parent centre (rows grow downwards), local shift with k2
+        double Yt = -(dy - 0.5) * c.w;
+        shift_coeffs(k2, X, Yt, Pc + Pp, +1, gm);
+        for (int a = 0; a < ncp; ++a)
+            for (int b = 0; b < ncc; ++b) {
+                int npp = a - Pp, nch = b - Pc;  // parent index n'', child index n
+                zc sc = std::exp(log_scale(npp, k2, Rp) - log_scale(nch, k2, Rc));
+                zc v = sc * gm[(Pc + Pp) + (npp - nch)];
+                l2l[((size_t)pos * ncp + a) * ncc + b] = {v.real(), v.imag()};
+            }
+    }
+    std::vector<cx<float>> m2m32(m2m.size()), l2l32(l2l.size());
+    for (size_t i = 0; i < m2m.size(); ++i) m2m32[i] = {(float)m2m[i].re, (float)m2m[i].im};
+    for (size_t i = 0; i < l2l.size(); ++i) l2l32[i] = {(float)l2l[i].re, (float)l2l[i].im};
+    int rc;
+    if ((rc = upload(T.m2m64, m2m.data(), m2m.size() * sizeof(cx<double>)))) return rc;
+    if ((rc = upload(T.m2m32, m2m32.data(), m2m32.size() * sizeof(cx<float>)))) return rc;
+    if ((rc = upload(T.l2l64, l2l.data(), l2l.size() * sizeof(cx<double>)))) return rc;
+    if ((rc = upload(T.l2l32, l2l32.data(), l2l32.size() * sizeof(cx<float>)))) return rc;
+    return LMFMM_OK;
+}
+
+// M2L tables of one level: one class per (target row, source row, column offset).
+static int build_m2l_tables(lmfmm_plan_s *p, const Geometry &g, int l)
+{
+    LevelTables &T = p->lt[l];
+    const Level &lv = g.lev[l];
+    int P = lv.P, nc = lv.nc;
+    double w = lv.w, R = w / std::sqrt(2.0), c = contour_c(p->med);
+    std::vector<int> cls_index(28, -1);
+    NodeList nl;
+    std::vector<int> node_cls, node_local, cP, cQ;
+    std::vector<int64_t> toff, aoff;
+    std::vector<double> geo;
+    int64_t tsum = 0;
+    int slot = 0;
+    for (int rt = 0; rt < 2 && rt < lv.rows_t; ++rt)
+        for (int rs = 0; rs < 2 && rs < lv.rows_s; ++rs)
+            for (int dc = -3; dc <= 3; ++dc) {
+                if (rt == 0 && rs == 0 && std::abs(dc) <= 1) continue;
+                double dxc = -dc * w;  // x_t - x_s with source column = target column + dc
+                double yt = -(rt + 0.5) * w, ys = (rs + 0.5) * w;
+                double a = ys - yt;
+                double psi = std::atan2(std::fabs(dxc), a), sgn = dxc >= 0 ? 1.0 : -1.0;
+                double rho = std::hypot(dxc, a);
+                double h = std::fabs(dxc) > 0 ? std::min(0.25 * c, 3.0 / std::fabs(dxc)) : 0.25 * c;
+                int nmp = std::max(16, (int)std::ceil(4.0 * c / h));
+                int start = nl.count();
+                add_bump(nl, c, h, nmp);
+                double umax = 2.0 * P + 60.0;
+                double e0 = std::min(c, 2.0 / rho);
+                for (int k = 0; k < 4; ++k) add_ray_panel(nl, c, psi, sgn, e0 * k / 4, e0 * (k + 1) / 4);
+                for (double t = e0; t * rho < umax; t += 2.0 / rho) add_ray_panel(nl, c, psi, sgn, t, t + 2.0 / rho);
+                int Q = nl.count() - start;
+                for (int i = 0; i < Q; ++i) {
+                    node_cls.push_back(slot);
+                    node_local.push_back(i);
+                }
+                cls_index[(rt * 2 + rs) * 7 + dc + 3] = slot;
+                cP.push_back(P);
+                cQ.push_back(Q);
+                toff.push_back(tsum);
+                aoff.push_back((int64_t)slot * nc * nc);
+                tsum += (int64_t)Q * nc;
+                geo.push_back(dxc);
+                geo.push_back(yt);
+                geo.push_back(ys);
+                geo.push_back(R);
+                ++slot;
+            }
+    T.nslots = slot;
+    T.nodes = nl.count();
+    int rc;
+    if ((rc = upload(T.cls, cls_index.data(), 28 * sizeof(int)))) return rc;
+    if (slot == 0) return LMFMM_OK;
+    DevBuf d_lw, d_ncls, d_nloc, d_geo, d_P, d_Q, d_toff, d_aoff, d_T, d_S;
+    if ((rc = upload(d_lw, nl.lw.data(), nl.lw.size() * sizeof(double)))) return rc;
+    if ((rc = upload(d_ncls, node_cls.data(), node_cls.size() * sizeof(int)))) return rc;
+    if ((rc = upload(d_nloc, node_local.data(), node_local.size() * sizeof(int)))) return rc;
+    if ((rc = upload(d_geo, geo.data(), geo.size() * sizeof(double)))) return rc;
+    if ((rc = upload(d_P, cP.data(), cP.size() * sizeof(int)))) return rc;
+    if ((rc = upload(d_Q, cQ.data(), cQ.size() * sizeof(int)))) return rc;
+    if ((rc = upload(d_toff, toff.data(), toff.size() * sizeof(int64_t)))) return rc;
+    if ((rc = upload(d_aoff, aoff.data(), aoff.size() * sizeof(int64_t)))) return rc;
+    if ((rc = d_T.ensure((size_t)tsum * sizeof(cx<double>)))) return rc;
+    if ((rc = d_S.ensure((size_t)tsum * sizeof(cx<double>)))) return rc;
+    if ((rc = T.a64.ensure((size_t)slot * nc * nc * sizeof(cx<double>)))) return rc;
+    if ((rc = T.a32.ensure((size_t)slot * nc * nc * sizeof(cx<float>)))) return rc;
+    launch_m2l_tables((const double *)d_lw.p, (const int *)d_ncls.p, (const int *)d_nloc.p, nl.count(),
+                      (const double *)d_geo.p, p->med, (const int *)d_P.p, (const int *)d_Q.p,
+                      (const int64_t *)d_toff.p, (const int64_t *)d_aoff.p, slot, nc, (cx<double> *)d_T.p,
+                      (cx<double> *)d_S.p, (cx<double> *)T.a64.p, (cx<float> *)T.a32.p, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    d_lw.release();
+    d_ncls.release();
+    d_nloc.release();
+    d_geo.release();
+    d_P.release();
+    d_Q.release();
+    d_toff.release();
+    d_aoff.release();
+    d_T.release();
+    d_S.release();
+    return LMFMM_OK;
+}
+
+// Near-field node table on the contour: bump over [-c, c] plus the two rays at
+// 45 degrees (valid for x1 - x0 >= 0; |x1 - x0| is used by evenness).  The
+// panel count covers pairs down to a vertical gap a_min.
+static int build_near_table(DevBuf &buf, const Medium &med, double dxmax, double amin, double &c_out, double &h_out,
+                            double &t0_out, int &nmid_out, int &npan_out)
+{
+    double c = contour_c(med);
+    double h = std::min(0.25 * c, 3.0 / std::max(dxmax, 1e-300));
+    int nmp = std::max(16, (int)std::ceil(4.0 * c / h));
+    double t0 = c / 8.0;
+    double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
+    int npan = 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0))));
+    npan = std::min(npan, 64);
+    NodeList nl;
+    add_bump(nl, c, h, nmp);
+    int nmid = nl.count();
+    for (int m = 0; m < npan; ++m) {
+        double ta = m == 0 ? 0.0 : t0 * std::ldexp(1.0, m - 1), tb = t0 * std::ldexp(1.0, m);
+        add_ray_panel(nl, c, M_PI / 4, 1.0, ta, tb);
+    }
+    DevBuf lw;
+    int rc;
+    if ((rc = upload(lw, nl.lw.data(), nl.lw.size() * sizeof(double)))) return rc;
+    if ((rc = buf.ensure((size_t)nl.count() * sizeof(Node)))) return rc;
+    launch_node_table((const double *)lw.p, nl.count(), med, (Node *)buf.p, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    lw.release();
+    c_out = c;
+    h_out = h;
+    t0_out = t0;
+    nmid_out = nmid;
+    npan_out = npan;
+    return LMFMM_OK;
+}
+
+static int ensure_far_tables(lmfmm_plan_s *p, const Geometry &g)
+{
+    bool same = p->t_L == g.L && p->t_W == g.W;
+    for (int l = 1; same && l <= g.L; ++l) same = p->t_P[l] == g.lev[l].P;
+    if (same) return LMFMM_OK;
+    double t_start = (double)clock() / CLOCKS_PER_SEC;
+    int rc;
+    for (int l = 2; l <= g.L; ++l)
+        if ((rc = build_m2l_tables(p, g, l))) return rc;
+    for (int l = 3; l <= g.L; ++l)
+        if ((rc = build_shift_tables(p, g, l))) return rc;
+    p->t_L = g.L;
+    p->t_W = g.W;
+    for (int l = 0; l <= MAXLEV; ++l) p->t_P[l] = l <= g.L ? g.lev[l].P : 0;
+    p->table_seconds = (double)clock() / CLOCKS_PER_SEC - t_start;
+    return LMFMM_OK;
+}
+
+static int ensure_near_table(lmfmm_plan_s *p, const Geometry &g, double amin)
+{
+    double dxmax = 2.0 * g.lev[g.L].w;
+    double c = contour_c(p->med);
+    double h = std::min(0.25 * c, 3.0 / dxmax);
+    double t0 = c / 8.0;
+    double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
+    int npan = std::min(64, 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0)))));
+    if (p->near_nodes.p && p->n_h == h && p->n_npan >= npan) return LMFMM_OK;
+    int rc = build_near_table(p->near_nodes, p->med, dxmax, amin, p->n_c, p->n_h, p->n_t0, p->n_nmid, p->n_npan);
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *lmfmm_status_string(int s)
+{
+    switch (s) {
+    case LMFMM_OK: return "ok";
+    case LMFMM_EINVAL: return "invalid argument";
+    case LMFMM_EDOMAIN: return "point outside its layer or domain";
+    case LMFMM_ENOMEM: return "out of memory";
+    case LMFMM_EHIP: return "HIP runtime error";
+    case LMFMM_ETOL: return "tolerance cannot be met";
+    case LMFMM_ENODEV: return "no GPU";
+    default: return "unknown status";
+    }
+}
+
+const char *lmfmm_last_error(void) { return g_last_error.c_str(); }
+
+int lmfmm_create(const double k[6], double d, int order, double tol, lmfmm_plan *out)
+{
+    if (!out) return fail(LMFMM_EINVAL, "out is null");
+    *out = nullptr;
+    if (!k) return fail(LMFMM_EINVAL, "k is null");
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(k[i])) return fail(LMFMM_EINVAL, "wave numbers must be finite");
+    if (!(k[0] > 0 && k[2] > 0 && k[4] > 0)) return fail(LMFMM_EINVAL, "Re k must be positive");
+    if (k[1] < 0 || k[3] < 0 || k[5] < 0) return fail(LMFMM_EINVAL, "Im k must be >= 0");
+    if (!(d > 0) || !std::isfinite(d)) return fail(LMFMM_EINVAL, "d must be positive");
+    if (order < 1 || order > 256) return fail(LMFMM_EINVAL, "order must be in [1, 256]");
+    if (!(tol > 0 && tol < 1)) return fail(LMFMM_EINVAL, "tol must be in (0, 1)");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(LMFMM_ENODEV, "no HIP device available");
+    lmfmm_plan_s *p = new (std::nothrow) lmfmm_plan_s();
+    if (!p) return fail(LMFMM_ENOMEM, "plan allocation failed");
+    p->med.k1 = {k[0], k[1]};
+    p->med.k2 = {k[2], k[3]};
+    p->med.k3 = {k[4], k[5]};
+    p->med.d = d;
+    p->order = order;
+    p->tol = tol;
+    std::memset(&p->stats, 0, sizeof(p->stats));
+    if (hipHostMalloc((void **)&p->h_bbox, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete p;
+        return fail(LMFMM_ENOMEM, "pinned allocation failed");
+    }
+    if (p->bbox_dev.ensure(8 * 520 * sizeof(double))) {
+        hipHostFree(p->h_bbox);
+        delete p;
+        return LMFMM_ENOMEM;
+    }
+    *out = p;
+    return LMFMM_OK;
+}
+
+int lmfmm_destroy(lmfmm_plan p)
+{
+    if (!p) return fail(LMFMM_EINVAL, "plan is null");
+    hipDeviceSynchronize();
+    p->ws.release();
+    p->bbox_dev.release();
+    p->near_nodes.release();
+    p->dir_nodes.release();
+    for (auto &t : p->lt) {
+        t.m2m64.release();
+        t.m2m32.release();
+        t.l2l64.release();
+        t.l2l32.release();
+        t.a64.release();
+        t.a32.release();
+        t.cls.release();
+    }
+    if (p->h_bbox) hipHostFree(p->h_bbox);
+    delete p;
+    return LMFMM_OK;
+}
+
+int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
+{
+    if (!p || !key || !value) return fail(LMFMM_EINVAL, "null argument");
+    std::string k(key), v(value);
+    if (k == "levels") {
+        if (v == "auto") {
+            p->levels_opt = 0;
+            return LMFMM_OK;
+        }
+        int L = std::atoi(value);
+        if (L < 1 || L > MAXLEV) return fail(LMFMM_EINVAL, "levels must be in [1, 24] or auto");
+        p->levels_opt = L;
+        return LMFMM_OK;
+    }
+    if (k == "fixed_order") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "fixed_order must be 0 or 1");
+        p->fixed_order = v == "1";
+        return LMFMM_OK;
+    }
+    if (k == "near" || k == "far") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "near/far must be 0 or 1");
+        (k == "near" ? p->do_near : p->do_far) = v == "1";
+        return LMFMM_OK;
+    }
+    if (k == "domain") {
+        if (v == "auto") {
+            p->have_domain = false;
+            return LMFMM_OK;
+        }
+        double a[4];
+        if (std::sscanf(value, "%lf,%lf,%lf,%lf", &a[0], &a[1], &a[2], &a[3]) != 4)
+            return fail(LMFMM_EINVAL, "domain must be 'xmin,xmax,ys_max,yt_min' or auto");
+        if (!(a[1] >= a[0]) || !(a[2] > 0) || !(a[3] < 0)) return fail(LMFMM_EINVAL, "bad domain");
+        std::memcpy(p->dom, a, sizeof a);
+        p->have_domain = true;
+        return LMFMM_OK;
+    }
+    return fail(LMFMM_EINVAL, "unknown option '" + k + "'");
+}
+
+int lmfmm_get_stats(lmfmm_plan p, lmfmm_stats *s)
+{
+    if (!p || !s) return fail(LMFMM_EINVAL, "null argument");
+    *s = p->stats;
+    return LMFMM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Apply
+// ---------------------------------------------------------------------------
+static int check_common(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, const double *tgt, const void *in,
+                        void *out, int nrhs, int prec)
+{
+    if (!p) return fail(LMFMM_EINVAL, "plan is null");
+    if (ns < 0 || nt < 0) return fail(LMFMM_EINVAL, "negative size");
+    if (ns > (int64_t)1 << 30 || nt > (int64_t)1 << 30) return fail(LMFMM_EINVAL, "too many points");
+    if (nrhs < 1 || nrhs > 64) return fail(LMFMM_EINVAL, "nrhs must be in [1, 64]");
+    if (prec != LMFMM_C128 && prec != LMFMM_C64_MIXED) return fail(LMFMM_EINVAL, "unknown precision");
+    if ((ns > 0 && !src) || (nt > 0 && !tgt)) return fail(LMFMM_EINVAL, "null coordinates");
+    if ((ns > 0 && !in) || (nt > 0 && !out)) return fail(LMFMM_EINVAL, "null density or output");
+    return LMFMM_OK;
+}
+
+// Bounding box of the points (host readback) or the fixed domain.
+static int get_bbox(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, const double *tgt, hipStream_t st,
+                    double *bb)
+{
+    if (p->have_domain) {
+        bb[0] = p->dom[0];
+        bb[1] = p->dom[1];
+        bb[2] = 0.0;
+        bb[3] = p->dom[2];
+        bb[4] = p->dom[3];
+        bb[5] = 0.0;
+        bb[6] = 0.0;
+        return LMFMM_OK;
+    }
+    int64_t n = ns + nt;
+    int nblk = bbox_blocks(n);
+    double *part = (double *)p->bbox_dev.p, *outp = part + 8 * 512;
+    launch_bbox(src, ns, tgt, nt, p->med.d, part, nblk, outp, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(p->h_bbox, outp, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(bb, p->h_bbox, 8 * sizeof(double));
+    if (bb[6] > 0) return fail(LMFMM_EDOMAIN, std::to_string((long long)bb[6]) + " point(s) outside their layer");
+    return LMFMM_OK;
+}
+
+template <typename T>
+static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt,
+                      void *u, int nrhs, int prec, hipStream_t st)
+{
+    if (nt == 0) return LMFMM_OK;
+    int rc;
+    if (ns == 0) {
+        launch_zero_bytes(u, (size_t)nt * nrhs * sizeof(cx<T>), st);
+        HIPCHK(hipGetLastError());
+        return LMFMM_OK;
+    }
+    double bb[8];
+    if ((rc = get_bbox(p, ns, src, nt, tgt, st, bb))) return rc;
+    Geometry &g = p->geo;
+    if ((rc = make_geometry(p, bb, ns, nrhs, g))) return rc;
+    const int L = g.L;
+    if (g.lev[L].P > 256) return fail(LMFMM_EINVAL, "leaf-level expansion order above 256: use more levels");
+    bool far = p->do_far && L >= 2;
+    if (far && (rc = ensure_far_tables(p, g))) return rc;
+    double amin = p->have_domain ? 1e-9 * g.W : std::max(bb[2], 0.0) + std::max(-bb[5], 0.0);
+    if (!(amin > 0)) amin = 1e-9 * g.W;
+    if ((rc = ensure_near_table(p, g, amin))) return rc;
+
+    // workspace
+    const Level &lv = g.lev[L];
+    int64_t n = ns + nt;
+    int64_t nbox = (int64_t)(lv.rows_s + lv.rows_t) * lv.ncol;
+    int nblk = sort_blocks(n);
+    size_t need = 0;
+    need += 2 * (size_t)n * 4 + 2 * (size_t)n * 4 + (size_t)256 * nblk * 4 + 2 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
+    need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 16 * 256;
+    if ((rc = p->ws.ensure(need))) return rc;
+    Carve cv{(char *)p->ws.p};
+    SortBufs sb;
+    sb.key_a = cv.take<uint32_t>(n);
+    sb.key_b = cv.take<uint32_t>(n);
+    sb.idx_a = cv.take<int32_t>(n);
+    sb.idx_b = cv.take<int32_t>(n);
+    sb.hist = cv.take<uint32_t>((size_t)256 * nblk);
+    sb.nblk = nblk;
+    int32_t *start = cv.take<int32_t>(nbox), *end = cv.take<int32_t>(nbox);
+    double *xs = cv.take<double>(n), *ys = cv.take<double>(n);
+    cx<T> *M = cv.take<cx<T>>(g.ncoef_s > 0 ? g.ncoef_s : 1);
+    cx<T> *Lc = cv.take<cx<T>>(g.ncoef_t > 0 ? g.ncoef_t : 1);
+    int32_t *err = cv.take<int32_t>(1);
+    p->d_err = err;
+
+    // Step 1: tree
+    launch_fill_i32(err, 1, 0, st);
+    launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, p->med.d, sb.key_a,
+                sb.idx_a, err, st);
+    int bits = 1;
+    while (((int64_t)1 << bits) < nbox) ++bits;
+    int which = launch_radix_sort(sb, n, bits, st);
+    uint32_t *key = which ? sb.key_b : sb.key_a;
+    int32_t *idx = which ? sb.idx_b : sb.idx_a;
+    launch_leaf_ranges(key, idx, n, nbox, start, end, src, ns, tgt, nt, xs, ys, st);
+
+    // Step 2: upward pass
+    if (far) {
+        launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, p->med, M, st);
+        for (int l = L; l >= 3; --l) {
+            const LevelTables &tb = p->lt[l];
+            const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
+            launch_m2m<T>(g, l, tab, M, nrhs, st);
+        }
+        // Step 3: downward pass
+        for (int l = 2; l <= L; ++l) {
+            const LevelTables &tb = p->lt[l];
+            const cx<T> *atab = (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p);
+            const cx<T> *l2l = nullptr;
+            if (l >= 3) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
+            launch_m2l<T>(g, l, atab, (const int *)tb.cls.p, M, Lc, nrhs, l2l, 1, st);
+        }
+    }
+    // Step 4: local evaluation and direct interactions
+    launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, p->med, Lc, (const Node *)p->near_nodes.p,
+                       p->n_nmid, p->n_npan, p->n_t0, far ? 1 : 0, p->do_near ? 1 : 0, u, st);
+    HIPCHK(hipGetLastError());
+
+    // statistics (host-side counts)
+    lmfmm_stats &s = p->stats;
+    s.levels = L;
+    for (int l = 0; l < 32; ++l) s.order[l] = l <= L ? g.lev[l].P : 0;
+    s.root_x_lo = g.x_lo;
+    s.root_width = g.W;
+    s.leaves_src = (int64_t)lv.rows_s * lv.ncol;
+    s.leaves_tgt = (int64_t)lv.rows_t * lv.ncol;
+    s.near_nodes_mid = p->n_nmid;
+    s.near_nodes_ray = p->n_npan * NGL;
+    int ncls = 0;
+    int64_t nn = 0;
+    for (int l = 2; l <= L && far; ++l) {
+        ncls += p->lt[l].nslots;
+        nn += p->lt[l].nodes;
+    }
+    s.m2l_classes = ncls;
+    s.m2l_nodes = nn;
+    s.table_seconds = p->table_seconds;
+    return LMFMM_OK;
+}
+
+extern "C" {
+
+int lmfmm_apply(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt, void *u,
+                int nrhs, int prec, void *stream)
+{
+    int rc = check_common(p, ns, src, nt, tgt, q, u, nrhs, prec);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    return prec == LMFMM_C128 ? apply_impl<double>(p, ns, src, q, nt, tgt, u, nrhs, prec, st)
+                              : apply_impl<float>(p, ns, src, q, nt, tgt, u, nrhs, prec, st);
+}
+
+int lmfmm_direct(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt, void *u,
+                 int nrhs, int prec, void *stream)
+{
+    int rc = check_common(p, ns, src, nt, tgt, q, u, nrhs, prec);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (nt == 0) return LMFMM_OK;
+    if (ns == 0) {
+        launch_zero_bytes(u, (size_t)nt * nrhs * (prec == LMFMM_C128 ? 16 : 8), st);
+        return LMFMM_OK;
+    }
+    bool saved = p->have_domain;
+    p->have_domain = false;
+    double bb[8];
+    rc = get_bbox(p, ns, src, nt, tgt, st, bb);
+    p->have_domain = saved;
+    if (rc) return rc;
+    double dxmax = std::max(bb[1] - bb[0], 1e-12);
+    double amin = std::max(bb[2], 0.0) + std::max(-bb[5], 0.0);
+    double c = contour_c(p->med), h = std::min(0.25 * c, 3.0 / dxmax), t0 = c / 8.0;
+    double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
+    int npan = std::min(64, 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0)))));
+    if (!p->dir_nodes.p || p->d_h != h || p->d_npan < npan) {
+        double cc, hh, tt;
+        int nm, np;
+        if ((rc = build_near_table(p->dir_nodes, p->med, dxmax, amin, cc, hh, tt, nm, np))) return rc;
+        p->d_h = hh;
+        p->d_nmid = nm;
+        p->d_npan = np;
+        p->d_t0 = tt;
+    }
+    launch_direct(src, ns, q, tgt, nt, nrhs, prec, (const Node *)p->dir_nodes.p, p->d_nmid, p->d_npan, p->d_t0, u,
+                  st);
+    HIPCHK(hipGetLastError());
+    return LMFMM_OK;
+}
+
+int lmfmm_apply_adjoint(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, const double *tgt, const void *w,
+                        void *v, int nrhs, int prec, void *stream)
+{
+    (void)ns; (void)src; (void)nt; (void)tgt; (void)w; (void)v; (void)nrhs; (void)prec; (void)stream;
+    if (!p) return fail(LMFMM_EINVAL, "plan is null");
+    return fail(LMFMM_EINVAL, "adjoint not available in this build");
+}
+
+int lmfmm_grad_coords(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt,
+                      const void *w, double *dsrc, double *dtgt, int nrhs, int prec, void *stream)
+{
+    (void)ns; (void)src; (void)q; (void)nt; (void)tgt; (void)w; (void)dsrc; (void)dtgt; (void)nrhs; (void)prec;
+    (void)stream;
+    if (!p) return fail(LMFMM_EINVAL, "plan is null");
+    return fail(LMFMM_EINVAL, "coordinate gradients not available in this build");
+}
+
+int lmfmm_sync_status(lmfmm_plan p, void *stream)
+{
+    if (!p) return fail(LMFMM_EINVAL, "plan is null");
+    hipStream_t st = (hipStream_t)stream;
+    if (p->d_err) {
+        HIPCHK(hipMemcpyAsync(p->h_bbox + 8, p->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int32_t e;
+        std::memcpy(&e, p->h_bbox + 8, sizeof e);
+        if (e) return fail(LMFMM_EDOMAIN, "a point lies outside the domain or its layer");
+        return LMFMM_OK;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return LMFMM_OK;
+}
+
+}  // extern "C"

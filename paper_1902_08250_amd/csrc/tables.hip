@@ -1,0 +1,162 @@
+// Quadrature-node tables (Algorithm 1, Step 1: "precompute necessary tables").
+//
+//  * Near-field table: on a contour fixed per plan and tree, the FP64 values
+//    lambda_n, s1(lambda_n), s2(lambda_n) and D_n = weight_n sigma_2^t / (4 pi s2).
+//  * M2L translation matrices (Lemma M2L, the remark on precomputing A per
+//    level): for a translation class with target centre (x_t, y_t) and source
+//    centre (x_s, y_s),
+//      Ahat_{p,q} = Int That_p(lam) Shat_q(lam) e^{s2 y_t - s1 y_s + i lam (x_t - x_s)}
+//                       sigma_2^t / (4 pi s2) d lam,
+//      That_p = (i (lam - s2) R/2)^p / p!,   That_{-m} = (-i (lam + s2) R/2)^m / m!,
+//      Shat_q = (-i (lam + s1) R/2)^q / q!,  Shat_{-m} = ( i (lam - s1) R/2)^m / m!,
+//    i.e. A_{p,q} of the lemma with the expansion scalings folded in.  The
+//    integral is a sum over the class's contour nodes, so the table is the
+//    contraction That * diag(D) * Shat over nodes.
+#include "lmfmm_internal.h"
+
+namespace lmfmm {
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_node_table(const double *__restrict__ lamw, int n, Medium med,
+                                                    Node *__restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cx<double> lam = {lamw[4 * i], lamw[4 * i + 1]};
+    cx<double> wt = {lamw[4 * i + 2], lamw[4 * i + 3]};
+    cx<double> s1 = sroot_d(lam, med.k1), s2 = sroot_d(lam, med.k2);
+    cx<double> sg = sigma2t_d(lam, med, s1, s2);
+    cx<double> D = cdiv(wt * sg, (4.0 * M_PI) * s2);
+    Node nd;
+    nd.lr = lam.re;
+    nd.li = lam.im;
+    nd.s1r = s1.re;
+    nd.s1i = s1.im;
+    nd.s2r = s2.re;
+    nd.s2i = s2.im;
+    nd.dr = D.re;
+    nd.di = D.im;
+    out[i] = nd;
+}
+
+// lam +- s without cancellation: the larger of the two is formed directly and
+// the other from (lam + s)(lam - s) = k^2.
+__device__ inline void plus_minus(cx<double> lam, cx<double> s, cx<double> k, cx<double> &a, cx<double> &b)
+{
+    a = lam + s;
+    b = lam - s;
+    if (cabs2(a) >= cabs2(b))
+        b = cdiv(k * k, a);
+    else
+        a = cdiv(k * k, b);
+}
+
+// One thread per node of any class.  cls_geo[c] = {dx_c, y_t, y_s, R}.
+__global__ void __launch_bounds__(256) k_m2l_factors(const double *__restrict__ lamw,
+                                                     const int *__restrict__ node_cls,
+                                                     const int *__restrict__ node_local, int ntot,
+                                                     const double *__restrict__ cls_geo, Medium med,
+                                                     const int *__restrict__ cls_P, const int *__restrict__ cls_Q,
+                                                     const int64_t *__restrict__ cls_toff,
+                                                     cx<double> *__restrict__ Tm, cx<double> *__restrict__ Sm)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot) return;
+    int c = node_cls[i], n = node_local[i];
+    int P = cls_P[c], Q = cls_Q[c], nc = 2 * P + 1;
+    double dxc = cls_geo[4 * c], yt = cls_geo[4 * c + 1], ys = cls_geo[4 * c + 2], R = cls_geo[4 * c + 3];
+    cx<double> lam = {lamw[4 * i], lamw[4 * i + 1]};
+    cx<double> wt = {lamw[4 * i + 2], lamw[4 * i + 3]};
+    cx<double> s1 = sroot_d(lam, med.k1), s2 = sroot_d(lam, med.k2);
+    cx<double> sg = sigma2t_d(lam, med, s1, s2);
+    cx<double> E = cexp_d(s2 * yt - s1 * ys + mk(-lam.im * dxc, lam.re * dxc));
+    cx<double> D = cdiv(wt * E * sg, (4.0 * M_PI) * s2);
+    cx<double> a1, b1, a2, b2;
+    plus_minus(lam, s1, med.k1, a1, b1);
+    plus_minus(lam, s2, med.k2, a2, b2);
+    double hR = 0.5 * R;
+    cx<double> I1 = {0.0, 1.0};
+    cx<double> tp = (I1 * b2) * hR, tn = (-I1 * a2) * hR;  // That ratios
+    cx<double> sp = (-I1 * a1) * hR, sn = (I1 * b1) * hR;  // Shat ratios
+    cx<double> *T = Tm + cls_toff[c];                      // [nc][Q]
+    cx<double> *S = Sm + cls_toff[c];                      // [Q][nc]
+    T[(int64_t)P * Q + n] = mk(1.0, 0.0);
+    S[(int64_t)n * nc + P] = D;
+    cx<double> vtp = mk(1.0, 0.0), vtn = mk(1.0, 0.0), vsp = D, vsn = D;
+    for (int m = 1; m <= P; ++m) {
+        double im = 1.0 / m;
+        vtp = vtp * (tp * im);
+        vtn = vtn * (tn * im);
+        vsp = vsp * (sp * im);
+        vsn = vsn * (sn * im);
+        T[(int64_t)(P + m) * Q + n] = vtp;
+        T[(int64_t)(P - m) * Q + n] = vtn;
+        S[(int64_t)n * nc + P + m] = vsp;
+        S[(int64_t)n * nc + P - m] = vsn;
+    }
+}
+
+// Ahat[c][q][p] = sum_n T[c][p][n] S[c][n][q]; 16x16 output tile per block,
+// FP64 complex with LDS-staged K tiles; writes FP64 and FP32 copies.
+constexpr int CT = 16, CK = 32;
+__global__ void __launch_bounds__(256) k_m2l_contract(const int *__restrict__ cls_P, const int *__restrict__ cls_Q,
+                                                      const int64_t *__restrict__ cls_toff,
+                                                      const int64_t *__restrict__ cls_aoff,
+                                                      const cx<double> *__restrict__ Tm,
+                                                      const cx<double> *__restrict__ Sm, cx<double> *__restrict__ A,
+                                                      cx<float> *__restrict__ A32)
+{
+    int c = blockIdx.z;
+    int P = cls_P[c], Q = cls_Q[c], nc = 2 * P + 1;
+    int p0 = blockIdx.x * CT, q0 = blockIdx.y * CT;
+    if (p0 >= nc || q0 >= nc) return;
+    const cx<double> *T = Tm + cls_toff[c];
+    const cx<double> *S = Sm + cls_toff[c];
+    __shared__ cx<double> Ts[CT][CK + 1];
+    __shared__ cx<double> Ss[CK][CT + 1];
+    int tx = threadIdx.x % CT, ty = threadIdx.x / CT;  // tx -> p, ty -> q
+    cx<double> acc = {0.0, 0.0};
+    for (int k0 = 0; k0 < Q; k0 += CK) {
+        for (int t = threadIdx.x; t < CT * CK; t += 256) {
+            int pp = t / CK, kk = t % CK;
+            int p = p0 + pp, k = k0 + kk;
+            Ts[pp][kk] = (p < nc && k < Q) ? T[(int64_t)p * Q + k] : mk(0.0, 0.0);
+            int kk2 = t / CT, qq = t % CT;
+            int q = q0 + qq, k2 = k0 + kk2;
+            Ss[kk2][qq] = (q < nc && k2 < Q) ? S[(int64_t)k2 * nc + q] : mk(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int kk = 0; kk < CK; ++kk) cfma(acc, Ts[tx][kk], Ss[kk][ty]);
+        __syncthreads();
+    }
+    int p = p0 + tx, q = q0 + ty;
+    if (p < nc && q < nc) {
+        int64_t o = cls_aoff[c] + (int64_t)q * nc + p;
+        A[o] = acc;
+        A32[o] = mk((float)acc.re, (float)acc.im);
+    }
+}
+
+}  // namespace
+
+void launch_node_table(const double *lamw, int n, Medium med, Node *out, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_node_table, dim3((n + 255) / 256), dim3(256), 0, st, lamw, n, med, out);
+}
+
+void launch_m2l_tables(const double *lamw, const int *node_cls, const int *node_local, int ntot,
+                       const double *cls_geo, Medium med, const int *cls_P, const int *cls_Q,
+                       const int64_t *cls_toff, const int64_t *cls_aoff, int ncls, int ncmax, cx<double> *Tm,
+                       cx<double> *Sm, cx<double> *A, cx<float> *A32, hipStream_t st)
+{
+    if (ntot <= 0 || ncls <= 0) return;
+    hipLaunchKernelGGL(k_m2l_factors, dim3((ntot + 255) / 256), dim3(256), 0, st, lamw, node_cls, node_local, ntot,
+                       cls_geo, med, cls_P, cls_Q, cls_toff, Tm, Sm);
+    int tiles = (ncmax + CT - 1) / CT;
+    hipLaunchKernelGGL(k_m2l_contract, dim3(tiles, tiles, ncls), dim3(256), 0, st, cls_P, cls_Q, cls_toff, cls_aoff,
+                       Tm, Sm, A, A32);
+}
+
+}  // namespace lmfmm

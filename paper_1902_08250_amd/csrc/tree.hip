@@ -1,0 +1,351 @@
+// Quadtree construction (Algorithm 1, Step 1): bounding box and layer checks,
+// leaf keys, a stable LSD radix sort of the keys, and leaf ranges.
+//
+// The tree is uniform with its root square split at the interface y = 0, so
+// every box holds either sources (above) or targets (below).  A leaf key is
+// (row, column) of the level-L box; target keys follow all source keys, so one
+// sort orders both point sets and the sorted array holds sources first.
+#include "lmfmm_internal.h"
+
+namespace lmfmm {
+
+namespace {
+
+constexpr int BB_THREADS = 256;
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__device__ inline double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Per-block partial bounding box: xmin, xmax over all points; source y min/max;
+// target y min/max; count of points outside their layer or not finite.
+__global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__restrict__ src, int64_t ns,
+                                                             const double *__restrict__ tgt, int64_t nt, double d,
+                                                             double *__restrict__ partial)
+{
+    double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += stride) {
+        double x = src[i], y = src[ns + i];
+        bool ok = isfinite(x) && isfinite(y) && y > 0.0;
+        if (ok) {
+            v[0] = fmin(v[0], x);
+            v[1] = fmax(v[1], x);
+            v[2] = fmin(v[2], y);
+            v[3] = fmax(v[3], y);
+        } else {
+            v[6] += 1.0;
+        }
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
+        double x = tgt[i], y = tgt[nt + i];
+        bool ok = isfinite(x) && isfinite(y) && y < 0.0 && y > -d;
+        if (ok) {
+            v[0] = fmin(v[0], x);
+            v[1] = fmax(v[1], x);
+            v[4] = fmin(v[4], y);
+            v[5] = fmax(v[5], y);
+        } else {
+            v[6] += 1.0;
+        }
+    }
+    __shared__ double red[BB_THREADS / 64][7];
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double r[7];
+    r[0] = wave_min(v[0]);
+    r[1] = wave_max(v[1]);
+    r[2] = wave_min(v[2]);
+    r[3] = wave_max(v[3]);
+    r[4] = wave_min(v[4]);
+    r[5] = wave_max(v[5]);
+    r[6] = wave_sum(v[6]);
+    if (lane == 0)
+        for (int j = 0; j < 7; ++j) red[wv][j] = r[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BB_THREADS / 64; ++w) {
+            r[0] = fmin(r[0], red[w][0]);
+            r[1] = fmax(r[1], red[w][1]);
+            r[2] = fmin(r[2], red[w][2]);
+            r[3] = fmax(r[3], red[w][3]);
+            r[4] = fmin(r[4], red[w][4]);
+            r[5] = fmax(r[5], red[w][5]);
+            r[6] += red[w][6];
+        }
+        for (int j = 0; j < 7; ++j) partial[blockIdx.x * 8 + j] = r[j];
+    }
+}
+
+__global__ void __launch_bounds__(64) k_bbox_final(const double *__restrict__ partial, int nblk,
+                                                   double *__restrict__ out)
+{
+    double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += 64) {
+        const double *p = partial + b * 8;
+        v[0] = fmin(v[0], p[0]);
+        v[1] = fmax(v[1], p[1]);
+        v[2] = fmin(v[2], p[2]);
+        v[3] = fmax(v[3], p[3]);
+        v[4] = fmin(v[4], p[4]);
+        v[5] = fmax(v[5], p[5]);
+        v[6] += p[6];
+    }
+    v[0] = wave_min(v[0]);
+    v[1] = wave_max(v[1]);
+    v[2] = wave_min(v[2]);
+    v[3] = wave_max(v[3]);
+    v[4] = wave_min(v[4]);
+    v[5] = wave_max(v[5]);
+    v[6] = wave_sum(v[6]);
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < 7; ++j) out[j] = v[j];
+        out[7] = 0.0;
+    }
+}
+
+// Leaf key of every point.  Sources (y > 0) take row floor(y/w) above the
+// interface, targets row floor(-y/w) below it; columns are relative to
+// col_lo.  Out-of-range rows/columns (points outside a fixed domain) and
+// points in the wrong layer raise the error flag and are clamped.
+__global__ void __launch_bounds__(256) k_keys(const double *__restrict__ src, int64_t ns,
+                                              const double *__restrict__ tgt, int64_t nt, double x_lo, double invw,
+                                              int col_lo, int ncol, int rows_s, int rows_t, double d,
+                                              uint32_t *__restrict__ key, int32_t *__restrict__ idx,
+                                              int32_t *__restrict__ err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns + nt) return;
+    bool tg = i >= ns;
+    double x = tg ? tgt[i - ns] : src[i];
+    double y = tg ? tgt[nt + i - ns] : src[ns + i];
+    bool bad = !(isfinite(x) && isfinite(y)) || (tg ? !(y < 0.0 && y > -d) : !(y > 0.0));
+    double fc = floor((x - x_lo) * invw) - (double)col_lo;
+    double fr = floor((tg ? -y : y) * invw);
+    int rows = tg ? rows_t : rows_s;
+    if (!(fc >= 0.0 && fc < (double)ncol && fr >= 0.0 && fr < (double)rows)) bad = true;
+    int c = (int)fmin(fmax(fc, 0.0), (double)(ncol - 1));
+    int r = (int)fmin(fmax(fr, 0.0), (double)(rows - 1));
+    if (bad) atomicOr(err, 1);
+    uint32_t k = (uint32_t)r * (uint32_t)ncol + (uint32_t)c;
+    if (tg) k += (uint32_t)rows_s * (uint32_t)ncol;
+    key[i] = k;
+    idx[i] = (int32_t)i;
+}
+
+// Radix sort pass, step 1: per-tile digit histogram, stored digit-major.
+__global__ void __launch_bounds__(RS_THREADS) k_rs_upsweep(const uint32_t *__restrict__ key, int64_t n, int shift,
+                                                           uint32_t *__restrict__ hist, int nblk)
+{
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int j = threadIdx.x; j < RS_TILE; j += RS_THREADS) {
+        int64_t g = base + j;
+        if (g < n) atomicAdd(&cnt[(key[g] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Step 2: exclusive scan of the digit-major histogram (one block).
+__global__ void __launch_bounds__(1024) k_rs_scan(uint32_t *__restrict__ hist, int64_t total)
+{
+    __shared__ uint32_t part[1024];
+    int64_t chunk = (total + 1023) / 1024;
+    int64_t lo = threadIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += hist[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - s;
+    for (int64_t i = lo; i < hi; ++i) {
+        uint32_t c = hist[i];
+        hist[i] = run;
+        run += c;
+    }
+}
+
+// Step 3: stable scatter.  Each tile is processed in rounds of 256 elements in
+// index order; within a round an element's rank among equal digits comes from
+// wave ballots over the 8 digit bits plus the counts of earlier waves.
+__global__ void __launch_bounds__(RS_THREADS) k_rs_downsweep(const uint32_t *__restrict__ kin,
+                                                             const int32_t *__restrict__ iin,
+                                                             uint32_t *__restrict__ kout, int32_t *__restrict__ iout,
+                                                             int64_t n, int shift, const uint32_t *__restrict__ hist,
+                                                             int nblk)
+{
+    constexpr int NW = RS_THREADS / 64;
+    __shared__ uint32_t offs[256];
+    __shared__ uint32_t wcnt[NW][256];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    offs[tid] = hist[(int64_t)tid * nblk + blockIdx.x];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t g = base + (int64_t)r * RS_THREADS + tid;
+        bool act = g < n;
+        uint32_t k = act ? kin[g] : 0u;
+        uint32_t dg = (k >> shift) & 255u;
+        for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        uint64_t m = __ballot(act);
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (dg >> b) & 1u;
+            uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        uint32_t rank = (uint32_t)__popcll(m & lt);
+        if (act && rank == 0) wcnt[wv][dg] = (uint32_t)__popcll(m);
+        __syncthreads();
+        {
+            uint32_t acc = offs[tid];
+            for (int w = 0; w < NW; ++w) {
+                uint32_t c = wcnt[w][tid];
+                wcnt[w][tid] = acc;
+                acc += c;
+            }
+            offs[tid] = acc;
+        }
+        __syncthreads();
+        if (act) {
+            uint32_t pos = wcnt[wv][dg] + rank;
+            kout[pos] = k;
+            iout[pos] = iin[g];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Leaf ranges [start, end) per key and the sorted coordinates.
+__global__ void __launch_bounds__(256) k_leaf_ranges(const uint32_t *__restrict__ key,
+                                                     const int32_t *__restrict__ idx, int64_t n,
+                                                     int32_t *__restrict__ start, int32_t *__restrict__ end,
+                                                     const double *__restrict__ src, int64_t ns,
+                                                     const double *__restrict__ tgt, int64_t nt,
+                                                     double *__restrict__ xs, double *__restrict__ ys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t k = key[i];
+    if (i == 0 || key[i - 1] != k) start[k] = (int32_t)i;
+    if (i == n - 1 || key[i + 1] != k) end[k] = (int32_t)(i + 1);
+    int64_t o = idx[i];
+    if (o < ns) {
+        xs[i] = src[o];
+        ys[i] = src[ns + o];
+    } else {
+        xs[i] = tgt[o - ns];
+        ys[i] = tgt[nt + o - ns];
+    }
+}
+
+}  // namespace
+
+int bbox_blocks(int64_t n)
+{
+    int64_t b = (n + 4095) / 4096;
+    if (b < 1) b = 1;
+    if (b > 512) b = 512;
+    return (int)b;
+}
+
+void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double d, double *partial, int nblk,
+                 double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(BB_THREADS), 0, st, src, ns, tgt, nt, d, partial);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, partial, nblk, out);
+}
+
+void launch_keys(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
+                 int ncol, int rows_s, int rows_t, double d, uint32_t *key, int32_t *idx, int32_t *err,
+                 hipStream_t st)
+{
+    int64_t n = ns + nt;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, ns, tgt, nt, x_lo, 1.0 / w,
+                       col_lo, ncol, rows_s, rows_t, d, key, idx, err);
+}
+
+int sort_blocks(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
+
+int launch_radix_sort(SortBufs &b, int64_t n, int bits, hipStream_t st)
+{
+    int passes = (bits + 7) / 8;
+    int nblk = sort_blocks(n);
+    uint32_t *kin = b.key_a, *kout = b.key_b;
+    int32_t *iin = b.idx_a, *iout = b.idx_b;
+    for (int p = 0; p < passes; ++p) {
+        int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_upsweep, dim3(nblk), dim3(RS_THREADS), 0, st, kin, n, shift, b.hist, nblk);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, b.hist, (int64_t)256 * nblk);
+        hipLaunchKernelGGL(k_rs_downsweep, dim3(nblk), dim3(RS_THREADS), 0, st, kin, iin, kout, iout, n, shift,
+                           b.hist, nblk);
+        uint32_t *tk = kin;
+        kin = kout;
+        kout = tk;
+        int32_t *ti = iin;
+        iin = iout;
+        iout = ti;
+    }
+    return (passes & 1) ? 1 : 0;
+}
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st)
+{
+    int64_t n = (int64_t)(nbytes / 4);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t *)p, n);
+}
+
+void launch_leaf_ranges(const uint32_t *key, const int32_t *idx, int64_t n, int64_t nbox, int32_t *start,
+                        int32_t *end, const double *src, int64_t ns, const double *tgt, int64_t nt, double *xs,
+                        double *ys, hipStream_t st)
+{
+    launch_fill_i32(start, nbox, 0, st);
+    launch_fill_i32(end, nbox, 0, st);
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_leaf_ranges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, key, idx, n, start, end,
+                       src, ns, tgt, nt, xs, ys);
+}
+
+}  // namespace lmfmm
