@@ -74,11 +74,17 @@ int lmfmm_destroy(lmfmm_plan plan);
 /* Set an option (string key/value).  Keys:
  *   "levels"      quadtree depth L >= 1, or "auto" (default, ~40 points/leaf)
  *   "fixed_order" "1": use exactly `order` at every level, ignoring tol
- *   "domain"      "x_lo,width": fix the root square [x_lo, x_lo+width] x
- *                 [-width/2, width/2] (skips the bounding-box readback, so
- *                 an apply queues no host synchronisation); "auto" to clear
+ *   "domain"      "xmin,xmax,ys_max,yt_min": use this box in place of the
+ *                 points' bounding box (x range of all points, largest
+ *                 source y, smallest target y); skips the bounding-box
+ *                 readback, so an apply queues no host synchronisation.
+ *                 Points outside it raise the device error flag (see
+ *                 lmfmm_sync_status).  "auto" (default) clears it.
  *   "near"        "1" (default) / "0": include / skip the near field
  *   "far"         "1" (default) / "0": include / skip the far field
+ *   "timing"      "1": record HIP events around every stage of each apply
+ *                 on the apply's stream and accumulate their durations in
+ *                 lmfmm_stats.stage_ms; "0" stops; "reset" zeroes the sums
  * Returns LMFMM_EINVAL for an unknown key or malformed value. */
 int lmfmm_set_option(lmfmm_plan plan, const char *key, const char *value);
 
@@ -130,6 +136,11 @@ typedef struct {
     int m2l_classes;       /* translation classes with a table               */
     int64_t m2l_nodes;     /* quadrature nodes summed over all classes       */
     double table_seconds;  /* host wall time of the last M2L table rebuild   */
+    /* with the "timing" option: summed event durations (ms) and launch counts
+     * per stage: 0 tree build, 1 P2M, 2 M2M, 3 M2L+L2L, 4 L2P+near field    */
+    double stage_ms[8];
+    int64_t stage_launches[8];
+    int64_t timed_applies;
 } lmfmm_stats;
 
 int lmfmm_get_stats(lmfmm_plan plan, lmfmm_stats *stats);

@@ -224,7 +224,27 @@ struct lmfmm_plan_s {
     Geometry geo;
     lmfmm_stats stats;
     int32_t *d_err = nullptr;  // device error flag of the last apply (in the workspace)
+
+    // stage timing
+    bool timing = false;
+    bool ev_pending = false;
+    hipEvent_t ev[6] = {};
+    int ev_launch[5] = {0, 0, 0, 0, 0};
 };
+
+// Fold the events of the previous timed apply into the statistics.
+static void collect_timing(lmfmm_plan_s *p)
+{
+    if (!p->ev_pending) return;
+    hipEventSynchronize(p->ev[5]);
+    for (int s = 0; s < 5; ++s) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev[s], p->ev[s + 1]) == hipSuccess) p->stats.stage_ms[s] += ms;
+        p->stats.stage_launches[s] += p->ev_launch[s];
+    }
+    p->stats.timed_applies += 1;
+    p->ev_pending = false;
+}
 
 static double kmax_re(const Medium &m) { return std::max(m.k1.re, std::max(m.k2.re, m.k3.re)); }
 static double contour_c(const Medium &m) { return std::max(1.0, 1.25 * kmax_re(m)); }
@@ -614,6 +634,8 @@ int lmfmm_destroy(lmfmm_plan p)
         t.cls.release();
     }
     if (p->h_bbox) hipHostFree(p->h_bbox);
+    for (int i = 0; i < 6; ++i)
+        if (p->ev[i]) hipEventDestroy(p->ev[i]);
     delete p;
     return LMFMM_OK;
 }
@@ -642,6 +664,24 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         (k == "near" ? p->do_near : p->do_far) = v == "1";
         return LMFMM_OK;
     }
+    if (k == "timing") {
+        if (v == "reset") {
+            collect_timing(p);
+            for (int i = 0; i < 8; ++i) {
+                p->stats.stage_ms[i] = 0;
+                p->stats.stage_launches[i] = 0;
+            }
+            p->stats.timed_applies = 0;
+            return LMFMM_OK;
+        }
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "timing must be 0, 1 or reset");
+        if (v == "1" && !p->ev[0])
+            for (int i = 0; i < 6; ++i)
+                if (hipEventCreate(&p->ev[i]) != hipSuccess) return fail(LMFMM_EHIP, "hipEventCreate failed");
+        collect_timing(p);
+        p->timing = v == "1";
+        return LMFMM_OK;
+    }
     if (k == "domain") {
         if (v == "auto") {
             p->have_domain = false;
@@ -661,6 +701,7 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
 int lmfmm_get_stats(lmfmm_plan p, lmfmm_stats *s)
 {
     if (!p || !s) return fail(LMFMM_EINVAL, "null argument");
+    collect_timing(p);
     *s = p->stats;
     return LMFMM_OK;
 }
@@ -756,7 +797,15 @@ static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q
     int32_t *err = cv.take<int32_t>(1);
     p->d_err = err;
 
+    collect_timing(p);
+    const bool tm = p->timing;
+    auto mark = [&](int i) {
+        if (tm) hipEventRecord(p->ev[i], st);
+    };
+    int nlaunch[5] = {0, 0, 0, 0, 0};
+
     // Step 1: tree
+    mark(0);
     launch_fill_i32(err, 1, 0, st);
     launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, p->med.d, sb.key_a,
                 sb.idx_a, err, st);
@@ -766,16 +815,27 @@ static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q
     uint32_t *key = which ? sb.key_b : sb.key_a;
     int32_t *idx = which ? sb.idx_b : sb.idx_a;
     launch_leaf_ranges(key, idx, n, nbox, start, end, src, ns, tgt, nt, xs, ys, st);
+    nlaunch[0] = 5 + 3 * ((bits + 7) / 8);
+    mark(1);
 
     // Step 2: upward pass
     if (far) {
         launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, p->med, M, st);
+        nlaunch[1] = 1;
+    }
+    mark(2);
+    if (far) {
+        nlaunch[2] = L - 2;
         for (int l = L; l >= 3; --l) {
             const LevelTables &tb = p->lt[l];
             const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
             launch_m2m<T>(g, l, tab, M, nrhs, st);
         }
+    }
+    mark(3);
+    if (far) {
         // Step 3: downward pass
+        nlaunch[3] = L - 1;
         for (int l = 2; l <= L; ++l) {
             const LevelTables &tb = p->lt[l];
             const cx<T> *atab = (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p);
@@ -784,10 +844,17 @@ static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q
             launch_m2l<T>(g, l, atab, (const int *)tb.cls.p, M, Lc, nrhs, l2l, 1, st);
         }
     }
+    mark(4);
     // Step 4: local evaluation and direct interactions
     launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, p->med, Lc, (const Node *)p->near_nodes.p,
                        p->n_nmid, p->n_npan, p->n_t0, far ? 1 : 0, p->do_near ? 1 : 0, u, st);
+    nlaunch[4] = 1;
+    mark(5);
     HIPCHK(hipGetLastError());
+    if (tm) {
+        for (int i = 0; i < 5; ++i) p->ev_launch[i] = nlaunch[i];
+        p->ev_pending = true;
+    }
 
     // statistics (host-side counts)
     lmfmm_stats &s = p->stats;

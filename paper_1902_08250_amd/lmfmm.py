@@ -33,7 +33,8 @@ class Stats(ctypes.Structure):
                 ("root_width", ctypes.c_double), ("near_pairs", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("leaves_src", ctypes.c_int64), ("leaves_tgt", ctypes.c_int64), ("near_nodes_mid", ctypes.c_int),
                 ("near_nodes_ray", ctypes.c_int), ("m2l_classes", ctypes.c_int), ("m2l_nodes", ctypes.c_int64),
-                ("table_seconds", ctypes.c_double)]
+                ("table_seconds", ctypes.c_double), ("stage_ms", ctypes.c_double * 8),
+                ("stage_launches", ctypes.c_int64 * 8), ("timed_applies", ctypes.c_int64)]
 
 
 EXPORTS = ["lmfmm_create", "lmfmm_destroy", "lmfmm_set_option", "lmfmm_apply", "lmfmm_apply_adjoint",
@@ -190,4 +191,6 @@ class Plan:
         _check(lib().lmfmm_get_stats(self._h, ctypes.byref(s)))
         d = {f: getattr(s, f) for f, _ in Stats._fields_}
         d["order"] = list(s.order)[: s.levels + 1]
+        d["stage_ms"] = list(s.stage_ms)[:5]
+        d["stage_launches"] = list(s.stage_launches)[:5]
         return d
