@@ -66,104 +66,182 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ start, c
 }
 
 // ---------------------------------------------------------------------------
-// M2M: one wave per parent box at level lp = lc - 1.
-// tab: [4 children][nc_child][nc_parent] (transposed for coalesced reads).
-// Child position c = 2*dy + dx (dx: column parity, dy: row parity).
+// Translations as batched complex contractions over boxes.
+//
+// out[b][p] = sum_k A[k][p] X_b[k] for a tile of 16 boxes and 64 output
+// coefficients per block, K staged through LDS in chunks of 32.  The three
+// translations differ only in where X_b comes from and where the result goes:
+//   L2L (Lemma L2L): A = shift table of one child position, X_b = the local
+//        expansion of parent b (with its pending M2L partials); result ->
+//        the child of b at that position;
+//   M2L (Lemma M2L): A = Ahat of one class (target row, source row, column
+//        offset); X_b = the multipole of the source box of target column b,
+//        zero where the class does not apply; result -> partial[class][b];
+//   M2M (Lemma M2M): A = the four child tables stacked along K; X_b = the
+//        four children of parent b; result -> parent b.
+// M2L partials are summed, in class order, by the next reader of the level's
+// local expansions (the child level's L2L or the leaf evaluation).
 // ---------------------------------------------------------------------------
+constexpr int GB = 16, GP = 64;
+// K chunk: 64 for FP32, 32 for FP64 (about 33 KB of A in LDS either way)
 template <typename T>
-__global__ void __launch_bounds__(64) k_m2m(const cx<T> *__restrict__ Mc, cx<T> *__restrict__ Mp,
-                                            const cx<T> *__restrict__ tab, int nrhs, int ncc, int ncp, int ncol_c,
-                                            int col_lo_c, int rows_c, int ncol_p, int col_lo_p)
+struct Chunk {
+    static constexpr int GK = sizeof(T) == 4 ? 64 : 32;
+    static constexpr int NA = GK * GP / 256;  // A elements staged per thread
+    static constexpr int NX = GB * GK / 256;  // X elements staged per thread
+};
+
+// Loads of one K chunk are issued into registers together (and the next
+// chunk is fetched while the current one is multiplied), so a block pays
+// one memory latency per chunk instead of one per element.
+template <typename T, typename XF, typename OF>
+__device__ inline void box_gemm(const cx<T> *__restrict__ A, int nk, int nout, int nbox, int b0, int p0, XF xload,
+                                OF store, cx<T> (*Xs)[Chunk<T>::GK + 1], cx<T> (*As)[GP + 1])
 {
-    extern __shared__ unsigned char smem_raw[];
-    cx<T> *C = reinterpret_cast<cx<T> *>(smem_raw);  // [4][ncc]
-    const int box = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
-    const int prow = box / ncol_p, pcol = col_lo_p + box % ncol_p;
-    for (int c = 0; c < 4; ++c) {
-        int dx = c & 1, dy = c >> 1;
-        int crow = 2 * prow + dy, ccol = 2 * pcol + dx - col_lo_c;
-        bool ok = crow < rows_c && ccol >= 0 && ccol < ncol_c;
-        const cx<T> *src = Mc + (((int64_t)crow * ncol_c + ccol) * nrhs + r) * ncc;
-        for (int t = lane; t < ncc; t += 64) C[c * ncc + t] = ok ? src[t] : mk<T>(0, 0);
-    }
-    __syncthreads();
-    for (int n = lane; n < ncp; n += 64) {
-        cx<T> acc = mk<T>(0, 0);
-        for (int c = 0; c < 4; ++c) {
-            const cx<T> *tc = tab + (int64_t)c * ncc * ncp;
-            const cx<T> *mc = C + c * ncc;
-            for (int k = 0; k < ncc; ++k) cfma(acc, tc[(int64_t)k * ncp + n], mc[k]);
+    constexpr int GK = Chunk<T>::GK, NA = Chunk<T>::NA, NX = Chunk<T>::NX;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    cx<T> acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = mk<T>(0, 0);
+    cx<T> ra[NA], rx[NX];
+    auto fetch = [&](int k0) {
+        const int kc = nk - k0 < GK ? nk - k0 : GK;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            int t = tid + 256 * i, kk = t / GP, pp = t % GP;
+            ra[i] = (kk < kc && p0 + pp < nout) ? A[(int64_t)(k0 + kk) * nout + p0 + pp] : mk<T>(0, 0);
         }
-        Mp[((int64_t)box * nrhs + r) * ncp + n] = acc;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            int t = tid + 256 * i, bb = t / GK, kk = t % GK;
+            rx[i] = (kk < kc && b0 + bb < nbox) ? xload(b0 + bb, k0 + kk) : mk<T>(0, 0);
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < nk; k0 += GK) {
+        const int kc = nk - k0 < GK ? nk - k0 : GK;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            int t = tid + 256 * i;
+            As[t / GP][t % GP] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            int t = tid + 256 * i;
+            Xs[t / GK][t % GK] = rx[i];
+        }
+        __syncthreads();
+        if (k0 + GK < nk) fetch(k0 + GK);
+        for (int kk = 0; kk < kc; ++kk) {
+            cx<T> a = As[kk][lane];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cfma(acc[j], a, Xs[wv * 4 + j][kk]);
+        }
+        __syncthreads();
     }
+    const int p = p0 + lane;
+    if (p < nout)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int b = b0 + wv * 4 + j;
+            if (b < nbox) store(b, p, acc[j]);
+        }
 }
 
-// ---------------------------------------------------------------------------
-// Fused L2L + M2L at level l: one wave per target box.
-// l2l: [4 child positions][nc_parent][nc] or null at the top level.
-// atab: M2L tables, [class][nc (q)][nc (p)]; cls_index[(rt*2+rs)*7 + dcol+3]
-// gives the class slot or -1.
-// ---------------------------------------------------------------------------
+// Class slots of one level grouped by target row (row 0 and row 1).
+struct RowSlots {
+    int n[2];
+    int s[2][14];
+};
+
+// Local expansion of a box including the M2L partials not yet folded in.
 template <typename T>
-__global__ void __launch_bounds__(64) k_m2l_l2l(const cx<T> *__restrict__ Ms, const cx<T> *__restrict__ Lp,
-                                                cx<T> *__restrict__ Lc, const cx<T> *__restrict__ atab,
-                                                const int *__restrict__ cls_index, const cx<T> *__restrict__ l2l,
-                                                int nrhs, int nc, int ncp, int ncol, int col_lo, int rows_s,
-                                                int ncol_p, int col_lo_p, int do_m2l)
+__device__ inline cx<T> local_value(const cx<T> *__restrict__ Lc, int base, const cx<T> *__restrict__ part,
+                                    const RowSlots &rsl, int row, int col_local, int ncol, int nrhs, int r, int nc,
+                                    int k)
 {
-    extern __shared__ unsigned char smem_raw[];
-    cx<T> *S = reinterpret_cast<cx<T> *>(smem_raw);  // [max(nc, ncp)]
-    const int box = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
-    const int row = box / ncol, cl = box % ncol, col = col_lo + cl;
-    constexpr int MAXACC = 16;  // nc <= 1024
-    cx<T> acc[MAXACC];
-    for (int a = 0; a < MAXACC; ++a) acc[a] = mk<T>(0, 0);
-    // L2L from the parent
-    if (l2l) {
-        int prow = row >> 1, pcol = (col >> 1) - col_lo_p;
-        int c = ((row & 1) << 1) | (col & 1);
-        const cx<T> *src = Lp + (((int64_t)prow * ncol_p + pcol) * nrhs + r) * ncp;
-        for (int t = lane; t < ncp; t += 64) S[t] = src[t];
-        __syncthreads();
-        const cx<T> *tc = l2l + (int64_t)c * ncp * nc;
-#pragma unroll
-        for (int a = 0; a < MAXACC; ++a) {
-            int p = lane + 64 * a;
-            if (p < nc)
-                for (int k = 0; k < ncp; ++k) cfma(acc[a], tc[(int64_t)k * nc + p], S[k]);
-        }
-        __syncthreads();
+    cx<T> v = base ? Lc[(((int64_t)row * ncol + col_local) * nrhs + r) * nc + k] : mk<T>(0, 0);
+    if (row < 2)
+        for (int i = 0; i < rsl.n[row]; ++i)
+            v += part[(((int64_t)rsl.s[row][i] * ncol + col_local) * nrhs + r) * nc + k];
+    return v;
+}
+
+struct DownArgs {
+    // level l
+    int nc, ncol, col_lo, rows_s, rows_t, nslots;
+    // level l - 1
+    int ncp, ncol_p, col_lo_p, rows_t_p, base_p;
+    int has_l2l;
+    RowSlots rsl_p;  // parent level's classes by target row
+};
+
+// Downward pass of one level: blockIdx.z in [0, 4 nrhs) is L2L (when the
+// parent level has local expansions), the rest M2L partials.
+template <typename T>
+__global__ void __launch_bounds__(256) k_down(DownArgs a, int nrhs, const cx<T> *__restrict__ Lp,
+                                              const cx<T> *__restrict__ part_p, const cx<T> *__restrict__ l2l,
+                                              cx<T> *__restrict__ Lc,
+                                              const cx<T> *__restrict__ Ms, const cx<T> *__restrict__ atab,
+                                              const int *__restrict__ cls_of, cx<T> *__restrict__ part)
+{
+    __shared__ cx<T> Xs[GB][Chunk<T>::GK + 1];
+    __shared__ cx<T> As[Chunk<T>::GK][GP + 1];
+    const int b0 = blockIdx.x * GB, p0 = blockIdx.y * GP;
+    int z = blockIdx.z;
+    if (a.has_l2l && z < 4 * nrhs) {
+        const int pos = z / nrhs, r = z % nrhs;
+        const int nbox = a.rows_t_p * a.ncol_p;
+        if (b0 >= nbox) return;
+        const int dx = pos & 1, dy = pos >> 1;
+        auto xload = [&](int b, int k) {
+            int prow = b / a.ncol_p, pcl = b % a.ncol_p;
+            return local_value<T>(Lp, a.base_p, part_p, a.rsl_p, prow, pcl, a.ncol_p, nrhs, r, a.ncp, k);
+        };
+        auto store = [&](int b, int p, cx<T> v) {
+            int prow = b / a.ncol_p, pcol = a.col_lo_p + b % a.ncol_p;
+            int crow = 2 * prow + dy, ccl = 2 * pcol + dx - a.col_lo;
+            if (crow < a.rows_t && ccl >= 0 && ccl < a.ncol) Lc[(((int64_t)crow * a.ncol + ccl) * nrhs + r) * a.nc + p] = v;
+        };
+        box_gemm<T>(l2l + (int64_t)pos * a.ncp * a.nc, a.ncp, a.nc, nbox, b0, p0, xload, store, Xs, As);
+        return;
     }
-    // M2L from the interaction list (only the two rows next to the interface)
-    if (do_m2l && row < 2) {
-        for (int rs = 0; rs < 2 && rs < rows_s; ++rs) {
-            for (int dc = -3; dc <= 3; ++dc) {
-                int slot = cls_index[(row * 2 + rs) * 7 + dc + 3];
-                if (slot < 0) continue;
-                int cs = col + dc;
-                int dp = (cs >> 1) - (col >> 1);
-                if (dp > 1 || dp < -1) continue;
-                int csl = cs - col_lo;
-                if (csl < 0 || csl >= ncol) continue;
-                const cx<T> *src = Ms + (((int64_t)rs * ncol + csl) * nrhs + r) * nc;
-                for (int t = lane; t < nc; t += 64) S[t] = src[t];
-                __syncthreads();
-                const cx<T> *A = atab + (int64_t)slot * nc * nc;
-#pragma unroll
-                for (int a = 0; a < MAXACC; ++a) {
-                    int p = lane + 64 * a;
-                    if (p < nc)
-                        for (int k = 0; k < nc; ++k) cfma(acc[a], A[(int64_t)k * nc + p], S[k]);
-                }
-                __syncthreads();
-            }
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < MAXACC; ++a) {
-        int p = lane + 64 * a;
-        if (p < nc) Lc[((int64_t)box * nrhs + r) * nc + p] = acc[a];
-    }
+    if (a.has_l2l) z -= 4 * nrhs;
+    const int slot = z / nrhs, r = z % nrhs;
+    const int nbox = a.ncol;
+    if (b0 >= nbox) return;
+    const int co = cls_of[slot];
+    const int rs = (co / 10) % 10, dc = co % 10 - 3;
+    auto xload = [&](int b, int k) {
+        int col = a.col_lo + b, cs = col + dc, csl = cs - a.col_lo;
+        int dp = (cs >> 1) - (col >> 1);
+        bool ok = rs < a.rows_s && csl >= 0 && csl < a.ncol && dp <= 1 && dp >= -1;
+        return ok ? Ms[(((int64_t)rs * a.ncol + csl) * nrhs + r) * a.nc + k] : mk<T>(0, 0);
+    };
+    auto store = [&](int b, int p, cx<T> v) { part[(((int64_t)slot * a.ncol + b) * nrhs + r) * a.nc + p] = v; };
+    box_gemm<T>(atab + (int64_t)slot * a.nc * a.nc, a.nc, a.nc, nbox, b0, p0, xload, store, Xs, As);
+}
+
+// Upward pass of one level: parents at level lc - 1 from their four children.
+template <typename T>
+__global__ void __launch_bounds__(256) k_up(const cx<T> *__restrict__ Mc, cx<T> *__restrict__ Mp,
+                                            const cx<T> *__restrict__ tab, int nrhs, int ncc, int ncp, int ncol_c,
+                                            int col_lo_c, int rows_c, int ncol_p, int col_lo_p, int rows_p)
+{
+    __shared__ cx<T> Xs[GB][Chunk<T>::GK + 1];
+    __shared__ cx<T> As[Chunk<T>::GK][GP + 1];
+    const int b0 = blockIdx.x * GB, p0 = blockIdx.y * GP, r = blockIdx.z;
+    const int nbox = rows_p * ncol_p;
+    if (b0 >= nbox) return;
+    auto xload = [&](int b, int k) {
+        int c = k / ncc, kk = k % ncc, dx = c & 1, dy = c >> 1;
+        int prow = b / ncol_p, pcol = col_lo_p + b % ncol_p;
+        int crow = 2 * prow + dy, ccl = 2 * pcol + dx - col_lo_c;
+        bool ok = crow < rows_c && ccl >= 0 && ccl < ncol_c;
+        return ok ? Mc[(((int64_t)crow * ncol_c + ccl) * nrhs + r) * ncc + kk] : mk<T>(0, 0);
+    };
+    auto store = [&](int b, int p, cx<T> v) { Mp[((int64_t)b * nrhs + r) * ncp + p] = v; };
+    box_gemm<T>(tab, 4 * ncc, ncp, nbox, b0, p0, xload, store, Xs, As);
 }
 
 // ---------------------------------------------------------------------------
@@ -173,8 +251,8 @@ __global__ void __launch_bounds__(64) k_m2l_l2l(const cx<T> *__restrict__ Ms, co
 // ---------------------------------------------------------------------------
 __device__ inline cx<double> node_term(const Node &nd, double y1, double y0, double dx)
 {
-    double er = nd.s2r * y1 - nd.s1r * y0 - nd.li * dx;
-    double ei = nd.s2i * y1 - nd.s1i * y0 + nd.lr * dx;
+    double er = nd.str * y1 - nd.ssr * y0 - nd.li * dx;
+    double ei = nd.sti * y1 - nd.ssi * y0 + nd.lr * dx;
     double m = exp(er), sn, cs;
     sincos(ei, &sn, &cs);
     double vr = m * cs, vi = m * sn;
@@ -224,7 +302,9 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
                                                  const double *__restrict__ ys, const cx<T> *__restrict__ q,
                                                  int64_t ns, int64_t nt, int nrhs, int P, int ncol, int col_lo,
                                                  int rows_s, double x_lo, double w, cx<T> k2, T invR,
-                                                 const cx<T> *__restrict__ Lc, const Node *__restrict__ nodes,
+                                                 const cx<T> *__restrict__ Lc, int base,
+                                                 const cx<T> *__restrict__ part, RowSlots rsl,
+                                                 const Node *__restrict__ nodes,
                                                  int nmid, int npan, double t0, int do_far, int do_near,
                                                  int64_t key_t0, cx<T> *__restrict__ u)
 {
@@ -241,7 +321,8 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
     if (e <= s) return;
     if (do_far) {
         for (int r = 0; r < nr; ++r)
-            for (int t = lane; t < nc; t += 64) Ls[r * nc + t] = Lc[((int64_t)box * nrhs + r0 + r) * nc + t];
+            for (int t = lane; t < nc; t += 64)
+                Ls[r * nc + t] = local_value<T>(Lc, base, part, rsl, row, cl, ncol, nrhs, r0 + r, nc, t);
         __syncthreads();
     }
     for (int c0 = s; c0 < e; c0 += 64) {
@@ -300,6 +381,147 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
     }
 }
 
+// Near-field derivative sums for the gradient: returns (sum D e^E lam, sum D e^E s_t)
+// so that d/dx1 = i sgn(x1 - x0) * first and d/dy1 = second.
+__device__ inline void pair_kernel_grad(const Node *__restrict__ nodes, int nmid, int npan, double t0, double y1,
+                                        double y0, double dx, bool act, cx<double> &GL, cx<double> &GS)
+{
+    int need = act ? panels_needed(y0 - y1, dx, t0, npan) : 0;
+    int wneed = wave_max_i(need);
+    GL = {0.0, 0.0};
+    GS = {0.0, 0.0};
+    auto add = [&](const Node &nd, cx<double> &al, cx<double> &as) {
+        cx<double> v = node_term(nd, y1, y0, dx);
+        al += v * cx<double>{nd.lr, nd.li};
+        as += v * cx<double>{nd.str, nd.sti};
+    };
+    for (int n = 0; n < nmid; ++n) add(nodes[n], GL, GS);
+    for (int m = 0; m < wneed; ++m) {
+        const Node *pn = nodes + nmid + m * 2 * NGL;
+        cx<double> al = {0.0, 0.0}, as = {0.0, 0.0};
+        for (int n = 0; n < 2 * NGL; ++n) add(pn[n], al, as);
+        if (m < need) {
+            GL += al;
+            GS += as;
+        }
+    }
+}
+
+// Coordinate gradient at the targets: gout[0][i] = Re sum_r c[r][i] du_r/dx(x_i),
+// gout[1][i] = ysign * Re sum_r c[r][i] du_r/dy(x_i), u = the field of densities q.
+// Far part: the local expansion's gradient is a local expansion of order P+1,
+//   d/dx (J_p e^{ip th}) = (k/2)(J_{p-1} e^{i(p-1)th} - J_{p+1} e^{i(p+1)th}),
+//   d/dy (J_p e^{ip th}) = (ik/2)(J_{p-1} e^{i(p-1)th} + J_{p+1} e^{i(p+1)th}),
+// rewritten for the scaled coefficients.  Near part: the integrand times
+// i lam sgn(x1 - x0) (x) or s_t (y).
+template <typename T, int PMAX>
+__global__ void __launch_bounds__(64) k_l2p_grad(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
+                                                 const int32_t *__restrict__ idx, const double *__restrict__ xs,
+                                                 const double *__restrict__ ys, const cx<T> *__restrict__ q,
+                                                 const cx<T> *__restrict__ cw, int64_t ns, int64_t nt, int nrhs,
+                                                 int r0, int nr, int accumulate,
+                                                 int P, int ncol, int col_lo, int rows_s, double x_lo, double w,
+                                                 cx<T> kt, T invR, const cx<T> *__restrict__ Lc, int base,
+                                                 const cx<T> *__restrict__ part, RowSlots rsl,
+                                                 const Node *__restrict__ nodes, int nmid, int npan, double t0,
+                                                 int do_far, int do_near, int64_t key_t0, double ysign,
+                                                 double *__restrict__ gout)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int ncg = 2 * (P + 1) + 1;           // gradient expansions have order P + 1
+    cx<T> *Gx = reinterpret_cast<cx<T> *>(smem_raw);  // [nr][ncg], right-hand sides r0 .. r0+nr-1
+    cx<T> *Gy = Gx + (size_t)nr * ncg;
+    const int box = blockIdx.x, lane = threadIdx.x;
+    const int row = box / ncol, cl = box % ncol, col = col_lo + cl;
+    const double cxp = x_lo + (col + 0.5) * w, cyp = -(row + 0.5) * w;
+    const int s = start[key_t0 + box], e = end[key_t0 + box];
+    if (e <= s) return;
+    const int nc = 2 * P + 1;
+    if (do_far) {
+        const T R = T(1) / invR;
+        const cx<T> hk2R = T(0.25) * R * (kt * kt);  // k^2 R / 4
+        for (int t = lane; t < nr * ncg; t += 64) {
+            int r = r0 + t / ncg, n = t % ncg - (P + 1);
+            auto Lh = [&](int m) {
+                return (m >= -P && m <= P) ? local_value<T>(Lc, base, part, rsl, row, cl, ncol, nrhs, r, nc, m + P)
+                                           : mk<T>(0, 0);
+            };
+            cx<T> up = Lh(n + 1), dn = Lh(n - 1);
+            // (k/2) s_{n+1}/s_n and (k/2) s_{n-1}/s_n
+            cx<T> fp = n >= 0 ? mk<T>(T(n + 1) * invR, T(0)) : hk2R * (T(1) / T(-n));
+            cx<T> fm = n > 0 ? hk2R * (T(1) / T(n)) : mk<T>(T(1 - n) * invR, T(0));
+            cx<T> a = fp * up, b = fm * dn;
+            Gx[t] = a - b;
+            cx<T> sum = a + b;
+            Gy[t] = mk<T>(-sum.im, sum.re);
+        }
+        __syncthreads();
+    }
+    for (int c0 = s; c0 < e; c0 += 64) {
+        int i = c0 + lane;
+        bool act = i < e;
+        int ii = act ? i : s;
+        double x1 = xs[ii], y1 = ys[ii];
+        int64_t oi = idx[ii] - ns;
+        double gx = 0.0, gy = 0.0;
+        if (do_far) {
+            cx<T> tm[PMAX + 1];
+            cx<T> J0;
+            T X = (T)(x1 - cxp), Y = (T)(y1 - cyp);
+            const int Pg = P + 1;
+            bessel_ratios<T, PMAX>(kt, X, Y, Pg, tm, J0);
+            cx<T> up = mk<T>(X * invR, Y * invR), dn = mk<T>(-X * invR, Y * invR);
+            for (int rr = 0; rr < nr; ++rr) {
+                const int r = r0 + rr;
+                const cx<T> *gxr = Gx + rr * ncg, *gyr = Gy + rr * ncg;
+                cx<T> ax = J0 * gxr[Pg], ay = J0 * gyr[Pg];
+                cx<T> vp = J0, vm = J0;
+#pragma unroll
+                for (int p = 1; p <= PMAX; ++p) {
+                    if (p <= Pg) {
+                        cx<T> f = T(2 * p) * tm[p];
+                        vp = vp * (f * up);
+                        vm = vm * (f * dn);
+                        cfma(ax, vp, gxr[Pg + p]);
+                        cfma(ax, vm, gxr[Pg - p]);
+                        cfma(ay, vp, gyr[Pg + p]);
+                        cfma(ay, vm, gyr[Pg - p]);
+                    }
+                }
+                cx<T> cr = act ? cw[(int64_t)r * nt + oi] : mk<T>(0, 0);
+                gx += (double)(cr.re * ax.re - cr.im * ax.im);
+                gy += (double)(cr.re * ay.re - cr.im * ay.im);
+            }
+        }
+        if (do_near && row == 0 && rows_s > 0) {
+            for (int dc = -1; dc <= 1; ++dc) {
+                int cs = cl + dc;
+                if (cs < 0 || cs >= ncol) continue;
+                int js = start[cs], je = end[cs];
+                for (int j = js; j < je; ++j) {
+                    double x0 = xs[j], y0 = ys[j];
+                    cx<double> GL, GS;
+                    pair_kernel_grad(nodes, nmid, npan, t0, y1, y0, fabs(x1 - x0), act, GL, GS);
+                    double sg = x1 > x0 ? 1.0 : (x1 < x0 ? -1.0 : 0.0);
+                    cx<double> GX = {-GL.im * sg, GL.re * sg};  // i sgn * GL
+                    int64_t o = idx[j];
+                    for (int r = r0; r < r0 + nr; ++r) {
+                        cx<T> qq = q[(int64_t)r * ns + o];
+                        cx<T> cr = act ? cw[(int64_t)r * nt + oi] : mk<T>(0, 0);
+                        cx<double> cq = cx<double>{(double)cr.re, (double)cr.im} * cx<double>{(double)qq.re, (double)qq.im};
+                        gx += cq.re * GX.re - cq.im * GX.im;
+                        gy += cq.re * GS.re - cq.im * GS.im;
+                    }
+                }
+            }
+        }
+        if (act) {
+            gout[oi] = accumulate ? gout[oi] + gx : gx;
+            gout[nt + oi] = accumulate ? gout[nt + oi] + ysign * gy : ysign * gy;
+        }
+    }
+}
+
 // Direct all-pairs sum (no tree): lanes over targets, loop over all sources.
 template <typename T>
 __global__ void __launch_bounds__(64) k_direct(const double *__restrict__ src, int64_t ns, const cx<T> *__restrict__ q,
@@ -339,29 +561,69 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     int CH = (int)((60 * 1024) / ((size_t)(lv.nc + nrhs) * sizeof(cx<T>)));
     CH = CH > 64 ? 64 : (CH < 1 ? 1 : CH);
     size_t sh = (size_t)CH * (lv.nc + nrhs) * sizeof(cx<T>);
-    cx<T> k1 = mk<T>((T)med.k1.re, (T)med.k1.im);
+    cx<double> kd = k_src(med);
+    cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
     hipLaunchKernelGGL((k_p2m<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
                        reinterpret_cast<const cx<T> *>(q), ns, nrhs, lv.P, lv.ncol, lv.col_lo, g.x_lo, lv.w, k1, invR,
                        CH, M + lv.off_s);
 }
 
+inline RowSlots row_slots(const int *cls_of_host, int nslots)
+{
+    RowSlots r;
+    r.n[0] = r.n[1] = 0;
+    for (int i = 0; i < nslots && cls_of_host; ++i) {
+        int rt = cls_of_host[i] / 100;
+        if (rt < 2 && r.n[rt] < 14) r.s[rt][r.n[rt]++] = i;
+    }
+    return r;
+}
+
 template <typename T, int PMAX>
 void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
                   const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med, const cx<T> *Lc,
-                  const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near, void *u, hipStream_t st)
+                  const cx<T> *part, const int *cls_of_host, int nslots, const Node *nodes, int nmid, int npan,
+                  double t0, int do_far, int do_near, void *u, hipStream_t st)
 {
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_t * lv.ncol;
     if (nbox == 0) return;
     size_t sh = (size_t)lv.nc * 8 * sizeof(cx<T>);
-    cx<T> k2 = mk<T>((T)med.k2.re, (T)med.k2.im);
+    cx<double> kd = k_tgt(med);
+    cx<T> k2 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
     int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
     hipLaunchKernelGGL((k_l2p_near<T, PMAX>), dim3(nbox, (nrhs + 7) / 8), dim3(64), sh, st, start, end, idx, xs, ys,
                        reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo,
-                       lv.w, k2, invR, Lc + lv.off_t, nodes, nmid, npan, t0, do_far, do_near, key_t0,
+                       lv.w, k2, invR, Lc + lv.off_t, g.L >= 3 ? 1 : 0, part, row_slots(cls_of_host, nslots), nodes,
+                       nmid, npan, t0, do_far, do_near, key_t0,
                        reinterpret_cast<cx<T> *>(u));
+}
+
+template <typename T, int PMAX>
+void grad_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
+                   const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med,
+                   const cx<T> *Lc, const cx<T> *part, const int *cls_of_host, int nslots, const Node *nodes,
+                   int nmid, int npan, double t0, int do_far, int do_near, double ysign, double *gout,
+                   hipStream_t st)
+{
+    const Level &lv = g.lev[g.L];
+    int nbox = lv.rows_t * lv.ncol;
+    if (nbox == 0) return;
+    cx<double> kd = k_tgt(med);
+    cx<T> kt = mk<T>((T)kd.re, (T)kd.im);
+    T invR = (T)(M_SQRT2 / lv.w);
+    int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
+    for (int r0 = 0; r0 < nrhs; r0 += 8) {
+        int nr = nrhs - r0 < 8 ? nrhs - r0 : 8;
+        size_t sh = (size_t)2 * nr * (2 * (lv.P + 1) + 1) * sizeof(cx<T>);
+        hipLaunchKernelGGL((k_l2p_grad<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
+                           reinterpret_cast<const cx<T> *>(q), reinterpret_cast<const cx<T> *>(cw), ns, nt, nrhs, r0,
+                           nr, r0 > 0 ? 1 : 0, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo, lv.w, kt, invR,
+                           Lc + lv.off_t, g.L >= 3 ? 1 : 0, part, row_slots(cls_of_host, nslots), nodes, nmid, npan, t0,
+                           do_far, do_near, key_t0, ysign, gout);
+    }
 }
 
 }  // namespace
@@ -387,44 +649,82 @@ void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int nrhs,
     const Level &c = g.lev[lc], &p = g.lev[lc - 1];
     int nbox = p.rows_s * p.ncol;
     if (nbox == 0) return;
-    size_t sh = (size_t)4 * c.nc * sizeof(cx<T>);
-    hipLaunchKernelGGL((k_m2m<T>), dim3(nbox, nrhs), dim3(64), sh, st, M + c.off_s, M + p.off_s, tab, nrhs, c.nc, p.nc,
-                       c.ncol, c.col_lo, c.rows_s, p.ncol, p.col_lo);
+    dim3 grid((nbox + GB - 1) / GB, (p.nc + GP - 1) / GP, nrhs);
+    hipLaunchKernelGGL((k_up<T>), grid, dim3(256), 0, st, M + c.off_s, M + p.off_s, tab, nrhs, c.nc, p.nc, c.ncol,
+                       c.col_lo, c.rows_s, p.ncol, p.col_lo, p.rows_s);
 }
 
 template <typename T>
-void launch_m2l(const Geometry &g, int l, const cx<T> *atab, const int *cls_index, const cx<T> *M, cx<T> *Lc,
-                int nrhs, const cx<T> *l2l_tab, int do_m2l, hipStream_t st)
+void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls_of,
+                 const int *cls_of_p_host, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
+                 const cx<T> *l2l_tab, hipStream_t st)
 {
     const Level &lv = g.lev[l], &pv = g.lev[l - 1];
-    int nbox = lv.rows_t * lv.ncol;
-    if (nbox == 0) return;
-    int ncmax = lv.nc > pv.nc ? lv.nc : pv.nc;
-    size_t sh = (size_t)ncmax * sizeof(cx<T>);
-    hipLaunchKernelGGL((k_m2l_l2l<T>), dim3(nbox, nrhs), dim3(64), sh, st, M + lv.off_s, Lc + pv.off_t, Lc + lv.off_t, atab,
-                       cls_index, l2l_tab, nrhs, lv.nc, pv.nc, lv.ncol, lv.col_lo, lv.rows_s, pv.ncol, pv.col_lo,
-                       do_m2l);
+    DownArgs a;
+    a.nc = lv.nc;
+    a.ncol = lv.ncol;
+    a.col_lo = lv.col_lo;
+    a.rows_s = lv.rows_s;
+    a.rows_t = lv.rows_t;
+    a.nslots = nslots;
+    a.ncp = pv.nc;
+    a.ncol_p = pv.ncol;
+    a.col_lo_p = pv.col_lo;
+    a.rows_t_p = pv.rows_t;
+    a.rsl_p = row_slots(cls_of_p_host, nslots_p);
+    a.base_p = l - 1 >= 3 ? 1 : 0;
+    a.has_l2l = l2l_tab != nullptr;
+    int nb_l2l = a.has_l2l ? (pv.rows_t * pv.ncol + GB - 1) / GB : 0;
+    int nb_m2l = (lv.ncol + GB - 1) / GB;
+    int gx = nb_l2l > nb_m2l ? nb_l2l : nb_m2l;
+    int gz = (a.has_l2l ? 4 * nrhs : 0) + nslots * nrhs;
+    if (gz == 0 || gx == 0) return;
+    dim3 grid(gx, (lv.nc + GP - 1) / GP, gz);
+    hipLaunchKernelGGL((k_down<T>), grid, dim3(256), 0, st, a, nrhs, Lc + pv.off_t, part_p, l2l_tab,
+                       Lc + lv.off_t, M + lv.off_s, atab, cls_of, part);
 }
 
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
-                     Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far,
-                     int do_near, void *u, hipStream_t st)
+                     Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots, const Node *nodes,
+                     int nmid, int npan, double t0, int do_far, int do_near, void *u, hipStream_t st)
 {
-    int P = g.lev[g.L].P;
+    int P = g.lev[g.L].P;  // cls_of: host copy of the leaf level's class codes
+#define LMFMM_L2P(PM)                                                                                        \
+    l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part, cls_of, nslots, nodes, nmid, \
+                        npan, t0, do_far, do_near, u, st)
     if (P <= 16)
-        l2p_dispatch<T, 16>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nodes, nmid, npan, t0, do_far,
-                            do_near, u, st);
+        LMFMM_L2P(16);
     else if (P <= 32)
-        l2p_dispatch<T, 32>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nodes, nmid, npan, t0, do_far,
-                            do_near, u, st);
+        LMFMM_L2P(32);
     else if (P <= 64)
-        l2p_dispatch<T, 64>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nodes, nmid, npan, t0, do_far,
-                            do_near, u, st);
+        LMFMM_L2P(64);
     else
-        l2p_dispatch<T, 256>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nodes, nmid, npan, t0, do_far,
-                             do_near, u, st);
+        LMFMM_L2P(256);
+#undef LMFMM_L2P
+}
+
+template <typename T>
+void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
+                     const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,
+                     const Geometry &g, Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots,
+                     const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near, double ysign,
+                     double *gout, hipStream_t st)
+{
+    int P = g.lev[g.L].P + 1;
+#define LMFMM_GR(PM)                                                                                          \
+    grad_dispatch<T, PM>(start, end, idx, xs, ys, q, cw, ns, nt, nrhs, g, med, Lc, part, cls_of, nslots, nodes, \
+                         nmid, npan, t0, do_far, do_near, ysign, gout, st)
+    if (P <= 16)
+        LMFMM_GR(16);
+    else if (P <= 32)
+        LMFMM_GR(32);
+    else if (P <= 64)
+        LMFMM_GR(64);
+    else
+        LMFMM_GR(256);
+#undef LMFMM_GR
 }
 
 void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, int nrhs, int prec,
@@ -445,11 +745,16 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
     template void launch_p2m<T>(const int32_t *, const int32_t *, const int32_t *, const double *, const double *,   \
                                 const void *, int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);        \
     template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int, hipStream_t);                   \
-    template void launch_m2l<T>(const Geometry &, int, const cx<T> *, const int *, const cx<T> *, cx<T> *, int,     \
-                                const cx<T> *, int, hipStream_t);                                                   \
+    template void launch_down<T>(const Geometry &, int, int, int, const cx<T> *, const int *, const int *,          \
+                                 const cx<T> *, cx<T> *, cx<T> *, const cx<T> *, int, const cx<T> *, hipStream_t);  \
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
-                                     const cx<T> *, const Node *, int, int, double, int, int, void *, hipStream_t);
+                                     const cx<T> *, const cx<T> *, const int *, int, const Node *, int, int, double, \
+                                     int, int, void *, hipStream_t);                                                \
+    template void launch_l2p_grad<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
+                                     const double *, const void *, const void *, int64_t, int64_t, int,             \
+                                     const Geometry &, Medium, const cx<T> *, const cx<T> *, const int *, int,      \
+                                     const Node *, int, int, double, int, int, double, double *, hipStream_t);
 LMFMM_INST(double)
 LMFMM_INST(float)
 

@@ -87,10 +87,20 @@ __host__ __device__ inline cx<double> csqrt_d(cx<double> z)
 // s_m(lam) = sqrt(lam^2 - k^2), principal branch.
 __host__ __device__ inline cx<double> sroot_d(cx<double> lam, cx<double> k) { return csqrt_d(lam * lam - k * k); }
 
+// The medium and the orientation of the operator.  adj = 0: the forward
+// operator (sources in the top layer carry k1, targets in the middle layer
+// k2).  adj = 1: the transposed operator in mirrored coordinates (x, -y):
+// substituting lam -> -lam in the Sommerfeld integral shows that G^T acting
+// on middle-layer densities is the same kind of operator with the roles of
+// (k1, s1) and (k2, s2) exchanged and the same density sigma_2^t / (4 pi s2).
 struct Medium {
     cx<double> k1, k2, k3;
     double d;
+    int adj;
 };
+// wave number of the multipole (source) side and of the local (target) side
+__host__ __device__ inline cx<double> k_src(const Medium &m) { return m.adj ? m.k2 : m.k1; }
+__host__ __device__ inline cx<double> k_tgt(const Medium &m) { return m.adj ? m.k1 : m.k2; }
 
 // sigma_2^t(lam) of the three-layer medium (Section 1; Section 3 Example 4),
 // with numerator and denominator divided by exp(d s2) so that every factor
@@ -123,8 +133,18 @@ template <typename T, int PMAX>
 __host__ __device__ inline void bessel_ratios(cx<T> k, T X, T Y, int P, cx<T> *tm, cx<T> &J0)
 {
     cx<T> z2 = (k * k) * (X * X + Y * Y);
-    T az = sqrt(sqrt(cabs2(z2)));
-    int N = P + 16 + (int)(az * T(1.2));
+    // Start of the backward recurrence: starting at N with t_{N+1} = 0 perturbs
+    // t_m by about prod_{j=m+1}^{N} |z|^2 / (4 j^2); take N so that this is
+    // below the working precision at m = P.
+    const T a2 = sqrt(cabs2(z2)) * T(0.25);
+    const T eps = sizeof(T) == 8 ? T(1e-17) : T(1e-8);
+    int N = P;
+    T prod = T(1);
+    while (N < P + 200 && (prod > eps || T(N * N) < a2)) {
+        ++N;
+        T f = a2 / T(N * N);
+        prod *= f < T(1) ? f : T(1);
+    }
     cx<T> t = mk<T>(0, 0), tprev = mk<T>(0, 0);
     // U = 2 sum_{even j >= max(m,2)} J_j / J_m, updated at every odd m:
     // U_{m-1} = 2 [m-1 >= 2] + U_{m+1} z^2 t_{m+1} t_m.
@@ -199,10 +219,11 @@ struct Geometry {
     int64_t ncoef_s, ncoef_t;  // total complex coefficients (times nrhs)
 };
 
-// Near-field node record (FP64): lambda, s1, s2 and the weighted density D =
-// dlam-weight * sigma_2^t / (4 pi s2).
+// Near-field node record (FP64): lambda, the source-side and target-side
+// square roots s_s = sqrt(lam^2 - k_src^2), s_t = sqrt(lam^2 - k_tgt^2), and the
+// weighted density D = dlam-weight * sigma_2^t / (4 pi s2).
 struct Node {
-    double lr, li, s1r, s1i, s2r, s2i, dr, di;
+    double lr, li, ssr, ssi, str, sti, dr, di;
 };
 
 constexpr int NGL = 16;  // Gauss-Legendre points per panel
@@ -211,8 +232,10 @@ constexpr int NGL = 16;  // Gauss-Legendre points per panel
 // Launch wrappers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 // tree.hip
-void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double d, double *partial,
-                 int nblk, double *out, hipStream_t st);
+// sources must satisfy 0 < y < ys_lim, targets yt_lim < y < 0
+void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
+                 double *partial, int nblk, double *out, hipStream_t st);
+void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st);
 int bbox_blocks(int64_t n);
 struct SortBufs {
     uint32_t *key_a, *key_b;
@@ -229,8 +252,8 @@ void launch_leaf_ranges(const uint32_t *key, const int32_t *idx, int64_t n, int6
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 void launch_keys(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
-                 int ncol, int rows_s, int rows_t, double d, uint32_t *key, int32_t *idx, int32_t *err,
-                 hipStream_t st);
+                 int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, uint32_t *key, int32_t *idx,
+                 int32_t *err, hipStream_t st);
 
 // expand.hip (T = double or float)
 template <typename T>
@@ -239,13 +262,20 @@ void launch_p2m(const int32_t *start, const int32_t *end, const int32_t *idx, co
 template <typename T>
 void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int nrhs, hipStream_t st);
 template <typename T>
-void launch_m2l(const Geometry &g, int l, const cx<T> *atab, const int *cls_index, const cx<T> *M, cx<T> *Lc,
-                int nrhs, const cx<T> *l2l_tab, int do_m2l, hipStream_t st);
+void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls_of,
+                 const int *cls_of_p, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
+                 const cx<T> *l2l_tab, hipStream_t st);
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
-                     Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far,
-                     int do_near, void *u, hipStream_t st);
+                     Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots, const Node *nodes,
+                     int nmid, int npan, double t0, int do_far, int do_near, void *u, hipStream_t st);
+template <typename T>
+void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
+                     const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,
+                     const Geometry &g, Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots,
+                     const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near, double ysign,
+                     double *gout, hipStream_t st);
 void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, int nrhs, int prec,
                    const Node *nodes, int nmid, int npan, double t0, void *u, hipStream_t st);
 

@@ -43,8 +43,8 @@ struct DevBuf {
     {
         if (bytes <= n && p) return LMFMM_OK;
         if (p) {
-            hipDeviceSynchronize();
-            hipFree(p);
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
             p = nullptr;
             n = 0;
         }
@@ -58,7 +58,7 @@ struct DevBuf {
     }
     void release()
     {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
         p = nullptr;
         n = 0;
     }
@@ -184,8 +184,37 @@ struct LevelTables {
     DevBuf m2m64, m2m32, l2l64, l2l32;  // [4][nc_in][nc_out]
     DevBuf a64, a32;                    // M2L tables [slot][nc][nc]
     DevBuf cls;                         // int[28]
+    DevBuf clsof;                       // int[nslots]: rt*100 + rs*10 + (dc+3)
+    std::vector<int> clsof_host;
     int nslots = 0;
     int64_t nodes = 0;
+};
+
+struct VarTables {
+    // far-field tables
+    int t_L = -1;
+    double t_W = -1;
+    int t_P[MAXLEV + 1] = {0};
+    LevelTables lt[MAXLEV + 1];
+    double table_seconds = 0;
+    // near-field node table
+    DevBuf near_nodes;
+    double n_c = 0, n_h = -1, n_t0 = 0;
+    int n_nmid = 0, n_npan = 0;
+    void release()
+    {
+        near_nodes.release();
+        for (auto &t : lt) {
+            t.m2m64.release();
+            t.m2m32.release();
+            t.l2l64.release();
+            t.l2l32.release();
+            t.a64.release();
+            t.a32.release();
+            t.cls.release();
+            t.clsof.release();
+        }
+    }
 };
 
 struct lmfmm_plan_s {
@@ -202,18 +231,9 @@ struct lmfmm_plan_s {
     double *h_bbox = nullptr;  // pinned
     DevBuf bbox_dev;
 
-    // cached far-field tables
-    int t_L = -1;
-    double t_W = -1;
-    int t_P[MAXLEV + 1] = {0};
-    LevelTables lt[MAXLEV + 1];
-    double table_seconds = 0;
-
-    // near-field node table
-    DevBuf near_nodes;
-    double n_c = 0, n_h = -1, n_t0 = 0;
-    int n_nmid = 0, n_npan = 0;
-    int64_t n_count = 0;
+    // cached tables of the forward (0) and transposed (1) operator
+    VarTables vt[2];
+    DevBuf mirror;  // mirrored coordinates for the transposed operator
 
     // direct-sum node table
     DevBuf dir_nodes;
@@ -236,7 +256,7 @@ struct lmfmm_plan_s {
 static void collect_timing(lmfmm_plan_s *p)
 {
     if (!p->ev_pending) return;
-    hipEventSynchronize(p->ev[5]);
+    (void)hipEventSynchronize(p->ev[5]);
     for (int s = 0; s < 5; ++s) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p->ev[s], p->ev[s + 1]) == hipSuccess) p->stats.stage_ms[s] += ms;
@@ -362,14 +382,16 @@ static int upload(DevBuf &b, const void *h, size_t bytes)
     return LMFMM_OK;
 }
 
-static int build_shift_tables(lmfmm_plan_s *p, const Geometry &g, int l)
+static int build_shift_tables(VarTables &vt, const Medium &med, const Geometry &g, int l)
 {
     // children at level l, parents at level l - 1
-    LevelTables &T = p->lt[l];
+    LevelTables &T = vt.lt[l];
     const Level &c = g.lev[l], &pa = g.lev[l - 1];
     int ncc = c.nc, ncp = pa.nc, Pc = c.P, Pp = pa.P;
     double Rc = c.w / std::sqrt(2.0), Rp = pa.w / std::sqrt(2.0);
-    zc k1(p->med.k1.re, p->med.k1.im), k2(p->med.k2.re, p->med.k2.im);
+    // multipole side (M2M) and local side (L2L) wave numbers
+    cx<double> kS = k_src(med), kT = k_tgt(med);
+    zc k1(kS.re, kS.im), k2(kT.re, kT.im);
     std::vector<cx<double>> m2m((size_t)4 * ncc * ncp), l2l((size_t)4 * ncp * ncc);
     std::vector<zc> gm;
     for (int pos = 0; pos < 4; ++pos) {
@@ -408,13 +430,13 @@ static int build_shift_tables(lmfmm_plan_s *p, const Geometry &g, int l)
 }
 
 // M2L tables of one level: one class per (target row, source row, column offset).
-static int build_m2l_tables(lmfmm_plan_s *p, const Geometry &g, int l)
+static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g, int l)
 {
-    LevelTables &T = p->lt[l];
+    LevelTables &T = vt.lt[l];
     const Level &lv = g.lev[l];
     int P = lv.P, nc = lv.nc;
-    double w = lv.w, R = w / std::sqrt(2.0), c = contour_c(p->med);
-    std::vector<int> cls_index(28, -1);
+    double w = lv.w, R = w / std::sqrt(2.0), c = contour_c(med);
+    std::vector<int> cls_index(28, -1), cls_of;
     NodeList nl;
     std::vector<int> node_cls, node_local, cP, cQ;
     std::vector<int64_t> toff, aoff;
@@ -444,6 +466,7 @@ static int build_m2l_tables(lmfmm_plan_s *p, const Geometry &g, int l)
                     node_local.push_back(i);
                 }
                 cls_index[(rt * 2 + rs) * 7 + dc + 3] = slot;
+                cls_of.push_back(rt * 100 + rs * 10 + (dc + 3));
                 cP.push_back(P);
                 cQ.push_back(Q);
                 toff.push_back(tsum);
@@ -460,6 +483,8 @@ static int build_m2l_tables(lmfmm_plan_s *p, const Geometry &g, int l)
     int rc;
     if ((rc = upload(T.cls, cls_index.data(), 28 * sizeof(int)))) return rc;
     if (slot == 0) return LMFMM_OK;
+    if ((rc = upload(T.clsof, cls_of.data(), cls_of.size() * sizeof(int)))) return rc;
+    T.clsof_host = cls_of;
     DevBuf d_lw, d_ncls, d_nloc, d_geo, d_P, d_Q, d_toff, d_aoff, d_T, d_S;
     if ((rc = upload(d_lw, nl.lw.data(), nl.lw.size() * sizeof(double)))) return rc;
     if ((rc = upload(d_ncls, node_cls.data(), node_cls.size() * sizeof(int)))) return rc;
@@ -474,7 +499,7 @@ static int build_m2l_tables(lmfmm_plan_s *p, const Geometry &g, int l)
     if ((rc = T.a64.ensure((size_t)slot * nc * nc * sizeof(cx<double>)))) return rc;
     if ((rc = T.a32.ensure((size_t)slot * nc * nc * sizeof(cx<float>)))) return rc;
     launch_m2l_tables((const double *)d_lw.p, (const int *)d_ncls.p, (const int *)d_nloc.p, nl.count(),
-                      (const double *)d_geo.p, p->med, (const int *)d_P.p, (const int *)d_Q.p,
+                      (const double *)d_geo.p, med, (const int *)d_P.p, (const int *)d_Q.p,
                       (const int64_t *)d_toff.p, (const int64_t *)d_aoff.p, slot, nc, (cx<double> *)d_T.p,
                       (cx<double> *)d_S.p, (cx<double> *)T.a64.p, (cx<float> *)T.a32.p, 0);
     HIPCHK(hipGetLastError());
@@ -528,35 +553,34 @@ static int build_near_table(DevBuf &buf, const Medium &med, double dxmax, double
     return LMFMM_OK;
 }
 
-static int ensure_far_tables(lmfmm_plan_s *p, const Geometry &g)
+static int ensure_far_tables(VarTables &vt, const Medium &med, const Geometry &g)
 {
-    bool same = p->t_L == g.L && p->t_W == g.W;
-    for (int l = 1; same && l <= g.L; ++l) same = p->t_P[l] == g.lev[l].P;
+    bool same = vt.t_L == g.L && vt.t_W == g.W;
+    for (int l = 1; same && l <= g.L; ++l) same = vt.t_P[l] == g.lev[l].P;
     if (same) return LMFMM_OK;
     double t_start = (double)clock() / CLOCKS_PER_SEC;
     int rc;
     for (int l = 2; l <= g.L; ++l)
-        if ((rc = build_m2l_tables(p, g, l))) return rc;
+        if ((rc = build_m2l_tables(vt, med, g, l))) return rc;
     for (int l = 3; l <= g.L; ++l)
-        if ((rc = build_shift_tables(p, g, l))) return rc;
-    p->t_L = g.L;
-    p->t_W = g.W;
-    for (int l = 0; l <= MAXLEV; ++l) p->t_P[l] = l <= g.L ? g.lev[l].P : 0;
-    p->table_seconds = (double)clock() / CLOCKS_PER_SEC - t_start;
+        if ((rc = build_shift_tables(vt, med, g, l))) return rc;
+    vt.t_L = g.L;
+    vt.t_W = g.W;
+    for (int l = 0; l <= MAXLEV; ++l) vt.t_P[l] = l <= g.L ? g.lev[l].P : 0;
+    vt.table_seconds = (double)clock() / CLOCKS_PER_SEC - t_start;
     return LMFMM_OK;
 }
 
-static int ensure_near_table(lmfmm_plan_s *p, const Geometry &g, double amin)
+static int ensure_near_table(VarTables &vt, const Medium &med, const Geometry &g, double amin)
 {
     double dxmax = 2.0 * g.lev[g.L].w;
-    double c = contour_c(p->med);
+    double c = contour_c(med);
     double h = std::min(0.25 * c, 3.0 / dxmax);
     double t0 = c / 8.0;
     double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
     int npan = std::min(64, 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0)))));
-    if (p->near_nodes.p && p->n_h == h && p->n_npan >= npan) return LMFMM_OK;
-    int rc = build_near_table(p->near_nodes, p->med, dxmax, amin, p->n_c, p->n_h, p->n_t0, p->n_nmid, p->n_npan);
-    return rc;
+    if (vt.near_nodes.p && vt.n_h == h && vt.n_npan >= npan) return LMFMM_OK;
+    return build_near_table(vt.near_nodes, med, dxmax, amin, vt.n_c, vt.n_h, vt.n_t0, vt.n_nmid, vt.n_npan);
 }
 
 // ---------------------------------------------------------------------------
@@ -600,6 +624,7 @@ int lmfmm_create(const double k[6], double d, int order, double tol, lmfmm_plan 
     p->med.k2 = {k[2], k[3]};
     p->med.k3 = {k[4], k[5]};
     p->med.d = d;
+    p->med.adj = 0;
     p->order = order;
     p->tol = tol;
     std::memset(&p->stats, 0, sizeof(p->stats));
@@ -608,7 +633,7 @@ int lmfmm_create(const double k[6], double d, int order, double tol, lmfmm_plan 
         return fail(LMFMM_ENOMEM, "pinned allocation failed");
     }
     if (p->bbox_dev.ensure(8 * 520 * sizeof(double))) {
-        hipHostFree(p->h_bbox);
+        (void)hipHostFree(p->h_bbox);
         delete p;
         return LMFMM_ENOMEM;
     }
@@ -619,23 +644,16 @@ int lmfmm_create(const double k[6], double d, int order, double tol, lmfmm_plan 
 int lmfmm_destroy(lmfmm_plan p)
 {
     if (!p) return fail(LMFMM_EINVAL, "plan is null");
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     p->ws.release();
     p->bbox_dev.release();
-    p->near_nodes.release();
     p->dir_nodes.release();
-    for (auto &t : p->lt) {
-        t.m2m64.release();
-        t.m2m32.release();
-        t.l2l64.release();
-        t.l2l32.release();
-        t.a64.release();
-        t.a32.release();
-        t.cls.release();
-    }
-    if (p->h_bbox) hipHostFree(p->h_bbox);
+    p->mirror.release();
+    p->vt[0].release();
+    p->vt[1].release();
+    if (p->h_bbox) (void)hipHostFree(p->h_bbox);
     for (int i = 0; i < 6; ++i)
-        if (p->ev[i]) hipEventDestroy(p->ev[i]);
+        if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
     delete p;
     return LMFMM_OK;
 }
@@ -712,7 +730,7 @@ int lmfmm_get_stats(lmfmm_plan p, lmfmm_stats *s)
 // Apply
 // ---------------------------------------------------------------------------
 static int check_common(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, const double *tgt, const void *in,
-                        void *out, int nrhs, int prec)
+                        const void *out, int nrhs, int prec)
 {
     if (!p) return fail(LMFMM_EINVAL, "plan is null");
     if (ns < 0 || nt < 0) return fail(LMFMM_EINVAL, "negative size");
@@ -724,9 +742,14 @@ static int check_common(lmfmm_plan p, int64_t ns, const double *src, int64_t nt,
     return LMFMM_OK;
 }
 
+// Layer bounds of the two point sets: forward, sources 0 < y and targets
+// -d < y < 0; transposed (mirrored coordinates), sources 0 < y < d, targets y < 0.
+static double ys_limit(const Medium &m) { return m.adj ? m.d : INFINITY; }
+static double yt_limit(const Medium &m) { return m.adj ? -INFINITY : -m.d; }
+
 // Bounding box of the points (host readback) or the fixed domain.
-static int get_bbox(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, const double *tgt, hipStream_t st,
-                    double *bb)
+static int get_bbox(lmfmm_plan p, const Medium &med, int64_t ns, const double *src, int64_t nt, const double *tgt,
+                    hipStream_t st, double *bb)
 {
     if (p->have_domain) {
         bb[0] = p->dom[0];
@@ -741,7 +764,7 @@ static int get_bbox(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, con
     int64_t n = ns + nt;
     int nblk = bbox_blocks(n);
     double *part = (double *)p->bbox_dev.p, *outp = part + 8 * 512;
-    launch_bbox(src, ns, tgt, nt, p->med.d, part, nblk, outp, st);
+    launch_bbox(src, ns, tgt, nt, ys_limit(med), yt_limit(med), part, nblk, outp, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(p->h_bbox, outp, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -750,28 +773,39 @@ static int get_bbox(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, con
     return LMFMM_OK;
 }
 
+// One pass of Algorithm 1 for the operator of orientation adj (0: forward,
+// 1: transposed in mirrored coordinates).  With gw == nullptr the field of the
+// densities q is written to u; otherwise the target-side coordinate gradient of
+// Re sum gw * field is written to gout ([2][nt], y component times ysign).
 template <typename T>
-static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt,
-                      void *u, int nrhs, int prec, hipStream_t st)
+static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, const void *q, int64_t nt,
+                      const double *tgt, void *u, int nrhs, hipStream_t st, const void *gw = nullptr,
+                      double *gout = nullptr, double ysign = 1.0)
 {
     if (nt == 0) return LMFMM_OK;
     int rc;
     if (ns == 0) {
-        launch_zero_bytes(u, (size_t)nt * nrhs * sizeof(cx<T>), st);
+        if (gw)
+            launch_zero_bytes(gout, (size_t)2 * nt * sizeof(double), st);
+        else
+            launch_zero_bytes(u, (size_t)nt * nrhs * sizeof(cx<T>), st);
         HIPCHK(hipGetLastError());
         return LMFMM_OK;
     }
+    Medium med = p->med;
+    med.adj = adj;
+    VarTables &vt = p->vt[adj];
     double bb[8];
-    if ((rc = get_bbox(p, ns, src, nt, tgt, st, bb))) return rc;
+    if ((rc = get_bbox(p, med, ns, src, nt, tgt, st, bb))) return rc;
     Geometry &g = p->geo;
     if ((rc = make_geometry(p, bb, ns, nrhs, g))) return rc;
     const int L = g.L;
-    if (g.lev[L].P > 256) return fail(LMFMM_EINVAL, "leaf-level expansion order above 256: use more levels");
+    if (g.lev[L].P > 255) return fail(LMFMM_EINVAL, "leaf-level expansion order above 255: use more levels");
     bool far = p->do_far && L >= 2;
-    if (far && (rc = ensure_far_tables(p, g))) return rc;
+    if (far && (rc = ensure_far_tables(vt, med, g))) return rc;
     double amin = p->have_domain ? 1e-9 * g.W : std::max(bb[2], 0.0) + std::max(-bb[5], 0.0);
     if (!(amin > 0)) amin = 1e-9 * g.W;
-    if ((rc = ensure_near_table(p, g, amin))) return rc;
+    if ((rc = ensure_near_table(vt, med, g, amin))) return rc;
 
     // workspace
     const Level &lv = g.lev[L];
@@ -780,7 +814,12 @@ static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q
     int nblk = sort_blocks(n);
     size_t need = 0;
     need += 2 * (size_t)n * 4 + 2 * (size_t)n * 4 + (size_t)256 * nblk * 4 + 2 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
-    need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 16 * 256;
+    need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 20 * 256;
+    int64_t part_off[MAXLEV + 2] = {0};
+    for (int l = 2; l <= L && far; ++l)
+        part_off[l + 1] = part_off[l] + (int64_t)vt.lt[l].nslots * g.lev[l].ncol * nrhs * g.lev[l].nc;
+    int64_t npart = far ? part_off[L + 1] : 0;
+    need += (size_t)npart * sizeof(cx<T>);
     if ((rc = p->ws.ensure(need))) return rc;
     Carve cv{(char *)p->ws.p};
     SortBufs sb;
@@ -796,19 +835,20 @@ static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q
     cx<T> *Lc = cv.take<cx<T>>(g.ncoef_t > 0 ? g.ncoef_t : 1);
     int32_t *err = cv.take<int32_t>(1);
     p->d_err = err;
+    cx<T> *part = cv.take<cx<T>>(npart > 0 ? npart : 1);
 
     collect_timing(p);
     const bool tm = p->timing;
     auto mark = [&](int i) {
-        if (tm) hipEventRecord(p->ev[i], st);
+        if (tm) (void)hipEventRecord(p->ev[i], st);
     };
     int nlaunch[5] = {0, 0, 0, 0, 0};
 
     // Step 1: tree
     mark(0);
     launch_fill_i32(err, 1, 0, st);
-    launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, p->med.d, sb.key_a,
-                sb.idx_a, err, st);
+    launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
+                yt_limit(med), sb.key_a, sb.idx_a, err, st);
     int bits = 1;
     while (((int64_t)1 << bits) < nbox) ++bits;
     int which = launch_radix_sort(sb, n, bits, st);
@@ -820,14 +860,14 @@ static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q
 
     // Step 2: upward pass
     if (far) {
-        launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, p->med, M, st);
+        launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, st);
         nlaunch[1] = 1;
     }
     mark(2);
     if (far) {
         nlaunch[2] = L - 2;
         for (int l = L; l >= 3; --l) {
-            const LevelTables &tb = p->lt[l];
+            const LevelTables &tb = vt.lt[l];
             const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
             launch_m2m<T>(g, l, tab, M, nrhs, st);
         }
@@ -837,17 +877,27 @@ static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q
         // Step 3: downward pass
         nlaunch[3] = L - 1;
         for (int l = 2; l <= L; ++l) {
-            const LevelTables &tb = p->lt[l];
+            const LevelTables &tb = vt.lt[l], &tp = vt.lt[l - 1];
             const cx<T> *atab = (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p);
             const cx<T> *l2l = nullptr;
             if (l >= 3) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
-            launch_m2l<T>(g, l, atab, (const int *)tb.cls.p, M, Lc, nrhs, l2l, 1, st);
+            int nsp = l >= 3 ? tp.nslots : 0;
+            launch_down<T>(g, l, tb.nslots, nsp, atab, (const int *)tb.clsof.p, l >= 3 ? tp.clsof_host.data() : nullptr,
+                           M, Lc, part + part_off[l], part + part_off[l - 1 >= 2 ? l - 1 : 2], nrhs, l2l, st);
         }
     }
     mark(4);
     // Step 4: local evaluation and direct interactions
-    launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, p->med, Lc, (const Node *)p->near_nodes.p,
-                       p->n_nmid, p->n_npan, p->n_t0, far ? 1 : 0, p->do_near ? 1 : 0, u, st);
+    const int *clsL = far ? vt.lt[L].clsof_host.data() : nullptr;
+    int nsL = far ? vt.lt[L].nslots : 0;
+    if (!gw)
+        launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
+                           (const Node *)vt.near_nodes.p, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0,
+                           p->do_near ? 1 : 0, u, st);
+    else
+        launch_l2p_grad<T>(start, end, idx, xs, ys, q, gw, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
+                           (const Node *)vt.near_nodes.p, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0,
+                           p->do_near ? 1 : 0, ysign, gout, st);
     nlaunch[4] = 1;
     mark(5);
     HIPCHK(hipGetLastError());
@@ -864,17 +914,32 @@ static int apply_impl(lmfmm_plan p, int64_t ns, const double *src, const void *q
     s.root_width = g.W;
     s.leaves_src = (int64_t)lv.rows_s * lv.ncol;
     s.leaves_tgt = (int64_t)lv.rows_t * lv.ncol;
-    s.near_nodes_mid = p->n_nmid;
-    s.near_nodes_ray = p->n_npan * NGL;
+    s.near_nodes_mid = vt.n_nmid;
+    s.near_nodes_ray = vt.n_npan * NGL;
     int ncls = 0;
     int64_t nn = 0;
     for (int l = 2; l <= L && far; ++l) {
-        ncls += p->lt[l].nslots;
-        nn += p->lt[l].nodes;
+        ncls += vt.lt[l].nslots;
+        nn += vt.lt[l].nodes;
     }
     s.m2l_classes = ncls;
     s.m2l_nodes = nn;
-    s.table_seconds = p->table_seconds;
+    s.table_seconds = vt.table_seconds;
+    return LMFMM_OK;
+}
+
+// Mirrored copies (x, -y) of both point sets for the transposed operator:
+// the targets become its sources and the sources its targets.
+static int mirror_points(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, const double *tgt,
+                         hipStream_t st, double *&msrc, double *&mtgt)
+{
+    int rc = p->mirror.ensure((size_t)2 * (ns + nt) * sizeof(double) + 512);
+    if (rc) return rc;
+    mtgt = (double *)p->mirror.p;             // mirrored original sources: targets of G^T
+    msrc = mtgt + 2 * ns;                     // mirrored original targets: sources of G^T
+    launch_mirror(src, ns, mtgt, st);
+    launch_mirror(tgt, nt, msrc, st);
+    HIPCHK(hipGetLastError());
     return LMFMM_OK;
 }
 
@@ -886,8 +951,8 @@ int lmfmm_apply(lmfmm_plan p, int64_t ns, const double *src, const void *q, int6
     int rc = check_common(p, ns, src, nt, tgt, q, u, nrhs, prec);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    return prec == LMFMM_C128 ? apply_impl<double>(p, ns, src, q, nt, tgt, u, nrhs, prec, st)
-                              : apply_impl<float>(p, ns, src, q, nt, tgt, u, nrhs, prec, st);
+    return prec == LMFMM_C128 ? apply_impl<double>(p, 0, ns, src, q, nt, tgt, u, nrhs, st)
+                              : apply_impl<float>(p, 0, ns, src, q, nt, tgt, u, nrhs, st);
 }
 
 int lmfmm_direct(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt, void *u,
@@ -904,7 +969,7 @@ int lmfmm_direct(lmfmm_plan p, int64_t ns, const double *src, const void *q, int
     bool saved = p->have_domain;
     p->have_domain = false;
     double bb[8];
-    rc = get_bbox(p, ns, src, nt, tgt, st, bb);
+    rc = get_bbox(p, p->med, ns, src, nt, tgt, st, bb);
     p->have_domain = saved;
     if (rc) return rc;
     double dxmax = std::max(bb[1] - bb[0], 1e-12);
@@ -930,18 +995,35 @@ int lmfmm_direct(lmfmm_plan p, int64_t ns, const double *src, const void *q, int
 int lmfmm_apply_adjoint(lmfmm_plan p, int64_t ns, const double *src, int64_t nt, const double *tgt, const void *w,
                         void *v, int nrhs, int prec, void *stream)
 {
-    (void)ns; (void)src; (void)nt; (void)tgt; (void)w; (void)v; (void)nrhs; (void)prec; (void)stream;
-    if (!p) return fail(LMFMM_EINVAL, "plan is null");
-    return fail(LMFMM_EINVAL, "adjoint not available in this build");
+    // v has n_src entries per right-hand side and w has n_tgt
+    int rc = check_common(p, nt, tgt, ns, src, w, v, nrhs, prec);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (ns == 0) return LMFMM_OK;
+    double *msrc = nullptr, *mtgt = nullptr;
+    if ((rc = mirror_points(p, ns, src, nt, tgt, st, msrc, mtgt))) return rc;
+    return prec == LMFMM_C128 ? apply_impl<double>(p, 1, nt, msrc, w, ns, mtgt, v, nrhs, st)
+                              : apply_impl<float>(p, 1, nt, msrc, w, ns, mtgt, v, nrhs, st);
 }
 
 int lmfmm_grad_coords(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt,
                       const void *w, double *dsrc, double *dtgt, int nrhs, int prec, void *stream)
 {
-    (void)ns; (void)src; (void)q; (void)nt; (void)tgt; (void)w; (void)dsrc; (void)dtgt; (void)nrhs; (void)prec;
-    (void)stream;
-    if (!p) return fail(LMFMM_EINVAL, "plan is null");
-    return fail(LMFMM_EINVAL, "coordinate gradients not available in this build");
+    int rc = check_common(p, ns, src, nt, tgt, q, w, nrhs, prec);
+    if (rc) return rc;
+    if ((ns > 0 && !dsrc) || (nt > 0 && !dtgt)) return fail(LMFMM_EINVAL, "null gradient output");
+    hipStream_t st = (hipStream_t)stream;
+    // target coordinates: gradient of the field of q contracted with w
+    rc = prec == LMFMM_C128 ? apply_impl<double>(p, 0, ns, src, q, nt, tgt, nullptr, nrhs, st, w, dtgt, 1.0)
+                            : apply_impl<float>(p, 0, ns, src, q, nt, tgt, nullptr, nrhs, st, w, dtgt, 1.0);
+    if (rc) return rc;
+    if (ns == 0) return LMFMM_OK;
+    // source coordinates: gradient of the transposed field of w contracted with q,
+    // in mirrored coordinates (d/dy0 = -d/dy')
+    double *msrc = nullptr, *mtgt = nullptr;
+    if ((rc = mirror_points(p, ns, src, nt, tgt, st, msrc, mtgt))) return rc;
+    return prec == LMFMM_C128 ? apply_impl<double>(p, 1, nt, msrc, w, ns, mtgt, nullptr, nrhs, st, q, dsrc, -1.0)
+                              : apply_impl<float>(p, 1, nt, msrc, w, ns, mtgt, nullptr, nrhs, st, q, dsrc, -1.0);
 }
 
 int lmfmm_sync_status(lmfmm_plan p, void *stream)

@@ -28,13 +28,14 @@ __global__ void __launch_bounds__(256) k_node_table(const double *__restrict__ l
     cx<double> s1 = sroot_d(lam, med.k1), s2 = sroot_d(lam, med.k2);
     cx<double> sg = sigma2t_d(lam, med, s1, s2);
     cx<double> D = cdiv(wt * sg, (4.0 * M_PI) * s2);
+    cx<double> ss = med.adj ? s2 : s1, stt = med.adj ? s1 : s2;
     Node nd;
     nd.lr = lam.re;
     nd.li = lam.im;
-    nd.s1r = s1.re;
-    nd.s1i = s1.im;
-    nd.s2r = s2.re;
-    nd.s2i = s2.im;
+    nd.ssr = ss.re;
+    nd.ssi = ss.im;
+    nd.str = stt.re;
+    nd.sti = stt.im;
     nd.dr = D.re;
     nd.di = D.im;
     out[i] = nd;
@@ -70,11 +71,13 @@ __global__ void __launch_bounds__(256) k_m2l_factors(const double *__restrict__ 
     cx<double> wt = {lamw[4 * i + 2], lamw[4 * i + 3]};
     cx<double> s1 = sroot_d(lam, med.k1), s2 = sroot_d(lam, med.k2);
     cx<double> sg = sigma2t_d(lam, med, s1, s2);
-    cx<double> E = cexp_d(s2 * yt - s1 * ys + mk(-lam.im * dxc, lam.re * dxc));
+    // source side (multipole, Shat) and target side (local, That)
+    cx<double> ss = med.adj ? s2 : s1, stt = med.adj ? s1 : s2;
+    cx<double> E = cexp_d(stt * yt - ss * ys + mk(-lam.im * dxc, lam.re * dxc));
     cx<double> D = cdiv(wt * E * sg, (4.0 * M_PI) * s2);
     cx<double> a1, b1, a2, b2;
-    plus_minus(lam, s1, med.k1, a1, b1);
-    plus_minus(lam, s2, med.k2, a2, b2);
+    plus_minus(lam, ss, k_src(med), a1, b1);
+    plus_minus(lam, stt, k_tgt(med), a2, b2);
     double hR = 0.5 * R;
     cx<double> I1 = {0.0, 1.0};
     cx<double> tp = (I1 * b2) * hR, tn = (-I1 * a2) * hR;  // That ratios

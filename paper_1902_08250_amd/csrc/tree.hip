@@ -35,14 +35,15 @@ __device__ inline double wave_sum(double v)
 // Per-block partial bounding box: xmin, xmax over all points; source y min/max;
 // target y min/max; count of points outside their layer or not finite.
 __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__restrict__ src, int64_t ns,
-                                                             const double *__restrict__ tgt, int64_t nt, double d,
+                                                             const double *__restrict__ tgt, int64_t nt,
+                                                             double ys_lim, double yt_lim,
                                                              double *__restrict__ partial)
 {
     double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += stride) {
         double x = src[i], y = src[ns + i];
-        bool ok = isfinite(x) && isfinite(y) && y > 0.0;
+        bool ok = isfinite(x) && isfinite(y) && y > 0.0 && y < ys_lim;
         if (ok) {
             v[0] = fmin(v[0], x);
             v[1] = fmax(v[1], x);
@@ -54,7 +55,7 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
         double x = tgt[i], y = tgt[nt + i];
-        bool ok = isfinite(x) && isfinite(y) && y < 0.0 && y > -d;
+        bool ok = isfinite(x) && isfinite(y) && y < 0.0 && y > yt_lim;
         if (ok) {
             v[0] = fmin(v[0], x);
             v[1] = fmax(v[1], x);
@@ -124,16 +125,16 @@ __global__ void __launch_bounds__(64) k_bbox_final(const double *__restrict__ pa
 // points in the wrong layer raise the error flag and are clamped.
 __global__ void __launch_bounds__(256) k_keys(const double *__restrict__ src, int64_t ns,
                                               const double *__restrict__ tgt, int64_t nt, double x_lo, double invw,
-                                              int col_lo, int ncol, int rows_s, int rows_t, double d,
-                                              uint32_t *__restrict__ key, int32_t *__restrict__ idx,
-                                              int32_t *__restrict__ err)
+                                              int col_lo, int ncol, int rows_s, int rows_t, double ys_lim,
+                                              double yt_lim, uint32_t *__restrict__ key,
+                                              int32_t *__restrict__ idx, int32_t *__restrict__ err)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns + nt) return;
     bool tg = i >= ns;
     double x = tg ? tgt[i - ns] : src[i];
     double y = tg ? tgt[nt + i - ns] : src[ns + i];
-    bool bad = !(isfinite(x) && isfinite(y)) || (tg ? !(y < 0.0 && y > -d) : !(y > 0.0));
+    bool bad = !(isfinite(x) && isfinite(y)) || (tg ? !(y < 0.0 && y > yt_lim) : !(y > 0.0 && y < ys_lim));
     double fc = floor((x - x_lo) * invw) - (double)col_lo;
     double fr = floor((tg ? -y : y) * invw);
     int rows = tg ? rows_t : rows_s;
@@ -160,29 +161,32 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_upsweep(const uint32_t *__res
         if (g < n) atomicAdd(&cnt[(key[g] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = cnt[threadIdx.x];
 }
 
-// Step 2: exclusive scan of the digit-major histogram (one block).
-__global__ void __launch_bounds__(1024) k_rs_scan(uint32_t *__restrict__ hist, int64_t total)
+// Step 2: exclusive scan in digit-major order of the block-major histogram
+// hist[block][digit] (one block; thread d owns digit d, loads are coalesced
+// across threads).
+__global__ void __launch_bounds__(256) k_rs_scan(uint32_t *__restrict__ hist, int nblk)
 {
-    __shared__ uint32_t part[1024];
-    int64_t chunk = (total + 1023) / 1024;
-    int64_t lo = threadIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
+    __shared__ uint32_t tot[256];
+    const int d = threadIdx.x;
     uint32_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += hist[i];
-    part[threadIdx.x] = s;
+#pragma unroll 8
+    for (int b = 0; b < nblk; ++b) s += hist[(int64_t)b * 256 + d];
+    tot[d] = s;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+    for (int o = 1; o < 256; o <<= 1) {
+        uint32_t v = d >= o ? tot[d - o] : 0u;
         __syncthreads();
-        part[threadIdx.x] += v;
+        tot[d] += v;
         __syncthreads();
     }
-    uint32_t run = part[threadIdx.x] - s;
-    for (int64_t i = lo; i < hi; ++i) {
-        uint32_t c = hist[i];
-        hist[i] = run;
+    uint32_t run = tot[d] - s;
+#pragma unroll 8
+    for (int b = 0; b < nblk; ++b) {
+        uint32_t c = hist[(int64_t)b * 256 + d];
+        hist[(int64_t)b * 256 + d] = run;
         run += c;
     }
 }
@@ -200,7 +204,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_downsweep(const uint32_t *__r
     __shared__ uint32_t offs[256];
     __shared__ uint32_t wcnt[NW][256];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    offs[tid] = hist[(int64_t)tid * nblk + blockIdx.x];
+    offs[tid] = hist[(int64_t)blockIdx.x * 256 + tid];
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     int64_t base = (int64_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ITEMS; ++r) {
@@ -277,27 +281,43 @@ __global__ void __launch_bounds__(256) k_leaf_ranges(const uint32_t *__restrict_
 
 int bbox_blocks(int64_t n)
 {
-    int64_t b = (n + 4095) / 4096;
+    int64_t b = (n + 1023) / 1024;
     if (b < 1) b = 1;
     if (b > 512) b = 512;
     return (int)b;
 }
 
-void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double d, double *partial, int nblk,
-                 double *out, hipStream_t st)
+void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
+                 double *partial, int nblk, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(BB_THREADS), 0, st, src, ns, tgt, nt, d, partial);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(BB_THREADS), 0, st, src, ns, tgt, nt, ys_lim, yt_lim,
+                       partial);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, partial, nblk, out);
 }
 
 void launch_keys(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
-                 int ncol, int rows_s, int rows_t, double d, uint32_t *key, int32_t *idx, int32_t *err,
-                 hipStream_t st)
+                 int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, uint32_t *key, int32_t *idx,
+                 int32_t *err, hipStream_t st)
 {
     int64_t n = ns + nt;
     if (n == 0) return;
     hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, ns, tgt, nt, x_lo, 1.0 / w,
-                       col_lo, ncol, rows_s, rows_t, d, key, idx, err);
+                       col_lo, ncol, rows_s, rows_t, ys_lim, yt_lim, key, idx, err);
+}
+
+__global__ void k_mirror(const double *__restrict__ xy, int64_t n, double *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        out[i] = xy[i];
+        out[n + i] = -xy[n + i];
+    }
+}
+
+void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mirror, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xy, n, out);
 }
 
 int sort_blocks(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
@@ -311,7 +331,7 @@ int launch_radix_sort(SortBufs &b, int64_t n, int bits, hipStream_t st)
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_upsweep, dim3(nblk), dim3(RS_THREADS), 0, st, kin, n, shift, b.hist, nblk);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, b.hist, (int64_t)256 * nblk);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(256), 0, st, b.hist, nblk);
         hipLaunchKernelGGL(k_rs_downsweep, dim3(nblk), dim3(RS_THREADS), 0, st, kin, iin, kout, iout, n, shift,
                            b.hist, nblk);
         uint32_t *tk = kin;

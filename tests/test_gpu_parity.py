@@ -108,3 +108,91 @@ def test_mixed_plain512_vs_oracle(torch_cuda, plain, golden512):
     err = rel(u.astype(np.complex128), golden512)
     say("mixed rel-l2", err)
     assert err < 1e-5
+
+
+@pytest.fixture(scope="module")
+def mid():
+    """4000 x 3000 points in the plain workload's slabs, 11 right-hand sides."""
+    rng = np.random.default_rng(77)
+    src, tgt, q, w = workloads.draw_instance(rng, 4000, 3000, (0, 1), (0.05, 1), (-0.95, -0.05), 11)
+    return dict(src=src, tgt=tgt, q=q, w=w, k=workloads.MEDIUM_A[0], d=workloads.MEDIUM_A[1])
+
+
+@pytest.fixture(scope="module")
+def mid_direct(torch_cuda, mid):
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("direct 4000x3000 nrhs=11")
+    pl = Plan(mid["k"], mid["d"], order=20, tol=1e-10)
+    return host(pl.direct(dev(mid["src"]), dev(mid["q"]), dev(mid["tgt"])))
+
+
+def test_mid_direct_sample_vs_oracle(mid, mid_direct, orc):
+    say("direct 4000x3000 sampled rows vs oracle")
+    sel = np.arange(0, 3000, 150)
+    ref = orc.apply(mid["src"], mid["q"][:2], mid["tgt"][:, sel], mid["k"], mid["d"])
+    assert rel(mid_direct[:2, sel], ref) < 1e-12
+
+
+@pytest.mark.parametrize("levels", [3, 4, 5, 6])
+def test_mid_fmm_vs_direct(torch_cuda, mid, mid_direct, levels):
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("fmm 4000x3000 nrhs=11 levels", levels)
+    pl = Plan(mid["k"], mid["d"], order=20, tol=1e-10, levels=levels)
+    u = host(pl.apply(dev(mid["src"]), dev(mid["q"]), dev(mid["tgt"])))
+    err = rel(u, mid_direct)
+    say("rel-l2", err, pl.stats()["order"])
+    assert err < 1e-10
+    # every right-hand side individually
+    for r in range(u.shape[0]):
+        assert rel(u[r], mid_direct[r]) < 1e-10
+
+
+def test_mid_mixed_vs_fp64(torch_cuda, mid, mid_direct):
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("mixed 4000x3000 nrhs=11 levels 5")
+    pl = Plan(mid["k"], mid["d"], order=16, tol=1e-6, levels=5)
+    u = host(pl.apply(dev(mid["src"]), dev(mid["q"].astype(np.complex64)), dev(mid["tgt"])))
+    err = rel(u.astype(np.complex128), mid_direct)
+    say("mixed rel-l2", err)
+    assert err < 5e-6
+
+
+def test_deterministic(torch_cuda, mid):
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("determinism 4000x3000")
+    pl = Plan(mid["k"], mid["d"], order=20, tol=1e-10, levels=5)
+    a = host(pl.apply(dev(mid["src"]), dev(mid["q"]), dev(mid["tgt"])))
+    b = host(pl.apply(dev(mid["src"]), dev(mid["q"]), dev(mid["tgt"])))
+    assert np.array_equal(a, b)
+
+
+def test_edge_cases(torch_cuda, plain, orc):
+    import torch
+    from paper_1902_08250_amd.lmfmm import Plan, LMFMMError
+    say("edge cases")
+    pl = Plan(plain["k"], plain["d"], order=20, tol=1e-10)
+    src, tgt, q = dev(plain["src"]), dev(plain["tgt"]), dev(plain["q"])
+    # no targets
+    u = pl.apply(src, q, tgt[:, :0].contiguous())
+    assert u.shape == (1, 0)
+    # no sources: zero field
+    u = host(pl.apply(src[:, :0].contiguous(), q[:, :0].contiguous(), tgt))
+    assert np.all(u == 0)
+    # one source, one target
+    s1, t1, q1 = plain["src"][:, :1], plain["tgt"][:, :1], plain["q"][:, :1]
+    u = host(pl.apply(dev(s1), dev(q1), dev(t1)))
+    ref = orc.apply(s1, q1, t1, plain["k"], plain["d"])
+    assert rel(u, ref) < 1e-12
+    # all points in a tiny cluster (one leaf) near the interface
+    rng = np.random.default_rng(3)
+    sc = np.stack([0.5 + 1e-3 * rng.random(50), 1e-4 + 1e-3 * rng.random(50)])
+    tc = np.stack([0.5 + 1e-3 * rng.random(40), -1e-4 - 1e-3 * rng.random(40)])
+    qc = (rng.standard_normal((1, 50)) + 1j * rng.standard_normal((1, 50)))
+    u = host(pl.apply(dev(sc), dev(qc), dev(tc)))
+    ref = orc.apply(sc, qc, tc, plain["k"], plain["d"])
+    assert rel(u, ref) < 1e-10
+    # a point in the wrong layer is rejected
+    bad = plain["tgt"].copy()
+    bad[1, 5] = 0.2
+    with pytest.raises(LMFMMError):
+        pl.apply(src, q, dev(bad))
