@@ -80,6 +80,10 @@ int lmfmm_destroy(lmfmm_plan plan);
  *                 readback, so an apply queues no host synchronisation.
  *                 Points outside it raise the device error flag (see
  *                 lmfmm_sync_status).  "auto" (default) clears it.
+ *   "kr_max"      largest k R (R = box half-diagonal, k = max |k1|, |k2|) of
+ *                 a level that carries expansions (default 8): coarser
+ *                 levels are skipped and the coarsest expansion level
+ *                 translates between all its non-adjacent boxes
  *   "near"        "1" (default) / "0": include / skip the near field
  *   "far"         "1" (default) / "0": include / skip the far field
  *   "timing"      "1": record HIP events around every stage of each apply

@@ -428,7 +428,8 @@ int orc_entry(const double *med, int flags, const double *opt, double x1, double
 
 /* u[r][i] = sum_j g(tgt_i, src_j) q[r][j].  src, tgt: SoA [2][n] (x then y);
  * q: [nrhs][n_src] interleaved complex; u: [nrhs][n_tgt] interleaved complex.
- * Targets are processed in parallel; sums are compensated. */
+ * The (target, source-chunk) tasks run in parallel; each chunk's sum is
+ * compensated and the chunks of a target are added in chunk order. */
 int orc_apply(const double *med, int flags, const double *opt, long n_src, const double *src, const double *q,
               long n_tgt, const double *tgt, double *u, int nrhs, int nthreads)
 {
@@ -441,12 +442,21 @@ int orc_apply(const double *med, int flags, const double *opt, long n_src, const
     if (rc) return rc;
     gl_init();
     set_threads(nthreads);
+    /* split the sources so that there are at least ~4 tasks per thread */
+    long nth = orc_max_threads();
+    long nchunk = 1;
+    if (n_tgt > 0 && n_tgt < 4 * nth) nchunk = (4 * nth + n_tgt - 1) / n_tgt;
+    if (nchunk > n_src) nchunk = n_src > 0 ? n_src : 1;
+    long clen = n_src > 0 ? (n_src + nchunk - 1) / nchunk : 0;
+    nsum_t *part = (nsum_t *)calloc((size_t)n_tgt * nchunk * nrhs + 1, sizeof(nsum_t));
+    if (!part) return ORC_EINVAL;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (long i = 0; i < n_tgt; ++i) {
-        nsum_t acc[64];
-        memset(acc, 0, sizeof(nsum_t) * nrhs);
-        for (long j = 0; j < n_src; ++j) {
+    for (long task = 0; task < n_tgt * nchunk; ++task) {
+        long i = task / nchunk, c = task % nchunk;
+        long j0 = c * clen, j1 = j0 + clen < n_src ? j0 + clen : n_src;
+        nsum_t *acc = part + (size_t)task * nrhs;
+        for (long j = j0; j < j1; ++j) {
             cplx g;
             if (entry(tgt[i], tgt[n_tgt + i], src[j], src[n_src + j], &m, &o, 1, &g, NULL)) bad = 1;
             for (int r = 0; r < nrhs; ++r) {
@@ -454,12 +464,17 @@ int orc_apply(const double *med, int flags, const double *opt, long n_src, const
                 nadd(&acc[r], g * (qr[2 * j] + I * qr[2 * j + 1]));
             }
         }
+    }
+    for (long i = 0; i < n_tgt; ++i)
         for (int r = 0; r < nrhs; ++r) {
-            cplx v = nval(&acc[r]);
+            nsum_t tot;
+            memset(&tot, 0, sizeof tot);
+            for (long c = 0; c < nchunk; ++c) nadd(&tot, nval(&part[((size_t)i * nchunk + c) * nrhs + r]));
+            cplx v = nval(&tot);
             u[2 * ((size_t)r * n_tgt + i)] = creal(v);
             u[2 * ((size_t)r * n_tgt + i) + 1] = cimag(v);
         }
-    }
+    free(part);
     return bad ? ORC_EINVAL : ORC_OK;
 }
 

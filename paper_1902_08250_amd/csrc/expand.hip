@@ -170,6 +170,7 @@ __device__ inline cx<T> local_value(const cx<T> *__restrict__ Lc, int base, cons
 struct DownArgs {
     // level l
     int nc, ncol, col_lo, rows_s, rows_t, nslots;
+    int top;  // 1 at the coarsest expansion level: every non-adjacent pair, no parent test
     // level l - 1
     int ncp, ncol_p, col_lo_p, rows_t_p, base_p;
     int has_l2l;
@@ -183,7 +184,7 @@ __global__ void __launch_bounds__(256) k_down(DownArgs a, int nrhs, const cx<T> 
                                               const cx<T> *__restrict__ part_p, const cx<T> *__restrict__ l2l,
                                               cx<T> *__restrict__ Lc,
                                               const cx<T> *__restrict__ Ms, const cx<T> *__restrict__ atab,
-                                              const int *__restrict__ cls_of, cx<T> *__restrict__ part)
+                                              const int *__restrict__ cls3, cx<T> *__restrict__ part)
 {
     __shared__ cx<T> Xs[GB][Chunk<T>::GK + 1];
     __shared__ cx<T> As[Chunk<T>::GK][GP + 1];
@@ -210,12 +211,11 @@ __global__ void __launch_bounds__(256) k_down(DownArgs a, int nrhs, const cx<T> 
     const int slot = z / nrhs, r = z % nrhs;
     const int nbox = a.ncol;
     if (b0 >= nbox) return;
-    const int co = cls_of[slot];
-    const int rs = (co / 10) % 10, dc = co % 10 - 3;
+    const int rs = cls3[3 * slot + 1], dc = cls3[3 * slot + 2];
     auto xload = [&](int b, int k) {
         int col = a.col_lo + b, cs = col + dc, csl = cs - a.col_lo;
         int dp = (cs >> 1) - (col >> 1);
-        bool ok = rs < a.rows_s && csl >= 0 && csl < a.ncol && dp <= 1 && dp >= -1;
+        bool ok = rs < a.rows_s && csl >= 0 && csl < a.ncol && (a.top || (dp <= 1 && dp >= -1));
         return ok ? Ms[(((int64_t)rs * a.ncol + csl) * nrhs + r) * a.nc + k] : mk<T>(0, 0);
     };
     auto store = [&](int b, int p, cx<T> v) { part[(((int64_t)slot * a.ncol + b) * nrhs + r) * a.nc + p] = v; };
@@ -569,15 +569,36 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
                        CH, M + lv.off_s);
 }
 
-inline RowSlots row_slots(const int *cls_of_host, int nslots)
+// cls3_host: (target row, source row, column offset) per class slot, or null
+// for a level whose partials are already folded into its local expansions.
+inline RowSlots row_slots(const int *cls3_host, int nslots)
 {
     RowSlots r;
     r.n[0] = r.n[1] = 0;
-    for (int i = 0; i < nslots && cls_of_host; ++i) {
-        int rt = cls_of_host[i] / 100;
+    for (int i = 0; i < nslots && cls3_host; ++i) {
+        int rt = cls3_host[3 * i];
         if (rt < 2 && r.n[rt] < 14) r.s[rt][r.n[rt]++] = i;
     }
     return r;
+}
+
+// Fold the M2L partials of the coarsest expansion level into its local
+// expansions: Lc[box] = sum over the classes of the box's row, in slot order.
+// row_off[rt] .. row_off[rt+1] are the slots whose target row is rt.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fold_top(const cx<T> *__restrict__ part, const int *__restrict__ row_off,
+                                                  int ncol, int nrhs, int nc, int64_t nout, cx<T> *__restrict__ Lc)
+{
+    int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= nout) return;
+    int p = (int)(o % nc);
+    int64_t t = o / nc;
+    int r = (int)(t % nrhs);
+    int64_t box = t / nrhs;
+    int rt = (int)(box / ncol), cl = (int)(box % ncol);
+    cx<T> v = mk<T>(0, 0);
+    for (int sl = row_off[rt]; sl < row_off[rt + 1]; ++sl) v += part[(((int64_t)sl * ncol + cl) * nrhs + r) * nc + p];
+    Lc[o] = v;
 }
 
 template <typename T, int PMAX>
@@ -596,7 +617,7 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
     hipLaunchKernelGGL((k_l2p_near<T, PMAX>), dim3(nbox, (nrhs + 7) / 8), dim3(64), sh, st, start, end, idx, xs, ys,
                        reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo,
-                       lv.w, k2, invR, Lc + lv.off_t, g.L >= 3 ? 1 : 0, part, row_slots(cls_of_host, nslots), nodes,
+                       lv.w, k2, invR, Lc + lv.off_t, 1, part, row_slots(cls_of_host, nslots), nodes,
                        nmid, npan, t0, do_far, do_near, key_t0,
                        reinterpret_cast<cx<T> *>(u));
 }
@@ -621,7 +642,7 @@ void grad_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx,
         hipLaunchKernelGGL((k_l2p_grad<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
                            reinterpret_cast<const cx<T> *>(q), reinterpret_cast<const cx<T> *>(cw), ns, nt, nrhs, r0,
                            nr, r0 > 0 ? 1 : 0, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo, lv.w, kt, invR,
-                           Lc + lv.off_t, g.L >= 3 ? 1 : 0, part, row_slots(cls_of_host, nslots), nodes, nmid, npan, t0,
+                           Lc + lv.off_t, 1, part, row_slots(cls_of_host, nslots), nodes, nmid, npan, t0,
                            do_far, do_near, key_t0, ysign, gout);
     }
 }
@@ -657,7 +678,7 @@ void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int nrhs,
 template <typename T>
 void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls_of,
                  const int *cls_of_p_host, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
-                 const cx<T> *l2l_tab, hipStream_t st)
+                 const cx<T> *l2l_tab, const int *top_row_off, hipStream_t st)
 {
     const Level &lv = g.lev[l], &pv = g.lev[l - 1];
     DownArgs a;
@@ -672,8 +693,9 @@ void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T>
     a.col_lo_p = pv.col_lo;
     a.rows_t_p = pv.rows_t;
     a.rsl_p = row_slots(cls_of_p_host, nslots_p);
-    a.base_p = l - 1 >= 3 ? 1 : 0;
+    a.base_p = 1;
     a.has_l2l = l2l_tab != nullptr;
+    a.top = top_row_off != nullptr;
     int nb_l2l = a.has_l2l ? (pv.rows_t * pv.ncol + GB - 1) / GB : 0;
     int nb_m2l = (lv.ncol + GB - 1) / GB;
     int gx = nb_l2l > nb_m2l ? nb_l2l : nb_m2l;
@@ -682,6 +704,11 @@ void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T>
     dim3 grid(gx, (lv.nc + GP - 1) / GP, gz);
     hipLaunchKernelGGL((k_down<T>), grid, dim3(256), 0, st, a, nrhs, Lc + pv.off_t, part_p, l2l_tab,
                        Lc + lv.off_t, M + lv.off_s, atab, cls_of, part);
+    if (top_row_off) {
+        int64_t nout = (int64_t)lv.rows_t * lv.ncol * nrhs * lv.nc;
+        hipLaunchKernelGGL((k_fold_top<T>), dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, part, top_row_off,
+                           lv.ncol, nrhs, lv.nc, nout, Lc + lv.off_t);
+    }
 }
 
 template <typename T>
@@ -746,7 +773,8 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
                                 const void *, int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);        \
     template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int, hipStream_t);                   \
     template void launch_down<T>(const Geometry &, int, int, int, const cx<T> *, const int *, const int *,          \
-                                 const cx<T> *, cx<T> *, cx<T> *, const cx<T> *, int, const cx<T> *, hipStream_t);  \
+                                 const cx<T> *, cx<T> *, cx<T> *, const cx<T> *, int, const cx<T> *, const int *,   \
+                                 hipStream_t);                                                                      \
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
                                      const cx<T> *, const cx<T> *, const int *, int, const Node *, int, int, double, \

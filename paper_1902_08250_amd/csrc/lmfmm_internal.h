@@ -215,6 +215,7 @@ struct Level {
 struct Geometry {
     double x_lo, W;
     int L;
+    int ltop;  // coarsest level carrying expansions (M2L among all its non-adjacent boxes)
     Level lev[MAXLEV + 1];
     int64_t ncoef_s, ncoef_t;  // total complex coefficients (times nrhs)
 };
@@ -262,9 +263,9 @@ void launch_p2m(const int32_t *start, const int32_t *end, const int32_t *idx, co
 template <typename T>
 void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int nrhs, hipStream_t st);
 template <typename T>
-void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls_of,
-                 const int *cls_of_p, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
-                 const cx<T> *l2l_tab, hipStream_t st);
+void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls3,
+                 const int *cls3_p_host, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
+                 const cx<T> *l2l_tab, const int *top_row_off, hipStream_t st);
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,

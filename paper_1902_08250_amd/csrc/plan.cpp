@@ -184,15 +184,17 @@ struct LevelTables {
     DevBuf m2m64, m2m32, l2l64, l2l32;  // [4][nc_in][nc_out]
     DevBuf a64, a32;                    // M2L tables [slot][nc][nc]
     DevBuf cls;                         // int[28]
-    DevBuf clsof;                       // int[nslots]: rt*100 + rs*10 + (dc+3)
+    DevBuf clsof;                       // int[3 * nslots]: target row, source row, column offset
     std::vector<int> clsof_host;
+    DevBuf rowoff;                      // top level only: slots of target row r are [rowoff[r], rowoff[r+1])
+    bool full = false;
     int nslots = 0;
     int64_t nodes = 0;
 };
 
 struct VarTables {
     // far-field tables
-    int t_L = -1;
+    int t_L = -1, t_top = -1;
     double t_W = -1;
     int t_P[MAXLEV + 1] = {0};
     LevelTables lt[MAXLEV + 1];
@@ -213,6 +215,7 @@ struct VarTables {
             t.a32.release();
             t.cls.release();
             t.clsof.release();
+            t.rowoff.release();
         }
     }
 };
@@ -223,6 +226,7 @@ struct lmfmm_plan_s {
     double tol = 1e-6;
     int levels_opt = 0;
     int fixed_order = 0;
+    double kr_max = 8.0;
     bool have_domain = false;
     double dom[4] = {0, 0, 0, 0};  // xmin, xmax, ys_max, yt_min
     bool do_near = true, do_far = true;
@@ -269,17 +273,43 @@ static void collect_timing(lmfmm_plan_s *p)
 static double kmax_re(const Medium &m) { return std::max(m.k1.re, std::max(m.k2.re, m.k3.re)); }
 static double contour_c(const Medium &m) { return std::max(1.0, 1.25 * kmax_re(m)); }
 
+// Smallest n with |J_n(z)| <= eps for real z > 0 (n >= z): Miller ratios.
+static int bessel_cutoff(double z, double eps)
+{
+    if (!(z > 0)) return 0;
+    int M = (int)std::ceil(z) + 80;
+    if (M > 1000) M = 1000;
+    std::vector<cx<double>> tm(1025);
+    cx<double> J0;
+    bessel_ratios<double, 1024>(cx<double>{z, 0.0}, 1.0, 0.0, M, tm.data(), J0);
+    double v = std::fabs(J0.re);
+    for (int n = 1; n <= M; ++n) {
+        v *= std::fabs(z * tm[n].re);  // |J_n / J_{n-1}| = |z t_n| (real argument)
+        if (n >= z && v <= eps) return n;
+    }
+    return M;
+}
+
+// Low-frequency limit for the expansions: a level carries multipole and
+// local expansions only if k R <= kr_max (R the box half-diagonal; plan
+// option "kr_max", default 8: above it the translation tables lose digits
+// to cancellation on the finite contour piece).
+
+static double kabs_max(const Medium &m)
+{
+    return std::max(std::abs(zc(m.k1.re, m.k1.im)), std::abs(zc(m.k2.re, m.k2.im)));
+}
+
 // Expansion order at a level: max(order, the order the tolerance needs for the
-// worst one-box-separated pair (ratio ~0.4 per term, Theorem 1), the order
-// the box size needs at the largest wave number).
+// worst one-box-separated pair (ratio ~0.4 per term, Theorem 1), the order at
+// which |J_P(|k| R)| falls below tol/100 for the level's box radius R).
 static int order_for_level(const lmfmm_plan_s *p, double w)
 {
     if (p->fixed_order) return p->order;
     double R = w / std::sqrt(2.0);
-    double kabs = std::max(std::abs(zc(p->med.k1.re, p->med.k1.im)), std::abs(zc(p->med.k2.re, p->med.k2.im)));
     int ptol = (int)std::ceil(std::log(p->tol) / std::log(0.4));
-    int phf = (int)std::ceil(1.2 * kabs * R + 10.0);
-    int P = std::max(p->order, std::max(ptol, phf));
+    int pj = bessel_cutoff(kabs_max(p->med) * R, 0.01 * p->tol);
+    int P = std::max(p->order, std::max(ptol, pj));
     return std::min(P, 480);
 }
 
@@ -331,6 +361,12 @@ static int make_geometry(lmfmm_plan_s *p, const double *bb, int64_t ns, int nrhs
         lv.nc = 2 * lv.P + 1;
     }
     g.lev[0] = g.lev[1];
+    g.ltop = L;
+    for (int l = 2; l <= L; ++l)
+        if (kabs_max(p->med) * g.lev[l].w / std::sqrt(2.0) <= p->kr_max) {
+            g.ltop = l;
+            break;
+        }
     for (int l = 1; l <= L; ++l) {
         Level &lv = g.lev[l];
         lv.off_s = offs;
@@ -430,22 +466,33 @@ static int build_shift_tables(VarTables &vt, const Medium &med, const Geometry &
 }
 
 // M2L tables of one level: one class per (target row, source row, column offset).
-static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g, int l)
+static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g, int l, bool full)
 {
     LevelTables &T = vt.lt[l];
+    T.full = full;
     const Level &lv = g.lev[l];
     int P = lv.P, nc = lv.nc;
     double w = lv.w, R = w / std::sqrt(2.0), c = contour_c(med);
-    std::vector<int> cls_index(28, -1), cls_of;
+    std::vector<int> cls_index(28, -1), cls_of, row_off;
     NodeList nl;
     std::vector<int> node_cls, node_local, cP, cQ;
     std::vector<int64_t> toff, aoff;
     std::vector<double> geo;
     int64_t tsum = 0;
     int slot = 0;
-    for (int rt = 0; rt < 2 && rt < lv.rows_t; ++rt)
-        for (int rs = 0; rs < 2 && rs < lv.rows_s; ++rs)
-            for (int dc = -3; dc <= 3; ++dc) {
+    // Classes (target row rt, source row rs, column offset dc = source - target
+    // column).  Standard level: rows 0/1 and |dc| <= 3 (children of adjacent
+    // parents); top level: every non-adjacent pair of its boxes.
+    const int nrt = full ? lv.rows_t : std::min(2, lv.rows_t);
+    const int nrs = full ? lv.rows_s : std::min(2, lv.rows_s);
+    const int dmax = full ? lv.ncol - 1 : 3;
+    if (full && (int64_t)nrt * nrs * (2 * dmax + 1) > 4096)
+        return fail(LMFMM_ETOL, "too many translation classes at the coarsest low-frequency level "
+                                "(wave number too large for the domain)");
+    for (int rt = 0; rt < nrt; ++rt) {
+        row_off.push_back(slot);
+        for (int rs = 0; rs < nrs; ++rs)
+            for (int dc = -dmax; dc <= dmax; ++dc) {
                 if (rt == 0 && rs == 0 && std::abs(dc) <= 1) continue;
                 double dxc = -dc * w;  // x_t - x_s with source column = target column + dc
                 double yt = -(rt + 0.5) * w, ys = (rs + 0.5) * w;
@@ -465,8 +512,10 @@ static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g,
                     node_cls.push_back(slot);
                     node_local.push_back(i);
                 }
-                cls_index[(rt * 2 + rs) * 7 + dc + 3] = slot;
-                cls_of.push_back(rt * 100 + rs * 10 + (dc + 3));
+                if (!full) cls_index[(rt * 2 + rs) * 7 + dc + 3] = slot;
+                cls_of.push_back(rt);
+                cls_of.push_back(rs);
+                cls_of.push_back(dc);
                 cP.push_back(P);
                 cQ.push_back(Q);
                 toff.push_back(tsum);
@@ -478,12 +527,15 @@ static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g,
                 geo.push_back(R);
                 ++slot;
             }
+    }
+    row_off.push_back(slot);
     T.nslots = slot;
     T.nodes = nl.count();
     int rc;
     if ((rc = upload(T.cls, cls_index.data(), 28 * sizeof(int)))) return rc;
     if (slot == 0) return LMFMM_OK;
     if ((rc = upload(T.clsof, cls_of.data(), cls_of.size() * sizeof(int)))) return rc;
+    if ((rc = upload(T.rowoff, row_off.data(), row_off.size() * sizeof(int)))) return rc;
     T.clsof_host = cls_of;
     DevBuf d_lw, d_ncls, d_nloc, d_geo, d_P, d_Q, d_toff, d_aoff, d_T, d_S;
     if ((rc = upload(d_lw, nl.lw.data(), nl.lw.size() * sizeof(double)))) return rc;
@@ -555,17 +607,20 @@ static int build_near_table(DevBuf &buf, const Medium &med, double dxmax, double
 
 static int ensure_far_tables(VarTables &vt, const Medium &med, const Geometry &g)
 {
-    bool same = vt.t_L == g.L && vt.t_W == g.W;
+    bool same = vt.t_L == g.L && vt.t_W == g.W && vt.t_top == g.ltop;
     for (int l = 1; same && l <= g.L; ++l) same = vt.t_P[l] == g.lev[l].P;
+    if (same && vt.lt[g.ltop].full) same = vt.lt[g.ltop].nslots > 0 || g.lev[g.ltop].rows_t == 0;
     if (same) return LMFMM_OK;
     double t_start = (double)clock() / CLOCKS_PER_SEC;
     int rc;
-    for (int l = 2; l <= g.L; ++l)
-        if ((rc = build_m2l_tables(vt, med, g, l))) return rc;
-    for (int l = 3; l <= g.L; ++l)
+    vt.t_L = -1;
+    for (int l = g.ltop; l <= g.L; ++l)
+        if ((rc = build_m2l_tables(vt, med, g, l, l == g.ltop))) return rc;
+    for (int l = g.ltop + 1; l <= g.L; ++l)
         if ((rc = build_shift_tables(vt, med, g, l))) return rc;
     vt.t_L = g.L;
     vt.t_W = g.W;
+    vt.t_top = g.ltop;
     for (int l = 0; l <= MAXLEV; ++l) vt.t_P[l] = l <= g.L ? g.lev[l].P : 0;
     vt.table_seconds = (double)clock() / CLOCKS_PER_SEC - t_start;
     return LMFMM_OK;
@@ -680,6 +735,12 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
     if (k == "near" || k == "far") {
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "near/far must be 0 or 1");
         (k == "near" ? p->do_near : p->do_far) = v == "1";
+        return LMFMM_OK;
+    }
+    if (k == "kr_max") {
+        double v2 = std::atof(value);
+        if (!(v2 >= 1.0 && v2 <= 200.0)) return fail(LMFMM_EINVAL, "kr_max must be in [1, 200]");
+        p->kr_max = v2;
         return LMFMM_OK;
     }
     if (k == "timing") {
@@ -816,7 +877,9 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     need += 2 * (size_t)n * 4 + 2 * (size_t)n * 4 + (size_t)256 * nblk * 4 + 2 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
     need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 20 * 256;
     int64_t part_off[MAXLEV + 2] = {0};
-    for (int l = 2; l <= L && far; ++l)
+    const int ltop = g.ltop;
+    for (int l = 0; l < ltop && l <= MAXLEV; ++l) part_off[l + 1] = 0;
+    for (int l = ltop; l <= L && far; ++l)
         part_off[l + 1] = part_off[l] + (int64_t)vt.lt[l].nslots * g.lev[l].ncol * nrhs * g.lev[l].nc;
     int64_t npart = far ? part_off[L + 1] : 0;
     need += (size_t)npart * sizeof(cx<T>);
@@ -865,8 +928,8 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     }
     mark(2);
     if (far) {
-        nlaunch[2] = L - 2;
-        for (int l = L; l >= 3; --l) {
+        nlaunch[2] = L - ltop;
+        for (int l = L; l >= ltop + 1; --l) {
             const LevelTables &tb = vt.lt[l];
             const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
             launch_m2m<T>(g, l, tab, M, nrhs, st);
@@ -875,21 +938,24 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     mark(3);
     if (far) {
         // Step 3: downward pass
-        nlaunch[3] = L - 1;
-        for (int l = 2; l <= L; ++l) {
+        nlaunch[3] = L - ltop + 2;
+        for (int l = ltop; l <= L; ++l) {
             const LevelTables &tb = vt.lt[l], &tp = vt.lt[l - 1];
             const cx<T> *atab = (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p);
             const cx<T> *l2l = nullptr;
-            if (l >= 3) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
-            int nsp = l >= 3 ? tp.nslots : 0;
-            launch_down<T>(g, l, tb.nslots, nsp, atab, (const int *)tb.clsof.p, l >= 3 ? tp.clsof_host.data() : nullptr,
-                           M, Lc, part + part_off[l], part + part_off[l - 1 >= 2 ? l - 1 : 2], nrhs, l2l, st);
+            if (l > ltop) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
+            // the parent's M2L partials are pending unless it is the top level (folded there)
+            bool pend_p = l - 1 > ltop;
+            launch_down<T>(g, l, tb.nslots, pend_p ? tp.nslots : 0, atab, (const int *)tb.clsof.p,
+                           pend_p ? tp.clsof_host.data() : nullptr, M, Lc, part + part_off[l],
+                           part + part_off[l > ltop ? l - 1 : l], nrhs, l2l, l == ltop ? (const int *)tb.rowoff.p : nullptr,
+                           st);
         }
     }
     mark(4);
     // Step 4: local evaluation and direct interactions
-    const int *clsL = far ? vt.lt[L].clsof_host.data() : nullptr;
-    int nsL = far ? vt.lt[L].nslots : 0;
+    const int *clsL = (far && L > ltop) ? vt.lt[L].clsof_host.data() : nullptr;
+    int nsL = (far && L > ltop) ? vt.lt[L].nslots : 0;
     if (!gw)
         launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
                            (const Node *)vt.near_nodes.p, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0,
@@ -918,7 +984,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     s.near_nodes_ray = vt.n_npan * NGL;
     int ncls = 0;
     int64_t nn = 0;
-    for (int l = 2; l <= L && far; ++l) {
+    for (int l = ltop; l <= L && far; ++l) {
         ncls += vt.lt[l].nslots;
         nn += vt.lt[l].nodes;
     }

@@ -137,3 +137,24 @@ def test_grad_mixed_vs_fp64(cuda):
     es, et = rel(host(ds32), host(ds64)), rel(host(dt32), host(dt64))
     say("mixed grad rel-l2 src", es, "tgt", et)
     assert es < 2e-5 and et < 2e-5
+
+
+def test_autograd_function(cuda):
+    import torch
+    from paper_1902_08250_amd.autograd import lmfmm_apply
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("autograd function 3000x2500")
+    src, tgt, q, w = problem(3000, 2500, 2, 27)
+    pl = Plan(K, D, order=20, tol=1e-10, levels=4)
+    s = dev(src).requires_grad_(True)
+    t = dev(tgt).requires_grad_(True)
+    qq = dev(q).requires_grad_(True)
+    ww = dev(w)
+    u = lmfmm_apply(pl, s, qq, t)
+    L = (ww * u).sum().real
+    L.backward()
+    v = host(pl.apply_adjoint(dev(src), dev(tgt), dev(w)))
+    ds, dt = pl.grad_coords(dev(src), dev(q), dev(tgt), dev(w))
+    assert rel(host(qq.grad), np.conj(v)) < 1e-13
+    assert rel(host(s.grad), host(ds)) < 1e-13
+    assert rel(host(t.grad), host(dt)) < 1e-13
