@@ -43,10 +43,16 @@ EXPORTS = ["lmfmm_create", "lmfmm_destroy", "lmfmm_set_option", "lmfmm_apply", "
 
 
 def lib():
-    """Load liblmfmm.so (raises if it has not been built)."""
+    """Load liblmfmm.so (raises if it has not been built).
+
+    torch is imported first: torch ships its own HIP runtime with the same
+    soname (libamdhip64.so.7) as the system one the library links, and the
+    first one loaded serves the whole process.  Loading torch's first keeps the
+    runtime torch was built against, which both sides then share."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (see above)
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1902_08250_amd.build`")
     L = ctypes.CDLL(LIB_PATH)

@@ -1,0 +1,132 @@
+"""Backward workload: N = M = 1e6 points in the plain slabs, medium
+k = (10, 20, 15) + 0.01i, d = 1, FP32 (mixed) forward; dL/dq (transposed
+operator) and dL/d(coordinates) for L = Re sum_i w_i u_i.
+
+Checks:
+  * mixed-precision gradients and adjoint against the FP64 ones (tol 1e-10);
+  * FP64 gradients against central differences (h = 1e-5) on a random subset
+    of 500 sources and 500 targets: the perturbed points are appended to the
+    point sets so that one extended apply (targets) and one extended
+    transposed apply (sources) give every difference quotient.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1902_08250_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def big():
+    return workloads.make(4)
+
+
+@pytest.fixture(scope="module")
+def ref64(big):
+    """FP64 reference gradients and adjoint (tol 1e-10)."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("fp64 reference gradients 1e6")
+    pl = Plan(big["k"], big["d"], order=16, tol=1e-10)
+    q, w = big["q"].astype(np.complex128), big["w"].astype(np.complex128)
+    s, t = dev(big["src"]), dev(big["tgt"])
+    t0 = time.perf_counter()
+    ds, dt = pl.grad_coords(s, dev(q), t, dev(w))
+    v = pl.apply_adjoint(s, t, dev(w))
+    ds, dt, v = host(ds), host(dt), host(v)
+    say("fp64 grad+adjoint", time.perf_counter() - t0, "s; orders", pl.stats()["order"])
+    return dict(ds=ds, dt=dt, v=v, plan=pl)
+
+
+def test_mixed_backward_vs_fp64(big, ref64):
+    import torch
+    from paper_1902_08250_amd.autograd import lmfmm_apply
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("mixed forward + backward 1e6")
+    pl = Plan(big["k"], big["d"], order=16, tol=1e-6)
+    s = dev(big["src"]).requires_grad_(True)
+    t = dev(big["tgt"]).requires_grad_(True)
+    q = dev(big["q"]).requires_grad_(True)
+    w = dev(big["w"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = lmfmm_apply(pl, s, q, t)
+    L = (w * u).sum().real
+    L.backward()
+    torch.cuda.synchronize()
+    say("mixed forward+backward", time.perf_counter() - t0, "s")
+    eq = rel(host(q.grad).astype(np.complex128), np.conj(ref64["v"]))
+    es = rel(host(s.grad), ref64["ds"])
+    et = rel(host(t.grad), ref64["dt"])
+    say("rel-l2 vs fp64: dL/dq", eq, "dL/dsrc", es, "dL/dtgt", et)
+    assert eq < 1e-5 and es < 1e-5 and et < 1e-5
+
+
+def test_fp64_gradient_central_differences(big):
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("central differences on 500 + 500 points, 1e6")
+    h = 1e-5
+    pl = Plan(big["k"], big["d"], order=16, tol=1e-12)
+    q, w = big["q"].astype(np.complex128), big["w"].astype(np.complex128)
+    src, tgt = big["src"], big["tgt"]
+    ns, nt = src.shape[1], tgt.shape[1]
+    rng = np.random.default_rng(404)
+    S = np.sort(rng.choice(ns, 500, replace=False))
+    T = np.sort(rng.choice(nt, 500, replace=False))
+    ds, dt = pl.grad_coords(dev(src), dev(q), dev(tgt), dev(w))
+    ds, dt = host(ds), host(dt)
+
+    def shifted(arr, sel):
+        out = [arr]
+        for comp in (0, 1):
+            for sgn in (1, -1):
+                a = arr[:, sel].copy()
+                a[comp] += sgn * h
+                out.append(a)
+        return np.ascontiguousarray(np.concatenate(out, axis=1))
+
+    # targets: field at x_i +- h e_x, +- h e_y
+    te = shifted(tgt, T)
+    u = host(pl.apply(dev(src), dev(q), dev(te)))
+    m = len(T)
+    ux = (u[:, nt:nt + m] - u[:, nt + m:nt + 2 * m]) / (2 * h)
+    uy = (u[:, nt + 2 * m:nt + 3 * m] - u[:, nt + 3 * m:nt + 4 * m]) / (2 * h)
+    fdx = np.real(np.sum(w[:, T] * ux, axis=0))
+    fdy = np.real(np.sum(w[:, T] * uy, axis=0))
+    gt = np.stack([dt[0, T], dt[1, T]])
+    et = np.linalg.norm(np.stack([fdx, fdy]) - gt) / np.linalg.norm(gt)
+    # sources: transposed field at x_j +- h e_x, +- h e_y
+    se = shifted(src, S)
+    v = host(pl.apply_adjoint(dev(se), dev(tgt), dev(w)))
+    m = len(S)
+    vx = (v[:, ns:ns + m] - v[:, ns + m:ns + 2 * m]) / (2 * h)
+    vy = (v[:, ns + 2 * m:ns + 3 * m] - v[:, ns + 3 * m:ns + 4 * m]) / (2 * h)
+    fsx = np.real(np.sum(q[:, S] * vx, axis=0))
+    fsy = np.real(np.sum(q[:, S] * vy, axis=0))
+    gs = np.stack([ds[0, S], ds[1, S]])
+    es = np.linalg.norm(np.stack([fsx, fsy]) - gs) / np.linalg.norm(gs)
+    say("central differences rel-l2: targets", et, "sources", es)
+    assert et < 1e-6 and es < 1e-6
