@@ -153,6 +153,40 @@ int lmfmm_get_stats(lmfmm_plan plan, lmfmm_stats *stats);
  * last apply (points outside the fixed domain or their layer). */
 int lmfmm_sync_status(lmfmm_plan plan, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched apply: many independent problems (own medium, points, densities).
+ * Not in the paper: a throughput interface for uneven problem sizes.
+ *
+ * lmfmm_batch_create makes one plan per instance; order_set lists candidate
+ * order floors (e.g. {12, 16, 20}) and tol the accuracy every candidate must
+ * meet (the order rule of lmfmm_create enforces it).  On the first
+ * lmfmm_batch_apply, and whenever the descriptors change, each instance's
+ * bounding box is read once, an autotuner times each (order floor, levels)
+ * candidate with HIP events and keeps the fastest, and all instances are
+ * captured into one HIP graph (four parallel branches).  Later calls with the
+ * same descriptors are one hipGraphLaunch on `stream` with no host sync.
+ * inst: host array of n_inst descriptors with device pointers; all instances
+ * use the same nrhs and precision.  Options: "tune" 0/1 (default 1), "graph"
+ * 0/1 (default 1); other keys are forwarded to every instance's plan.
+ * --------------------------------------------------------------------------- */
+typedef struct lmfmm_batch_s *lmfmm_batch;
+typedef struct {
+    int64_t n_src;
+    const double *src_xy; /* device [2][n_src] */
+    const void *q;        /* device [nrhs][n_src] */
+    int64_t n_tgt;
+    const double *tgt_xy; /* device [2][n_tgt] */
+    void *u;              /* device [nrhs][n_tgt], overwritten */
+} lmfmm_instance;
+
+int lmfmm_batch_create(int n_inst, const double *k /* [n_inst][6] */, const double *d /* [n_inst] */,
+                       const int *order_set, int n_orders, double tol, lmfmm_batch *out);
+int lmfmm_batch_destroy(lmfmm_batch batch);
+int lmfmm_batch_set_option(lmfmm_batch batch, const char *key, const char *value);
+int lmfmm_batch_apply(lmfmm_batch batch, const lmfmm_instance *inst, int nrhs, int precision, void *stream);
+/* The autotuner's choice for instance i and its measured time per apply (us). */
+int lmfmm_batch_get_choice(lmfmm_batch batch, int i, int *order, int *levels, double *us);
+
 const char *lmfmm_status_string(int status);
 const char *lmfmm_last_error(void);
 

@@ -228,6 +228,8 @@ struct lmfmm_plan_s {
     int fixed_order = 0;
     double kr_max = 8.0;
     bool have_domain = false;
+    bool have_box = false;        // pinned bounding box (set by the batch driver)
+    double box[6] = {0, 0, 0, 0, 0, 0};
     double dom[4] = {0, 0, 0, 0};  // xmin, xmax, ys_max, yt_min
     bool do_near = true, do_far = true;
 
@@ -812,6 +814,11 @@ static double yt_limit(const Medium &m) { return m.adj ? -INFINITY : -m.d; }
 static int get_bbox(lmfmm_plan p, const Medium &med, int64_t ns, const double *src, int64_t nt, const double *tgt,
                     hipStream_t st, double *bb)
 {
+    if (p->have_box && !med.adj) {
+        for (int i = 0; i < 6; ++i) bb[i] = p->box[i];
+        bb[6] = 0.0;
+        return LMFMM_OK;
+    }
     if (p->have_domain) {
         bb[0] = p->dom[0];
         bb[1] = p->dom[1];
@@ -864,7 +871,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     if (g.lev[L].P > 255) return fail(LMFMM_EINVAL, "leaf-level expansion order above 255: use more levels");
     bool far = p->do_far && L >= 2;
     if (far && (rc = ensure_far_tables(vt, med, g))) return rc;
-    double amin = p->have_domain ? 1e-9 * g.W : std::max(bb[2], 0.0) + std::max(-bb[5], 0.0);
+    double amin = std::max(bb[2], 0.0) + std::max(-bb[5], 0.0);
     if (!(amin > 0)) amin = 1e-9 * g.W;
     if ((rc = ensure_near_table(vt, med, g, amin))) return rc;
 
@@ -1105,6 +1112,273 @@ int lmfmm_sync_status(lmfmm_plan p, void *stream)
         return LMFMM_OK;
     }
     HIPCHK(hipStreamSynchronize(st));
+    return LMFMM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched apply: many independent problems in one graph launch.
+//
+// Preparation (first call, or when the instance descriptors change):
+//   1. each instance's bounding box is read once and pinned in its plan, so
+//      later applies queue no host synchronisation;
+//   2. the autotuner times every (order floor, levels) candidate per instance
+//      with HIP events and keeps the fastest (the tolerance is enforced for
+//      every candidate by the order rule);
+//   3. one apply per instance allocates its tables and workspace, then all
+//      instances are captured into one HIP graph, instance i on branch i % 4
+//      of a fork/join over four streams.
+// Every later call with the same descriptors is a single hipGraphLaunch.
+// ---------------------------------------------------------------------------
+struct lmfmm_batch_s {
+    int n = 0;
+    std::vector<lmfmm_plan_s *> plans;
+    std::vector<int> order_set;
+    double tol = 1e-6;
+    bool tune = true, graph = true;
+    // prepared state
+    bool prepared = false;
+    std::vector<lmfmm_instance> desc;
+    int nrhs = 0, prec = -1;
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> fork_ev, join_ev;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    std::vector<int> chosen_order, chosen_levels;
+    std::vector<double> chosen_us;
+};
+
+static void batch_drop_graph(lmfmm_batch_s *b)
+{
+    if (b->ge) (void)hipGraphExecDestroy(b->ge);
+    if (b->g) (void)hipGraphDestroy(b->g);
+    b->ge = nullptr;
+    b->g = nullptr;
+    b->prepared = false;
+}
+
+static int plan_apply_any(lmfmm_plan_s *p, const lmfmm_instance &in, int nrhs, int prec, hipStream_t st)
+{
+    return prec == LMFMM_C128 ? apply_impl<double>(p, 0, in.n_src, in.src_xy, in.q, in.n_tgt, in.tgt_xy, in.u, nrhs, st)
+                              : apply_impl<float>(p, 0, in.n_src, in.src_xy, in.q, in.n_tgt, in.tgt_xy, in.u, nrhs, st);
+}
+
+static bool same_desc(const lmfmm_instance &a, const lmfmm_instance &b)
+{
+    return a.n_src == b.n_src && a.src_xy == b.src_xy && a.q == b.q && a.n_tgt == b.n_tgt && a.tgt_xy == b.tgt_xy &&
+           a.u == b.u;
+}
+
+static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs, int prec, hipStream_t st)
+{
+    batch_drop_graph(b);
+    int rc;
+    b->chosen_order.assign(b->n, 0);
+    b->chosen_levels.assign(b->n, 0);
+    b->chosen_us.assign(b->n, 0.0);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int i = 0; i < b->n; ++i) {
+        lmfmm_plan_s *p = b->plans[i];
+        const lmfmm_instance &in = inst[i];
+        p->have_box = false;
+        if (in.n_src == 0 || in.n_tgt == 0) continue;
+        // 1. pin the bounding box
+        double bb[8];
+        if ((rc = get_bbox(p, p->med, in.n_src, in.src_xy, in.n_tgt, in.tgt_xy, st, bb))) return rc;
+        for (int j = 0; j < 6; ++j) p->box[j] = bb[j];
+        p->have_box = true;
+        // 2. autotune (order floor from the set, levels around the automatic choice)
+        p->levels_opt = 0;
+        Geometry g0;
+        if ((rc = make_geometry(p, bb, in.n_src, nrhs, g0))) return rc;
+        std::vector<int> Ls;
+        if (b->tune) {
+            for (int dl = -1; dl <= 1; ++dl)
+                if (g0.L + dl >= 1 && g0.L + dl <= MAXLEV) Ls.push_back(g0.L + dl);
+        } else {
+            Ls.push_back(g0.L);
+        }
+        std::vector<int> orders = b->tune ? b->order_set : std::vector<int>{b->order_set.front()};
+        double best = 1e300;
+        int bo = orders.front(), bl = Ls.front();
+        for (int o : orders)
+            for (int L : Ls) {
+                p->order = o;
+                p->levels_opt = L;
+                rc = plan_apply_any(p, in, nrhs, prec, st);  // builds tables
+                if (rc == LMFMM_ETOL) continue;
+                if (rc) return rc;
+                const int reps = 3;
+                HIPCHK(hipEventRecord(e0, st));
+                for (int r = 0; r < reps && rc == LMFMM_OK; ++r) rc = plan_apply_any(p, in, nrhs, prec, st);
+                if (rc) return rc;
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                double us = 1e3 * ms / reps;
+                if (us < best) {
+                    best = us;
+                    bo = o;
+                    bl = L;
+                }
+            }
+        p->order = bo;
+        p->levels_opt = bl;
+        b->chosen_order[i] = bo;
+        b->chosen_levels[i] = bl;
+        b->chosen_us[i] = best;
+        // 3. warm the chosen configuration (tables, workspace)
+        if ((rc = plan_apply_any(p, in, nrhs, prec, st))) return rc;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipStreamSynchronize(st));
+    b->desc.assign(inst, inst + b->n);
+    b->nrhs = nrhs;
+    b->prec = prec;
+    if (b->graph) {
+        // capture all instances on a private stream forked into four branches
+        if (!b->cap_stream) {
+            HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+            b->branch.resize(4);
+            b->fork_ev.resize(1);
+            b->join_ev.resize(4);
+            for (auto &s2 : b->branch) HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&b->fork_ev[0], hipEventDisableTiming));
+            for (auto &e : b->join_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        HIPCHK(hipEventRecord(b->fork_ev[0], b->cap_stream));
+        for (int k = 0; k < 4; ++k) HIPCHK(hipStreamWaitEvent(b->branch[k], b->fork_ev[0], 0));
+        int crc = LMFMM_OK;
+        for (int i = 0; i < b->n && crc == LMFMM_OK; ++i) {
+            lmfmm_plan_s *p = b->plans[i];
+            bool timing = p->timing;
+            p->timing = false;
+            crc = plan_apply_any(p, inst[i], nrhs, prec, b->branch[i % 4]);
+            p->timing = timing;
+        }
+        for (int k = 0; k < 4; ++k) {
+            (void)hipEventRecord(b->join_ev[k], b->branch[k]);
+            (void)hipStreamWaitEvent(b->cap_stream, b->join_ev[k], 0);
+        }
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
+        if (crc) {
+            if (g) (void)hipGraphDestroy(g);
+            return crc;
+        }
+        if (ce != hipSuccess) return fail(LMFMM_EHIP, std::string("graph capture failed: ") + hipGetErrorString(ce));
+        b->g = g;
+        HIPCHK(hipGraphInstantiate(&b->ge, g, nullptr, nullptr, 0));
+    }
+    b->prepared = true;
+    return LMFMM_OK;
+}
+
+extern "C" {
+
+int lmfmm_batch_create(int n_inst, const double *k, const double *d, const int *order_set, int n_orders, double tol,
+                       lmfmm_batch *out)
+{
+    if (!out) return fail(LMFMM_EINVAL, "out is null");
+    *out = nullptr;
+    if (n_inst < 1 || n_inst > 4096 || !k || !d) return fail(LMFMM_EINVAL, "bad instance count or media");
+    if (!order_set || n_orders < 1 || n_orders > 16) return fail(LMFMM_EINVAL, "bad order set");
+    lmfmm_batch_s *b = new (std::nothrow) lmfmm_batch_s();
+    if (!b) return fail(LMFMM_ENOMEM, "batch allocation failed");
+    b->n = n_inst;
+    b->tol = tol;
+    b->order_set.assign(order_set, order_set + n_orders);
+    std::sort(b->order_set.begin(), b->order_set.end());
+    for (int i = 0; i < n_inst; ++i) {
+        lmfmm_plan p = nullptr;
+        int rc = lmfmm_create(k + 6 * i, d[i], b->order_set.front(), tol, &p);
+        if (rc) {
+            for (auto q : b->plans) lmfmm_destroy(q);
+            delete b;
+            return rc;
+        }
+        b->plans.push_back(p);
+    }
+    *out = b;
+    return LMFMM_OK;
+}
+
+int lmfmm_batch_destroy(lmfmm_batch b)
+{
+    if (!b) return fail(LMFMM_EINVAL, "batch is null");
+    (void)hipDeviceSynchronize();
+    batch_drop_graph(b);
+    for (auto p : b->plans) lmfmm_destroy(p);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (auto s2 : b->branch) (void)hipStreamDestroy(s2);
+    for (auto e : b->fork_ev) (void)hipEventDestroy(e);
+    for (auto e : b->join_ev) (void)hipEventDestroy(e);
+    delete b;
+    return LMFMM_OK;
+}
+
+int lmfmm_batch_set_option(lmfmm_batch b, const char *key, const char *value)
+{
+    if (!b || !key || !value) return fail(LMFMM_EINVAL, "null argument");
+    std::string k(key), v(value);
+    if (k == "tune" || k == "graph") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "tune/graph must be 0 or 1");
+        (k == "tune" ? b->tune : b->graph) = v == "1";
+        batch_drop_graph(b);
+        return LMFMM_OK;
+    }
+    // any other key is forwarded to every instance's plan
+    for (auto p : b->plans) {
+        int rc = lmfmm_set_option(p, key, value);
+        if (rc) return rc;
+    }
+    batch_drop_graph(b);
+    return LMFMM_OK;
+}
+
+int lmfmm_batch_apply(lmfmm_batch b, const lmfmm_instance *inst, int nrhs, int prec, void *stream)
+{
+    if (!b || !inst) return fail(LMFMM_EINVAL, "null argument");
+    for (int i = 0; i < b->n; ++i) {
+        int rc = check_common(b->plans[i], inst[i].n_src, inst[i].src_xy, inst[i].n_tgt, inst[i].tgt_xy, inst[i].q,
+                              inst[i].u, nrhs, prec);
+        if (rc) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    bool same = b->prepared && nrhs == b->nrhs && prec == b->prec;
+    for (int i = 0; same && i < b->n; ++i) same = same_desc(inst[i], b->desc[i]);
+    if (!same) {
+        int rc = batch_prepare(b, inst, nrhs, prec, st);
+        if (rc) {
+            batch_drop_graph(b);
+            return rc;
+        }
+    }
+    if (b->ge) {
+        HIPCHK(hipGraphLaunch(b->ge, st));
+        return LMFMM_OK;
+    }
+    for (int i = 0; i < b->n; ++i) {
+        int rc = plan_apply_any(b->plans[i], inst[i], nrhs, prec, st);
+        if (rc) return rc;
+    }
+    return LMFMM_OK;
+}
+
+int lmfmm_batch_get_choice(lmfmm_batch b, int i, int *order, int *levels, double *us)
+{
+    if (!b || i < 0 || i >= b->n) return fail(LMFMM_EINVAL, "bad batch or index");
+    if (!b->prepared) return fail(LMFMM_EINVAL, "batch not prepared yet");
+    if (order) *order = b->chosen_order[i];
+    if (levels) *levels = b->chosen_levels[i];
+    if (us) *us = b->chosen_us[i];
     return LMFMM_OK;
 }
 

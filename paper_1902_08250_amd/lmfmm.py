@@ -37,9 +37,15 @@ class Stats(ctypes.Structure):
                 ("stage_launches", ctypes.c_int64 * 8), ("timed_applies", ctypes.c_int64)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("n_src", ctypes.c_int64), ("src_xy", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("n_tgt", ctypes.c_int64), ("tgt_xy", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
 EXPORTS = ["lmfmm_create", "lmfmm_destroy", "lmfmm_set_option", "lmfmm_apply", "lmfmm_apply_adjoint",
-           "lmfmm_grad_coords", "lmfmm_direct", "lmfmm_get_stats", "lmfmm_sync_status", "lmfmm_status_string",
-           "lmfmm_last_error"]
+           "lmfmm_grad_coords", "lmfmm_direct", "lmfmm_get_stats", "lmfmm_sync_status", "lmfmm_batch_create",
+           "lmfmm_batch_destroy", "lmfmm_batch_set_option", "lmfmm_batch_apply", "lmfmm_batch_get_choice",
+           "lmfmm_status_string", "lmfmm_last_error"]
 
 
 def lib():
@@ -69,6 +75,12 @@ def lib():
     L.lmfmm_grad_coords.argtypes = [P, I64, P, P, I64, P, P, P, P, I, I, P]
     L.lmfmm_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.lmfmm_sync_status.argtypes = [P, P]
+    L.lmfmm_batch_create.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I), I, D,
+                                     ctypes.POINTER(P)]
+    L.lmfmm_batch_destroy.argtypes = [P]
+    L.lmfmm_batch_set_option.argtypes = [P, ctypes.c_char_p, ctypes.c_char_p]
+    L.lmfmm_batch_apply.argtypes = [P, ctypes.POINTER(Instance), I, I, P]
+    L.lmfmm_batch_get_choice.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]
     L.lmfmm_status_string.argtypes = [I]
     L.lmfmm_status_string.restype = ctypes.c_char_p
     L.lmfmm_last_error.argtypes = []
@@ -200,3 +212,78 @@ class Plan:
         d["stage_ms"] = list(s.stage_ms)[:5]
         d["stage_launches"] = list(s.stage_launches)[:5]
         return d
+
+
+class Batch:
+    """Many independent problems applied in one graph launch (lmfmm_batch_*).
+
+    media: list of (k, d); order_set: candidate order floors for the autotuner."""
+
+    def __init__(self, media, order_set=(12, 16, 20), tol=1e-6, tune=True, graph=True):
+        L = lib()
+        n = len(media)
+        karr = (ctypes.c_double * (6 * n))()
+        darr = (ctypes.c_double * n)()
+        for i, (k, d) in enumerate(media):
+            kk = [complex(v) for v in k]
+            for j in range(3):
+                karr[6 * i + 2 * j] = kk[j].real
+                karr[6 * i + 2 * j + 1] = kk[j].imag
+            darr[i] = float(d)
+        oarr = (ctypes.c_int * len(order_set))(*order_set)
+        h = ctypes.c_void_p()
+        _check(L.lmfmm_batch_create(n, karr, darr, oarr, len(order_set), float(tol), ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self._keep = None
+        if not tune:
+            self.set_option("tune", "0")
+        if not graph:
+            self.set_option("graph", "0")
+
+    def set_option(self, key, value):
+        _check(lib().lmfmm_batch_set_option(self._h, key.encode(), str(value).encode()))
+
+    def apply(self, items, outs=None, stream=None):
+        """items: list of (src, q, tgt); returns the list of outputs u (reuses outs if given,
+        which keeps the descriptors fixed so that later calls replay the captured graph)."""
+        import torch
+        if len(items) != self.n:
+            raise ValueError("one (src, q, tgt) per instance")
+        arr = (Instance * self.n)()
+        if outs is None:
+            outs = []
+            for (src, q, tgt) in items:
+                q2 = q if q.dim() == 2 else q.unsqueeze(0)
+                outs.append(torch.empty((q2.shape[0], tgt.shape[1]), dtype=q.dtype, device=q.device))
+        nrhs, prec = None, None
+        keep = []
+        for i, ((src, q, tgt), u) in enumerate(zip(items, outs)):
+            src, tgt = _xy(src, "src"), _xy(tgt, "tgt")
+            q = _dens(q, src.shape[1], "q")
+            keep += [src, q, tgt, u]
+            nrhs = q.shape[0] if nrhs is None else nrhs
+            prec = _prec(q.dtype) if prec is None else prec
+            arr[i] = Instance(src.shape[1], src.data_ptr(), q.data_ptr(), tgt.shape[1], tgt.data_ptr(), u.data_ptr())
+        _check(lib().lmfmm_batch_apply(self._h, arr, nrhs, prec, _stream(stream)))
+        self._keep = keep
+        return outs
+
+    def choices(self):
+        out = []
+        for i in range(self.n):
+            o, L_, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+            _check(lib().lmfmm_batch_get_choice(self._h, i, ctypes.byref(o), ctypes.byref(L_), ctypes.byref(us)))
+            out.append(dict(order=o.value, levels=L_.value, us=us.value))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lmfmm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
