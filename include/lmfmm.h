@@ -84,6 +84,8 @@ int lmfmm_destroy(lmfmm_plan plan);
  *                 a level that carries expansions (default 8): coarser
  *                 levels are skipped and the coarsest expansion level
  *                 translates between all its non-adjacent boxes
+ *   "near_sweep"  "1" (default): near field by x-ordered sweeps over the node
+ *                 table; "0": the pairwise sum (same quadrature)
  *   "near"        "1" (default) / "0": include / skip the near field
  *   "far"         "1" (default) / "0": include / skip the far field
  *   "timing"      "1": record HIP events around every stage of each apply

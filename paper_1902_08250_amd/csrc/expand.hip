@@ -306,7 +306,8 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
                                                  const cx<T> *__restrict__ part, RowSlots rsl,
                                                  const Node *__restrict__ nodes,
                                                  int nmid, int npan, double t0, int do_far, int do_near,
-                                                 int64_t key_t0, cx<T> *__restrict__ u)
+                                                 int64_t key_t0, const cx<double> *__restrict__ unear, int nparts,
+                                                 cx<T> *__restrict__ u)
 {
     constexpr int RMAX = 8;
     extern __shared__ unsigned char smem_raw[];
@@ -357,19 +358,29 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
             for (int r = 0; r < RMAX; ++r) res[r] = {(double)acc[r].re, (double)acc[r].im};
         }
         if (do_near && row == 0 && rows_s > 0) {
-            for (int dc = -1; dc <= 1; ++dc) {
-                int cs = cl + dc;
-                if (cs < 0 || cs >= ncol) continue;
-                int js = start[cs], je = end[cs];  // row-0 source leaf
-                for (int j = js; j < je; ++j) {
-                    double x0 = xs[j], y0 = ys[j];
-                    cx<double> G = pair_kernel(nodes, nmid, npan, t0, y1, y0, fabs(x1 - x0), act);
-                    int64_t o = idx[j];
-                    for (int r = 0; r < RMAX; ++r)
-                        if (r < nr) {
-                            cx<T> qq = q[(int64_t)(r0 + r) * ns + o];
-                            cfma(res[r], G, cx<double>{(double)qq.re, (double)qq.im});
-                        }
+            if (unear) {
+                // near field computed by the sweep kernel: add its parts in order
+                if (act) {
+                    int64_t o = idx[i] - ns;
+                    for (int pp = 0; pp < nparts; ++pp)
+                        for (int r = 0; r < RMAX; ++r)
+                            if (r < nr) res[r] += unear[((int64_t)pp * nrhs + r0 + r) * nt + o];
+                }
+            } else {
+                for (int dc = -1; dc <= 1; ++dc) {
+                    int cs = cl + dc;
+                    if (cs < 0 || cs >= ncol) continue;
+                    int js = start[cs], je = end[cs];  // row-0 source leaf
+                    for (int j = js; j < je; ++j) {
+                        double x0 = xs[j], y0 = ys[j];
+                        cx<double> G = pair_kernel(nodes, nmid, npan, t0, y1, y0, fabs(x1 - x0), act);
+                        int64_t o = idx[j];
+                        for (int r = 0; r < RMAX; ++r)
+                            if (r < nr) {
+                                cx<T> qq = q[(int64_t)(r0 + r) * ns + o];
+                                cfma(res[r], G, cx<double>{(double)qq.re, (double)qq.im});
+                            }
+                    }
                 }
             }
         }
@@ -378,6 +389,175 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
             for (int r = 0; r < RMAX; ++r)
                 if (r < nr) u[(int64_t)(r0 + r) * nt + o] = mk<T>((T)res[r].re, (T)res[r].im);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Near field by x-ordered sweeps (S2T over adjacent leaves across the
+// interface).  For a fixed node lam_n of the pair-independent contour, the
+// pair term of source j and target i with x_j <= x_i is
+//   D_n e^{s_t y_i} * e^{i lam_n (x_i - x_j)} * e^{-s_s y_j} q_j,
+// so sweeping the block's points in increasing x while carrying
+//   V_n <- e^{i lam_n (x - x_prev)} V_n  (+ e^{-s_s y_j} q_j at a source)
+// gives sum_{j: x_j <= x_i} at every target; a sweep in decreasing x gives the
+// sources with x_j > x_i (|x_i - x_j| enters by evenness).  Every factor is
+// bounded (Re s >= 0, Im lam >= 0 on the rays, |Im lam| <= h on the bump), and
+// each pair's product equals its term in the pairwise sum.  Lanes are nodes;
+// the node sum at each target is a wave reduction in fixed order.
+// One block per (row-0 target leaf, rhs chunk of 8, node part); results go to
+// unear[part][rhs][target] and the leaf evaluation adds the parts in order.
+// ---------------------------------------------------------------------------
+constexpr int SW_NMAX = 2048;  // points per block held in LDS
+constexpr int SW_TCH = 64;     // targets per sweep chunk
+
+__device__ inline double wave_sum_d(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
+                                                   const int32_t *__restrict__ idx, const double *__restrict__ xs,
+                                                   const double *__restrict__ ys, const cx<T> *__restrict__ q,
+                                                   int64_t ns, int64_t nt, int nrhs, int ncol, int64_t key_t0,
+                                                   const Node *__restrict__ nodes, int nnodes, int nmid, int npan,
+                                                   double t0, int nparts, cx<double> *__restrict__ unear)
+{
+    constexpr int RMAX = 8;
+    __shared__ double sx[SW_NMAX], sy[SW_NMAX];
+    __shared__ int sord[SW_NMAX];
+    __shared__ double accr[SW_TCH][RMAX], acci[SW_TCH][RMAX];
+    const int cl = blockIdx.x, lane = threadIdx.x;
+    const int r0 = blockIdx.y * RMAX, nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
+    const int part = blockIdx.z;
+    const int ts = start[key_t0 + cl], te = end[key_t0 + cl];
+    if (te <= ts) return;
+    // the three adjacent row-0 source leaves are consecutive keys, so their
+    // sorted points form one contiguous range
+    int js = 0, je = 0;
+    bool any = false;
+    for (int dc = -1; dc <= 1; ++dc) {
+        int cs = cl + dc;
+        if (cs < 0 || cs >= ncol) continue;
+        int a = start[cs], b = end[cs];
+        if (b <= a) continue;
+        if (!any) js = a;
+        je = b;
+        any = true;
+    }
+    const int nS = any ? je - js : 0;
+    cx<double> *un = unear + (int64_t)part * nrhs * nt;
+    if (nS + SW_TCH > SW_NMAX) {
+        // oversized leaves: pairwise sum, lanes over targets (part 0 only)
+        for (int c0 = ts; c0 < te; c0 += 64) {
+            int i = c0 + lane;
+            bool act = i < te;
+            int ii = act ? i : ts;
+            double x1 = xs[ii], y1 = ys[ii];
+            cx<double> res[RMAX];
+            for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
+            if (part == 0)
+                for (int j = js; j < je; ++j) {
+                    cx<double> G = pair_kernel(nodes, nmid, npan, t0, y1, ys[j], fabs(x1 - xs[j]), act);
+                    int64_t o = idx[j];
+                    for (int r = 0; r < nr; ++r) {
+                        cx<T> qq = q[(int64_t)(r0 + r) * ns + o];
+                        cfma(res[r], G, cx<double>{(double)qq.re, (double)qq.im});
+                    }
+                }
+            if (act)
+                for (int r = 0; r < nr; ++r) un[(int64_t)(r0 + r) * nt + (idx[i] - ns)] = res[r];
+        }
+        return;
+    }
+    // nodes of this part
+    const int nper = (nnodes + nparts - 1) / nparts;
+    const int n0 = part * nper, n1 = n0 + nper < nnodes ? n0 + nper : nnodes;
+    // sources into LDS once
+    for (int k = lane; k < nS; k += 64) {
+        sx[k] = xs[js + k];
+        sy[k] = ys[js + k];
+    }
+    for (int tc = ts; tc < te; tc += SW_TCH) {
+        const int nT = te - tc < SW_TCH ? te - tc : SW_TCH;
+        const int n = nS + nT;
+        for (int k = lane; k < nT; k += 64) {
+            sx[nS + k] = xs[tc + k];
+            sy[nS + k] = ys[tc + k];
+        }
+        for (int k = lane; k < nT * RMAX; k += 64) {
+            accr[k / RMAX][k % RMAX] = 0.0;
+            acci[k / RMAX][k % RMAX] = 0.0;
+        }
+        __syncthreads();
+        // order by (x, sources before targets, index): rank by counting
+        for (int a = lane; a < n; a += 64) {
+            double xa = sx[a];
+            int ta = a >= nS;
+            int rank = 0;
+            for (int b = 0; b < n; ++b) {
+                double xb = sx[b];
+                int tb = b >= nS;
+                bool less = xb < xa || (xb == xa && (tb < ta || (tb == ta && b < a)));
+                rank += less ? 1 : 0;
+            }
+            sord[rank] = a;
+        }
+        __syncthreads();
+        for (int nb = n0; nb < n1; nb += 64) {
+            const int nn = nb + lane;
+            const bool act = nn < n1;
+            Node nd = nodes[act ? nn : n0];
+            if (!act) nd.dr = nd.di = 0.0;  // contributes nothing
+            for (int dir = 0; dir < 2; ++dir) {
+                cx<double> V[RMAX];
+                for (int r = 0; r < RMAX; ++r) V[r] = {0.0, 0.0};
+                double xprev = sx[sord[dir == 0 ? 0 : n - 1]];
+                for (int step = 0; step < n; ++step) {
+                    const int it = sord[dir == 0 ? step : n - 1 - step];
+                    const double x = sx[it], y = sy[it];
+                    const double dx = dir == 0 ? x - xprev : xprev - x;
+                    xprev = x;
+                    // V <- e^{i lam dx} V
+                    double m = exp(-nd.li * dx), sn, cs;
+                    sincos(nd.lr * dx, &sn, &cs);
+                    cx<double> f = {m * cs, m * sn};
+                    for (int r = 0; r < RMAX; ++r)
+                        if (r < nr) V[r] = V[r] * f;
+                    if (it < nS) {
+                        // source: V += e^{-s_s y} q
+                        cx<double> e = cexp_d(cx<double>{-nd.ssr * y, -nd.ssi * y});
+                        int64_t o = idx[js + it];
+                        for (int r = 0; r < RMAX; ++r)
+                            if (r < nr) {
+                                cx<T> qq = q[(int64_t)(r0 + r) * ns + o];
+                                cfma(V[r], e, cx<double>{(double)qq.re, (double)qq.im});
+                            }
+                    } else {
+                        // target: add D e^{s_t y} V summed over the wave's nodes
+                        cx<double> e = cexp_d(cx<double>{nd.str * y, nd.sti * y}) * cx<double>{nd.dr, nd.di};
+                        const int tl = it - nS;
+                        for (int r = 0; r < RMAX; ++r)
+                            if (r < nr) {
+                                cx<double> c = e * V[r];
+                                double cr = wave_sum_d(c.re), ci = wave_sum_d(c.im);
+                                if (lane == 0) {
+                                    accr[tl][r] += cr;
+                                    acci[tl][r] += ci;
+                                }
+                            }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int k = lane; k < nT * nr; k += 64) {
+            int tl = k / nr, r = k % nr;
+            int64_t o = idx[tc + tl] - ns;
+            un[(int64_t)(r0 + r) * nt + o] = cx<double>{accr[tl][r], acci[tl][r]};
+        }
+        __syncthreads();
     }
 }
 
@@ -605,7 +785,7 @@ template <typename T, int PMAX>
 void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
                   const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med, const cx<T> *Lc,
                   const cx<T> *part, const int *cls_of_host, int nslots, const Node *nodes, int nmid, int npan,
-                  double t0, int do_far, int do_near, void *u, hipStream_t st)
+                  double t0, int do_far, int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
 {
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_t * lv.ncol;
@@ -618,7 +798,7 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     hipLaunchKernelGGL((k_l2p_near<T, PMAX>), dim3(nbox, (nrhs + 7) / 8), dim3(64), sh, st, start, end, idx, xs, ys,
                        reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo,
                        lv.w, k2, invR, Lc + lv.off_t, 1, part, row_slots(cls_of_host, nslots), nodes,
-                       nmid, npan, t0, do_far, do_near, key_t0,
+                       nmid, npan, t0, do_far, do_near, key_t0, unear, nparts,
                        reinterpret_cast<cx<T> *>(u));
 }
 
@@ -715,12 +895,25 @@ template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
                      Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots, const Node *nodes,
-                     int nmid, int npan, double t0, int do_far, int do_near, void *u, hipStream_t st)
+                     int nmid, int npan, double t0, int do_far, int do_near, cx<double> *unear, void *u,
+                     hipStream_t st)
 {
     int P = g.lev[g.L].P;  // cls_of: host copy of the leaf level's class codes
+    const Level &lv = g.lev[g.L];
+    int nparts = 0;
+    if (do_near && unear && lv.rows_t > 0 && lv.rows_s > 0) {
+        // near field by sweeps: split the nodes over parts when there are few leaves
+        nparts = lv.ncol >= 1024 ? 1 : (lv.ncol >= 256 ? 2 : 4);
+        int nnodes = nmid + 2 * NGL * npan;
+        hipLaunchKernelGGL((k_near_sweep<T>), dim3(lv.ncol, (nrhs + 7) / 8, nparts), dim3(64), 0, st, start, end, idx,
+                           xs, ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol,
+                           (int64_t)lv.rows_s * lv.ncol, nodes, nnodes, nmid, npan, t0, nparts, unear);
+    } else {
+        unear = nullptr;
+    }
 #define LMFMM_L2P(PM)                                                                                        \
     l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part, cls_of, nslots, nodes, nmid, \
-                        npan, t0, do_far, do_near, u, st)
+                        npan, t0, do_far, do_near, unear, nparts, u, st)
     if (P <= 16)
         LMFMM_L2P(16);
     else if (P <= 32)
@@ -778,7 +971,7 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
                                      const cx<T> *, const cx<T> *, const int *, int, const Node *, int, int, double, \
-                                     int, int, void *, hipStream_t);                                                \
+                                     int, int, cx<double> *, void *, hipStream_t);                                  \
     template void launch_l2p_grad<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, const void *, int64_t, int64_t, int,             \
                                      const Geometry &, Medium, const cx<T> *, const cx<T> *, const int *, int,      \

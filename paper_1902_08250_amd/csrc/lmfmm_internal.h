@@ -270,7 +270,8 @@ template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
                      Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots, const Node *nodes,
-                     int nmid, int npan, double t0, int do_far, int do_near, void *u, hipStream_t st);
+                     int nmid, int npan, double t0, int do_far, int do_near, cx<double> *unear, void *u,
+                     hipStream_t st);
 template <typename T>
 void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,

@@ -232,6 +232,7 @@ struct lmfmm_plan_s {
     double box[6] = {0, 0, 0, 0, 0, 0};
     double dom[4] = {0, 0, 0, 0};  // xmin, xmax, ys_max, yt_min
     bool do_near = true, do_far = true;
+    bool near_sweep = true;  // near field by x-ordered sweeps (else pairwise)
 
     DevBuf ws;
     double *h_bbox = nullptr;  // pinned
@@ -734,6 +735,11 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         p->fixed_order = v == "1";
         return LMFMM_OK;
     }
+    if (k == "near_sweep") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "near_sweep must be 0 or 1");
+        p->near_sweep = v == "1";
+        return LMFMM_OK;
+    }
     if (k == "near" || k == "far") {
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "near/far must be 0 or 1");
         (k == "near" ? p->do_near : p->do_far) = v == "1";
@@ -890,6 +896,10 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         part_off[l + 1] = part_off[l] + (int64_t)vt.lt[l].nslots * g.lev[l].ncol * nrhs * g.lev[l].nc;
     int64_t npart = far ? part_off[L + 1] : 0;
     need += (size_t)npart * sizeof(cx<T>);
+    // near-field sweep results: up to 4 node parts x nrhs x targets (FP64)
+    const bool sweep = p->do_near && p->near_sweep && !gw;
+    int64_t nun = sweep ? (int64_t)4 * nrhs * nt : 0;
+    need += (size_t)nun * sizeof(cx<double>) + 256;
     if ((rc = p->ws.ensure(need))) return rc;
     Carve cv{(char *)p->ws.p};
     SortBufs sb;
@@ -906,6 +916,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     int32_t *err = cv.take<int32_t>(1);
     p->d_err = err;
     cx<T> *part = cv.take<cx<T>>(npart > 0 ? npart : 1);
+    cx<double> *unear = sweep ? cv.take<cx<double>>(nun) : nullptr;
 
     collect_timing(p);
     const bool tm = p->timing;
@@ -966,7 +977,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     if (!gw)
         launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
                            (const Node *)vt.near_nodes.p, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0,
-                           p->do_near ? 1 : 0, u, st);
+                           p->do_near ? 1 : 0, unear, u, st);
     else
         launch_l2p_grad<T>(start, end, idx, xs, ys, q, gw, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
                            (const Node *)vt.near_nodes.p, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0,

@@ -56,3 +56,22 @@ def test_near_interface_full_size(orc):
     err = rel(u[:, sel], ref)
     say("rel-l2", err, pl.stats()["order"])
     assert err < 1e-10
+
+
+@pytest.mark.parametrize("levels", [6, 9])
+def test_sweep_matches_pairwise(levels):
+    """The x-ordered sweep and the pairwise near-field sum use the same
+    quadrature nodes; they agree to rounding."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("sweep vs pairwise near field, levels", levels)
+    spec = workloads.make(2, n_src=20000, n_tgt=20000)
+    rng = np.random.default_rng(8)
+    src, tgt, q, _ = workloads.draw_instance(rng, 20000, 20000, (0, 1), (1e-4, 1e-3), (-1e-3, -1e-4), 3)
+    pl = Plan(spec["k"], spec["d"], order=20, tol=1e-10, levels=levels)
+    pl.set_option("far", "0")
+    a = pl.apply(dev(src), dev(q), dev(tgt)).cpu().numpy()
+    pl.set_option("near_sweep", "0")
+    b = pl.apply(dev(src), dev(q), dev(tgt)).cpu().numpy()
+    err = rel(a, b)
+    say("sweep vs pairwise rel-l2", err)
+    assert err < 1e-12
