@@ -8,14 +8,20 @@ one complete apply (bounding box, tree build, upward pass, M2L, downward pass,
 local evaluation and near field) with all inputs resident in HBM.
 
 Prints one JSON line with the throughput in source-target interactions/s,
-the same workload through the plain FP64 FMM, the roofline of the dominant
-kernel (HIP-event durations of its launches in the timed region) and the FP64
-oracle timed on this host's cores on a bounded sample of targets.
+the same workload through the plain FP64 FMM, the batched workload (16
+instances with their own media, 4 right-hand sides each) as one graph launch
+against the FP64 FMM applied instance by instance, the roofline of the
+dominant kernel (HIP-event durations of its launches in the timed region,
+algorithmic work from the plan's counts) and the FP64 oracle timed on this
+host's cores on a bounded sample of targets.
+
+--copy-probe MIB runs only a plain device copy of that size (the calibration
+kernel for the HBM byte counters) and exits.
 """
 import argparse
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -25,8 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_1902_08250_amd import workloads  # noqa: E402
+from paper_1902_08250_amd.prof_summary import source_hash  # noqa: E402
 
+# MI355X published peaks
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
+# kernel of each timing class on this workload (FP32 expansions, leaf order 16)
+KERNEL_NAMES = {"p2m": "k_p2m<float, 16>", "m2m": "k_up<float>", "m2l_l2l": "k_down<float>",
+                "fold_top": "k_fold_top<float>", "near_sweep": "k_near_sweep<float>",
+                "l2p_near": "k_l2p_near<float, 16>"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mixed_uniform_1e5.md")
 
 
 def parse():
@@ -35,20 +48,36 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 FMM leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     return ap.parse_args()
 
 
-def p2m_flops_per_point(P, kr):
-    """Arithmetic of the scaled-basis evaluation and accumulation of one point
-    (per right-hand side for the accumulation):
-      backward ratio recurrence, N = P + 16 + floor(1.2 |k r|) steps of
-      z^2 t (6) + subtract (1) + complex reciprocal (6) + normalisation
-      update every other step (6 per step)  -> 19 flops per step;
-      forward products: 2 q t (2) + f*up (6) + v*... (6), twice -> 26 per order;
-      accumulation: 2P+1 complex multiply-adds (8 flops each)."""
-    N = P + 16 + int(1.2 * kr)
-    return 19 * N + 26 * P + 8 * (2 * P + 1)
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(r"^\|\s*%s\s*\|[^\n]*?\|\s*bytes_per_launch=([0-9.eE+]+)" % re.escape(kernel), text, re.M)
+    return float(m.group(1)) if m else None
+
+
+def copy_probe(torch, mib):
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe": {"kernel": "elementwise mul by 1 (float32)", "read_bytes": 4 * n,
+                                     "write_bytes": 4 * n, "launches": 3}}), flush=True)
 
 
 def run_gpu(torch, Plan, w, precision, steps, warmup, timing=False):
@@ -71,7 +100,66 @@ def run_gpu(torch, Plan, w, precision, steps, warmup, timing=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = pl.stats()
-    return (t1 - t0) / steps, u.cpu().numpy(), st, pl
+    return (t1 - t0) / steps, u.cpu().numpy(), st
+
+
+def roofline(st):
+    """Dominant kernel of the timed applies (tree-build group excluded: it is
+    many small kernels) against the FP32 vector peak."""
+    nap = max(1, st["timed_applies"])
+    cand = {k: v for k, v in st["kernel_ms"].items() if k in KERNEL_NAMES and st["kernel_launches"][k] > 0}
+    dom = max(cand, key=cand.get)
+    ms_apply = cand[dom] / nap
+    launches = st["kernel_launches"][dom] / nap
+    avg_s = ms_apply / launches * 1e-3
+    flops_launch = st["kernel_flops"][dom] / launches
+    achieved = flops_launch / avg_s
+    kname = KERNEL_NAMES[dom]
+    traffic = recorded_traffic(kname)
+    return {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"], "traffic": traffic,
+            "flops_per_launch": flops_launch, "launches_per_apply": launches, "avg_launch_us": avg_s * 1e6,
+            "hbm_GBps_if_traffic": (traffic / avg_s / 1e9) if traffic else None}
+
+
+def batched_leg(torch, steps, warmup):
+    from paper_1902_08250_amd.lmfmm import Batch, Plan
+    inst = workloads.make_batched()
+    inter = float(sum(d["src"].shape[1] * d["tgt"].shape[1] * d["q"].shape[0] for d in inst))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    items = [(dev(d["src"]), dev(d["q"]), dev(d["tgt"])) for d in inst]
+    t0 = time.perf_counter()
+    b = Batch([(d["k"], d["d"]) for d in inst], order_set=(12, 16, 20), tol=1e-6)
+    outs = b.apply(items)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    for _ in range(warmup):
+        b.apply(items, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.apply(items, outs=outs)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    # plain FP64 FMM, instance after instance
+    items64 = [(s, dev(d["q"].astype(np.complex128)), t) for (s, _, t), d in zip(items, inst)]
+    plans = [Plan(d["k"], d["d"], order=16, tol=1e-10) for d in inst]
+    outs64 = [p.apply(*it) for p, it in zip(plans, items64)]
+    torch.cuda.synchronize()
+    n64 = max(2, steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(n64):
+        for p, it, o in zip(plans, items64, outs64):
+            p.apply(*it, out=o)
+    torch.cuda.synchronize()
+    t64 = (time.perf_counter() - t0) / n64
+    errs = [float(np.linalg.norm(o.cpu().numpy().astype(np.complex128) - r.cpu().numpy()) /
+                  np.linalg.norm(r.cpu().numpy())) for o, r in zip(outs, outs64)]
+    return {"workload": "batched: 16 instances, N log-uniform in [1e3, 2e5], own media, 4 RHS each, c64",
+            "value": inter / tb, "unit": "interactions/s", "ms_per_step": tb * 1e3,
+            "prepare_s": t_prep, "choices": b.choices(),
+            "fp64_fmm_sequential": {"value": inter / t64, "ms_per_step": t64 * 1e3},
+            "speedup_vs_fp64_sequential": t64 / tb, "rel_l2_max_vs_fp64_fmm": max(errs)}
 
 
 def main():
@@ -81,6 +169,9 @@ def main():
               "(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
+        return
     from paper_1902_08250_amd.lmfmm import Plan
 
     w = workloads.make(1)
@@ -88,35 +179,9 @@ def main():
     inter = float(n_src) * n_tgt * nrhs
 
     print(f"[bench] workload {w['name']}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-    t_mixed, u_mixed, st, pl = run_gpu(torch, Plan, w, "c64", args.steps, args.warmup, timing=True)
+    t_mixed, u_mixed, st = run_gpu(torch, Plan, w, "c64", args.steps, args.warmup, timing=True)
     print(f"[bench] mixed: {t_mixed * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-    t64, u64, st64, _ = run_gpu(torch, Plan, w, "c128", max(3, args.steps // 4), 1)
-    print(f"[bench] fp64: {t64 * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-    rel_mixed_fp64 = float(np.linalg.norm(u_mixed - u64) / np.linalg.norm(u64))
-
-    # roofline of the dominant stage kernel (single-launch stages measured by events)
-    names = ["tree", "p2m", "m2m", "m2l_l2l", "l2p_near"]
-    stage_ms = st["stage_ms"]
     nap = max(1, st["timed_applies"])
-    per_apply = [m / nap for m in stage_ms]
-    dom = int(np.argmax(per_apply))
-    L = st["levels"]
-    P_leaf = st["order"][L]
-    wL = st["root_width"] / 2 ** L
-    kr = abs(w["k"][1]) * wL / math.sqrt(2)
-    launches = max(1, st["stage_launches"][dom] // nap)
-    avg_launch_s = per_apply[dom] / launches * 1e-3
-    if names[dom] in ("p2m", "l2p_near"):
-        flops = p2m_flops_per_point(P_leaf, kr) * (n_src if names[dom] == "p2m" else n_tgt)
-        achieved = flops / avg_launch_s
-        roof = {"kernel": "k_p2m" if names[dom] == "p2m" else "k_l2p_near", "bound": "alu",
-                "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp32"], "traffic": None,
-                "avg_launch_us": avg_launch_s * 1e6}
-    else:
-        roof = {"kernel": names[dom], "bound": "alu", "achieved": None, "peak": PEAK["fp32"] / 1e12,
-                "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_launch_us": avg_launch_s * 1e6}
-
     out = {
         "metric": "source-target interactions/s at stated rel-l2 err; mixed+batched vs FP64 FMM",
         "value": inter / t_mixed,
@@ -133,12 +198,20 @@ def main():
         "config": {"workload": w["name"], "n_src": n_src, "n_tgt": n_tgt, "nrhs": nrhs, "order": w["order"],
                    "levels": w["levels"], "tol": w["tol"], "orders_by_level": st["order"],
                    "medium": "k=(10,20,15)+0.01i, d=1"},
-        "fp64_fmm": {"value": inter / t64, "ms_per_step": t64 * 1e3},
-        "mixed_over_fp64": t64 / t_mixed,
-        "rel_l2_mixed_vs_fp64_fmm": rel_mixed_fp64,
-        "stage_ms_per_apply": dict(zip(names, per_apply)),
-        "roofline": roof,
+        "kernel_ms_per_apply": {k: v / nap for k, v in st["kernel_ms"].items() if v > 0},
+        "kernel_launches_per_apply": {k: v / nap for k, v in st["kernel_launches"].items() if v > 0},
+        "m2l_pairs": st["m2l_pairs"],
+        "roofline": roofline(st),
     }
+    if not args.no_fp64:
+        t64, u64, _ = run_gpu(torch, Plan, w, "c128", max(3, args.steps // 4), 1)
+        print(f"[bench] fp64: {t64 * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+        out["fp64_fmm"] = {"value": inter / t64, "ms_per_step": t64 * 1e3}
+        out["mixed_over_fp64"] = t64 / t_mixed
+        out["rel_l2_mixed_vs_fp64_fmm"] = float(np.linalg.norm(u_mixed - u64) / np.linalg.norm(u64))
+    if not args.no_batched:
+        out["batched"] = batched_leg(torch, args.steps, args.warmup)
+        print(f"[bench] batched: {out['batched']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         import oracle
@@ -159,7 +232,8 @@ def main():
         out["cpu_baseline"] = {"value": rate, "unit": "interactions/s", "cores": cores, "kind": "oracle",
                                "sample": f"{n_s} seeded targets x {n_src} sources ({t_cpu:.1f} s)"}
         out["rel_l2_mixed_vs_oracle_sample"] = float(np.linalg.norm(u_mixed[:, sel] - ref) / np.linalg.norm(ref))
-        out["rel_l2_fp64_vs_oracle_sample"] = float(np.linalg.norm(u64[:, sel] - ref) / np.linalg.norm(ref))
+        if not args.no_fp64:
+            out["rel_l2_fp64_vs_oracle_sample"] = float(np.linalg.norm(u64[:, sel] - ref) / np.linalg.norm(ref))
     print(json.dumps(out), flush=True)
 
 

@@ -88,9 +88,10 @@ int lmfmm_destroy(lmfmm_plan plan);
  *                 table; "0": the pairwise sum (same quadrature)
  *   "near"        "1" (default) / "0": include / skip the near field
  *   "far"         "1" (default) / "0": include / skip the far field
- *   "timing"      "1": record HIP events around every stage of each apply
- *                 on the apply's stream and accumulate their durations in
- *                 lmfmm_stats.stage_ms; "0" stops; "reset" zeroes the sums
+ *   "timing"      "1": record a HIP event on the apply's stream before every
+ *                 kernel (or group of tree-build kernels) of each apply and
+ *                 accumulate the durations per kernel in
+ *                 lmfmm_stats.kernel_ms; "0" stops; "reset" zeroes the sums
  * Returns LMFMM_EINVAL for an unknown key or malformed value. */
 int lmfmm_set_option(lmfmm_plan plan, const char *key, const char *value);
 
@@ -133,8 +134,7 @@ typedef struct {
     int order[32];         /* expansion order used at levels 0..L            */
     double root_x_lo;      /* root square [x_lo, x_lo+width] x [-w/2, w/2]    */
     double root_width;
-    int64_t near_pairs;    /* source-target pairs evaluated by quadrature    */
-    int64_t m2l_pairs;     /* box pairs translated by M2L                    */
+    int64_t m2l_pairs;     /* box pairs translated by M2L (all levels)       */
     int64_t leaves_src;    /* leaf boxes covering the sources' bounding box   */
     int64_t leaves_tgt;
     int near_nodes_mid;    /* near-field quadrature nodes on the finite piece */
@@ -142,12 +142,25 @@ typedef struct {
     int m2l_classes;       /* translation classes with a table               */
     int64_t m2l_nodes;     /* quadrature nodes summed over all classes       */
     double table_seconds;  /* host wall time of the last M2L table rebuild   */
-    /* with the "timing" option: summed event durations (ms) and launch counts
-     * per stage: 0 tree build, 1 P2M, 2 M2M, 3 M2L+L2L, 4 L2P+near field    */
-    double stage_ms[8];
-    int64_t stage_launches[8];
+    /* Per kernel, indexed by LMFMM_K_*:
+     *   kernel_flops: algorithmic real floating-point operations of the last
+     *   apply (complex multiply-add = 8; translation and accumulation
+     *   contractions counted over the box pairs and points the method
+     *   defines, basis evaluations at 60 P per point);
+     * with the "timing" option, summed over the timed applies:
+     *   kernel_ms: event-measured duration, kernel_launches: launches.     */
+    double kernel_flops[8];
+    double kernel_ms[8];
+    int64_t kernel_launches[8];
     int64_t timed_applies;
 } lmfmm_stats;
+
+/* Kernel indices of lmfmm_stats.kernel_*: bounding box and tree build (all
+ * their kernels together), P2M, M2M, M2L + L2L, fold of the coarsest
+ * level's M2L partials, near-field sweep, L2P + near field (or its gradient
+ * form), the rest. */
+enum { LMFMM_K_TREE = 0, LMFMM_K_P2M = 1, LMFMM_K_M2M = 2, LMFMM_K_DOWN = 3, LMFMM_K_FOLD = 4,
+       LMFMM_K_SWEEP = 5, LMFMM_K_L2P = 6, LMFMM_K_OTHER = 7 };
 
 int lmfmm_get_stats(lmfmm_plan plan, lmfmm_stats *stats);
 

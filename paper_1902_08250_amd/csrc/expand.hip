@@ -858,7 +858,7 @@ void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int nrhs,
 template <typename T>
 void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls_of,
                  const int *cls_of_p_host, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
-                 const cx<T> *l2l_tab, const int *top_row_off, hipStream_t st)
+                 const cx<T> *l2l_tab, bool top, hipStream_t st)
 {
     const Level &lv = g.lev[l], &pv = g.lev[l - 1];
     DownArgs a;
@@ -875,7 +875,7 @@ void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T>
     a.rsl_p = row_slots(cls_of_p_host, nslots_p);
     a.base_p = 1;
     a.has_l2l = l2l_tab != nullptr;
-    a.top = top_row_off != nullptr;
+    a.top = top ? 1 : 0;
     int nb_l2l = a.has_l2l ? (pv.rows_t * pv.ncol + GB - 1) / GB : 0;
     int nb_m2l = (lv.ncol + GB - 1) / GB;
     int gx = nb_l2l > nb_m2l ? nb_l2l : nb_m2l;
@@ -884,33 +884,44 @@ void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T>
     dim3 grid(gx, (lv.nc + GP - 1) / GP, gz);
     hipLaunchKernelGGL((k_down<T>), grid, dim3(256), 0, st, a, nrhs, Lc + pv.off_t, part_p, l2l_tab,
                        Lc + lv.off_t, M + lv.off_s, atab, cls_of, part);
-    if (top_row_off) {
-        int64_t nout = (int64_t)lv.rows_t * lv.ncol * nrhs * lv.nc;
-        hipLaunchKernelGGL((k_fold_top<T>), dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, part, top_row_off,
-                           lv.ncol, nrhs, lv.nc, nout, Lc + lv.off_t);
-    }
+}
+
+template <typename T>
+void launch_fold_top(const Geometry &g, int l, const cx<T> *part, const int *row_off, cx<T> *Lc, int nrhs,
+                     hipStream_t st)
+{
+    const Level &lv = g.lev[l];
+    int64_t nout = (int64_t)lv.rows_t * lv.ncol * nrhs * lv.nc;
+    if (nout == 0) return;
+    hipLaunchKernelGGL((k_fold_top<T>), dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, part, row_off, lv.ncol,
+                       nrhs, lv.nc, nout, Lc + lv.off_t);
+}
+
+template <typename T>
+int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
+                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
+                      const Node *nodes, int nmid, int npan, double t0, cx<double> *unear, hipStream_t st)
+{
+    const Level &lv = g.lev[g.L];
+    if (lv.rows_t == 0 || lv.rows_s == 0 || lv.ncol == 0) return 0;
+    // split the nodes over parts when there are few leaves
+    int nparts = lv.ncol >= 1024 ? 1 : (lv.ncol >= 256 ? 2 : 4);
+    int nnodes = nmid + 2 * NGL * npan;
+    hipLaunchKernelGGL((k_near_sweep<T>), dim3(lv.ncol, (nrhs + 7) / 8, nparts), dim3(64), 0, st, start, end, idx, xs,
+                       ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol, (int64_t)lv.rows_s * lv.ncol,
+                       nodes, nnodes, nmid, npan, t0, nparts, unear);
+    return nparts;
 }
 
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
                      Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots, const Node *nodes,
-                     int nmid, int npan, double t0, int do_far, int do_near, cx<double> *unear, void *u,
-                     hipStream_t st)
+                     int nmid, int npan, double t0, int do_far, int do_near, const cx<double> *unear, int nparts,
+                     void *u, hipStream_t st)
 {
     int P = g.lev[g.L].P;  // cls_of: host copy of the leaf level's class codes
-    const Level &lv = g.lev[g.L];
-    int nparts = 0;
-    if (do_near && unear && lv.rows_t > 0 && lv.rows_s > 0) {
-        // near field by sweeps: split the nodes over parts when there are few leaves
-        nparts = lv.ncol >= 1024 ? 1 : (lv.ncol >= 256 ? 2 : 4);
-        int nnodes = nmid + 2 * NGL * npan;
-        hipLaunchKernelGGL((k_near_sweep<T>), dim3(lv.ncol, (nrhs + 7) / 8, nparts), dim3(64), 0, st, start, end, idx,
-                           xs, ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol,
-                           (int64_t)lv.rows_s * lv.ncol, nodes, nnodes, nmid, npan, t0, nparts, unear);
-    } else {
-        unear = nullptr;
-    }
+    if (!unear) nparts = 0;
 #define LMFMM_L2P(PM)                                                                                        \
     l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part, cls_of, nslots, nodes, nmid, \
                         npan, t0, do_far, do_near, unear, nparts, u, st)
@@ -966,12 +977,16 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
                                 const void *, int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);        \
     template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int, hipStream_t);                   \
     template void launch_down<T>(const Geometry &, int, int, int, const cx<T> *, const int *, const int *,          \
-                                 const cx<T> *, cx<T> *, cx<T> *, const cx<T> *, int, const cx<T> *, const int *,   \
+                                 const cx<T> *, cx<T> *, cx<T> *, const cx<T> *, int, const cx<T> *, bool,          \
                                  hipStream_t);                                                                      \
+    template void launch_fold_top<T>(const Geometry &, int, const cx<T> *, const int *, cx<T> *, int, hipStream_t); \
+    template int launch_near_sweep<T>(const int32_t *, const int32_t *, const int32_t *, const double *,            \
+                                      const double *, const void *, int64_t, int64_t, int, const Geometry &,        \
+                                      const Node *, int, int, double, cx<double> *, hipStream_t);                   \
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
                                      const cx<T> *, const cx<T> *, const int *, int, const Node *, int, int, double, \
-                                     int, int, cx<double> *, void *, hipStream_t);                                  \
+                                     int, int, const cx<double> *, int, void *, hipStream_t);                       \
     template void launch_l2p_grad<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, const void *, int64_t, int64_t, int,             \
                                      const Geometry &, Medium, const cx<T> *, const cx<T> *, const int *, int,      \

@@ -265,13 +265,21 @@ void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int n
 template <typename T>
 void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls3,
                  const int *cls3_p_host, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
-                 const cx<T> *l2l_tab, const int *top_row_off, hipStream_t st);
+                 const cx<T> *l2l_tab, bool top, hipStream_t st);
+template <typename T>
+void launch_fold_top(const Geometry &g, int l, const cx<T> *part, const int *row_off, cx<T> *Lc, int nrhs,
+                     hipStream_t st);
+// returns the number of node parts written to unear ([part][rhs][target])
+template <typename T>
+int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
+                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
+                      const Node *nodes, int nmid, int npan, double t0, cx<double> *unear, hipStream_t st);
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
                      Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots, const Node *nodes,
-                     int nmid, int npan, double t0, int do_far, int do_near, cx<double> *unear, void *u,
-                     hipStream_t st);
+                     int nmid, int npan, double t0, int do_far, int do_near, const cx<double> *unear, int nparts,
+                     void *u, hipStream_t st);
 template <typename T>
 void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,

@@ -252,25 +252,46 @@ struct lmfmm_plan_s {
     lmfmm_stats stats;
     int32_t *d_err = nullptr;  // device error flag of the last apply (in the workspace)
 
-    // stage timing
+    // per-kernel timing: an event before each timed kernel (or kernel group)
+    // and one after the last; interval j is attributed to ev_tag[j]
+    static constexpr int NEV = 96;
     bool timing = false;
     bool ev_pending = false;
-    hipEvent_t ev[6] = {};
-    int ev_launch[5] = {0, 0, 0, 0, 0};
+    hipEvent_t ev[NEV] = {};
+    int ev_tag[NEV] = {0};
+    int ev_nl[NEV] = {0};
+    int ev_n = 0;
+
+    // cached M2L pair counts per level for the last geometry
+    std::vector<int64_t> pair_key;
+    int64_t pair_count[MAXLEV + 1] = {0};
 };
 
 // Fold the events of the previous timed apply into the statistics.
 static void collect_timing(lmfmm_plan_s *p)
 {
-    if (!p->ev_pending) return;
-    (void)hipEventSynchronize(p->ev[5]);
-    for (int s = 0; s < 5; ++s) {
+    if (!p->ev_pending) {
+        p->ev_n = 0;  // an apply that failed part-way leaves no timing
+        return;
+    }
+    const int n = p->ev_n;
+    (void)hipEventSynchronize(p->ev[n - 1]);
+    for (int j = 0; j + 1 < n; ++j) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, p->ev[s], p->ev[s + 1]) == hipSuccess) p->stats.stage_ms[s] += ms;
-        p->stats.stage_launches[s] += p->ev_launch[s];
+        int t = p->ev_tag[j];
+        if (hipEventElapsedTime(&ms, p->ev[j], p->ev[j + 1]) == hipSuccess) p->stats.kernel_ms[t] += ms;
+        p->stats.kernel_launches[t] += p->ev_nl[j];
     }
     p->stats.timed_applies += 1;
     p->ev_pending = false;
+    p->ev_n = 0;
+}
+
+static int nbits(int64_t n)
+{
+    int b = 1;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
 }
 
 static double kmax_re(const Medium &m) { return std::max(m.k1.re, std::max(m.k2.re, m.k3.re)); }
@@ -710,7 +731,7 @@ int lmfmm_destroy(lmfmm_plan p)
     p->vt[0].release();
     p->vt[1].release();
     if (p->h_bbox) (void)hipHostFree(p->h_bbox);
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < lmfmm_plan_s::NEV; ++i)
         if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
     delete p;
     return LMFMM_OK;
@@ -755,15 +776,15 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         if (v == "reset") {
             collect_timing(p);
             for (int i = 0; i < 8; ++i) {
-                p->stats.stage_ms[i] = 0;
-                p->stats.stage_launches[i] = 0;
+                p->stats.kernel_ms[i] = 0;
+                p->stats.kernel_launches[i] = 0;
             }
             p->stats.timed_applies = 0;
             return LMFMM_OK;
         }
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "timing must be 0, 1 or reset");
         if (v == "1" && !p->ev[0])
-            for (int i = 0; i < 6; ++i)
+            for (int i = 0; i < lmfmm_plan_s::NEV; ++i)
                 if (hipEventCreate(&p->ev[i]) != hipSuccess) return fail(LMFMM_EHIP, "hipEventCreate failed");
         collect_timing(p);
         p->timing = v == "1";
@@ -851,6 +872,73 @@ static int get_bbox(lmfmm_plan p, const Medium &med, int64_t ns, const double *s
 // 1: transposed in mirrored coordinates).  With gw == nullptr the field of the
 // densities q is written to u; otherwise the target-side coordinate gradient of
 // Re sum gw * field is written to gout ([2][nt], y component times ysign).
+// Box pairs that M2L translates at level l: for each class slot (target row,
+// source row, column offset), the target columns whose source box exists and,
+// below the coarsest expansion level, whose parents are adjacent (the
+// interaction list).  Cached for the last geometry.
+static void m2l_pair_counts(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g)
+{
+    std::vector<int64_t> key = {g.L, g.ltop};
+    for (int l = g.ltop; l <= g.L; ++l) {
+        const Level &lv = g.lev[l];
+        key.insert(key.end(), {lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, vt.lt[l].nslots});
+    }
+    if (key == p->pair_key) return;
+    p->pair_key = key;
+    for (int l = 0; l <= MAXLEV; ++l) p->pair_count[l] = 0;
+    for (int l = g.ltop; l <= g.L; ++l) {
+        const Level &lv = g.lev[l];
+        const std::vector<int> &c3 = vt.lt[l].clsof_host;
+        int64_t cnt = 0;
+        for (int sl = 0; sl < vt.lt[l].nslots; ++sl) {
+            int rt = c3[3 * sl], rs = c3[3 * sl + 1], dc = c3[3 * sl + 2];
+            if (rt >= lv.rows_t || rs >= lv.rows_s) continue;
+            for (int b = 0; b < lv.ncol; ++b) {
+                int col = lv.col_lo + b, cs = col + dc, csl = cs - lv.col_lo;
+                if (csl < 0 || csl >= lv.ncol) continue;
+                int dp = (cs >> 1) - (col >> 1);
+                if (l == g.ltop || (dp >= -1 && dp <= 1)) ++cnt;
+            }
+        }
+        p->pair_count[l] = cnt;
+    }
+}
+
+// Algorithmic floating-point work of one apply per kernel (complex
+// multiply-add = 8 real operations; Bessel/exponential basis of order P at
+// 60 P per point).
+static void count_flops(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g, bool far, int64_t ns, int64_t nt,
+                        int nrhs, bool grad)
+{
+    double *f = p->stats.kernel_flops;
+    for (int i = 0; i < 8; ++i) f[i] = 0;
+    p->stats.m2l_pairs = 0;
+    if (!far) return;
+    m2l_pair_counts(p, vt, g);
+    const int L = g.L, ltop = g.ltop;
+    const double R = nrhs;
+    const Level &lf = g.lev[L];
+    f[LMFMM_K_P2M] = (double)ns * (60.0 * lf.P + 8.0 * lf.nc * R);
+    for (int l = L; l >= ltop + 1; --l) {
+        const Level &c = g.lev[l], &pa = g.lev[l - 1];
+        f[LMFMM_K_M2M] += (double)pa.rows_s * pa.ncol * 4.0 * c.nc * pa.nc * 8.0 * R;
+    }
+    int64_t pairs = 0;
+    for (int l = ltop; l <= L; ++l) {
+        const Level &lv = g.lev[l], &pa = g.lev[l - 1];
+        pairs += p->pair_count[l];
+        double w = (double)p->pair_count[l] * lv.nc * lv.nc;
+        if (l > ltop) w += (double)pa.rows_t * pa.ncol * 4.0 * pa.nc * lv.nc;
+        f[LMFMM_K_DOWN] += 8.0 * R * w;
+    }
+    p->stats.m2l_pairs = pairs;
+    f[LMFMM_K_FOLD] = 2.0 * R * vt.lt[ltop].nslots * g.lev[ltop].ncol * g.lev[ltop].nc;
+    if (grad)
+        f[LMFMM_K_L2P] = (double)nt * (60.0 * (lf.P + 1) + 3.0 * 8.0 * (lf.nc + 2) * R);
+    else
+        f[LMFMM_K_L2P] = (double)nt * (60.0 * lf.P + 8.0 * lf.nc * R);
+}
+
 template <typename T>
 static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, const void *q, int64_t nt,
                       const double *tgt, void *u, int nrhs, hipStream_t st, const void *gw = nullptr,
@@ -869,6 +957,19 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     Medium med = p->med;
     med.adj = adj;
     VarTables &vt = p->vt[adj];
+    collect_timing(p);
+    // event before each timed kernel (group); tag -1 closes the last interval
+    auto tick = [&](int tag, int nl) {
+        if (!p->timing || p->ev_n >= lmfmm_plan_s::NEV) return;
+        if (p->ev_n > 0 && tag == LMFMM_K_TREE && p->ev_tag[p->ev_n - 1] == tag) {
+            p->ev_nl[p->ev_n - 1] += nl;
+            return;
+        }
+        p->ev_tag[p->ev_n] = tag < 0 ? LMFMM_K_OTHER : tag;
+        p->ev_nl[p->ev_n] = nl;
+        (void)hipEventRecord(p->ev[p->ev_n++], st);
+    };
+    tick(LMFMM_K_TREE, p->have_domain || p->have_box ? 0 : 2);
     double bb[8];
     if ((rc = get_bbox(p, med, ns, src, nt, tgt, st, bb))) return rc;
     Geometry &g = p->geo;
@@ -918,45 +1019,27 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     cx<T> *part = cv.take<cx<T>>(npart > 0 ? npart : 1);
     cx<double> *unear = sweep ? cv.take<cx<double>>(nun) : nullptr;
 
-    collect_timing(p);
-    const bool tm = p->timing;
-    auto mark = [&](int i) {
-        if (tm) (void)hipEventRecord(p->ev[i], st);
-    };
-    int nlaunch[5] = {0, 0, 0, 0, 0};
-
     // Step 1: tree
-    mark(0);
+    tick(LMFMM_K_TREE, 5 + 3 * ((nbits(nbox) + 7) / 8));
     launch_fill_i32(err, 1, 0, st);
     launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
                 yt_limit(med), sb.key_a, sb.idx_a, err, st);
-    int bits = 1;
-    while (((int64_t)1 << bits) < nbox) ++bits;
-    int which = launch_radix_sort(sb, n, bits, st);
+    int which = launch_radix_sort(sb, n, nbits(nbox), st);
     uint32_t *key = which ? sb.key_b : sb.key_a;
     int32_t *idx = which ? sb.idx_b : sb.idx_a;
     launch_leaf_ranges(key, idx, n, nbox, start, end, src, ns, tgt, nt, xs, ys, st);
-    nlaunch[0] = 5 + 3 * ((bits + 7) / 8);
-    mark(1);
 
     // Step 2: upward pass
     if (far) {
+        tick(LMFMM_K_P2M, 1);
         launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, st);
-        nlaunch[1] = 1;
-    }
-    mark(2);
-    if (far) {
-        nlaunch[2] = L - ltop;
         for (int l = L; l >= ltop + 1; --l) {
             const LevelTables &tb = vt.lt[l];
             const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
+            tick(LMFMM_K_M2M, 1);
             launch_m2m<T>(g, l, tab, M, nrhs, st);
         }
-    }
-    mark(3);
-    if (far) {
         // Step 3: downward pass
-        nlaunch[3] = L - ltop + 2;
         for (int l = ltop; l <= L; ++l) {
             const LevelTables &tb = vt.lt[l], &tp = vt.lt[l - 1];
             const cx<T> *atab = (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p);
@@ -964,31 +1047,39 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             if (l > ltop) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
             // the parent's M2L partials are pending unless it is the top level (folded there)
             bool pend_p = l - 1 > ltop;
+            tick(LMFMM_K_DOWN, 1);
             launch_down<T>(g, l, tb.nslots, pend_p ? tp.nslots : 0, atab, (const int *)tb.clsof.p,
                            pend_p ? tp.clsof_host.data() : nullptr, M, Lc, part + part_off[l],
-                           part + part_off[l > ltop ? l - 1 : l], nrhs, l2l, l == ltop ? (const int *)tb.rowoff.p : nullptr,
-                           st);
+                           part + part_off[l > ltop ? l - 1 : l], nrhs, l2l, l == ltop, st);
+            if (l == ltop) {
+                tick(LMFMM_K_FOLD, 1);
+                launch_fold_top<T>(g, l, part + part_off[l], (const int *)tb.rowoff.p, Lc, nrhs, st);
+            }
         }
     }
-    mark(4);
     // Step 4: local evaluation and direct interactions
     const int *clsL = (far && L > ltop) ? vt.lt[L].clsof_host.data() : nullptr;
     int nsL = (far && L > ltop) ? vt.lt[L].nslots : 0;
-    if (!gw)
+    const Node *nnodes = (const Node *)vt.near_nodes.p;
+    int nparts = 0;
+    if (!gw) {
+        if (sweep) {
+            tick(LMFMM_K_SWEEP, 1);
+            nparts = launch_near_sweep<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, nnodes, vt.n_nmid, vt.n_npan,
+                                          vt.n_t0, unear, st);
+        }
+        tick(LMFMM_K_L2P, 1);
         launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
-                           (const Node *)vt.near_nodes.p, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0,
-                           p->do_near ? 1 : 0, unear, u, st);
-    else
+                           nnodes, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0, p->do_near ? 1 : 0,
+                           nparts ? unear : nullptr, nparts, u, st);
+    } else {
+        tick(LMFMM_K_L2P, (nrhs + 7) / 8);
         launch_l2p_grad<T>(start, end, idx, xs, ys, q, gw, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
-                           (const Node *)vt.near_nodes.p, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0,
-                           p->do_near ? 1 : 0, ysign, gout, st);
-    nlaunch[4] = 1;
-    mark(5);
-    HIPCHK(hipGetLastError());
-    if (tm) {
-        for (int i = 0; i < 5; ++i) p->ev_launch[i] = nlaunch[i];
-        p->ev_pending = true;
+                           nnodes, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0, p->do_near ? 1 : 0, ysign, gout, st);
     }
+    tick(-1, 0);
+    HIPCHK(hipGetLastError());
+    if (p->ev_n > 0) p->ev_pending = true;
 
     // statistics (host-side counts)
     lmfmm_stats &s = p->stats;
@@ -1009,6 +1100,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     s.m2l_classes = ncls;
     s.m2l_nodes = nn;
     s.table_seconds = vt.table_seconds;
+    count_flops(p, vt, g, far, ns, nt, nrhs, gw != nullptr);
     return LMFMM_OK;
 }
 

@@ -30,11 +30,16 @@ class LMFMMError(RuntimeError):
 
 class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("order", ctypes.c_int * 32), ("root_x_lo", ctypes.c_double),
-                ("root_width", ctypes.c_double), ("near_pairs", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
+                ("root_width", ctypes.c_double), ("m2l_pairs", ctypes.c_int64),
                 ("leaves_src", ctypes.c_int64), ("leaves_tgt", ctypes.c_int64), ("near_nodes_mid", ctypes.c_int),
                 ("near_nodes_ray", ctypes.c_int), ("m2l_classes", ctypes.c_int), ("m2l_nodes", ctypes.c_int64),
-                ("table_seconds", ctypes.c_double), ("stage_ms", ctypes.c_double * 8),
-                ("stage_launches", ctypes.c_int64 * 8), ("timed_applies", ctypes.c_int64)]
+                ("table_seconds", ctypes.c_double), ("kernel_flops", ctypes.c_double * 8),
+                ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_int64 * 8),
+                ("timed_applies", ctypes.c_int64)]
+
+
+# kernel indices of Stats.kernel_* (LMFMM_K_* in lmfmm.h)
+KERNELS = ["tree", "p2m", "m2m", "m2l_l2l", "fold_top", "near_sweep", "l2p_near", "other"]
 
 
 class Instance(ctypes.Structure):
@@ -209,8 +214,8 @@ class Plan:
         _check(lib().lmfmm_get_stats(self._h, ctypes.byref(s)))
         d = {f: getattr(s, f) for f, _ in Stats._fields_}
         d["order"] = list(s.order)[: s.levels + 1]
-        d["stage_ms"] = list(s.stage_ms)[:5]
-        d["stage_launches"] = list(s.stage_launches)[:5]
+        for f in ("kernel_flops", "kernel_ms", "kernel_launches"):
+            d[f] = dict(zip(KERNELS, list(getattr(s, f))))
         return d
 
 
