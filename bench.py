@@ -37,8 +37,7 @@ from paper_1902_08250_amd.prof_summary import source_hash  # noqa: E402
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
 # kernel of each timing class on this workload (FP32 expansions, leaf order 16)
 KERNEL_NAMES = {"p2m": "k_p2m<float, 16>", "m2m": "k_up<float>", "m2l_l2l": "k_down<float>",
-                "fold_top": "k_fold_top<float>", "near_sweep": "k_near_sweep<float>",
-                "l2p_near": "k_l2p_near<float, 16>"}
+                "near_sweep": "k_near_sweep<float>", "l2p_near": "k_l2p_near<float, 16>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mixed_uniform_1e5.md")
 
 
@@ -81,26 +80,41 @@ def copy_probe(torch, mib):
 
 
 def run_gpu(torch, Plan, w, precision, steps, warmup, timing=False):
+    """Times `steps` applies (the second warm-up apply captures the launch
+    sequence as a HIP graph, the timed ones replay it).  With timing, the same
+    steps are run again kernel by kernel with HIP start/stop events on every
+    kernel launch of the apply's stream, for the per-kernel durations."""
     dt = torch.complex128 if precision == "c128" else torch.complex64
     src = torch.from_numpy(w["src"]).cuda()
     tgt = torch.from_numpy(w["tgt"]).cuda()
     q = torch.from_numpy(w["q"].astype(np.complex128 if precision == "c128" else np.complex64)).cuda()
     u = torch.empty((q.shape[0], tgt.shape[1]), dtype=dt, device="cuda")
     pl = Plan(w["k"], w["d"], order=w["order"], tol=w["tol"] if precision == "c64" else 1e-10, levels=w["levels"])
-    for _ in range(warmup):
+    for _ in range(max(warmup, 2)):
         pl.apply(src, q, tgt, out=u)
     torch.cuda.synchronize()
-    if timing:
-        pl.set_option("timing", "1")
-        pl.set_option("timing", "reset")
-    torch.cuda.synchronize()
+    g0 = pl.stats()["graph_applies"]
     t0 = time.perf_counter()
     for _ in range(steps):
         pl.apply(src, q, tgt, out=u)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = pl.stats()
-    return (t1 - t0) / steps, u.cpu().numpy(), st
+    st["graph_applies"] -= g0
+    out = u.cpu().numpy()
+    if timing:
+        pl.set_option("timing", "1")
+        pl.apply(src, q, tgt, out=u)
+        pl.set_option("timing", "reset")
+        t2 = time.perf_counter()
+        for _ in range(steps):
+            pl.apply(src, q, tgt, out=u)
+        torch.cuda.synchronize()
+        st_t = pl.stats()
+        st_t["ms_per_step_kernel_by_kernel"] = (time.perf_counter() - t2) / steps * 1e3
+        st_t["graph_applies"] = st["graph_applies"]
+        st = st_t
+    return (t1 - t0) / steps, out, st
 
 
 def roofline(st):
@@ -199,8 +213,10 @@ def main():
                    "levels": w["levels"], "tol": w["tol"], "orders_by_level": st["order"],
                    "medium": "k=(10,20,15)+0.01i, d=1"},
         "kernel_ms_per_apply": {k: v / nap for k, v in st["kernel_ms"].items() if v > 0},
+        "ms_per_step_kernel_by_kernel_with_events": st["ms_per_step_kernel_by_kernel"],
         "kernel_launches_per_apply": {k: v / nap for k, v in st["kernel_launches"].items() if v > 0},
         "m2l_pairs": st["m2l_pairs"],
+        "graph_applies_in_timed_region": st["graph_applies"],
         "roofline": roofline(st),
     }
     if not args.no_fp64:

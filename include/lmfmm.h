@@ -84,6 +84,10 @@ int lmfmm_destroy(lmfmm_plan plan);
  *                 a level that carries expansions (default 8): coarser
  *                 levels are skipped and the coarsest expansion level
  *                 translates between all its non-adjacent boxes
+ *   "graph"       "1" (default): when two consecutive applies have the same
+ *                 geometry, pointers, sizes and tables, the second captures
+ *                 its launch sequence in a HIP graph and later ones replay it
+ *                 (one launch); "0": always launch kernel by kernel
  *   "near_sweep"  "1" (default): near field by x-ordered sweeps over the node
  *                 table; "0": the pairwise sum (same quadrature)
  *   "near"        "1" (default) / "0": include / skip the near field
@@ -153,14 +157,14 @@ typedef struct {
     double kernel_ms[8];
     int64_t kernel_launches[8];
     int64_t timed_applies;
+    int64_t graph_applies;  /* applies run as a captured HIP graph (lifetime)  */
 } lmfmm_stats;
 
 /* Kernel indices of lmfmm_stats.kernel_*: bounding box and tree build (all
- * their kernels together), P2M, M2M, M2L + L2L, fold of the coarsest
- * level's M2L partials, near-field sweep, L2P + near field (or its gradient
- * form), the rest. */
-enum { LMFMM_K_TREE = 0, LMFMM_K_P2M = 1, LMFMM_K_M2M = 2, LMFMM_K_DOWN = 3, LMFMM_K_FOLD = 4,
-       LMFMM_K_SWEEP = 5, LMFMM_K_L2P = 6, LMFMM_K_OTHER = 7 };
+ * their kernels together), P2M, M2M, M2L + L2L, near-field sweep, L2P + near
+ * field (or its gradient form); 6 and 7 are unused. */
+enum { LMFMM_K_TREE = 0, LMFMM_K_P2M = 1, LMFMM_K_M2M = 2, LMFMM_K_DOWN = 3, LMFMM_K_SWEEP = 4, LMFMM_K_L2P = 5,
+       LMFMM_K_OTHER = 6 };
 
 int lmfmm_get_stats(lmfmm_plan plan, lmfmm_stats *stats);
 

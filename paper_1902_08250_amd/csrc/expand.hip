@@ -66,182 +66,200 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ start, c
 }
 
 // ---------------------------------------------------------------------------
-// Translations as batched complex contractions over boxes.
-//
-// out[b][p] = sum_k A[k][p] X_b[k] for a tile of 16 boxes and 64 output
-// coefficients per block, K staged through LDS in chunks of 32.  The three
-// translations differ only in where X_b comes from and where the result goes:
-//   L2L (Lemma L2L): A = shift table of one child position, X_b = the local
-//        expansion of parent b (with its pending M2L partials); result ->
-//        the child of b at that position;
-//   M2L (Lemma M2L): A = Ahat of one class (target row, source row, column
-//        offset); X_b = the multipole of the source box of target column b,
-//        zero where the class does not apply; result -> partial[class][b];
-//   M2M (Lemma M2M): A = the four child tables stacked along K; X_b = the
-//        four children of parent b; result -> parent b.
-// M2L partials are summed, in class order, by the next reader of the level's
-// local expansions (the child level's L2L or the leaf evaluation).
+// Translations (Lemma M2M, Lemma M2L, Lemma L2L) as one matrix-vector product
+// per (table, vector) item: out[p] += sum_k A[k][p] x[k], A a per-level table
+// (M2M and L2L: one per child position; M2L: one per translation class) and
+// x the expansion being translated.  A wave evaluates one item with lanes over
+// the output coefficients p: it stages x in LDS and issues the loads of a
+// whole K chunk of its table column at once, so an item costs about one
+// memory round trip.  The waves of a block take the items of one output box
+// in turn; their sums are added in wave order through LDS, so the result does
+// not depend on scheduling.
 // ---------------------------------------------------------------------------
-constexpr int GB = 16, GP = 64;
-// K chunk: 64 for FP32, 32 for FP64 (about 33 KB of A in LDS either way)
 template <typename T>
-struct Chunk {
-    static constexpr int GK = sizeof(T) == 4 ? 64 : 32;
-    static constexpr int NA = GK * GP / 256;  // A elements staged per thread
-    static constexpr int NX = GB * GK / 256;  // X elements staged per thread
+struct Tr {
+    static constexpr int R = sizeof(T) == 4 ? 4 : 2;    // right-hand sides per pass
+    static constexpr int KC = sizeof(T) == 4 ? 48 : 24;  // table rows loaded per round trip
 };
 
-// Loads of one K chunk are issued into registers together (and the next
-// chunk is fetched while the current one is multiplied), so a block pays
-// one memory latency per chunk instead of one per element.
-template <typename T, typename XF, typename OF>
-__device__ inline void box_gemm(const cx<T> *__restrict__ A, int nk, int nout, int nbox, int b0, int p0, XF xload,
-                                OF store, cx<T> (*Xs)[Chunk<T>::GK + 1], cx<T> (*As)[GP + 1])
+// Per-wave LDS: x chunk [R][KC] and the wave's partial sums [R][64].
+template <typename T>
+struct WaveLds {
+    cx<T> x[Tr<T>::R][Tr<T>::KC];
+    cx<T> out[Tr<T>::R][64];
+};
+
+// acc[r] += sum_{k < nk} A[k * nout + p] x[r * xstride + k], p = p0 + lane,
+// r < nr.  Every lane of the wave calls this with the same arguments.
+template <typename T>
+__device__ inline void item_matvec(const cx<T> *__restrict__ A, int nk, int nout, int p0,
+                                   const cx<T> *__restrict__ x, int64_t xstride, int nr, WaveLds<T> &lds,
+                                   cx<T> (&acc)[Tr<T>::R])
 {
-    constexpr int GK = Chunk<T>::GK, NA = Chunk<T>::NA, NX = Chunk<T>::NX;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    cx<T> acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = mk<T>(0, 0);
-    cx<T> ra[NA], rx[NX];
-    auto fetch = [&](int k0) {
-        const int kc = nk - k0 < GK ? nk - k0 : GK;
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            int t = tid + 256 * i, kk = t / GP, pp = t % GP;
-            ra[i] = (kk < kc && p0 + pp < nout) ? A[(int64_t)(k0 + kk) * nout + p0 + pp] : mk<T>(0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-            int t = tid + 256 * i, bb = t / GK, kk = t % GK;
-            rx[i] = (kk < kc && b0 + bb < nbox) ? xload(b0 + bb, k0 + kk) : mk<T>(0, 0);
-        }
-    };
-    fetch(0);
-    for (int k0 = 0; k0 < nk; k0 += GK) {
-        const int kc = nk - k0 < GK ? nk - k0 : GK;
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            int t = tid + 256 * i;
-            As[t / GP][t % GP] = ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-            int t = tid + 256 * i;
-            Xs[t / GK][t % GK] = rx[i];
-        }
-        __syncthreads();
-        if (k0 + GK < nk) fetch(k0 + GK);
-        for (int kk = 0; kk < kc; ++kk) {
-            cx<T> a = As[kk][lane];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) cfma(acc[j], a, Xs[wv * 4 + j][kk]);
-        }
-        __syncthreads();
-    }
+    constexpr int R = Tr<T>::R, KC = Tr<T>::KC;
+    const int lane = threadIdx.x & 63;
     const int p = p0 + lane;
-    if (p < nout)
+    const int pc = p < nout ? p : nout - 1;
+    for (int k0 = 0; k0 < nk; k0 += KC) {
+        const int kc = nk - k0 < KC ? nk - k0 : KC;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < KC)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int b = b0 + wv * 4 + j;
-            if (b < nbox) store(b, p, acc[j]);
+            for (int r = 0; r < R; ++r)
+                lds.x[r][lane] = (r < nr && lane < kc) ? x[r * xstride + k0 + lane] : mk<T>(0, 0);
+        cx<T> av[KC];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const int k = k0 + (j < kc ? j : kc - 1);
+            av[j] = A[(int64_t)k * nout + pc];
         }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j0 = 0; j0 < KC; j0 += 8) {
+            if (j0 < kc) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (r < nr)
+#pragma unroll
+                        for (int j = j0; j < j0 + 8; ++j) cfma(acc[r], av[j], lds.x[r][j]);
+            }
+        }
+    }
 }
 
-// Class slots of one level grouped by target row (row 0 and row 1).
-struct RowSlots {
-    int n[2];
-    int s[2][14];
-};
-
-// Local expansion of a box including the M2L partials not yet folded in.
-template <typename T>
-__device__ inline cx<T> local_value(const cx<T> *__restrict__ Lc, int base, const cx<T> *__restrict__ part,
-                                    const RowSlots &rsl, int row, int col_local, int ncol, int nrhs, int r, int nc,
-                                    int k)
+// Sum of the waves' partials in wave order by wave 0; writes out[r * ostride + p].
+template <typename T, int NW>
+__device__ inline void block_reduce_store(WaveLds<T> *lds, const cx<T> (&acc)[Tr<T>::R], int nr, int p0, int nout,
+                                          cx<T> *__restrict__ out, int64_t ostride)
 {
-    cx<T> v = base ? Lc[(((int64_t)row * ncol + col_local) * nrhs + r) * nc + k] : mk<T>(0, 0);
-    if (row < 2)
-        for (int i = 0; i < rsl.n[row]; ++i)
-            v += part[(((int64_t)rsl.s[row][i] * ncol + col_local) * nrhs + r) * nc + k];
-    return v;
+    constexpr int R = Tr<T>::R;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[w].out[r][lane] = acc[r];
+    __syncthreads();
+    if (w == 0 && p0 + lane < nout)
+        for (int r = 0; r < nr; ++r) {
+            cx<T> v = lds[0].out[r][lane];
+#pragma unroll
+            for (int i = 1; i < NW; ++i) v += lds[i].out[r][lane];
+            out[r * ostride + p0 + lane] = v;
+        }
+    __syncthreads();
+}
+
+// Upward pass of one level (Lemma M2M): one block per parent box at level
+// lc - 1; wave w translates the child at position w (dx = w & 1, dy = w >> 1).
+template <typename T>
+__global__ void __launch_bounds__(256) k_up(const cx<T> *__restrict__ Mc, cx<T> *__restrict__ Mp,
+                                            const cx<T> *__restrict__ tab, int nrhs, int ncc, int ncp, int ncol_c,
+                                            int col_lo_c, int rows_c, int ncol_p, int col_lo_p)
+{
+    constexpr int R = Tr<T>::R;
+    __shared__ WaveLds<T> lds[4];
+    const int b = blockIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int prow = b / ncol_p, pcol = col_lo_p + b % ncol_p;
+    const int crow = 2 * prow + (w >> 1), ccl = 2 * pcol + (w & 1) - col_lo_c;
+    const bool ok = crow < rows_c && ccl >= 0 && ccl < ncol_c;
+    const cx<T> *x = Mc + ((int64_t)crow * ncol_c + ccl) * nrhs * ncc;
+    const cx<T> *A = tab + (int64_t)w * ncc * ncp;
+    for (int r0 = 0; r0 < nrhs; r0 += R) {
+        const int nr = nrhs - r0 < R ? nrhs - r0 : R;
+        for (int p0 = 0; p0 < ncp; p0 += 64) {
+            cx<T> acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+            if (ok) item_matvec<T>(A, ncc, ncp, p0, x + (int64_t)r0 * ncc, ncc, nr, lds[w], acc);
+            block_reduce_store<T, 4>(lds, acc, nr, p0, ncp, Mp + ((int64_t)b * nrhs + r0) * ncp, ncp);
+        }
+    }
 }
 
 struct DownArgs {
     // level l
-    int nc, ncol, col_lo, rows_s, rows_t, nslots;
-    int top;  // 1 at the coarsest expansion level: every non-adjacent pair, no parent test
+    int nc, ncol, col_lo, rows_s, rows_t;
+    int top;     // 1 at the coarsest expansion level: every non-adjacent pair, no parent test
+    int nrt;     // target rows with M2L classes (their slots: row_off[row] .. row_off[row + 1])
+    int nb_m2l;  // blocks with one box each: rows < nrt
     // level l - 1
-    int ncp, ncol_p, col_lo_p, rows_t_p, base_p;
+    int ncp, ncol_p, col_lo_p, rows_t_p;
     int has_l2l;
-    RowSlots rsl_p;  // parent level's classes by target row
 };
 
-// Downward pass of one level: blockIdx.z in [0, 4 nrhs) is L2L (when the
-// parent level has local expansions), the rest M2L partials.
+// Downward pass of one level: L_box = L2L(parent's L) + sum over the box's
+// interaction list of M2L (Lemma L2L, Lemma M2L).  Blocks below nb_m2l take
+// one box of the M2L rows each (items: the L2L shift, then the row's class
+// slots, dealt to the waves in turn; the waves' sums are added in order);
+// the remaining blocks take DW boxes of the deeper rows, one per wave, whose
+// only item is the L2L shift.
+constexpr int DW = 8;
 template <typename T>
-__global__ void __launch_bounds__(256) k_down(DownArgs a, int nrhs, const cx<T> *__restrict__ Lp,
-                                              const cx<T> *__restrict__ part_p, const cx<T> *__restrict__ l2l,
-                                              cx<T> *__restrict__ Lc,
-                                              const cx<T> *__restrict__ Ms, const cx<T> *__restrict__ atab,
-                                              const int *__restrict__ cls3, cx<T> *__restrict__ part)
+__global__ void __launch_bounds__(64 * DW) k_down(DownArgs a, int nrhs, const cx<T> *__restrict__ Lp,
+                                                  const cx<T> *__restrict__ l2l, cx<T> *__restrict__ Lc,
+                                                  const cx<T> *__restrict__ Ms, const cx<T> *__restrict__ atab,
+                                                  const int *__restrict__ cls3, const int *__restrict__ row_off)
 {
-    __shared__ cx<T> Xs[GB][Chunk<T>::GK + 1];
-    __shared__ cx<T> As[Chunk<T>::GK][GP + 1];
-    const int b0 = blockIdx.x * GB, p0 = blockIdx.y * GP;
-    int z = blockIdx.z;
-    if (a.has_l2l && z < 4 * nrhs) {
-        const int pos = z / nrhs, r = z % nrhs;
-        const int nbox = a.rows_t_p * a.ncol_p;
-        if (b0 >= nbox) return;
-        const int dx = pos & 1, dy = pos >> 1;
-        auto xload = [&](int b, int k) {
-            int prow = b / a.ncol_p, pcl = b % a.ncol_p;
-            return local_value<T>(Lp, a.base_p, part_p, a.rsl_p, prow, pcl, a.ncol_p, nrhs, r, a.ncp, k);
-        };
-        auto store = [&](int b, int p, cx<T> v) {
-            int prow = b / a.ncol_p, pcol = a.col_lo_p + b % a.ncol_p;
-            int crow = 2 * prow + dy, ccl = 2 * pcol + dx - a.col_lo;
-            if (crow < a.rows_t && ccl >= 0 && ccl < a.ncol) Lc[(((int64_t)crow * a.ncol + ccl) * nrhs + r) * a.nc + p] = v;
-        };
-        box_gemm<T>(l2l + (int64_t)pos * a.ncp * a.nc, a.ncp, a.nc, nbox, b0, p0, xload, store, Xs, As);
-        return;
+    constexpr int R = Tr<T>::R;
+    __shared__ WaveLds<T> lds[DW];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool m2l_block = (int)blockIdx.x < a.nb_m2l;
+    int64_t box;
+    int first, step, nitems, s0 = 0;
+    if (m2l_block) {
+        box = blockIdx.x;
+        const int row = (int)(box / a.ncol);
+        s0 = row_off[row];
+        nitems = a.has_l2l + row_off[row + 1] - s0;
+        first = w;
+        step = DW;
+    } else {
+        box = (int64_t)a.nrt * a.ncol + (int64_t)(blockIdx.x - a.nb_m2l) * DW + w;
+        if (box >= (int64_t)a.rows_t * a.ncol) return;  // whole wave; no block barrier on this path
+        nitems = a.has_l2l;
+        first = 0;
+        step = 1;
     }
-    if (a.has_l2l) z -= 4 * nrhs;
-    const int slot = z / nrhs, r = z % nrhs;
-    const int nbox = a.ncol;
-    if (b0 >= nbox) return;
-    const int rs = cls3[3 * slot + 1], dc = cls3[3 * slot + 2];
-    auto xload = [&](int b, int k) {
-        int col = a.col_lo + b, cs = col + dc, csl = cs - a.col_lo;
-        int dp = (cs >> 1) - (col >> 1);
-        bool ok = rs < a.rows_s && csl >= 0 && csl < a.ncol && (a.top || (dp <= 1 && dp >= -1));
-        return ok ? Ms[(((int64_t)rs * a.ncol + csl) * nrhs + r) * a.nc + k] : mk<T>(0, 0);
-    };
-    auto store = [&](int b, int p, cx<T> v) { part[(((int64_t)slot * a.ncol + b) * nrhs + r) * a.nc + p] = v; };
-    box_gemm<T>(atab + (int64_t)slot * a.nc * a.nc, a.nc, a.nc, nbox, b0, p0, xload, store, Xs, As);
-}
-
-// Upward pass of one level: parents at level lc - 1 from their four children.
-template <typename T>
-__global__ void __launch_bounds__(256) k_up(const cx<T> *__restrict__ Mc, cx<T> *__restrict__ Mp,
-                                            const cx<T> *__restrict__ tab, int nrhs, int ncc, int ncp, int ncol_c,
-                                            int col_lo_c, int rows_c, int ncol_p, int col_lo_p, int rows_p)
-{
-    __shared__ cx<T> Xs[GB][Chunk<T>::GK + 1];
-    __shared__ cx<T> As[Chunk<T>::GK][GP + 1];
-    const int b0 = blockIdx.x * GB, p0 = blockIdx.y * GP, r = blockIdx.z;
-    const int nbox = rows_p * ncol_p;
-    if (b0 >= nbox) return;
-    auto xload = [&](int b, int k) {
-        int c = k / ncc, kk = k % ncc, dx = c & 1, dy = c >> 1;
-        int prow = b / ncol_p, pcol = col_lo_p + b % ncol_p;
-        int crow = 2 * prow + dy, ccl = 2 * pcol + dx - col_lo_c;
-        bool ok = crow < rows_c && ccl >= 0 && ccl < ncol_c;
-        return ok ? Mc[(((int64_t)crow * ncol_c + ccl) * nrhs + r) * ncc + kk] : mk<T>(0, 0);
-    };
-    auto store = [&](int b, int p, cx<T> v) { Mp[((int64_t)b * nrhs + r) * ncp + p] = v; };
-    box_gemm<T>(tab, 4 * ncc, ncp, nbox, b0, p0, xload, store, Xs, As);
+    const int row = (int)(box / a.ncol), col = a.col_lo + (int)(box % a.ncol);
+    const int prow = row >> 1, pcl = (col >> 1) - a.col_lo_p, pos = (col & 1) + 2 * (row & 1);
+    const bool pok = prow < a.rows_t_p && pcl >= 0 && pcl < a.ncol_p;
+    for (int r0 = 0; r0 < nrhs; r0 += R) {
+        const int nr = nrhs - r0 < R ? nrhs - r0 : R;
+        for (int p0 = 0; p0 < a.nc; p0 += 64) {
+            cx<T> acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+            for (int i = first; i < nitems; i += step) {
+                const cx<T> *A, *x;
+                int nk;
+                bool ok;
+                if (i < a.has_l2l) {
+                    A = l2l + (int64_t)pos * a.ncp * a.nc;
+                    x = Lp + (((int64_t)prow * a.ncol_p + pcl) * nrhs + r0) * a.ncp;
+                    nk = a.ncp;
+                    ok = pok;
+                } else {
+                    const int slot = s0 + i - a.has_l2l;
+                    const int rs = cls3[3 * slot + 1], dc = cls3[3 * slot + 2];
+                    const int cs = col + dc, csl = cs - a.col_lo, dp = (cs >> 1) - (col >> 1);
+                    A = atab + (int64_t)slot * a.nc * a.nc;
+                    x = Ms + (((int64_t)rs * a.ncol + csl) * nrhs + r0) * a.nc;
+                    nk = a.nc;
+                    ok = rs < a.rows_s && csl >= 0 && csl < a.ncol && (a.top || (dp <= 1 && dp >= -1));
+                }
+                if (ok) item_matvec<T>(A, nk, a.nc, p0, x, nk, nr, lds[w], acc);
+            }
+            cx<T> *out = Lc + (box * nrhs + r0) * a.nc;
+            if (m2l_block) {
+                block_reduce_store<T, DW>(lds, acc, nr, p0, a.nc, out, a.nc);
+            } else {
+                const int p = p0 + (threadIdx.x & 63);
+                if (p < a.nc)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r < nr) out[r * a.nc + p] = acc[r];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -302,9 +320,7 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
                                                  const double *__restrict__ ys, const cx<T> *__restrict__ q,
                                                  int64_t ns, int64_t nt, int nrhs, int P, int ncol, int col_lo,
                                                  int rows_s, double x_lo, double w, cx<T> k2, T invR,
-                                                 const cx<T> *__restrict__ Lc, int base,
-                                                 const cx<T> *__restrict__ part, RowSlots rsl,
-                                                 const Node *__restrict__ nodes,
+                                                 const cx<T> *__restrict__ Lc, const Node *__restrict__ nodes,
                                                  int nmid, int npan, double t0, int do_far, int do_near,
                                                  int64_t key_t0, const cx<double> *__restrict__ unear, int nparts,
                                                  cx<T> *__restrict__ u)
@@ -323,7 +339,7 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
     if (do_far) {
         for (int r = 0; r < nr; ++r)
             for (int t = lane; t < nc; t += 64)
-                Ls[r * nc + t] = local_value<T>(Lc, base, part, rsl, row, cl, ncol, nrhs, r0 + r, nc, t);
+                Ls[r * nc + t] = Lc[(((int64_t)row * ncol + cl) * nrhs + r0 + r) * nc + t];
         __syncthreads();
     }
     for (int c0 = s; c0 < e; c0 += 64) {
@@ -601,8 +617,7 @@ __global__ void __launch_bounds__(64) k_l2p_grad(const int32_t *__restrict__ sta
                                                  const cx<T> *__restrict__ cw, int64_t ns, int64_t nt, int nrhs,
                                                  int r0, int nr, int accumulate,
                                                  int P, int ncol, int col_lo, int rows_s, double x_lo, double w,
-                                                 cx<T> kt, T invR, const cx<T> *__restrict__ Lc, int base,
-                                                 const cx<T> *__restrict__ part, RowSlots rsl,
+                                                 cx<T> kt, T invR, const cx<T> *__restrict__ Lc,
                                                  const Node *__restrict__ nodes, int nmid, int npan, double t0,
                                                  int do_far, int do_near, int64_t key_t0, double ysign,
                                                  double *__restrict__ gout)
@@ -623,8 +638,7 @@ __global__ void __launch_bounds__(64) k_l2p_grad(const int32_t *__restrict__ sta
         for (int t = lane; t < nr * ncg; t += 64) {
             int r = r0 + t / ncg, n = t % ncg - (P + 1);
             auto Lh = [&](int m) {
-                return (m >= -P && m <= P) ? local_value<T>(Lc, base, part, rsl, row, cl, ncol, nrhs, r, nc, m + P)
-                                           : mk<T>(0, 0);
+                return (m >= -P && m <= P) ? Lc[(((int64_t)row * ncol + cl) * nrhs + r) * nc + m + P] : mk<T>(0, 0);
             };
             cx<T> up = Lh(n + 1), dn = Lh(n - 1);
             // (k/2) s_{n+1}/s_n and (k/2) s_{n-1}/s_n
@@ -744,48 +758,16 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     cx<double> kd = k_src(med);
     cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
-    hipLaunchKernelGGL((k_p2m<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
+    LMFMM_LAUNCH((k_p2m<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
                        reinterpret_cast<const cx<T> *>(q), ns, nrhs, lv.P, lv.ncol, lv.col_lo, g.x_lo, lv.w, k1, invR,
                        CH, M + lv.off_s);
-}
-
-// cls3_host: (target row, source row, column offset) per class slot, or null
-// for a level whose partials are already folded into its local expansions.
-inline RowSlots row_slots(const int *cls3_host, int nslots)
-{
-    RowSlots r;
-    r.n[0] = r.n[1] = 0;
-    for (int i = 0; i < nslots && cls3_host; ++i) {
-        int rt = cls3_host[3 * i];
-        if (rt < 2 && r.n[rt] < 14) r.s[rt][r.n[rt]++] = i;
-    }
-    return r;
-}
-
-// Fold the M2L partials of the coarsest expansion level into its local
-// expansions: Lc[box] = sum over the classes of the box's row, in slot order.
-// row_off[rt] .. row_off[rt+1] are the slots whose target row is rt.
-template <typename T>
-__global__ void __launch_bounds__(256) k_fold_top(const cx<T> *__restrict__ part, const int *__restrict__ row_off,
-                                                  int ncol, int nrhs, int nc, int64_t nout, cx<T> *__restrict__ Lc)
-{
-    int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (o >= nout) return;
-    int p = (int)(o % nc);
-    int64_t t = o / nc;
-    int r = (int)(t % nrhs);
-    int64_t box = t / nrhs;
-    int rt = (int)(box / ncol), cl = (int)(box % ncol);
-    cx<T> v = mk<T>(0, 0);
-    for (int sl = row_off[rt]; sl < row_off[rt + 1]; ++sl) v += part[(((int64_t)sl * ncol + cl) * nrhs + r) * nc + p];
-    Lc[o] = v;
 }
 
 template <typename T, int PMAX>
 void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
                   const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med, const cx<T> *Lc,
-                  const cx<T> *part, const int *cls_of_host, int nslots, const Node *nodes, int nmid, int npan,
-                  double t0, int do_far, int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
+                  const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near,
+                  const cx<double> *unear, int nparts, void *u, hipStream_t st)
 {
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_t * lv.ncol;
@@ -795,19 +777,17 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     cx<T> k2 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
     int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
-    hipLaunchKernelGGL((k_l2p_near<T, PMAX>), dim3(nbox, (nrhs + 7) / 8), dim3(64), sh, st, start, end, idx, xs, ys,
+    LMFMM_LAUNCH((k_l2p_near<T, PMAX>), dim3(nbox, (nrhs + 7) / 8), dim3(64), sh, st, start, end, idx, xs, ys,
                        reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo,
-                       lv.w, k2, invR, Lc + lv.off_t, 1, part, row_slots(cls_of_host, nslots), nodes,
-                       nmid, npan, t0, do_far, do_near, key_t0, unear, nparts,
+                       lv.w, k2, invR, Lc + lv.off_t, nodes, nmid, npan, t0, do_far, do_near, key_t0, unear, nparts,
                        reinterpret_cast<cx<T> *>(u));
 }
 
 template <typename T, int PMAX>
 void grad_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
                    const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med,
-                   const cx<T> *Lc, const cx<T> *part, const int *cls_of_host, int nslots, const Node *nodes,
-                   int nmid, int npan, double t0, int do_far, int do_near, double ysign, double *gout,
-                   hipStream_t st)
+                   const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near,
+                   double ysign, double *gout, hipStream_t st)
 {
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_t * lv.ncol;
@@ -819,11 +799,10 @@ void grad_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx,
     for (int r0 = 0; r0 < nrhs; r0 += 8) {
         int nr = nrhs - r0 < 8 ? nrhs - r0 : 8;
         size_t sh = (size_t)2 * nr * (2 * (lv.P + 1) + 1) * sizeof(cx<T>);
-        hipLaunchKernelGGL((k_l2p_grad<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
+        LMFMM_LAUNCH((k_l2p_grad<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
                            reinterpret_cast<const cx<T> *>(q), reinterpret_cast<const cx<T> *>(cw), ns, nt, nrhs, r0,
                            nr, r0 > 0 ? 1 : 0, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo, lv.w, kt, invR,
-                           Lc + lv.off_t, 1, part, row_slots(cls_of_host, nslots), nodes, nmid, npan, t0,
-                           do_far, do_near, key_t0, ysign, gout);
+                           Lc + lv.off_t, nodes, nmid, npan, t0, do_far, do_near, key_t0, ysign, gout);
     }
 }
 
@@ -850,15 +829,13 @@ void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int nrhs,
     const Level &c = g.lev[lc], &p = g.lev[lc - 1];
     int nbox = p.rows_s * p.ncol;
     if (nbox == 0) return;
-    dim3 grid((nbox + GB - 1) / GB, (p.nc + GP - 1) / GP, nrhs);
-    hipLaunchKernelGGL((k_up<T>), grid, dim3(256), 0, st, M + c.off_s, M + p.off_s, tab, nrhs, c.nc, p.nc, c.ncol,
-                       c.col_lo, c.rows_s, p.ncol, p.col_lo, p.rows_s);
+    LMFMM_LAUNCH((k_up<T>), dim3(nbox), dim3(256), 0, st, M + c.off_s, M + p.off_s, tab, nrhs, c.nc, p.nc,
+                       c.ncol, c.col_lo, c.rows_s, p.ncol, p.col_lo);
 }
 
 template <typename T>
-void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls_of,
-                 const int *cls_of_p_host, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
-                 const cx<T> *l2l_tab, bool top, hipStream_t st)
+void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, const int *row_off, int nrt,
+                 const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, hipStream_t st)
 {
     const Level &lv = g.lev[l], &pv = g.lev[l - 1];
     DownArgs a;
@@ -867,34 +844,19 @@ void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T>
     a.col_lo = lv.col_lo;
     a.rows_s = lv.rows_s;
     a.rows_t = lv.rows_t;
-    a.nslots = nslots;
+    a.top = top ? 1 : 0;
+    a.nrt = atab ? (nrt < lv.rows_t ? nrt : lv.rows_t) : 0;
+    a.nb_m2l = a.nrt * lv.ncol;
     a.ncp = pv.nc;
     a.ncol_p = pv.ncol;
     a.col_lo_p = pv.col_lo;
     a.rows_t_p = pv.rows_t;
-    a.rsl_p = row_slots(cls_of_p_host, nslots_p);
-    a.base_p = 1;
     a.has_l2l = l2l_tab != nullptr;
-    a.top = top ? 1 : 0;
-    int nb_l2l = a.has_l2l ? (pv.rows_t * pv.ncol + GB - 1) / GB : 0;
-    int nb_m2l = (lv.ncol + GB - 1) / GB;
-    int gx = nb_l2l > nb_m2l ? nb_l2l : nb_m2l;
-    int gz = (a.has_l2l ? 4 * nrhs : 0) + nslots * nrhs;
-    if (gz == 0 || gx == 0) return;
-    dim3 grid(gx, (lv.nc + GP - 1) / GP, gz);
-    hipLaunchKernelGGL((k_down<T>), grid, dim3(256), 0, st, a, nrhs, Lc + pv.off_t, part_p, l2l_tab,
-                       Lc + lv.off_t, M + lv.off_s, atab, cls_of, part);
-}
-
-template <typename T>
-void launch_fold_top(const Geometry &g, int l, const cx<T> *part, const int *row_off, cx<T> *Lc, int nrhs,
-                     hipStream_t st)
-{
-    const Level &lv = g.lev[l];
-    int64_t nout = (int64_t)lv.rows_t * lv.ncol * nrhs * lv.nc;
-    if (nout == 0) return;
-    hipLaunchKernelGGL((k_fold_top<T>), dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, part, row_off, lv.ncol,
-                       nrhs, lv.nc, nout, Lc + lv.off_t);
+    int64_t rest = (int64_t)(lv.rows_t - a.nrt) * lv.ncol;
+    int64_t nblk = a.nb_m2l + (a.has_l2l ? (rest + DW - 1) / DW : 0);
+    if (nblk == 0) return;
+    LMFMM_LAUNCH((k_down<T>), dim3((unsigned)nblk), dim3(64 * DW), 0, st, a, nrhs, Lc + pv.off_t, l2l_tab,
+                       Lc + lv.off_t, M + lv.off_s, atab, cls3, row_off);
 }
 
 template <typename T>
@@ -907,7 +869,7 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
     // split the nodes over parts when there are few leaves
     int nparts = lv.ncol >= 1024 ? 1 : (lv.ncol >= 256 ? 2 : 4);
     int nnodes = nmid + 2 * NGL * npan;
-    hipLaunchKernelGGL((k_near_sweep<T>), dim3(lv.ncol, (nrhs + 7) / 8, nparts), dim3(64), 0, st, start, end, idx, xs,
+    LMFMM_LAUNCH((k_near_sweep<T>), dim3(lv.ncol, (nrhs + 7) / 8, nparts), dim3(64), 0, st, start, end, idx, xs,
                        ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol, (int64_t)lv.rows_s * lv.ncol,
                        nodes, nnodes, nmid, npan, t0, nparts, unear);
     return nparts;
@@ -916,15 +878,14 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
-                     Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots, const Node *nodes,
-                     int nmid, int npan, double t0, int do_far, int do_near, const cx<double> *unear, int nparts,
-                     void *u, hipStream_t st)
+                     Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far,
+                     int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
 {
-    int P = g.lev[g.L].P;  // cls_of: host copy of the leaf level's class codes
+    int P = g.lev[g.L].P;
     if (!unear) nparts = 0;
-#define LMFMM_L2P(PM)                                                                                        \
-    l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part, cls_of, nslots, nodes, nmid, \
-                        npan, t0, do_far, do_near, unear, nparts, u, st)
+#define LMFMM_L2P(PM)                                                                                          \
+    l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nodes, nmid, npan, t0, do_far, \
+                        do_near, unear, nparts, u, st)
     if (P <= 16)
         LMFMM_L2P(16);
     else if (P <= 32)
@@ -939,14 +900,13 @@ void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *id
 template <typename T>
 void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,
-                     const Geometry &g, Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots,
-                     const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near, double ysign,
-                     double *gout, hipStream_t st)
+                     const Geometry &g, Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0,
+                     int do_far, int do_near, double ysign, double *gout, hipStream_t st)
 {
     int P = g.lev[g.L].P + 1;
-#define LMFMM_GR(PM)                                                                                          \
-    grad_dispatch<T, PM>(start, end, idx, xs, ys, q, cw, ns, nt, nrhs, g, med, Lc, part, cls_of, nslots, nodes, \
-                         nmid, npan, t0, do_far, do_near, ysign, gout, st)
+#define LMFMM_GR(PM)                                                                                             \
+    grad_dispatch<T, PM>(start, end, idx, xs, ys, q, cw, ns, nt, nrhs, g, med, Lc, nodes, nmid, npan, t0, do_far, \
+                         do_near, ysign, gout, st)
     if (P <= 16)
         LMFMM_GR(16);
     else if (P <= 32)
@@ -976,21 +936,19 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
     template void launch_p2m<T>(const int32_t *, const int32_t *, const int32_t *, const double *, const double *,   \
                                 const void *, int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);        \
     template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int, hipStream_t);                   \
-    template void launch_down<T>(const Geometry &, int, int, int, const cx<T> *, const int *, const int *,          \
-                                 const cx<T> *, cx<T> *, cx<T> *, const cx<T> *, int, const cx<T> *, bool,          \
-                                 hipStream_t);                                                                      \
-    template void launch_fold_top<T>(const Geometry &, int, const cx<T> *, const int *, cx<T> *, int, hipStream_t); \
+    template void launch_down<T>(const Geometry &, int, const cx<T> *, const int *, const int *, int, const cx<T> *, \
+                                 cx<T> *, int, const cx<T> *, bool, hipStream_t);                                   \
     template int launch_near_sweep<T>(const int32_t *, const int32_t *, const int32_t *, const double *,            \
                                       const double *, const void *, int64_t, int64_t, int, const Geometry &,        \
                                       const Node *, int, int, double, cx<double> *, hipStream_t);                   \
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
-                                     const cx<T> *, const cx<T> *, const int *, int, const Node *, int, int, double, \
-                                     int, int, const cx<double> *, int, void *, hipStream_t);                       \
+                                     const cx<T> *, const Node *, int, int, double, int, int, const cx<double> *,   \
+                                     int, void *, hipStream_t);                                                     \
     template void launch_l2p_grad<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, const void *, int64_t, int64_t, int,             \
-                                     const Geometry &, Medium, const cx<T> *, const cx<T> *, const int *, int,      \
-                                     const Node *, int, int, double, int, int, double, double *, hipStream_t);
+                                     const Geometry &, Medium, const cx<T> *, const Node *, int, int, double, int,  \
+                                     int, double, double *, hipStream_t);
 LMFMM_INST(double)
 LMFMM_INST(float)
 

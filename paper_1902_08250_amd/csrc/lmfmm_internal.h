@@ -5,6 +5,7 @@
 // multipole and local expansions, and the launch wrappers of every kernel.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -12,6 +13,31 @@
 #include <vector>
 
 namespace lmfmm {
+
+// Start/stop events for the next timed kernel launch of this host thread
+// (set by a plan in timing mode, consumed by LMFMM_LAUNCH): the runtime
+// stamps them at the kernel's own start and end.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+inline LaunchTiming &launch_timing()
+{
+    static thread_local LaunchTiming t;
+    return t;
+}
+
+#define LMFMM_LAUNCH(K, grid, block, sh, st, ...)                                    \
+    do {                                                                             \
+        ::lmfmm::LaunchTiming &lt_ = ::lmfmm::launch_timing();                       \
+        if (lt_.start) {                                                             \
+            hipEvent_t a_ = lt_.start, b_ = lt_.stop;                                \
+            lt_.start = lt_.stop = nullptr;                                          \
+            hipExtLaunchKernelGGL(K, grid, block, sh, st, a_, b_, 0, __VA_ARGS__);   \
+        } else {                                                                     \
+            hipLaunchKernelGGL(K, grid, block, sh, st, __VA_ARGS__);                 \
+        }                                                                            \
+    } while (0)
+
 
 // ---------------------------------------------------------------------------
 // Complex arithmetic (device and host)
@@ -262,13 +288,11 @@ void launch_p2m(const int32_t *start, const int32_t *end, const int32_t *idx, co
                 const void *q, int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st);
 template <typename T>
 void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int nrhs, hipStream_t st);
+// downward pass of level l: M2L (class slots of target row r: row_off[r] ..
+// row_off[r + 1], rows < nrt) plus L2L from level l - 1 (l2l_tab non-null)
 template <typename T>
-void launch_down(const Geometry &g, int l, int nslots, int nslots_p, const cx<T> *atab, const int *cls3,
-                 const int *cls3_p_host, const cx<T> *M, cx<T> *Lc, cx<T> *part, const cx<T> *part_p, int nrhs,
-                 const cx<T> *l2l_tab, bool top, hipStream_t st);
-template <typename T>
-void launch_fold_top(const Geometry &g, int l, const cx<T> *part, const int *row_off, cx<T> *Lc, int nrhs,
-                     hipStream_t st);
+void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, const int *row_off, int nrt,
+                 const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, hipStream_t st);
 // returns the number of node parts written to unear ([part][rhs][target])
 template <typename T>
 int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
@@ -277,15 +301,13 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
-                     Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots, const Node *nodes,
-                     int nmid, int npan, double t0, int do_far, int do_near, const cx<double> *unear, int nparts,
-                     void *u, hipStream_t st);
+                     Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far,
+                     int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st);
 template <typename T>
 void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,
-                     const Geometry &g, Medium med, const cx<T> *Lc, const cx<T> *part, const int *cls_of, int nslots,
-                     const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near, double ysign,
-                     double *gout, hipStream_t st);
+                     const Geometry &g, Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0,
+                     int do_far, int do_near, double ysign, double *gout, hipStream_t st);
 void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, int nrhs, int prec,
                    const Node *nodes, int nmid, int npan, double t0, void *u, hipStream_t st);
 

@@ -189,6 +189,7 @@ struct LevelTables {
     DevBuf rowoff;                      // top level only: slots of target row r are [rowoff[r], rowoff[r+1])
     bool full = false;
     int nslots = 0;
+    int nrt = 0;  // target rows with classes (row_off has nrt + 1 entries)
     int64_t nodes = 0;
 };
 
@@ -197,6 +198,8 @@ struct VarTables {
     int t_L = -1, t_top = -1;
     double t_W = -1;
     int t_P[MAXLEV + 1] = {0};
+    std::vector<int> t_shape;  // row and column counts the class sets were built for
+    uint64_t version = 0;      // bumped on every rebuild of any table
     LevelTables lt[MAXLEV + 1];
     double table_seconds = 0;
     // near-field node table
@@ -254,13 +257,25 @@ struct lmfmm_plan_s {
 
     // per-kernel timing: an event before each timed kernel (or kernel group)
     // and one after the last; interval j is attributed to ev_tag[j]
+    // timing entries j: events ev[2j] (start) and ev[2j + 1] (stop), either
+    // stamped by the runtime at a kernel's start and end or recorded around
+    // a group of kernels (bounding box and tree build)
     static constexpr int NEV = 96;
     bool timing = false;
     bool ev_pending = false;
     hipEvent_t ev[NEV] = {};
-    int ev_tag[NEV] = {0};
-    int ev_nl[NEV] = {0};
+    int ev_tag[NEV / 2] = {0};
+    int ev_nl[NEV / 2] = {0};
     int ev_n = 0;
+
+    // replay of the apply's launch sequence as a HIP graph: captured on the
+    // second consecutive apply with the same key (geometry, pointers, sizes,
+    // tables, flags), replayed while the key stays the same
+    bool use_graph = true;
+    std::vector<uint64_t> gkey, last_key;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 
     // cached M2L pair counts per level for the last geometry
     std::vector<int64_t> pair_key;
@@ -275,11 +290,11 @@ static void collect_timing(lmfmm_plan_s *p)
         return;
     }
     const int n = p->ev_n;
-    (void)hipEventSynchronize(p->ev[n - 1]);
-    for (int j = 0; j + 1 < n; ++j) {
+    (void)hipEventSynchronize(p->ev[2 * n - 1]);
+    for (int j = 0; j < n; ++j) {
         float ms = 0.f;
         int t = p->ev_tag[j];
-        if (hipEventElapsedTime(&ms, p->ev[j], p->ev[j + 1]) == hipSuccess) p->stats.kernel_ms[t] += ms;
+        if (hipEventElapsedTime(&ms, p->ev[2 * j], p->ev[2 * j + 1]) == hipSuccess) p->stats.kernel_ms[t] += ms;
         p->stats.kernel_launches[t] += p->ev_nl[j];
     }
     p->stats.timed_applies += 1;
@@ -554,6 +569,7 @@ static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g,
     }
     row_off.push_back(slot);
     T.nslots = slot;
+    T.nrt = slot > 0 ? nrt : 0;
     T.nodes = nl.count();
     int rc;
     if ((rc = upload(T.cls, cls_index.data(), 28 * sizeof(int)))) return rc;
@@ -629,11 +645,28 @@ static int build_near_table(DevBuf &buf, const Medium &med, double dxmax, double
     return LMFMM_OK;
 }
 
+// The translation classes of a level depend on the rows next to the interface
+// (at most two per side) and, at the coarsest expansion level, on all its rows
+// and columns.
+static std::vector<int> class_shape(const Geometry &g)
+{
+    std::vector<int> k;
+    for (int l = g.ltop; l <= g.L; ++l) {
+        const Level &lv = g.lev[l];
+        if (l == g.ltop)
+            k.insert(k.end(), {lv.rows_t, lv.rows_s, lv.ncol});
+        else
+            k.insert(k.end(), {std::min(2, lv.rows_t), std::min(2, lv.rows_s)});
+    }
+    return k;
+}
+
 static int ensure_far_tables(VarTables &vt, const Medium &med, const Geometry &g)
 {
     bool same = vt.t_L == g.L && vt.t_W == g.W && vt.t_top == g.ltop;
     for (int l = 1; same && l <= g.L; ++l) same = vt.t_P[l] == g.lev[l].P;
-    if (same && vt.lt[g.ltop].full) same = vt.lt[g.ltop].nslots > 0 || g.lev[g.ltop].rows_t == 0;
+    std::vector<int> shape = class_shape(g);
+    if (same) same = shape == vt.t_shape;
     if (same) return LMFMM_OK;
     double t_start = (double)clock() / CLOCKS_PER_SEC;
     int rc;
@@ -645,6 +678,8 @@ static int ensure_far_tables(VarTables &vt, const Medium &med, const Geometry &g
     vt.t_L = g.L;
     vt.t_W = g.W;
     vt.t_top = g.ltop;
+    vt.t_shape = shape;
+    vt.version++;
     for (int l = 0; l <= MAXLEV; ++l) vt.t_P[l] = l <= g.L ? g.lev[l].P : 0;
     vt.table_seconds = (double)clock() / CLOCKS_PER_SEC - t_start;
     return LMFMM_OK;
@@ -659,6 +694,7 @@ static int ensure_near_table(VarTables &vt, const Medium &med, const Geometry &g
     double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
     int npan = std::min(64, 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0)))));
     if (vt.near_nodes.p && vt.n_h == h && vt.n_npan >= npan) return LMFMM_OK;
+    vt.version++;
     return build_near_table(vt.near_nodes, med, dxmax, amin, vt.n_c, vt.n_h, vt.n_t0, vt.n_nmid, vt.n_npan);
 }
 
@@ -733,6 +769,9 @@ int lmfmm_destroy(lmfmm_plan p)
     if (p->h_bbox) (void)hipHostFree(p->h_bbox);
     for (int i = 0; i < lmfmm_plan_s::NEV; ++i)
         if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     delete p;
     return LMFMM_OK;
 }
@@ -754,6 +793,12 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
     if (k == "fixed_order") {
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "fixed_order must be 0 or 1");
         p->fixed_order = v == "1";
+        return LMFMM_OK;
+    }
+    if (k == "graph") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "graph must be 0 or 1");
+        p->use_graph = v == "1";
+        p->last_key.clear();
         return LMFMM_OK;
     }
     if (k == "near_sweep") {
@@ -932,7 +977,6 @@ static void count_flops(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g,
         f[LMFMM_K_DOWN] += 8.0 * R * w;
     }
     p->stats.m2l_pairs = pairs;
-    f[LMFMM_K_FOLD] = 2.0 * R * vt.lt[ltop].nslots * g.lev[ltop].ncol * g.lev[ltop].nc;
     if (grad)
         f[LMFMM_K_L2P] = (double)nt * (60.0 * (lf.P + 1) + 3.0 * 8.0 * (lf.nc + 2) * R);
     else
@@ -959,17 +1003,37 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     VarTables &vt = p->vt[adj];
     collect_timing(p);
     // event before each timed kernel (group); tag -1 closes the last interval
-    auto tick = [&](int tag, int nl) {
-        if (!p->timing || p->ev_n >= lmfmm_plan_s::NEV) return;
-        if (p->ev_n > 0 && tag == LMFMM_K_TREE && p->ev_tag[p->ev_n - 1] == tag) {
-            p->ev_nl[p->ev_n - 1] += nl;
-            return;
-        }
-        p->ev_tag[p->ev_n] = tag < 0 ? LMFMM_K_OTHER : tag;
-        p->ev_nl[p->ev_n] = nl;
-        (void)hipEventRecord(p->ev[p->ev_n++], st);
+    // timed kernel: its start/stop events ride on its own launch; a group
+    // (bounding box and tree build) is bracketed by recorded events
+    auto timed = [&](int tag, int nl) {
+        if (!p->timing || p->ev_n >= lmfmm_plan_s::NEV / 2) return;
+        const int j = p->ev_n;
+        p->ev_tag[j] = tag;
+        p->ev_nl[j] = nl;
+        launch_timing() = {p->ev[2 * j], p->ev[2 * j + 1]};
     };
-    tick(LMFMM_K_TREE, p->have_domain || p->have_box ? 0 : 2);
+    auto timed_done = [&]() {  // after the launcher: keep the entry only if a kernel took the events
+        LaunchTiming &lt = launch_timing();
+        if (!p->timing || p->ev_n >= lmfmm_plan_s::NEV / 2) return;
+        if (lt.start)
+            lt = LaunchTiming{};
+        else
+            ++p->ev_n;
+    };
+    auto group_begin = [&](int tag, hipStream_t sx) {
+        if (!p->timing || p->ev_n >= lmfmm_plan_s::NEV / 2) return;
+        p->ev_tag[p->ev_n] = tag;
+        p->ev_nl[p->ev_n] = 0;
+        (void)hipEventRecord(p->ev[2 * p->ev_n], sx);
+    };
+    auto group_end = [&](int nl, hipStream_t sx) {
+        if (!p->timing || p->ev_n >= lmfmm_plan_s::NEV / 2) return;
+        p->ev_nl[p->ev_n] = nl;
+        (void)hipEventRecord(p->ev[2 * p->ev_n + 1], sx);
+        ++p->ev_n;
+    };
+    const bool have_bb = p->have_domain || (p->have_box && !adj);
+    group_begin(LMFMM_K_TREE, st);
     double bb[8];
     if ((rc = get_bbox(p, med, ns, src, nt, tgt, st, bb))) return rc;
     Geometry &g = p->geo;
@@ -990,13 +1054,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     size_t need = 0;
     need += 2 * (size_t)n * 4 + 2 * (size_t)n * 4 + (size_t)256 * nblk * 4 + 2 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
     need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 20 * 256;
-    int64_t part_off[MAXLEV + 2] = {0};
     const int ltop = g.ltop;
-    for (int l = 0; l < ltop && l <= MAXLEV; ++l) part_off[l + 1] = 0;
-    for (int l = ltop; l <= L && far; ++l)
-        part_off[l + 1] = part_off[l] + (int64_t)vt.lt[l].nslots * g.lev[l].ncol * nrhs * g.lev[l].nc;
-    int64_t npart = far ? part_off[L + 1] : 0;
-    need += (size_t)npart * sizeof(cx<T>);
     // near-field sweep results: up to 4 node parts x nrhs x targets (FP64)
     const bool sweep = p->do_near && p->near_sweep && !gw;
     int64_t nun = sweep ? (int64_t)4 * nrhs * nt : 0;
@@ -1016,70 +1074,134 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     cx<T> *Lc = cv.take<cx<T>>(g.ncoef_t > 0 ? g.ncoef_t : 1);
     int32_t *err = cv.take<int32_t>(1);
     p->d_err = err;
-    cx<T> *part = cv.take<cx<T>>(npart > 0 ? npart : 1);
     cx<double> *unear = sweep ? cv.take<cx<double>>(nun) : nullptr;
 
-    // Step 1: tree
-    tick(LMFMM_K_TREE, 5 + 3 * ((nbits(nbox) + 7) / 8));
-    launch_fill_i32(err, 1, 0, st);
-    launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
-                yt_limit(med), sb.key_a, sb.idx_a, err, st);
-    int which = launch_radix_sort(sb, n, nbits(nbox), st);
-    uint32_t *key = which ? sb.key_b : sb.key_a;
-    int32_t *idx = which ? sb.idx_b : sb.idx_a;
-    launch_leaf_ranges(key, idx, n, nbox, start, end, src, ns, tgt, nt, xs, ys, st);
+    // the launch sequence (Steps 1-4) on stream sx
+    auto launch_all = [&](hipStream_t sx) {
+        // Step 1: tree
+        launch_fill_i32(err, 1, 0, sx);
+        launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
+                    yt_limit(med), sb.key_a, sb.idx_a, err, sx);
+        int which = launch_radix_sort(sb, n, nbits(nbox), sx);
+        uint32_t *key = which ? sb.key_b : sb.key_a;
+        int32_t *idx = which ? sb.idx_b : sb.idx_a;
+        launch_leaf_ranges(key, idx, n, nbox, start, end, src, ns, tgt, nt, xs, ys, sx);
+        group_end((have_bb ? 0 : 3) + 5 + 3 * ((nbits(nbox) + 7) / 8), sx);
 
-    // Step 2: upward pass
-    if (far) {
-        tick(LMFMM_K_P2M, 1);
-        launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, st);
-        for (int l = L; l >= ltop + 1; --l) {
-            const LevelTables &tb = vt.lt[l];
-            const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
-            tick(LMFMM_K_M2M, 1);
-            launch_m2m<T>(g, l, tab, M, nrhs, st);
-        }
-        // Step 3: downward pass
-        for (int l = ltop; l <= L; ++l) {
-            const LevelTables &tb = vt.lt[l], &tp = vt.lt[l - 1];
-            const cx<T> *atab = (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p);
-            const cx<T> *l2l = nullptr;
-            if (l > ltop) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
-            // the parent's M2L partials are pending unless it is the top level (folded there)
-            bool pend_p = l - 1 > ltop;
-            tick(LMFMM_K_DOWN, 1);
-            launch_down<T>(g, l, tb.nslots, pend_p ? tp.nslots : 0, atab, (const int *)tb.clsof.p,
-                           pend_p ? tp.clsof_host.data() : nullptr, M, Lc, part + part_off[l],
-                           part + part_off[l > ltop ? l - 1 : l], nrhs, l2l, l == ltop, st);
-            if (l == ltop) {
-                tick(LMFMM_K_FOLD, 1);
-                launch_fold_top<T>(g, l, part + part_off[l], (const int *)tb.rowoff.p, Lc, nrhs, st);
+        // Step 2: upward pass
+        if (far) {
+            timed(LMFMM_K_P2M, 1);
+            launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, sx);
+            timed_done();
+            for (int l = L; l >= ltop + 1; --l) {
+                const LevelTables &tb = vt.lt[l];
+                const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
+                timed(LMFMM_K_M2M, 1);
+                launch_m2m<T>(g, l, tab, M, nrhs, sx);
+                timed_done();
+            }
+            // Step 3: downward pass
+            for (int l = ltop; l <= L; ++l) {
+                const LevelTables &tb = vt.lt[l];
+                const cx<T> *atab = tb.nslots > 0 ? (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p) : nullptr;
+                const cx<T> *l2l = nullptr;
+                if (l > ltop) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
+                timed(LMFMM_K_DOWN, 1);
+                launch_down<T>(g, l, atab, (const int *)tb.clsof.p, (const int *)tb.rowoff.p, tb.nrt, M, Lc, nrhs, l2l,
+                               l == ltop, sx);
+                timed_done();
             }
         }
-    }
-    // Step 4: local evaluation and direct interactions
-    const int *clsL = (far && L > ltop) ? vt.lt[L].clsof_host.data() : nullptr;
-    int nsL = (far && L > ltop) ? vt.lt[L].nslots : 0;
-    const Node *nnodes = (const Node *)vt.near_nodes.p;
-    int nparts = 0;
-    if (!gw) {
-        if (sweep) {
-            tick(LMFMM_K_SWEEP, 1);
-            nparts = launch_near_sweep<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, nnodes, vt.n_nmid, vt.n_npan,
-                                          vt.n_t0, unear, st);
+        // Step 4: local evaluation and direct interactions
+        const Node *nnodes = (const Node *)vt.near_nodes.p;
+        int nparts = 0;
+        if (!gw) {
+            if (sweep) {
+                timed(LMFMM_K_SWEEP, 1);
+                nparts = launch_near_sweep<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, nnodes, vt.n_nmid, vt.n_npan,
+                                              vt.n_t0, unear, sx);
+                timed_done();
+            }
+            timed(LMFMM_K_L2P, 1);
+            launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nnodes, vt.n_nmid, vt.n_npan,
+                               vt.n_t0, far ? 1 : 0, p->do_near ? 1 : 0, nparts ? unear : nullptr, nparts, u, sx);
+            timed_done();
+        } else {
+            timed(LMFMM_K_L2P, 1);  // the first right-hand-side chunk
+            launch_l2p_grad<T>(start, end, idx, xs, ys, q, gw, ns, nt, nrhs, g, med, Lc, nnodes, vt.n_nmid, vt.n_npan,
+                               vt.n_t0, far ? 1 : 0, p->do_near ? 1 : 0, ysign, gout, sx);
+            timed_done();
         }
-        tick(LMFMM_K_L2P, 1);
-        launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
-                           nnodes, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0, p->do_near ? 1 : 0,
-                           nparts ? unear : nullptr, nparts, u, st);
-    } else {
-        tick(LMFMM_K_L2P, (nrhs + 7) / 8);
-        launch_l2p_grad<T>(start, end, idx, xs, ys, q, gw, ns, nt, nrhs, g, med, Lc, part + part_off[L], clsL, nsL,
-                           nnodes, vt.n_nmid, vt.n_npan, vt.n_t0, far ? 1 : 0, p->do_near ? 1 : 0, ysign, gout, st);
+    };
+    // key of everything the launch sequence bakes into its kernel arguments
+    std::vector<uint64_t> key;
+    {
+        auto put = [&](uint64_t v) { key.push_back(v); };
+        auto putp = [&](const void *ptr) { put((uint64_t)(uintptr_t)ptr); };
+        uint64_t ys_bits;
+        std::memcpy(&ys_bits, &ysign, 8);
+        put(sizeof(T));
+        put((uint64_t)adj);
+        putp(src);
+        putp(q);
+        putp(tgt);
+        putp(u);
+        putp(gw);
+        putp(gout);
+        put(ys_bits);
+        put((uint64_t)ns);
+        put((uint64_t)nt);
+        put((uint64_t)nrhs);
+        putp(p->ws.p);
+        put(vt.version);
+        put((uint64_t)far | (uint64_t)p->do_near << 1 | (uint64_t)sweep << 2);
+        std::vector<uint64_t> gb((sizeof(Geometry) + 7) / 8, 0);
+        std::memcpy(gb.data(), &g, sizeof(Geometry));
+        key.insert(key.end(), gb.begin(), gb.end());
     }
-    tick(-1, 0);
+    // (timing mode launches kernel by kernel: the events ride on the launches)
+    const bool graph_ok = p->use_graph && !p->timing;
+    if (graph_ok && p->gexec && key == p->gkey) {
+        // replay
+        HIPCHK(hipGraphLaunch(p->gexec, st));
+        p->stats.graph_applies++;
+    } else if (graph_ok && key == p->last_key) {
+        // second apply with this key: capture it on the plan's stream and replay
+        if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+        p->gkey.clear();
+        if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+        bool ok = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            launch_all(p->cap);
+            hipGraph_t gr = nullptr;
+            ok = hipStreamEndCapture(p->cap, &gr) == hipSuccess && gr;
+            if (ok) ok = hipGraphInstantiate(&p->gexec, gr, nullptr, nullptr, 0) == hipSuccess;
+            if (ok) {
+                p->graph = gr;
+                p->gkey = key;
+            } else {
+                if (gr) (void)hipGraphDestroy(gr);
+                p->gexec = nullptr;
+            }
+        }
+        (void)hipGetLastError();
+        if (ok) {
+            HIPCHK(hipGraphLaunch(p->gexec, st));
+            p->stats.graph_applies++;
+        } else {
+            // capture is not available here: stay with direct launches for this key
+            p->use_graph = false;
+            launch_all(st);
+        }
+    } else {
+        p->last_key = key;
+        launch_all(st);
+    }
     HIPCHK(hipGetLastError());
-    if (p->ev_n > 0) p->ev_pending = true;
+    if (p->ev_n > 0 && p->timing) p->ev_pending = true;
 
     // statistics (host-side counts)
     lmfmm_stats &s = p->stats;
@@ -1407,6 +1529,7 @@ int lmfmm_batch_create(int n_inst, const double *k, const double *d, const int *
             delete b;
             return rc;
         }
+        p->use_graph = false;  // the batch captures its instances' launches itself
         b->plans.push_back(p);
     }
     *out = b;

@@ -35,11 +35,11 @@ class Stats(ctypes.Structure):
                 ("near_nodes_ray", ctypes.c_int), ("m2l_classes", ctypes.c_int), ("m2l_nodes", ctypes.c_int64),
                 ("table_seconds", ctypes.c_double), ("kernel_flops", ctypes.c_double * 8),
                 ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_int64 * 8),
-                ("timed_applies", ctypes.c_int64)]
+                ("timed_applies", ctypes.c_int64), ("graph_applies", ctypes.c_int64)]
 
 
 # kernel indices of Stats.kernel_* (LMFMM_K_* in lmfmm.h)
-KERNELS = ["tree", "p2m", "m2m", "m2l_l2l", "fold_top", "near_sweep", "l2p_near", "other"]
+KERNELS = ["tree", "p2m", "m2m", "m2l_l2l", "near_sweep", "l2p_near", "other", "unused"]
 
 
 class Instance(ctypes.Structure):

@@ -196,3 +196,60 @@ def test_edge_cases(torch_cuda, plain, orc):
     bad[1, 5] = 0.2
     with pytest.raises(LMFMMError):
         pl.apply(src, q, dev(bad))
+
+
+def test_table_cache_follows_row_counts(torch_cuda, plain, orc):
+    """Two applies on one plan with the same root width and levels but point
+    sets of different depth: the second must match a fresh plan (the class
+    sets of the interface rows and of the coarsest level differ)."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("table cache: shallow then deep point sets, same root width")
+    rng = np.random.default_rng(11)
+    k, d = plain["k"], plain["d"]
+    s1, t1, q1, _ = workloads.draw_instance(rng, 3000, 2000, (0, 1), (0.05, 0.1), (-0.1, -0.05), 1)
+    s2, t2, q2, _ = workloads.draw_instance(rng, 3000, 2000, (0, 1), (0.05, 0.45), (-0.45, -0.05), 1)
+    pl = Plan(k, d, order=20, tol=1e-10, levels=4)
+    pl.apply(dev(s1), dev(q1), dev(t1))
+    u_reused = host(pl.apply(dev(s2), dev(q2), dev(t2)))
+    u_fresh = host(Plan(k, d, order=20, tol=1e-10, levels=4).apply(dev(s2), dev(q2), dev(t2)))
+    assert np.array_equal(u_reused, u_fresh)
+    sel = np.arange(0, 2000, 100)
+    ref = orc.apply(s2, q2, t2[:, sel], k, d)
+    err = rel(u_reused[:, sel], ref)
+    say("rel-l2 vs oracle", err)
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_graph_replay_matches_direct(torch_cuda, mid, precision):
+    """Repeated applies on fixed buffers: the first launches kernel by kernel,
+    the second captures a HIP graph, later ones replay it.  The densities are
+    rewritten in place between applies (eager work and a synchronisation in
+    between); every replay must equal the kernel-by-kernel result bit for bit."""
+    import torch
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("graph replay vs direct launches", precision)
+    dt = np.complex128 if precision == "c128" else np.complex64
+    tol = 1e-10 if precision == "c128" else 1e-6
+    pl = Plan(mid["k"], mid["d"], order=16, tol=tol, levels=5)
+    ref_pl = Plan(mid["k"], mid["d"], order=16, tol=tol, levels=5)
+    ref_pl.set_option("graph", "0")
+    src, tgt = dev(mid["src"]), dev(mid["tgt"])
+    q = dev(mid["q"][:3].astype(dt))
+    u = torch.empty((3, tgt.shape[1]), dtype=q.dtype, device="cuda")
+    rng = np.random.default_rng(8)
+    for it in range(7):
+        if it == 5:  # timing mode launches kernel by kernel with per-kernel events
+            pl.set_option("timing", "1")
+        new = rng.standard_normal((3, src.shape[1])) + 1j * rng.standard_normal((3, src.shape[1]))
+        q.copy_(torch.from_numpy(new.astype(dt)).cuda())
+        torch.cuda.synchronize()
+        pl.apply(src, q, tgt, out=u)
+        got = host(u)
+        want = host(ref_pl.apply(src, q, tgt))
+        assert np.array_equal(got, want), f"apply {it}"
+    st = pl.stats()
+    say("timed applies", st["timed_applies"], "graph applies", st["graph_applies"], "k_down ms",
+        st["kernel_ms"]["m2l_l2l"])
+    assert st["kernel_ms"]["m2l_l2l"] > 0
+    assert st["graph_applies"] == 4 and st["timed_applies"] == 2
