@@ -260,8 +260,11 @@ constexpr int NGL = 16;  // Gauss-Legendre points per panel
 // ---------------------------------------------------------------------------
 // tree.hip
 // sources must satisfy 0 < y < ys_lim, targets yt_lim < y < 0
+// bounding box and bad-point count of both point sets in one launch: the last
+// block writes out[0..6] and then the 64-bit sequence number seq at out + 8
+// (host-mapped memory) and rearms counter (zero between launches)
 void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
-                 double *partial, int nblk, double *out, hipStream_t st);
+                 double *partial, unsigned *counter, int nblk, double *out, uint64_t seq, hipStream_t st);
 void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st);
 int bbox_blocks(int64_t n);
 struct SortBufs {
@@ -277,6 +280,8 @@ void launch_leaf_ranges(const uint32_t *key, const int32_t *idx, int64_t n, int6
                         int32_t *end, const double *src, int64_t ns, const double *tgt, int64_t nt, double *xs,
                         double *ys, hipStream_t st);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+// zero three int32 ranges in one launch
+void launch_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb, int32_t *c, int64_t nc, hipStream_t st);
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 void launch_keys(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
                  int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, uint32_t *key, int32_t *idx,

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <immintrin.h>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -238,8 +241,10 @@ struct lmfmm_plan_s {
     bool near_sweep = true;  // near field by x-ordered sweeps (else pairwise)
 
     DevBuf ws;
-    double *h_bbox = nullptr;  // pinned
-    DevBuf bbox_dev;
+    double *h_bbox = nullptr;  // pinned, host-coherent: [0..6] box, [8] sequence number, [12] error copy
+    double *d_bbox = nullptr;  // its device address
+    uint64_t bbox_seq = 0;
+    DevBuf bbox_dev;           // per-block partials [512][8], then the block counter
 
     // cached tables of the forward (0) and transposed (1) operator
     VarTables vt[2];
@@ -743,14 +748,19 @@ int lmfmm_create(const double k[6], double d, int order, double tol, lmfmm_plan 
     p->order = order;
     p->tol = tol;
     std::memset(&p->stats, 0, sizeof(p->stats));
-    if (hipHostMalloc((void **)&p->h_bbox, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&p->h_bbox, 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&p->d_bbox, p->h_bbox, 0) != hipSuccess) {
+        if (p->h_bbox) (void)hipHostFree(p->h_bbox);
         delete p;
         return fail(LMFMM_ENOMEM, "pinned allocation failed");
     }
-    if (p->bbox_dev.ensure(8 * 520 * sizeof(double))) {
+    std::memset(p->h_bbox, 0, 16 * sizeof(double));
+    if (p->bbox_dev.ensure(8 * 520 * sizeof(double)) ||
+        hipMemset(p->bbox_dev.p, 0, 8 * 520 * sizeof(double)) != hipSuccess) {
         (void)hipHostFree(p->h_bbox);
         delete p;
-        return LMFMM_ENOMEM;
+        return fail(LMFMM_ENOMEM, "device allocation failed");
     }
     *out = p;
     return LMFMM_OK;
@@ -903,12 +913,26 @@ static int get_bbox(lmfmm_plan p, const Medium &med, int64_t ns, const double *s
     }
     int64_t n = ns + nt;
     int nblk = bbox_blocks(n);
-    double *part = (double *)p->bbox_dev.p, *outp = part + 8 * 512;
-    launch_bbox(src, ns, tgt, nt, ys_limit(med), yt_limit(med), part, nblk, outp, st);
+    double *part = (double *)p->bbox_dev.p;
+    unsigned *counter = (unsigned *)(part + 8 * 512);
+    const uint64_t seq = ++p->bbox_seq;
+    launch_bbox(src, ns, tgt, nt, ys_limit(med), yt_limit(med), part, counter, nblk, p->d_bbox, seq, st);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(p->h_bbox, outp, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    std::memcpy(bb, p->h_bbox, 8 * sizeof(double));
+    // the kernel writes the result into host-coherent memory: spin on its
+    // sequence number (a short wait in the usual case), else synchronize
+    volatile uint64_t *flag = reinterpret_cast<volatile uint64_t *>(p->h_bbox + 8);
+    const auto t0 = std::chrono::steady_clock::now();
+    while (*flag != seq) {
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+            HIPCHK(hipStreamSynchronize(st));
+            break;
+        }
+        _mm_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    if (*flag != seq) return fail(LMFMM_EHIP, "bounding-box result did not arrive");
+    std::memcpy(bb, p->h_bbox, 7 * sizeof(double));
+    bb[7] = 0.0;
     if (bb[6] > 0) return fail(LMFMM_EDOMAIN, std::to_string((long long)bb[6]) + " point(s) outside their layer");
     return LMFMM_OK;
 }
@@ -1056,7 +1080,9 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 20 * 256;
     const int ltop = g.ltop;
     // near-field sweep results: up to 4 node parts x nrhs x targets (FP64)
-    const bool sweep = p->do_near && p->near_sweep && !gw;
+    // direct interactions exist only between row-0 leaves on both sides
+    const bool near_on = p->do_near && !(bb[2] >= lv.w) && !(bb[5] <= -lv.w);
+    const bool sweep = near_on && p->near_sweep && !gw;
     int64_t nun = sweep ? (int64_t)4 * nrhs * nt : 0;
     need += (size_t)nun * sizeof(cx<double>) + 256;
     if ((rc = p->ws.ensure(need))) return rc;
@@ -1079,7 +1105,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     // the launch sequence (Steps 1-4) on stream sx
     auto launch_all = [&](hipStream_t sx) {
         // Step 1: tree
-        launch_fill_i32(err, 1, 0, sx);
+        launch_zero3(err, 1, start, nbox, end, nbox, sx);
         launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
                     yt_limit(med), sb.key_a, sb.idx_a, err, sx);
         int which = launch_radix_sort(sb, n, nbits(nbox), sx);
@@ -1124,12 +1150,12 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             }
             timed(LMFMM_K_L2P, 1);
             launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nnodes, vt.n_nmid, vt.n_npan,
-                               vt.n_t0, far ? 1 : 0, p->do_near ? 1 : 0, nparts ? unear : nullptr, nparts, u, sx);
+                               vt.n_t0, far ? 1 : 0, near_on ? 1 : 0, nparts ? unear : nullptr, nparts, u, sx);
             timed_done();
         } else {
             timed(LMFMM_K_L2P, 1);  // the first right-hand-side chunk
             launch_l2p_grad<T>(start, end, idx, xs, ys, q, gw, ns, nt, nrhs, g, med, Lc, nnodes, vt.n_nmid, vt.n_npan,
-                               vt.n_t0, far ? 1 : 0, p->do_near ? 1 : 0, ysign, gout, sx);
+                               vt.n_t0, far ? 1 : 0, near_on ? 1 : 0, ysign, gout, sx);
             timed_done();
         }
     };
@@ -1154,7 +1180,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         put((uint64_t)nrhs);
         putp(p->ws.p);
         put(vt.version);
-        put((uint64_t)far | (uint64_t)p->do_near << 1 | (uint64_t)sweep << 2);
+        put((uint64_t)far | (uint64_t)near_on << 1 | (uint64_t)sweep << 2);
         std::vector<uint64_t> gb((sizeof(Geometry) + 7) / 8, 0);
         std::memcpy(gb.data(), &g, sizeof(Geometry));
         key.insert(key.end(), gb.begin(), gb.end());
@@ -1329,10 +1355,10 @@ int lmfmm_sync_status(lmfmm_plan p, void *stream)
     if (!p) return fail(LMFMM_EINVAL, "plan is null");
     hipStream_t st = (hipStream_t)stream;
     if (p->d_err) {
-        HIPCHK(hipMemcpyAsync(p->h_bbox + 8, p->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(p->h_bbox + 12, p->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         int32_t e;
-        std::memcpy(&e, p->h_bbox + 8, sizeof e);
+        std::memcpy(&e, p->h_bbox + 12, sizeof e);
         if (e) return fail(LMFMM_EDOMAIN, "a point lies outside the domain or its layer");
         return LMFMM_OK;
     }

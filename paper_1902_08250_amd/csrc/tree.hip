@@ -36,8 +36,8 @@ __device__ inline double wave_sum(double v)
 // target y min/max; count of points outside their layer or not finite.
 __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__restrict__ src, int64_t ns,
                                                              const double *__restrict__ tgt, int64_t nt,
-                                                             double ys_lim, double yt_lim,
-                                                             double *__restrict__ partial)
+                                                             double ys_lim, double yt_lim, double *partial,
+                                                             unsigned *counter, double *out, uint64_t seq)
 {
     double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -78,6 +78,7 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
     if (lane == 0)
         for (int j = 0; j < 7; ++j) red[wv][j] = r[j];
     __syncthreads();
+    __shared__ int last;
     if (threadIdx.x == 0) {
         for (int w = 1; w < BB_THREADS / 64; ++w) {
             r[0] = fmin(r[0], red[w][0]);
@@ -88,36 +89,41 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
             r[5] = fmax(r[5], red[w][5]);
             r[6] += red[w][6];
         }
-        for (int j = 0; j < 7; ++j) partial[blockIdx.x * 8 + j] = r[j];
+        for (int j = 0; j < 7; ++j)
+            __hip_atomic_store(&partial[blockIdx.x * 8 + j], r[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = t == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x >= 64) return;
+    // the last block to finish: reduce the partials of all blocks
+    double v2[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) {
+        double q[7];
+        for (int j = 0; j < 7; ++j) q[j] = __hip_atomic_load(&partial[b * 8 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v2[0] = fmin(v2[0], q[0]);
+        v2[1] = fmax(v2[1], q[1]);
+        v2[2] = fmin(v2[2], q[2]);
+        v2[3] = fmax(v2[3], q[3]);
+        v2[4] = fmin(v2[4], q[4]);
+        v2[5] = fmax(v2[5], q[5]);
+        v2[6] += q[6];
+    }
+    v2[0] = wave_min(v2[0]);
+    v2[1] = wave_max(v2[1]);
+    v2[2] = wave_min(v2[2]);
+    v2[3] = wave_max(v2[3]);
+    v2[4] = wave_min(v2[4]);
+    v2[5] = wave_max(v2[5]);
+    v2[6] = wave_sum(v2[6]);
+    if (threadIdx.x == 0) {
+        // result, then its sequence number, in host-visible memory; rearm the counter
+        for (int j = 0; j < 7; ++j) __hip_atomic_store(&out[j], v2[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(reinterpret_cast<uint64_t *>(out + 8), seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-__global__ void __launch_bounds__(64) k_bbox_final(const double *__restrict__ partial, int nblk,
-                                                   double *__restrict__ out)
-{
-    double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
-    for (int b = threadIdx.x; b < nblk; b += 64) {
-        const double *p = partial + b * 8;
-        v[0] = fmin(v[0], p[0]);
-        v[1] = fmax(v[1], p[1]);
-        v[2] = fmin(v[2], p[2]);
-        v[3] = fmax(v[3], p[3]);
-        v[4] = fmin(v[4], p[4]);
-        v[5] = fmax(v[5], p[5]);
-        v[6] += p[6];
-    }
-    v[0] = wave_min(v[0]);
-    v[1] = wave_max(v[1]);
-    v[2] = wave_min(v[2]);
-    v[3] = wave_max(v[3]);
-    v[4] = wave_min(v[4]);
-    v[5] = wave_max(v[5]);
-    v[6] = wave_sum(v[6]);
-    if (threadIdx.x == 0) {
-        for (int j = 0; j < 7; ++j) out[j] = v[j];
-        out[7] = 0.0;
-    }
-}
 
 // Leaf key of every point.  Sources (y > 0) take row floor(y/w) above the
 // interface, targets row floor(-y/w) below it; columns are relative to
@@ -288,11 +294,10 @@ int bbox_blocks(int64_t n)
 }
 
 void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
-                 double *partial, int nblk, double *out, hipStream_t st)
+                 double *partial, unsigned *counter, int nblk, double *out, uint64_t seq, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(BB_THREADS), 0, st, src, ns, tgt, nt, ys_lim, yt_lim,
-                       partial);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, partial, nblk, out);
+                       partial, counter, out, seq);
 }
 
 void launch_keys(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
@@ -344,6 +349,25 @@ int launch_radix_sort(SortBufs &b, int64_t n, int bits, hipStream_t st)
     return (passes & 1) ? 1 : 0;
 }
 
+__global__ void __launch_bounds__(256) k_zero3(int32_t *__restrict__ a, int64_t na, int32_t *__restrict__ b,
+                                               int64_t nb, int32_t *__restrict__ c, int64_t nc)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < na)
+        a[i] = 0;
+    else if (i < na + nb)
+        b[i - na] = 0;
+    else if (i < na + nb + nc)
+        c[i - na - nb] = 0;
+}
+
+void launch_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb, int32_t *c, int64_t nc, hipStream_t st)
+{
+    int64_t n = na + nb + nc;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, na, b, nb, c, nc);
+}
+
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
 {
     if (n <= 0) return;
@@ -361,8 +385,6 @@ void launch_leaf_ranges(const uint32_t *key, const int32_t *idx, int64_t n, int6
                         int32_t *end, const double *src, int64_t ns, const double *tgt, int64_t nt, double *xs,
                         double *ys, hipStream_t st)
 {
-    launch_fill_i32(start, nbox, 0, st);
-    launch_fill_i32(end, nbox, 0, st);
     if (n == 0) return;
     hipLaunchKernelGGL(k_leaf_ranges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, key, idx, n, start, end,
                        src, ns, tgt, nt, xs, ys);
