@@ -267,25 +267,23 @@ void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, d
                  double *partial, unsigned *counter, int nblk, double *out, uint64_t seq, hipStream_t st);
 void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st);
 int bbox_blocks(int64_t n);
-struct SortBufs {
-    uint32_t *key_a, *key_b;
-    int32_t *idx_a, *idx_b;
-    uint32_t *hist;  // 256 * nblk
-    int nblk;
+// Points grouped by leaf (counting sort; every leaf in increasing original
+// index).  cnt: nbox counts, zero on entry.  Results: start/end[nbox] (leaf
+// ranges in the grouped order), idx[n] (original index, targets offset by
+// n_src), xs/ys[n] (grouped coordinates).  key, perm: n; scratch: 2n.
+struct TreeBufs {
+    uint32_t *key;
+    int32_t *cnt, *start, *end, *perm, *scratch, *idx;
+    double *xs, *ys;
 };
-int sort_blocks(int64_t n);
-// returns 0 if the result ends in key_a/idx_a, 1 if in key_b/idx_b
-int launch_radix_sort(SortBufs &b, int64_t n, int bits, hipStream_t st);
-void launch_leaf_ranges(const uint32_t *key, const int32_t *idx, int64_t n, int64_t nbox, int32_t *start,
-                        int32_t *end, const double *src, int64_t ns, const double *tgt, int64_t nt, double *xs,
-                        double *ys, hipStream_t st);
+void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
+                 int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, const TreeBufs &b, int32_t *err,
+                 hipStream_t st);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 // zero three int32 ranges in one launch
 void launch_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb, int32_t *c, int64_t nc, hipStream_t st);
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
-void launch_keys(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
-                 int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, uint32_t *key, int32_t *idx,
-                 int32_t *err, hipStream_t st);
+
 
 // expand.hip (T = double or float)
 template <typename T>

@@ -307,13 +307,6 @@ static void collect_timing(lmfmm_plan_s *p)
     p->ev_n = 0;
 }
 
-static int nbits(int64_t n)
-{
-    int b = 1;
-    while (((int64_t)1 << b) < n) ++b;
-    return b;
-}
-
 static double kmax_re(const Medium &m) { return std::max(m.k1.re, std::max(m.k2.re, m.k3.re)); }
 static double contour_c(const Medium &m) { return std::max(1.0, 1.25 * kmax_re(m)); }
 
@@ -1074,9 +1067,8 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     const Level &lv = g.lev[L];
     int64_t n = ns + nt;
     int64_t nbox = (int64_t)(lv.rows_s + lv.rows_t) * lv.ncol;
-    int nblk = sort_blocks(n);
     size_t need = 0;
-    need += 2 * (size_t)n * 4 + 2 * (size_t)n * 4 + (size_t)256 * nblk * 4 + 2 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
+    need += 5 * (size_t)n * 4 + 3 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
     need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 20 * 256;
     const int ltop = g.ltop;
     // near-field sweep results: up to 4 node parts x nrhs x targets (FP64)
@@ -1087,15 +1079,18 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     need += (size_t)nun * sizeof(cx<double>) + 256;
     if ((rc = p->ws.ensure(need))) return rc;
     Carve cv{(char *)p->ws.p};
-    SortBufs sb;
-    sb.key_a = cv.take<uint32_t>(n);
-    sb.key_b = cv.take<uint32_t>(n);
-    sb.idx_a = cv.take<int32_t>(n);
-    sb.idx_b = cv.take<int32_t>(n);
-    sb.hist = cv.take<uint32_t>((size_t)256 * nblk);
-    sb.nblk = nblk;
-    int32_t *start = cv.take<int32_t>(nbox), *end = cv.take<int32_t>(nbox);
-    double *xs = cv.take<double>(n), *ys = cv.take<double>(n);
+    TreeBufs tb;
+    tb.key = cv.take<uint32_t>(n);
+    tb.perm = cv.take<int32_t>(n);
+    tb.scratch = cv.take<int32_t>(2 * n);
+    tb.idx = cv.take<int32_t>(n);
+    tb.cnt = cv.take<int32_t>(nbox);
+    tb.start = cv.take<int32_t>(nbox);
+    tb.end = cv.take<int32_t>(nbox);
+    tb.xs = cv.take<double>(n);
+    tb.ys = cv.take<double>(n);
+    int32_t *start = tb.start, *end = tb.end, *idx = tb.idx;
+    double *xs = tb.xs, *ys = tb.ys;
     cx<T> *M = cv.take<cx<T>>(g.ncoef_s > 0 ? g.ncoef_s : 1);
     cx<T> *Lc = cv.take<cx<T>>(g.ncoef_t > 0 ? g.ncoef_t : 1);
     int32_t *err = cv.take<int32_t>(1);
@@ -1105,14 +1100,10 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     // the launch sequence (Steps 1-4) on stream sx
     auto launch_all = [&](hipStream_t sx) {
         // Step 1: tree
-        launch_zero3(err, 1, start, nbox, end, nbox, sx);
-        launch_keys(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
-                    yt_limit(med), sb.key_a, sb.idx_a, err, sx);
-        int which = launch_radix_sort(sb, n, nbits(nbox), sx);
-        uint32_t *key = which ? sb.key_b : sb.key_a;
-        int32_t *idx = which ? sb.idx_b : sb.idx_a;
-        launch_leaf_ranges(key, idx, n, nbox, start, end, src, ns, tgt, nt, xs, ys, sx);
-        group_end((have_bb ? 0 : 3) + 5 + 3 * ((nbits(nbox) + 7) / 8), sx);
+        launch_zero3(err, 1, tb.cnt, nbox, nullptr, 0, sx);
+        launch_tree(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
+                    yt_limit(med), tb, err, sx);
+        group_end((have_bb ? 0 : 1) + 5, sx);
 
         // Step 2: upward pass
         if (far) {
@@ -1132,6 +1123,12 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 const cx<T> *atab = tb.nslots > 0 ? (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p) : nullptr;
                 const cx<T> *l2l = nullptr;
                 if (l > ltop) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
+                if (!atab && !l2l) {
+                    // coarsest level without translation classes: no far field reaches it
+                    const Level &lt = g.lev[l];
+                    launch_zero_bytes(Lc + lt.off_t, (size_t)lt.rows_t * lt.ncol * nrhs * lt.nc * sizeof(cx<T>), sx);
+                    continue;
+                }
                 timed(LMFMM_K_DOWN, 1);
                 launch_down<T>(g, l, atab, (const int *)tb.clsof.p, (const int *)tb.rowoff.p, tb.nrt, M, Lc, nrhs, l2l,
                                l == ltop, sx);

@@ -1,10 +1,14 @@
 // Quadtree construction (Algorithm 1, Step 1): bounding box and layer checks,
-// leaf keys, a stable LSD radix sort of the keys, and leaf ranges.
+// leaf keys, and the points grouped by leaf.
 //
 // The tree is uniform with its root square split at the interface y = 0, so
 // every box holds either sources (above) or targets (below).  A leaf key is
 // (row, column) of the level-L box; target keys follow all source keys, so one
-// sort orders both point sets and the sorted array holds sources first.
+// grouping orders both point sets and the grouped array holds sources first.
+// Grouping is a counting sort: per-leaf counts (atomics), one exclusive scan
+// for the leaf ranges, a scatter (atomic cursors), and a per-leaf sort of the
+// scattered original indices, so that every leaf lists its points in
+// increasing original index whatever order the atomics took.
 #include "lmfmm_internal.h"
 
 namespace lmfmm {
@@ -12,9 +16,6 @@ namespace lmfmm {
 namespace {
 
 constexpr int BB_THREADS = 256;
-constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 8;
-constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 
 __device__ inline double wave_min(double v)
 {
@@ -129,11 +130,11 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
 // interface, targets row floor(-y/w) below it; columns are relative to
 // col_lo.  Out-of-range rows/columns (points outside a fixed domain) and
 // points in the wrong layer raise the error flag and are clamped.
-__global__ void __launch_bounds__(256) k_keys(const double *__restrict__ src, int64_t ns,
-                                              const double *__restrict__ tgt, int64_t nt, double x_lo, double invw,
-                                              int col_lo, int ncol, int rows_s, int rows_t, double ys_lim,
-                                              double yt_lim, uint32_t *__restrict__ key,
-                                              int32_t *__restrict__ idx, int32_t *__restrict__ err)
+__global__ void __launch_bounds__(256) k_tree_count(const double *__restrict__ src, int64_t ns,
+                                                    const double *__restrict__ tgt, int64_t nt, double x_lo,
+                                                    double invw, int col_lo, int ncol, int rows_s, int rows_t,
+                                                    double ys_lim, double yt_lim, uint32_t *__restrict__ key,
+                                                    int32_t *__restrict__ cnt, int32_t *__restrict__ err)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns + nt) return;
@@ -151,101 +152,145 @@ __global__ void __launch_bounds__(256) k_keys(const double *__restrict__ src, in
     uint32_t k = (uint32_t)r * (uint32_t)ncol + (uint32_t)c;
     if (tg) k += (uint32_t)rows_s * (uint32_t)ncol;
     key[i] = k;
-    idx[i] = (int32_t)i;
+    atomicAdd(&cnt[k], 1);
 }
 
-// Radix sort pass, step 1: per-tile digit histogram, stored digit-major.
-__global__ void __launch_bounds__(RS_THREADS) k_rs_upsweep(const uint32_t *__restrict__ key, int64_t n, int shift,
-                                                           uint32_t *__restrict__ hist, int nblk)
+// Exclusive scan of the leaf counts by one block, in LDS tiles of SC_TILE
+// counts (loaded and stored coalesced): start[b], end[b]; the counts become
+// the scatter cursors (= start).
+constexpr int SC_THREADS = 1024, SC_PER = 8, SC_TILE = SC_THREADS * SC_PER;
+__global__ void __launch_bounds__(SC_THREADS) k_tree_scan(int32_t *__restrict__ cnt, int64_t nbox,
+                                                          int32_t *__restrict__ start, int32_t *__restrict__ end)
 {
-    __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
-    __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int j = threadIdx.x; j < RS_TILE; j += RS_THREADS) {
-        int64_t g = base + j;
-        if (g < n) atomicAdd(&cnt[(key[g] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = cnt[threadIdx.x];
-}
-
-// Step 2: exclusive scan in digit-major order of the block-major histogram
-// hist[block][digit] (one block; thread d owns digit d, loads are coalesced
-// across threads).
-__global__ void __launch_bounds__(256) k_rs_scan(uint32_t *__restrict__ hist, int nblk)
-{
-    __shared__ uint32_t tot[256];
-    const int d = threadIdx.x;
-    uint32_t s = 0;
-#pragma unroll 8
-    for (int b = 0; b < nblk; ++b) s += hist[(int64_t)b * 256 + d];
-    tot[d] = s;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        uint32_t v = d >= o ? tot[d - o] : 0u;
-        __syncthreads();
-        tot[d] += v;
-        __syncthreads();
-    }
-    uint32_t run = tot[d] - s;
-#pragma unroll 8
-    for (int b = 0; b < nblk; ++b) {
-        uint32_t c = hist[(int64_t)b * 256 + d];
-        hist[(int64_t)b * 256 + d] = run;
-        run += c;
-    }
-}
-
-// Step 3: stable scatter.  Each tile is processed in rounds of 256 elements in
-// index order; within a round an element's rank among equal digits comes from
-// wave ballots over the 8 digit bits plus the counts of earlier waves.
-__global__ void __launch_bounds__(RS_THREADS) k_rs_downsweep(const uint32_t *__restrict__ kin,
-                                                             const int32_t *__restrict__ iin,
-                                                             uint32_t *__restrict__ kout, int32_t *__restrict__ iout,
-                                                             int64_t n, int shift, const uint32_t *__restrict__ hist,
-                                                             int nblk)
-{
-    constexpr int NW = RS_THREADS / 64;
-    __shared__ uint32_t offs[256];
-    __shared__ uint32_t wcnt[NW][256];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    offs[tid] = hist[(int64_t)blockIdx.x * 256 + tid];
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int r = 0; r < RS_ITEMS; ++r) {
-        int64_t g = base + (int64_t)r * RS_THREADS + tid;
-        bool act = g < n;
-        uint32_t k = act ? kin[g] : 0u;
-        uint32_t dg = (k >> shift) & 255u;
-        for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        uint64_t m = __ballot(act);
-        for (int b = 0; b < 8; ++b) {
-            bool bit = (dg >> b) & 1u;
-            uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+    __shared__ int32_t tile[SC_TILE];
+    __shared__ int32_t wsum[SC_THREADS / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int32_t carry = 0;
+    for (int64_t t0 = 0; t0 < nbox; t0 += SC_TILE) {
+#pragma unroll
+        for (int k = 0; k < SC_PER; ++k) {
+            int64_t b = t0 + k * SC_THREADS + t;
+            tile[k * SC_THREADS + t] = b < nbox ? cnt[b] : 0;
         }
-        uint32_t rank = (uint32_t)__popcll(m & lt);
-        if (act && rank == 0) wcnt[wv][dg] = (uint32_t)__popcll(m);
         __syncthreads();
-        {
-            uint32_t acc = offs[tid];
-            for (int w = 0; w < NW; ++w) {
-                uint32_t c = wcnt[w][tid];
-                wcnt[w][tid] = acc;
-                acc += c;
+        int32_t c[SC_PER], s = 0;
+#pragma unroll
+        for (int k = 0; k < SC_PER; ++k) {
+            c[k] = tile[t * SC_PER + k];
+            s += c[k];
+        }
+        int32_t v = s;  // inclusive scan over the wave, then over the waves
+        for (int o = 1; o < 64; o <<= 1) {
+            int32_t u = __shfl_up(v, o);
+            if (lane >= o) v += u;
+        }
+        if (lane == 63) wsum[wv] = v;
+        __syncthreads();
+        if (wv == 0) {
+            int32_t w = lane < SC_THREADS / 64 ? wsum[lane] : 0;
+            for (int o = 1; o < SC_THREADS / 64; o <<= 1) {
+                int32_t u = __shfl_up(w, o);
+                if (lane >= o) w += u;
             }
-            offs[tid] = acc;
+            if (lane < SC_THREADS / 64) wsum[lane] = w;
         }
         __syncthreads();
-        if (act) {
-            uint32_t pos = wcnt[wv][dg] + rank;
-            kout[pos] = k;
-            iout[pos] = iin[g];
+        int32_t run = carry + v - s + (wv > 0 ? wsum[wv - 1] : 0);
+#pragma unroll
+        for (int k = 0; k < SC_PER; ++k) {
+            tile[t * SC_PER + k] = run;
+            run += c[k];
+        }
+        carry += wsum[SC_THREADS / 64 - 1];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SC_PER; ++k) {
+            int64_t b = t0 + k * SC_THREADS + t;
+            if (b < nbox) {
+                int32_t st = tile[k * SC_THREADS + t];
+                int32_t n_b = cnt[b];
+                start[b] = st;
+                end[b] = st + n_b;
+                cnt[b] = st;
+            }
         }
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(256) k_tree_scatter(const uint32_t *__restrict__ key, int64_t n,
+                                                      int32_t *__restrict__ cursor, int32_t *__restrict__ perm)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t pos = atomicAdd(&cursor[key[i]], 1);
+    perm[pos] = (int32_t)i;
+}
+
+__device__ inline void cswap(int32_t &a, int32_t &b, bool up)
+{
+    if ((a > b) == up) {
+        int32_t t = a;
+        a = b;
+        b = t;
+    }
+}
+
+// One wave per leaf: sort the leaf's scattered original indices (bitonic; in
+// registers up to 64 points, in LDS up to LF_LDS, else in the leaf's own
+// slice of the scratch array), then write idx and gather the coordinates.
+constexpr int LF_LDS = 4096;
+__global__ void __launch_bounds__(64) k_tree_leaf(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
+                                                  const int32_t *__restrict__ perm, int32_t *__restrict__ scratch,
+                                                  int32_t *__restrict__ idx, const double *__restrict__ src,
+                                                  int64_t ns, const double *__restrict__ tgt, int64_t nt,
+                                                  double *__restrict__ xs, double *__restrict__ ys)
+{
+    __shared__ int32_t sh[LF_LDS];
+    const int b = blockIdx.x, lane = threadIdx.x;
+    const int s = start[b], nb = end[b] - s;
+    if (nb <= 0) return;
+    auto emit = [&](int k, int32_t o) {
+        idx[s + k] = o;
+        if (o < ns) {
+            xs[s + k] = src[o];
+            ys[s + k] = src[ns + o];
+        } else {
+            xs[s + k] = tgt[o - ns];
+            ys[s + k] = tgt[nt + o - ns];
+        }
+    };
+    if (nb <= 64) {
+        int32_t v = lane < nb ? perm[s + lane] : INT32_MAX;
+        for (int k = 2; k <= 64; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                int32_t w = __shfl_xor(v, j);
+                bool up = (lane & k) == 0, low = (lane & j) == 0;
+                v = (low == up) ? min(v, w) : max(v, w);
+            }
+        if (lane < nb) emit(lane, v);
+        return;
+    }
+    int m = 128;
+    while (m < nb) m <<= 1;
+    // the array being sorted: LDS, or the slice [2 s, 2 s + m) of scratch (m <= 2 nb)
+    int32_t *a = m <= LF_LDS ? sh : scratch + 2 * (int64_t)s;
+    for (int i = lane; i < m; i += 64) a[i] = i < nb ? perm[s + i] : INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < m; i += 64) {
+                int p = i ^ j;
+                if (p > i) {
+                    int32_t x = a[i], y = a[p];
+                    cswap(x, y, (i & k) == 0);
+                    a[i] = x;
+                    a[p] = y;
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = lane; i < nb; i += 64) emit(i, a[i]);
 }
 
 __global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
@@ -261,28 +306,6 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
 }
 
 // Leaf ranges [start, end) per key and the sorted coordinates.
-__global__ void __launch_bounds__(256) k_leaf_ranges(const uint32_t *__restrict__ key,
-                                                     const int32_t *__restrict__ idx, int64_t n,
-                                                     int32_t *__restrict__ start, int32_t *__restrict__ end,
-                                                     const double *__restrict__ src, int64_t ns,
-                                                     const double *__restrict__ tgt, int64_t nt,
-                                                     double *__restrict__ xs, double *__restrict__ ys)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t k = key[i];
-    if (i == 0 || key[i - 1] != k) start[k] = (int32_t)i;
-    if (i == n - 1 || key[i + 1] != k) end[k] = (int32_t)(i + 1);
-    int64_t o = idx[i];
-    if (o < ns) {
-        xs[i] = src[o];
-        ys[i] = src[ns + o];
-    } else {
-        xs[i] = tgt[o - ns];
-        ys[i] = tgt[nt + o - ns];
-    }
-}
-
 }  // namespace
 
 int bbox_blocks(int64_t n)
@@ -300,15 +323,6 @@ void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, d
                        partial, counter, out, seq);
 }
 
-void launch_keys(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
-                 int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, uint32_t *key, int32_t *idx,
-                 int32_t *err, hipStream_t st)
-{
-    int64_t n = ns + nt;
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, ns, tgt, nt, x_lo, 1.0 / w,
-                       col_lo, ncol, rows_s, rows_t, ys_lim, yt_lim, key, idx, err);
-}
 
 __global__ void k_mirror(const double *__restrict__ xy, int64_t n, double *__restrict__ out)
 {
@@ -325,29 +339,6 @@ void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st)
     hipLaunchKernelGGL(k_mirror, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xy, n, out);
 }
 
-int sort_blocks(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
-
-int launch_radix_sort(SortBufs &b, int64_t n, int bits, hipStream_t st)
-{
-    int passes = (bits + 7) / 8;
-    int nblk = sort_blocks(n);
-    uint32_t *kin = b.key_a, *kout = b.key_b;
-    int32_t *iin = b.idx_a, *iout = b.idx_b;
-    for (int p = 0; p < passes; ++p) {
-        int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_upsweep, dim3(nblk), dim3(RS_THREADS), 0, st, kin, n, shift, b.hist, nblk);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(256), 0, st, b.hist, nblk);
-        hipLaunchKernelGGL(k_rs_downsweep, dim3(nblk), dim3(RS_THREADS), 0, st, kin, iin, kout, iout, n, shift,
-                           b.hist, nblk);
-        uint32_t *tk = kin;
-        kin = kout;
-        kout = tk;
-        int32_t *ti = iin;
-        iin = iout;
-        iout = ti;
-    }
-    return (passes & 1) ? 1 : 0;
-}
 
 __global__ void __launch_bounds__(256) k_zero3(int32_t *__restrict__ a, int64_t na, int32_t *__restrict__ b,
                                                int64_t nb, int32_t *__restrict__ c, int64_t nc)
@@ -381,13 +372,20 @@ void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st)
     hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t *)p, n);
 }
 
-void launch_leaf_ranges(const uint32_t *key, const int32_t *idx, int64_t n, int64_t nbox, int32_t *start,
-                        int32_t *end, const double *src, int64_t ns, const double *tgt, int64_t nt, double *xs,
-                        double *ys, hipStream_t st)
+void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
+                 int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, const TreeBufs &b, int32_t *err,
+                 hipStream_t st)
 {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_leaf_ranges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, key, idx, n, start, end,
-                       src, ns, tgt, nt, xs, ys);
+    const int64_t n = ns + nt;
+    const int64_t nbox = (int64_t)(rows_s + rows_t) * ncol;
+    if (n == 0 || nbox == 0) return;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_tree_count, dim3(g), dim3(256), 0, st, src, ns, tgt, nt, x_lo, 1.0 / w, col_lo, ncol, rows_s,
+                       rows_t, ys_lim, yt_lim, b.key, b.cnt, err);
+    hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(SC_THREADS), 0, st, b.cnt, nbox, b.start, b.end);
+    hipLaunchKernelGGL(k_tree_scatter, dim3(g), dim3(256), 0, st, b.key, n, b.cnt, b.perm);
+    hipLaunchKernelGGL(k_tree_leaf, dim3((unsigned)nbox), dim3(64), 0, st, b.start, b.end, b.perm, b.scratch, b.idx,
+                       src, ns, tgt, nt, b.xs, b.ys);
 }
 
 }  // namespace lmfmm

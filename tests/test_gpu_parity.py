@@ -253,3 +253,28 @@ def test_graph_replay_matches_direct(torch_cuda, mid, precision):
         st["kernel_ms"]["m2l_l2l"])
     assert st["kernel_ms"]["m2l_l2l"] > 0
     assert st["graph_applies"] == 4 and st["timed_applies"] == 2
+
+
+def test_large_leaves(torch_cuda, plain):
+    """Leaves of about 6000 and 300 points (the per-leaf ordering runs in the
+    scratch array and in LDS) next to small ones: FMM against the direct sum,
+    and two applies bit for bit equal."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("large leaves: clusters of 6000 and 300 sources, levels 3")
+    rng = np.random.default_rng(21)
+    k, d = plain["k"], plain["d"]
+    sa = np.stack([0.2 + 5e-4 * rng.random(6000), 0.3 + 5e-4 * rng.random(6000)])
+    sb = np.stack([0.7 + 1e-3 * rng.random(300), 0.6 + 1e-3 * rng.random(300)])
+    su = np.stack([rng.random(500), 0.05 + 0.95 * rng.random(500)])
+    src = np.ascontiguousarray(np.concatenate([sa, sb, su], axis=1)[:, rng.permutation(6800)])
+    tgt = np.stack([rng.random(400), -0.05 - 0.9 * rng.random(400)])
+    q = rng.standard_normal((2, 6800)) + 1j * rng.standard_normal((2, 6800))
+    pl = Plan(k, d, order=20, tol=1e-10, levels=3)
+    pl.set_option("graph", "0")
+    u1 = host(pl.apply(dev(src), dev(q), dev(tgt)))
+    u2 = host(pl.apply(dev(src), dev(q), dev(tgt)))
+    assert np.array_equal(u1, u2)
+    ref = host(pl.direct(dev(src), dev(q), dev(tgt)))
+    err = rel(u1, ref)
+    say("rel-l2 vs direct", err)
+    assert err < 1e-10
