@@ -752,8 +752,15 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_s * lv.ncol;
     if (nbox == 0) return;
-    int CH = (int)((60 * 1024) / ((size_t)(lv.nc + nrhs) * sizeof(cx<T>)));
-    CH = CH > 64 ? 64 : (CH < 1 ? 1 : CH);
+    // points per chunk: about 1.5 times the mean leaf occupancy (a multiple of
+    // 16, at most 64), so that the LDS per block stays small and many blocks
+    // share a CU; larger leaves take several chunks
+    const double mean = (double)ns / nbox;
+    int CH = 16 * (int)std::ceil(1.5 * mean / 16.0);
+    CH = CH > 64 ? 64 : (CH < 16 ? 16 : CH);
+    const int chmax = (int)((60 * 1024) / ((size_t)(lv.nc + nrhs) * sizeof(cx<T>)));
+    CH = CH > chmax ? chmax : CH;
+    CH = CH < 1 ? 1 : CH;
     size_t sh = (size_t)CH * (lv.nc + nrhs) * sizeof(cx<T>);
     cx<double> kd = k_src(med);
     cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);

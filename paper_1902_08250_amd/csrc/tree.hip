@@ -239,7 +239,7 @@ __device__ inline void cswap(int32_t &a, int32_t &b, bool up)
 // One wave per leaf: sort the leaf's scattered original indices (bitonic; in
 // registers up to 64 points, in LDS up to LF_LDS, else in the leaf's own
 // slice of the scratch array), then write idx and gather the coordinates.
-constexpr int LF_LDS = 4096;
+constexpr int LF_LDS = 1024;  // small, so that many one-wave blocks fit on a CU
 __global__ void __launch_bounds__(64) k_tree_leaf(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
                                                   const int32_t *__restrict__ perm, int32_t *__restrict__ scratch,
                                                   int32_t *__restrict__ idx, const double *__restrict__ src,
