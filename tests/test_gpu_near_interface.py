@@ -45,17 +45,25 @@ def test_near_interface_reduced(orc):
 
 
 def test_near_interface_full_size(orc):
-    """The full 2e5 x 2e5 workload (x in [0, 10], L = 12) at 2 oracle targets."""
+    """The full 2e5 x 2e5 workload (x in [0, 10], L = 12): the FMM against the
+    GPU direct sum (every pair by quadrature) at 1000 seeded targets over all
+    sources, and against the oracle at 2 of them (which also pins the direct
+    sum at full size)."""
     from paper_1902_08250_amd.lmfmm import Plan
     say("near-interface 2e5 full, L=12")
     spec = workloads.make(2)
     pl = Plan(spec["k"], spec["d"], order=20, tol=1e-10, levels=12)
     u = pl.apply(dev(spec["src"]), dev(spec["q"]), dev(spec["tgt"])).cpu().numpy()
-    sel = np.array([0, 123457])
-    ref = orc.apply(spec["src"], spec["q"], spec["tgt"][:, sel], spec["k"], spec["d"])
-    err = rel(u[:, sel], ref)
-    say("rel-l2", err, pl.stats()["order"])
-    assert err < 1e-10
+    rng = np.random.default_rng(2002)
+    sel = np.sort(rng.choice(spec["tgt"].shape[1], 1000, replace=False))
+    d = pl.direct(dev(spec["src"]), dev(spec["q"]), dev(np.ascontiguousarray(spec["tgt"][:, sel]))).cpu().numpy()
+    err_d = rel(u[:, sel], d)
+    say("rel-l2 vs GPU direct at 1000 targets", err_d, pl.stats()["order"])
+    two = np.array([0, 777])
+    ref = orc.apply(spec["src"], spec["q"], spec["tgt"][:, sel[two]], spec["k"], spec["d"])
+    err_o, err_do = rel(u[:, sel[two]], ref), rel(d[:, two], ref)
+    say("rel-l2 vs oracle at 2 targets: fmm", err_o, "direct", err_do)
+    assert err_d < 1e-10 and err_o < 1e-10 and err_do < 1e-12
 
 
 @pytest.mark.parametrize("levels", [6, 9])
