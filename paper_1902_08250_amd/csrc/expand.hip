@@ -717,21 +717,26 @@ __global__ void __launch_bounds__(64) k_l2p_grad(const int32_t *__restrict__ sta
 }
 
 // Direct all-pairs sum (no tree): lanes over targets, loop over all sources.
+// Direct sum over all pairs: block (target tile of 64, rhs chunk of 8,
+// source chunk z) sums sources [z cs, (z + 1) cs) for its targets.  With one
+// chunk it writes u; otherwise FP64 partials part[z][rhs][target], added in
+// chunk order by k_direct_reduce.
 template <typename T>
 __global__ void __launch_bounds__(64) k_direct(const double *__restrict__ src, int64_t ns, const cx<T> *__restrict__ q,
                                                const double *__restrict__ tgt, int64_t nt, int nrhs,
                                                const Node *__restrict__ nodes, int nmid, int npan, double t0,
-                                               cx<T> *__restrict__ u)
+                                               int64_t cs, cx<double> *__restrict__ part, cx<T> *__restrict__ u)
 {
     constexpr int RMAX = 8;
     int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int r0 = blockIdx.y * RMAX;
     const int nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
+    const int64_t j0 = (int64_t)blockIdx.z * cs, j1 = j0 + cs < ns ? j0 + cs : ns;
     bool act = i < nt;
     double x1 = act ? tgt[i] : tgt[0], y1 = act ? tgt[nt + i] : tgt[nt];
     cx<double> res[RMAX];
     for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
-    for (int64_t j = 0; j < ns; ++j) {
+    for (int64_t j = j0; j < j1; ++j) {
         double x0 = src[j], y0 = src[ns + j];
         cx<double> G = pair_kernel(nodes, nmid, npan, t0, y1, y0, fabs(x1 - x0), act);
         for (int r = 0; r < RMAX; ++r)
@@ -740,9 +745,25 @@ __global__ void __launch_bounds__(64) k_direct(const double *__restrict__ src, i
                 cfma(res[r], G, cx<double>{(double)qq.re, (double)qq.im});
             }
     }
-    if (act)
+    if (!act) return;
+    if (part) {
+        for (int r = 0; r < RMAX; ++r)
+            if (r < nr) part[((int64_t)blockIdx.z * nrhs + r0 + r) * nt + i] = res[r];
+    } else {
         for (int r = 0; r < RMAX; ++r)
             if (r < nr) u[(int64_t)(r0 + r) * nt + i] = mk<T>((T)res[r].re, (T)res[r].im);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_direct_reduce(const cx<double> *__restrict__ part, int nchunk, int64_t m,
+                                                       cx<T> *__restrict__ u)
+{
+    int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= m) return;
+    cx<double> v = {0.0, 0.0};
+    for (int z = 0; z < nchunk; ++z) v += part[(int64_t)z * m + o];
+    u[o] = mk<T>((T)v.re, (T)v.im);
 }
 
 template <typename T, int PMAX>
@@ -925,18 +946,41 @@ void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *id
 #undef LMFMM_GR
 }
 
+int direct_chunks(int64_t ns, int64_t nt, int nrhs)
+{
+    // enough blocks to fill the GPU, at least 256 sources per chunk, and at
+    // most 256 MiB of partials
+    int64_t tiles = ((nt + 63) / 64) * ((nrhs + 7) / 8);
+    int64_t z = (2048 + tiles - 1) / tiles;
+    int64_t zmax = (ns + 255) / 256;
+    int64_t zmem = ((int64_t)256 << 20) / std::max<int64_t>(1, nt * nrhs * 16);
+    z = std::min(z, std::min(zmax, zmem));
+    return (int)std::max<int64_t>(1, z);
+}
+
 void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, int nrhs, int prec,
-                   const Node *nodes, int nmid, int npan, double t0, void *u, hipStream_t st)
+                   const Node *nodes, int nmid, int npan, double t0, int nchunk, cx<double> *part, void *u,
+                   hipStream_t st)
 {
     if (nt == 0) return;
-    dim3 grid((unsigned)((nt + 63) / 64), (unsigned)((nrhs + 7) / 8));
-    if (prec == 0)
+    int64_t cs = (ns + nchunk - 1) / nchunk;
+    dim3 grid((unsigned)((nt + 63) / 64), (unsigned)((nrhs + 7) / 8), (unsigned)nchunk);
+    cx<double> *pp = nchunk > 1 ? part : nullptr;
+    const int64_t m = nt * nrhs;
+    if (prec == 0) {
         hipLaunchKernelGGL((k_direct<double>), grid, dim3(64), 0, st, src, ns,
-                           reinterpret_cast<const cx<double> *>(q), tgt, nt, nrhs, nodes, nmid, npan, t0,
+                           reinterpret_cast<const cx<double> *>(q), tgt, nt, nrhs, nodes, nmid, npan, t0, cs, pp,
                            reinterpret_cast<cx<double> *>(u));
-    else
+        if (pp)
+            hipLaunchKernelGGL((k_direct_reduce<double>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, pp,
+                               nchunk, m, reinterpret_cast<cx<double> *>(u));
+    } else {
         hipLaunchKernelGGL((k_direct<float>), grid, dim3(64), 0, st, src, ns, reinterpret_cast<const cx<float> *>(q),
-                           tgt, nt, nrhs, nodes, nmid, npan, t0, reinterpret_cast<cx<float> *>(u));
+                           tgt, nt, nrhs, nodes, nmid, npan, t0, cs, pp, reinterpret_cast<cx<float> *>(u));
+        if (pp)
+            hipLaunchKernelGGL((k_direct_reduce<float>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, pp,
+                               nchunk, m, reinterpret_cast<cx<float> *>(u));
+    }
 }
 
 #define LMFMM_INST(T)                                                                                               \

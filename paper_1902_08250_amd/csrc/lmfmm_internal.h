@@ -8,6 +8,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -311,8 +312,12 @@ void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *id
                      const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,
                      const Geometry &g, Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0,
                      int do_far, int do_near, double ysign, double *gout, hipStream_t st);
+// direct sum over all pairs, split into nchunk source chunks (partials in
+// part: nchunk * nrhs * nt, needed when nchunk > 1); direct_chunks picks nchunk
+int direct_chunks(int64_t ns, int64_t nt, int nrhs);
 void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, int nrhs, int prec,
-                   const Node *nodes, int nmid, int npan, double t0, void *u, hipStream_t st);
+                   const Node *nodes, int nmid, int npan, double t0, int nchunk, cx<double> *part, void *u,
+                   hipStream_t st);
 
 // tables.hip
 void launch_node_table(const double *lamw, int n, Medium med, Node *out, hipStream_t st);

@@ -250,8 +250,8 @@ struct lmfmm_plan_s {
     VarTables vt[2];
     DevBuf mirror;  // mirrored coordinates for the transposed operator
 
-    // direct-sum node table
-    DevBuf dir_nodes;
+    // direct-sum node table and source-chunk partials
+    DevBuf dir_nodes, dir_part;
     double d_h = -1;
     int d_nmid = 0, d_npan = 0;
     double d_t0 = 0;
@@ -607,6 +607,11 @@ static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g,
     return LMFMM_OK;
 }
 
+// Length of the first ray panel of a pair-independent table: the ray
+// integrand decays like exp(-t (a + dx)/sqrt 2), so the first panel must be
+// short against 1/dx_max as well as against c.
+static double ray_t0(double c, double dxmax) { return std::min(c / 8.0, 0.5 / std::max(dxmax, 1e-300)); }
+
 // Near-field node table on the contour: bump over [-c, c] plus the two rays at
 // 45 degrees (valid for x1 - x0 >= 0; |x1 - x0| is used by evenness).  The
 // panel count covers pairs down to a vertical gap a_min.
@@ -616,7 +621,7 @@ static int build_near_table(DevBuf &buf, const Medium &med, double dxmax, double
     double c = contour_c(med);
     double h = std::min(0.25 * c, 3.0 / std::max(dxmax, 1e-300));
     int nmp = std::max(16, (int)std::ceil(4.0 * c / h));
-    double t0 = c / 8.0;
+    double t0 = ray_t0(c, dxmax);
     double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
     int npan = 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0))));
     npan = std::min(npan, 64);
@@ -688,10 +693,10 @@ static int ensure_near_table(VarTables &vt, const Medium &med, const Geometry &g
     double dxmax = 2.0 * g.lev[g.L].w;
     double c = contour_c(med);
     double h = std::min(0.25 * c, 3.0 / dxmax);
-    double t0 = c / 8.0;
+    double t0 = ray_t0(c, dxmax);
     double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
     int npan = std::min(64, 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0)))));
-    if (vt.near_nodes.p && vt.n_h == h && vt.n_npan >= npan) return LMFMM_OK;
+    if (vt.near_nodes.p && vt.n_h == h && vt.n_t0 == t0 && vt.n_npan >= npan) return LMFMM_OK;
     vt.version++;
     return build_near_table(vt.near_nodes, med, dxmax, amin, vt.n_c, vt.n_h, vt.n_t0, vt.n_nmid, vt.n_npan);
 }
@@ -766,6 +771,7 @@ int lmfmm_destroy(lmfmm_plan p)
     p->ws.release();
     p->bbox_dev.release();
     p->dir_nodes.release();
+    p->dir_part.release();
     p->mirror.release();
     p->vt[0].release();
     p->vt[1].release();
@@ -1295,10 +1301,10 @@ int lmfmm_direct(lmfmm_plan p, int64_t ns, const double *src, const void *q, int
     if (rc) return rc;
     double dxmax = std::max(bb[1] - bb[0], 1e-12);
     double amin = std::max(bb[2], 0.0) + std::max(-bb[5], 0.0);
-    double c = contour_c(p->med), h = std::min(0.25 * c, 3.0 / dxmax), t0 = c / 8.0;
+    double c = contour_c(p->med), h = std::min(0.25 * c, 3.0 / dxmax), t0 = ray_t0(c, dxmax);
     double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
     int npan = std::min(64, 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0)))));
-    if (!p->dir_nodes.p || p->d_h != h || p->d_npan < npan) {
+    if (!p->dir_nodes.p || p->d_h != h || p->d_t0 != t0 || p->d_npan < npan) {
         double cc, hh, tt;
         int nm, np;
         if ((rc = build_near_table(p->dir_nodes, p->med, dxmax, amin, cc, hh, tt, nm, np))) return rc;
@@ -1307,8 +1313,10 @@ int lmfmm_direct(lmfmm_plan p, int64_t ns, const double *src, const void *q, int
         p->d_npan = np;
         p->d_t0 = tt;
     }
-    launch_direct(src, ns, q, tgt, nt, nrhs, prec, (const Node *)p->dir_nodes.p, p->d_nmid, p->d_npan, p->d_t0, u,
-                  st);
+    const int nchunk = direct_chunks(ns, nt, nrhs);
+    if (nchunk > 1 && (rc = p->dir_part.ensure((size_t)nchunk * nt * nrhs * sizeof(cx<double>)))) return rc;
+    launch_direct(src, ns, q, tgt, nt, nrhs, prec, (const Node *)p->dir_nodes.p, p->d_nmid, p->d_npan, p->d_t0,
+                  nchunk, (cx<double> *)p->dir_part.p, u, st);
     HIPCHK(hipGetLastError());
     return LMFMM_OK;
 }
