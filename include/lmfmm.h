@@ -161,10 +161,11 @@ typedef struct {
 } lmfmm_stats;
 
 /* Kernel indices of lmfmm_stats.kernel_*: bounding box and tree build (all
- * their kernels together), P2M, M2M, M2L + L2L, near-field sweep, L2P + near
- * field (or its gradient form); 6 and 7 are unused. */
+ * their kernels together), P2M, M2M, M2L (all levels in one launch),
+ * near-field sweep, L2P + near field (or its gradient form), L2L; 7 is
+ * unused. */
 enum { LMFMM_K_TREE = 0, LMFMM_K_P2M = 1, LMFMM_K_M2M = 2, LMFMM_K_DOWN = 3, LMFMM_K_SWEEP = 4, LMFMM_K_L2P = 5,
-       LMFMM_K_OTHER = 6 };
+       LMFMM_K_L2L = 6, LMFMM_K_OTHER = 7 };
 
 int lmfmm_get_stats(lmfmm_plan plan, lmfmm_stats *stats);
 

@@ -184,14 +184,17 @@ struct DownArgs {
     // level l - 1
     int ncp, ncol_p, col_lo_p, rows_t_p;
     int has_l2l;
+    int add_rows;  // rows whose stored local expansion (M2L of an earlier launch) is added to the L2L shift
 };
 
 // Downward pass of one level: L_box = L2L(parent's L) + sum over the box's
 // interaction list of M2L (Lemma L2L, Lemma M2L).  Blocks below nb_m2l take
 // one box of the M2L rows each (items: the L2L shift, then the row's class
 // slots, dealt to the waves in turn; the waves' sums are added in order);
-// the remaining blocks take DW boxes of the deeper rows, one per wave, whose
-// only item is the L2L shift.
+// the remaining blocks take DW boxes, one per wave, whose only item is the
+// L2L shift, plus the stored value in rows below add_rows.  The apply runs
+// the M2L of all levels first (k_m2l_all) and then this kernel level by level
+// in its L2L form (nb_m2l = 0, add_rows = the interface rows).
 constexpr int DW = 8;
 template <typename T>
 __global__ void __launch_bounds__(64 * DW) k_down(DownArgs a, int nrhs, const cx<T> *__restrict__ Lp,
@@ -256,8 +259,59 @@ __global__ void __launch_bounds__(64 * DW) k_down(DownArgs a, int nrhs, const cx
                 if (p < a.nc)
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        if (r < nr) out[r * a.nc + p] = acc[r];
+                        if (r < nr) out[r * a.nc + p] = row < a.add_rows ? acc[r] + out[r * a.nc + p] : acc[r];
             }
+        }
+    }
+}
+
+// M2L of every expansion level in one launch (Lemma M2L): one block per
+// target box of a level's interface rows (all rows at the coarsest level);
+// the box's class slots are dealt to the waves in turn and the waves' sums
+// added in order.  The result is stored as the box's local expansion, which
+// the level's L2L launch then adds to the shifted parent expansion.
+constexpr int M2L_MAXLEV = 26;
+template <typename T>
+struct M2LLevels {
+    int n;
+    int blk0[M2L_MAXLEV + 1];  // first block of each listed level; blk0[n] = total
+    int nc[M2L_MAXLEV], ncol[M2L_MAXLEV], col_lo[M2L_MAXLEV], rows_s[M2L_MAXLEV], top[M2L_MAXLEV];
+    int64_t off_s[M2L_MAXLEV], off_t[M2L_MAXLEV];
+    const cx<T> *atab[M2L_MAXLEV];
+    const int *cls3[M2L_MAXLEV];
+    const int *row_off[M2L_MAXLEV];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(64 * DW) k_m2l_all(M2LLevels<T> a, int nrhs, const cx<T> *__restrict__ M,
+                                                     cx<T> *__restrict__ Lc)
+{
+    constexpr int R = Tr<T>::R;
+    __shared__ WaveLds<T> lds[DW];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int li = 0;
+    while (li + 1 < a.n && (int)blockIdx.x >= a.blk0[li + 1]) ++li;
+    const int box = blockIdx.x - a.blk0[li];
+    const int nc = a.nc[li], ncol = a.ncol[li], col_lo = a.col_lo[li];
+    const int row = box / ncol, col = col_lo + box % ncol;
+    const int *row_off = a.row_off[li], *cls3 = a.cls3[li];
+    const int s0 = row_off[row], nitems = row_off[row + 1] - s0;
+    const cx<T> *Ms = M + a.off_s[li];
+    for (int r0 = 0; r0 < nrhs; r0 += R) {
+        const int nr = nrhs - r0 < R ? nrhs - r0 : R;
+        for (int p0 = 0; p0 < nc; p0 += 64) {
+            cx<T> acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+            for (int i = w; i < nitems; i += DW) {
+                const int slot = s0 + i;
+                const int rs = cls3[3 * slot + 1], dc = cls3[3 * slot + 2];
+                const int cs = col + dc, csl = cs - col_lo, dp = (cs >> 1) - (col >> 1);
+                if (rs < a.rows_s[li] && csl >= 0 && csl < ncol && (a.top[li] || (dp <= 1 && dp >= -1)))
+                    item_matvec<T>(a.atab[li] + (int64_t)slot * nc * nc, nc, nc, p0,
+                                   Ms + (((int64_t)rs * ncol + csl) * nrhs + r0) * nc, nc, nr, lds[w], acc);
+            }
+            block_reduce_store<T, DW>(lds, acc, nr, p0, nc, Lc + a.off_t[li] + ((int64_t)box * nrhs + r0) * nc, nc);
         }
     }
 }
@@ -863,7 +917,7 @@ void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int nrhs,
 
 template <typename T>
 void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, const int *row_off, int nrt,
-                 const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, hipStream_t st)
+                 const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, int add_rows, hipStream_t st)
 {
     const Level &lv = g.lev[l], &pv = g.lev[l - 1];
     DownArgs a;
@@ -880,11 +934,42 @@ void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, c
     a.col_lo_p = pv.col_lo;
     a.rows_t_p = pv.rows_t;
     a.has_l2l = l2l_tab != nullptr;
+    a.add_rows = add_rows;
     int64_t rest = (int64_t)(lv.rows_t - a.nrt) * lv.ncol;
     int64_t nblk = a.nb_m2l + (a.has_l2l ? (rest + DW - 1) / DW : 0);
     if (nblk == 0) return;
     LMFMM_LAUNCH((k_down<T>), dim3((unsigned)nblk), dim3(64 * DW), 0, st, a, nrhs, Lc + pv.off_t, l2l_tab,
                        Lc + lv.off_t, M + lv.off_s, atab, cls3, row_off);
+}
+
+template <typename T>
+void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab, const int *const *cls3,
+                    const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, hipStream_t st)
+{
+    M2LLevels<T> a;
+    a.n = 0;
+    int blk = 0;
+    for (int l = l0; l <= l1 && a.n < M2L_MAXLEV; ++l) {
+        const Level &lv = g.lev[l];
+        const int rows = nrt[l - l0] < lv.rows_t ? nrt[l - l0] : lv.rows_t;
+        if (!atab[l - l0] || rows <= 0 || lv.ncol <= 0) continue;
+        const int i = a.n++;
+        a.blk0[i] = blk;
+        a.nc[i] = lv.nc;
+        a.ncol[i] = lv.ncol;
+        a.col_lo[i] = lv.col_lo;
+        a.rows_s[i] = lv.rows_s;
+        a.top[i] = l == g.ltop;
+        a.off_s[i] = lv.off_s;
+        a.off_t[i] = lv.off_t;
+        a.atab[i] = atab[l - l0];
+        a.cls3[i] = cls3[l - l0];
+        a.row_off[i] = row_off[l - l0];
+        blk += rows * lv.ncol;
+    }
+    a.blk0[a.n] = blk;
+    if (blk == 0) return;
+    LMFMM_LAUNCH((k_m2l_all<T>), dim3(blk), dim3(64 * DW), 0, st, a, nrhs, M, Lc);
 }
 
 template <typename T>
@@ -988,7 +1073,9 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
                                 const void *, int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);        \
     template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int, hipStream_t);                   \
     template void launch_down<T>(const Geometry &, int, const cx<T> *, const int *, const int *, int, const cx<T> *, \
-                                 cx<T> *, int, const cx<T> *, bool, hipStream_t);                                   \
+                                 cx<T> *, int, const cx<T> *, bool, int, hipStream_t);                              \
+    template void launch_m2l_all<T>(const Geometry &, int, int, const cx<T> *const *, const int *const *,           \
+                                    const int *const *, const int *, const cx<T> *, cx<T> *, int, hipStream_t);     \
     template int launch_near_sweep<T>(const int32_t *, const int32_t *, const int32_t *, const double *,            \
                                       const double *, const void *, int64_t, int64_t, int, const Geometry &,        \
                                       const Node *, int, int, double, cx<double> *, hipStream_t);                   \

@@ -995,9 +995,8 @@ static void count_flops(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g,
     for (int l = ltop; l <= L; ++l) {
         const Level &lv = g.lev[l], &pa = g.lev[l - 1];
         pairs += p->pair_count[l];
-        double w = (double)p->pair_count[l] * lv.nc * lv.nc;
-        if (l > ltop) w += (double)pa.rows_t * pa.ncol * 4.0 * pa.nc * lv.nc;
-        f[LMFMM_K_DOWN] += 8.0 * R * w;
+        f[LMFMM_K_DOWN] += 8.0 * R * (double)p->pair_count[l] * lv.nc * lv.nc;
+        if (l > ltop) f[LMFMM_K_L2L] += 8.0 * R * (double)pa.rows_t * pa.ncol * 4.0 * pa.nc * lv.nc;
     }
     p->stats.m2l_pairs = pairs;
     if (grad)
@@ -1123,21 +1122,35 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 launch_m2m<T>(g, l, tab, M, nrhs, sx);
                 timed_done();
             }
-            // Step 3: downward pass
+            // Step 3: downward pass.  M2L of every level in one launch (the
+            // coarsest level between all its non-adjacent boxes), stored as the
+            // local expansions of the interface rows; then level by level the
+            // L2L shift of the parent's expansion, adding the stored M2L.
+            const cx<T> *atab[MAXLEV + 1] = {};
+            const int *cls3[MAXLEV + 1] = {}, *roff[MAXLEV + 1] = {};
+            int nrt[MAXLEV + 1] = {0};
             for (int l = ltop; l <= L; ++l) {
-                const LevelTables &tb = vt.lt[l];
-                const cx<T> *atab = tb.nslots > 0 ? (const cx<T> *)(sizeof(T) == 8 ? tb.a64.p : tb.a32.p) : nullptr;
-                const cx<T> *l2l = nullptr;
-                if (l > ltop) l2l = (const cx<T> *)(sizeof(T) == 8 ? tb.l2l64.p : tb.l2l32.p);
-                if (!atab && !l2l) {
-                    // coarsest level without translation classes: no far field reaches it
-                    const Level &lt = g.lev[l];
-                    launch_zero_bytes(Lc + lt.off_t, (size_t)lt.rows_t * lt.ncol * nrhs * lt.nc * sizeof(cx<T>), sx);
-                    continue;
-                }
-                timed(LMFMM_K_DOWN, 1);
-                launch_down<T>(g, l, atab, (const int *)tb.clsof.p, (const int *)tb.rowoff.p, tb.nrt, M, Lc, nrhs, l2l,
-                               l == ltop, sx);
+                const LevelTables &tl = vt.lt[l];
+                if (tl.nslots == 0) continue;
+                atab[l - ltop] = (const cx<T> *)(sizeof(T) == 8 ? tl.a64.p : tl.a32.p);
+                cls3[l - ltop] = (const int *)tl.clsof.p;
+                roff[l - ltop] = (const int *)tl.rowoff.p;
+                nrt[l - ltop] = std::min(tl.nrt, g.lev[l].rows_t);
+            }
+            if (!atab[0]) {
+                // coarsest level without translation classes: no far field reaches it
+                const Level &lt = g.lev[ltop];
+                launch_zero_bytes(Lc + lt.off_t, (size_t)lt.rows_t * lt.ncol * nrhs * lt.nc * sizeof(cx<T>), sx);
+            }
+            timed(LMFMM_K_DOWN, 1);
+            launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, sx);
+            timed_done();
+            for (int l = ltop + 1; l <= L; ++l) {
+                const LevelTables &tl = vt.lt[l];
+                const cx<T> *l2l = (const cx<T> *)(sizeof(T) == 8 ? tl.l2l64.p : tl.l2l32.p);
+                timed(LMFMM_K_L2L, 1);
+                launch_down<T>(g, l, (const cx<T> *)nullptr, nullptr, nullptr, 0, M, Lc, nrhs, l2l, false,
+                               nrt[l - ltop], sx);
                 timed_done();
             }
         }

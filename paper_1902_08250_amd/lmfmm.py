@@ -39,7 +39,7 @@ class Stats(ctypes.Structure):
 
 
 # kernel indices of Stats.kernel_* (LMFMM_K_* in lmfmm.h)
-KERNELS = ["tree", "p2m", "m2m", "m2l_l2l", "near_sweep", "l2p_near", "other", "unused"]
+KERNELS = ["tree", "p2m", "m2m", "m2l", "near_sweep", "l2p_near", "l2l", "other"]
 
 
 class Instance(ctypes.Structure):
