@@ -368,7 +368,7 @@ __device__ inline cx<double> pair_kernel(const Node *__restrict__ nodes, int nmi
 // Fused L2P + S2T per target leaf; lanes over targets (chunks of 64).
 // Writes u[r][original index] (no accumulation across kernels).
 // ---------------------------------------------------------------------------
-template <typename T, int PMAX>
+template <typename T, int PMAX, int RMAX>
 __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
                                                  const int32_t *__restrict__ idx, const double *__restrict__ xs,
                                                  const double *__restrict__ ys, const cx<T> *__restrict__ q,
@@ -379,7 +379,6 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
                                                  int64_t key_t0, const cx<double> *__restrict__ unear, int nparts,
                                                  cx<T> *__restrict__ u)
 {
-    constexpr int RMAX = 8;
     extern __shared__ unsigned char smem_raw[];
     const int nc = 2 * P + 1;
     cx<T> *Ls = reinterpret_cast<cx<T> *>(smem_raw);  // [RMAX][nc]
@@ -486,7 +485,7 @@ __device__ inline double wave_sum_d(double v)
     return v;
 }
 
-template <typename T>
+template <typename T, int RMAX>
 __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
                                                    const int32_t *__restrict__ idx, const double *__restrict__ xs,
                                                    const double *__restrict__ ys, const cx<T> *__restrict__ q,
@@ -494,7 +493,6 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
                                                    const Node *__restrict__ nodes, int nnodes, int nmid, int npan,
                                                    double t0, int nparts, cx<double> *__restrict__ unear)
 {
-    constexpr int RMAX = 8;
     __shared__ double sx[SW_NMAX], sy[SW_NMAX];
     __shared__ int sord[SW_NMAX];
     __shared__ double accr[SW_TCH][RMAX], acci[SW_TCH][RMAX];
@@ -859,10 +857,17 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     cx<T> k2 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
     int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
-    LMFMM_LAUNCH((k_l2p_near<T, PMAX>), dim3(nbox, (nrhs + 7) / 8), dim3(64), sh, st, start, end, idx, xs, ys,
-                       reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo,
-                       lv.w, k2, invR, Lc + lv.off_t, nodes, nmid, npan, t0, do_far, do_near, key_t0, unear, nparts,
-                       reinterpret_cast<cx<T> *>(u));
+    // one right-hand side: a kernel without the per-rhs loops
+#define LMFMM_L2P_LAUNCH(RM)                                                                                      \
+    LMFMM_LAUNCH((k_l2p_near<T, PMAX, RM>), dim3(nbox, (nrhs + RM - 1) / RM), dim3(64), sh, st, start, end, idx, xs, \
+                 ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo,  \
+                 lv.w, k2, invR, Lc + lv.off_t, nodes, nmid, npan, t0, do_far, do_near, key_t0, unear, nparts,       \
+                 reinterpret_cast<cx<T> *>(u))
+    if (nrhs == 1)
+        LMFMM_L2P_LAUNCH(1);
+    else
+        LMFMM_L2P_LAUNCH(8);
+#undef LMFMM_L2P_LAUNCH
 }
 
 template <typename T, int PMAX>
@@ -982,9 +987,15 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
     // split the nodes over parts when there are few leaves
     int nparts = lv.ncol >= 1024 ? 1 : (lv.ncol >= 256 ? 2 : 4);
     int nnodes = nmid + 2 * NGL * npan;
-    LMFMM_LAUNCH((k_near_sweep<T>), dim3(lv.ncol, (nrhs + 7) / 8, nparts), dim3(64), 0, st, start, end, idx, xs,
-                       ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol, (int64_t)lv.rows_s * lv.ncol,
-                       nodes, nnodes, nmid, npan, t0, nparts, unear);
+#define LMFMM_SWEEP_LAUNCH(RM)                                                                                     \
+    LMFMM_LAUNCH((k_near_sweep<T, RM>), dim3(lv.ncol, (nrhs + RM - 1) / RM, nparts), dim3(64), 0, st, start, end, idx, \
+                 xs, ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol, (int64_t)lv.rows_s * lv.ncol,     \
+                 nodes, nnodes, nmid, npan, t0, nparts, unear)
+    if (nrhs == 1)
+        LMFMM_SWEEP_LAUNCH(1);
+    else
+        LMFMM_SWEEP_LAUNCH(8);
+#undef LMFMM_SWEEP_LAUNCH
     return nparts;
 }
 

@@ -53,7 +53,15 @@ def test_near_interface_full_size(orc):
     say("near-interface 2e5 full, L=12")
     spec = workloads.make(2)
     pl = Plan(spec["k"], spec["d"], order=20, tol=1e-10, levels=12)
-    u = pl.apply(dev(spec["src"]), dev(spec["q"]), dev(spec["tgt"])).cpu().numpy()
+    s_, q_, t_ = dev(spec["src"]), dev(spec["q"]), dev(spec["tgt"])
+    u = pl.apply(s_, q_, t_).cpu().numpy()
+    import time
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.apply(s_, q_, t_)
+    torch.cuda.synchronize()
+    say("apply time (tables built) %.2f ms" % (1e3 * (time.perf_counter() - t0)))
     rng = np.random.default_rng(2002)
     sel = np.sort(rng.choice(spec["tgt"].shape[1], 1000, replace=False))
     d = pl.direct(dev(spec["src"]), dev(spec["q"]), dev(np.ascontiguousarray(spec["tgt"][:, sel]))).cpu().numpy()
