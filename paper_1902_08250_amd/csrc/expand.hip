@@ -374,12 +374,14 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
                                                  const double *__restrict__ ys, const cx<T> *__restrict__ q,
                                                  int64_t ns, int64_t nt, int nrhs, int P, int ncol, int col_lo,
                                                  int rows_s, double x_lo, double w, cx<T> k2, T invR,
-                                                 const cx<T> *__restrict__ Lc, const Node *__restrict__ nodes,
-                                                 int nmid, int npan, double t0, int do_far, int do_near,
-                                                 int64_t key_t0, const cx<double> *__restrict__ unear, int nparts,
+                                                 const cx<T> *__restrict__ Lc, LeafShift<T> sh,
+                                                 const Node *__restrict__ nodes, int nmid, int npan, double t0,
+                                                 int do_far, int do_near, int64_t key_t0,
+                                                 const cx<double> *__restrict__ unear, int nparts,
                                                  cx<T> *__restrict__ u)
 {
     extern __shared__ unsigned char smem_raw[];
+    __shared__ WaveLds<T> wl;
     const int nc = 2 * P + 1;
     cx<T> *Ls = reinterpret_cast<cx<T> *>(smem_raw);  // [RMAX][nc]
     const int box = blockIdx.x, lane = threadIdx.x;
@@ -389,7 +391,36 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
     const double cxp = x_lo + (col + 0.5) * w, cyp = -(row + 0.5) * w;
     const int s = start[key_t0 + box], e = end[key_t0 + box];
     if (e <= s) return;
-    if (do_far) {
+    if (do_far && sh.tab) {
+        // the leaf's local expansion: L2L shift of the parent's (Lemma L2L),
+        // plus the stored M2L result in the interface rows
+        constexpr int R = Tr<T>::R;
+        const int prow = row >> 1, pcl = (col >> 1) - sh.col_lo_p, pos = (col & 1) + 2 * (row & 1);
+        const bool pok = prow < sh.rows_p && pcl >= 0 && pcl < sh.ncol_p;
+        const cx<T> *x = sh.Lp + ((int64_t)prow * sh.ncol_p + pcl) * nrhs * sh.ncp;
+        const bool add = row < sh.add_rows;
+        for (int rr = 0; rr < nr; rr += R) {
+            const int nrr = nr - rr < R ? nr - rr : R;
+            for (int p0 = 0; p0 < nc; p0 += 64) {
+                cx<T> acc[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+                if (pok)
+                    item_matvec<T>(sh.tab + (int64_t)pos * sh.ncp * nc, sh.ncp, nc, p0,
+                                   x + (int64_t)(r0 + rr) * sh.ncp, sh.ncp, nrr, wl, acc);
+                const int p = p0 + lane;
+                if (p < nc)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r < nrr) {
+                            cx<T> v = acc[r];
+                            if (add) v += Lc[(((int64_t)row * ncol + cl) * nrhs + r0 + rr + r) * nc + p];
+                            Ls[(rr + r) * nc + p] = v;
+                        }
+            }
+        }
+        __syncthreads();
+    } else if (do_far) {
         for (int r = 0; r < nr; ++r)
             for (int t = lane; t < nc; t += 64)
                 Ls[r * nc + t] = Lc[(((int64_t)row * ncol + cl) * nrhs + r0 + r) * nc + t];
@@ -846,8 +877,8 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
 template <typename T, int PMAX>
 void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
                   const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med, const cx<T> *Lc,
-                  const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near,
-                  const cx<double> *unear, int nparts, void *u, hipStream_t st)
+                  const LeafShift<T> &shift, const Node *nodes, int nmid, int npan, double t0, int do_far,
+                  int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
 {
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_t * lv.ncol;
@@ -861,7 +892,7 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
 #define LMFMM_L2P_LAUNCH(RM)                                                                                      \
     LMFMM_LAUNCH((k_l2p_near<T, PMAX, RM>), dim3(nbox, (nrhs + RM - 1) / RM), dim3(64), sh, st, start, end, idx, xs, \
                  ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo,  \
-                 lv.w, k2, invR, Lc + lv.off_t, nodes, nmid, npan, t0, do_far, do_near, key_t0, unear, nparts,       \
+                 lv.w, k2, invR, Lc + lv.off_t, shift, nodes, nmid, npan, t0, do_far, do_near, key_t0, unear, nparts,\
                  reinterpret_cast<cx<T> *>(u))
     if (nrhs == 1)
         LMFMM_L2P_LAUNCH(1);
@@ -1002,14 +1033,14 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
-                     Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far,
-                     int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
+                     Medium med, const cx<T> *Lc, const LeafShift<T> &shift, const Node *nodes, int nmid, int npan,
+                     double t0, int do_far, int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
 {
     int P = g.lev[g.L].P;
     if (!unear) nparts = 0;
 #define LMFMM_L2P(PM)                                                                                          \
-    l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nodes, nmid, npan, t0, do_far, \
-                        do_near, unear, nparts, u, st)
+    l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, shift, nodes, nmid, npan, t0, \
+                        do_far, do_near, unear, nparts, u, st)
     if (P <= 16)
         LMFMM_L2P(16);
     else if (P <= 32)
@@ -1092,8 +1123,8 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
                                       const Node *, int, int, double, cx<double> *, hipStream_t);                   \
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
-                                     const cx<T> *, const Node *, int, int, double, int, int, const cx<double> *,   \
-                                     int, void *, hipStream_t);                                                     \
+                                     const cx<T> *, const LeafShift<T> &, const Node *, int, int, double, int, int, \
+                                     const cx<double> *, int, void *, hipStream_t);                                 \
     template void launch_l2p_grad<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, const void *, int64_t, int64_t, int,             \
                                      const Geometry &, Medium, const cx<T> *, const Node *, int, int, double, int,  \

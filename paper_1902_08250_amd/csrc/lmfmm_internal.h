@@ -311,11 +311,21 @@ template <typename T>
 int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                       const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
                       const Node *nodes, int nmid, int npan, double t0, cx<double> *unear, hipStream_t st);
+// The leaf level's L2L shift done by the leaf evaluation itself: tab (null:
+// read the stored leaf expansions instead), parent expansions Lp of level
+// L - 1 (ncp coefficients, ncol_p columns from col_lo_p, rows_p rows), and
+// add_rows: leaf rows whose stored M2L result is added.
+template <typename T>
+struct LeafShift {
+    const cx<T> *tab = nullptr;
+    const cx<T> *Lp = nullptr;
+    int ncp = 0, ncol_p = 0, col_lo_p = 0, rows_p = 0, add_rows = 0;
+};
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
-                     Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far,
-                     int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st);
+                     Medium med, const cx<T> *Lc, const LeafShift<T> &shift, const Node *nodes, int nmid, int npan,
+                     double t0, int do_far, int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st);
 template <typename T>
 void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,

@@ -999,10 +999,17 @@ static void count_flops(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g,
         if (l > ltop) f[LMFMM_K_L2L] += 8.0 * R * (double)pa.rows_t * pa.ncol * 4.0 * pa.nc * lv.nc;
     }
     p->stats.m2l_pairs = pairs;
-    if (grad)
+    if (grad) {
         f[LMFMM_K_L2P] = (double)nt * (60.0 * (lf.P + 1) + 3.0 * 8.0 * (lf.nc + 2) * R);
-    else
+    } else {
         f[LMFMM_K_L2P] = (double)nt * (60.0 * lf.P + 8.0 * lf.nc * R);
+        if (L > ltop) {  // the leaf level's L2L runs inside the leaf evaluation
+            const Level &pa = g.lev[L - 1];
+            const double wl = 8.0 * R * (double)pa.rows_t * pa.ncol * 4.0 * pa.nc * lf.nc;
+            f[LMFMM_K_L2L] -= wl;
+            f[LMFMM_K_L2P] += wl;
+        }
+    }
 }
 
 template <typename T>
@@ -1111,6 +1118,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         group_end((have_bb ? 0 : 1) + 5, sx);
 
         // Step 2: upward pass
+        LeafShift<T> shift;
         if (far) {
             timed(LMFMM_K_P2M, 1);
             launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, sx);
@@ -1145,7 +1153,20 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             timed(LMFMM_K_DOWN, 1);
             launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, sx);
             timed_done();
-            for (int l = ltop + 1; l <= L; ++l) {
+            // the leaf level's shift is done by the leaf evaluation (forward apply)
+            const int l2l_last = (!gw && L > ltop) ? L - 1 : L;
+            if (l2l_last < L) {
+                const LevelTables &tl = vt.lt[L];
+                const Level &pv = g.lev[L - 1];
+                shift.tab = (const cx<T> *)(sizeof(T) == 8 ? tl.l2l64.p : tl.l2l32.p);
+                shift.Lp = Lc + pv.off_t;
+                shift.ncp = pv.nc;
+                shift.ncol_p = pv.ncol;
+                shift.col_lo_p = pv.col_lo;
+                shift.rows_p = pv.rows_t;
+                shift.add_rows = nrt[L - ltop];
+            }
+            for (int l = ltop + 1; l <= l2l_last; ++l) {
                 const LevelTables &tl = vt.lt[l];
                 const cx<T> *l2l = (const cx<T> *)(sizeof(T) == 8 ? tl.l2l64.p : tl.l2l32.p);
                 timed(LMFMM_K_L2L, 1);
@@ -1165,7 +1186,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 timed_done();
             }
             timed(LMFMM_K_L2P, 1);
-            launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, nnodes, vt.n_nmid, vt.n_npan,
+            launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, shift, nnodes, vt.n_nmid, vt.n_npan,
                                vt.n_t0, far ? 1 : 0, near_on ? 1 : 0, nparts ? unear : nullptr, nparts, u, sx);
             timed_done();
         } else {
