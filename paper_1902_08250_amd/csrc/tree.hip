@@ -310,11 +310,11 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
 
 int bbox_blocks(int64_t n)
 {
-    // at most 64 blocks, so that the last block reduces the partials with
-    // one load per lane of its first wave
-    int64_t b = (n + 4095) / 4096;
+    // about 1024 points per block, at most 256 blocks (the last block's first
+    // wave reduces at most four partials per lane)
+    int64_t b = (n + 1023) / 1024;
     if (b < 1) b = 1;
-    if (b > 64) b = 64;
+    if (b > 256) b = 256;
     return (int)b;
 }
 
