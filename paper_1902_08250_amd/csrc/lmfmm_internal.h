@@ -280,7 +280,6 @@ struct TreeBufs {
 void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
                  int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, const TreeBufs &b, int32_t *err,
                  hipStream_t st);
-void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 // zero three int32 ranges in one launch
 void launch_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb, int32_t *c, int64_t nc, hipStream_t st);
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);

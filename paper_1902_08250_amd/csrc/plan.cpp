@@ -186,11 +186,9 @@ struct LevelTables {
     int P = 0, Pp = 0;
     DevBuf m2m64, m2m32, l2l64, l2l32;  // [4][nc_in][nc_out]
     DevBuf a64, a32;                    // M2L tables [slot][nc][nc]
-    DevBuf cls;                         // int[28]
     DevBuf clsof;                       // int[3 * nslots]: target row, source row, column offset
     std::vector<int> clsof_host;
-    DevBuf rowoff;                      // top level only: slots of target row r are [rowoff[r], rowoff[r+1])
-    bool full = false;
+    DevBuf rowoff;                      // slots of target row r are [rowoff[r], rowoff[r+1])
     int nslots = 0;
     int nrt = 0;  // target rows with classes (row_off has nrt + 1 entries)
     int64_t nodes = 0;
@@ -219,7 +217,6 @@ struct VarTables {
             t.l2l32.release();
             t.a64.release();
             t.a32.release();
-            t.cls.release();
             t.clsof.release();
             t.rowoff.release();
         }
@@ -506,11 +503,10 @@ static int build_shift_tables(VarTables &vt, const Medium &med, const Geometry &
 static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g, int l, bool full)
 {
     LevelTables &T = vt.lt[l];
-    T.full = full;
     const Level &lv = g.lev[l];
     int P = lv.P, nc = lv.nc;
     double w = lv.w, R = w / std::sqrt(2.0), c = contour_c(med);
-    std::vector<int> cls_index(28, -1), cls_of, row_off;
+    std::vector<int> cls_of, row_off;
     NodeList nl;
     std::vector<int> node_cls, node_local, cP, cQ;
     std::vector<int64_t> toff, aoff;
@@ -549,7 +545,6 @@ static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g,
                     node_cls.push_back(slot);
                     node_local.push_back(i);
                 }
-                if (!full) cls_index[(rt * 2 + rs) * 7 + dc + 3] = slot;
                 cls_of.push_back(rt);
                 cls_of.push_back(rs);
                 cls_of.push_back(dc);
@@ -570,7 +565,6 @@ static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g,
     T.nrt = slot > 0 ? nrt : 0;
     T.nodes = nl.count();
     int rc;
-    if ((rc = upload(T.cls, cls_index.data(), 28 * sizeof(int)))) return rc;
     if (slot == 0) return LMFMM_OK;
     if ((rc = upload(T.clsof, cls_of.data(), cls_of.size() * sizeof(int)))) return rc;
     if ((rc = upload(T.rowoff, row_off.data(), row_off.size() * sizeof(int)))) return rc;

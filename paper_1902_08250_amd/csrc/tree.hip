@@ -299,11 +299,6 @@ __global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
     if (i < n) p[i] = 0u;
 }
 
-__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
 
 // Leaf ranges [start, end) per key and the sorted coordinates.
 }  // namespace
@@ -361,11 +356,6 @@ void launch_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb, int32_t *c, in
     hipLaunchKernelGGL(k_zero3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, na, b, nb, c, nc);
 }
 
-void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
-{
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
-}
 
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st)
 {
