@@ -3,14 +3,16 @@
 //  * P2M  (source-to-multipole, Definition "Multipole Expansion"): per source
 //    leaf, M_q = sum_j q_j J_q(k1 r_j) e^{-i q theta_j}, stored scaled.
 //  * M2M  (Lemma M2M): free-space Helmholtz shift with k1, 4 children -> parent.
-//  * M2L + L2L (Lemma M2L, Lemma L2L): at each level, every target box in the
-//    two rows nearest the interface gathers its interaction list through the
-//    Sommerfeld translation tables; every target box also receives its
-//    parent's local expansion shifted with the free-space operator for k2.
+//  * M2L (Lemma M2L): at every level in one launch, each target box in the
+//    two rows nearest the interface (every row at the coarsest level) gathers
+//    its interaction list through the Sommerfeld translation tables.
+//  * L2L (Lemma L2L): level by level, every target box receives its parent's
+//    local expansion shifted with the free-space operator for k2, plus its own
+//    M2L result.
 //  * L2P + S2T (Definition "Local Expansion"; direct interactions): per
-//    target leaf, the local expansion is evaluated at the targets and the
-//    adjacent source leaves across the interface are summed by contour
-//    quadrature of g_2^t.
+//    target leaf, the leaf's L2L shift, then the local expansion evaluated at
+//    the targets, plus the direct interactions of the adjacent source leaves
+//    across the interface (contour quadrature of g_2^t, by sweeps or pairs).
 //
 // Expansions are stored scaled: Mhat_q = s_q M_q and Lhat_p = L_p / s_p with
 // s_q = |q|! (2/(k R))^|q|, R the box half-diagonal, which keeps FP32 in
