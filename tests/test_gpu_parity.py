@@ -278,3 +278,45 @@ def test_large_leaves(torch_cuda, plain):
     err = rel(u1, ref)
     say("rel-l2 vs direct", err)
     assert err < 1e-10
+
+
+def test_fixed_domain(torch_cuda, mid, mid_direct):
+    """With the domain given up front there is no bounding-box readback: the
+    result matches the direct sum, and a point outside the domain is reported
+    by the device-side check through sync_status."""
+    from paper_1902_08250_amd.lmfmm import Plan, LMFMMError
+    say("fixed domain 4000x3000 nrhs=11, levels 5")
+    pl = Plan(mid["k"], mid["d"], order=20, tol=1e-10, levels=5)
+    pl.set_option("domain", "0,1,1,-0.95")
+    u = host(pl.apply(dev(mid["src"]), dev(mid["q"]), dev(mid["tgt"])))
+    pl.sync_status()
+    err = rel(u, mid_direct)
+    say("rel-l2 vs direct", err)
+    assert err < 1e-10
+    bad = mid["src"].copy()
+    bad[0, 7] = 1.5  # x outside [0, 1]
+    pl.apply(dev(bad), dev(mid["q"]), dev(mid["tgt"]))
+    with pytest.raises(LMFMMError):
+        pl.sync_status()
+    # the next apply with valid points clears the flag
+    pl.apply(dev(mid["src"]), dev(mid["q"]), dev(mid["tgt"]))
+    pl.sync_status()
+
+
+def test_error_decays_with_order(torch_cuda, plain, golden512):
+    """Truncation error of the expansions (Theorem 1 and the translation
+    lemmas of Section 3): at a fixed order p at every level, the error
+    against the oracle falls geometrically in p until it reaches the FP64
+    rounding floor."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    errs = []
+    for p in (12, 16, 20, 24, 28, 32):
+        say("fmm 512x512 L=3 fixed p =", p)
+        pl = Plan(plain["k"], plain["d"], order=p, tol=1e-10, levels=3, fixed_order=True)
+        u = host(pl.apply(dev(plain["src"]), dev(plain["q"]), dev(plain["tgt"])))
+        errs.append(rel(u, golden512))
+    say("rel-l2 by order", errs)
+    for a, b in zip(errs, errs[1:]):
+        if a > 1e-10:
+            assert b < 0.6 * a
+    assert errs[-1] < 1e-9
