@@ -37,7 +37,7 @@ from paper_1902_08250_amd.prof_summary import source_hash  # noqa: E402
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
 # kernel of each timing class on this workload (FP32 expansions, leaf order 16)
 KERNEL_NAMES = {"p2m": "k_p2m<float, 16>", "m2m": "k_up<float>", "m2l": "k_m2l_all<float>", "l2l": "k_down<float>",
-                "near_sweep": "k_near_sweep<float>", "l2p_near": "k_l2p_near<float, 16>"}
+                "near_sweep": "k_near_sweep<float>", "l2p_near": "k_l2p<float, 16, 1>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mixed_uniform_1e5.md")
 
 

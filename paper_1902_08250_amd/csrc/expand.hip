@@ -24,46 +24,63 @@ namespace lmfmm {
 namespace {
 
 // ---------------------------------------------------------------------------
-// P2M: one wave per source leaf; lanes over points, then lanes over outputs.
+// P2M: a block takes G consecutive source leaves, whose points are contiguous
+// in the sorted order, and walks those points in chunks of CH: a thread per
+// point evaluates the point's scaled basis into LDS, then threads over
+// (leaf, right-hand side, coefficient) add the points of their leaf in the
+// chunk, in index order.  The output block of the G leaves is contiguous, and
+// so are the threads' stores.  Leaves without points get zeros.
 // ---------------------------------------------------------------------------
+constexpr int P2M_THREADS = 256;
+constexpr int LEAF_GMAX = 32;  // leaves per block (P2M and L2P)
 template <typename T, int PMAX>
-__global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
-                                            const int32_t *__restrict__ idx, const double *__restrict__ xs,
-                                            const double *__restrict__ ys, const cx<T> *__restrict__ q, int64_t ns,
-                                            int nrhs, int P, int ncol, int col_lo, double x_lo, double w, cx<T> k1,
-                                            T invR, int CH, cx<T> *__restrict__ M)
+__global__ void __launch_bounds__(P2M_THREADS) k_p2m(const int32_t *__restrict__ start,
+                                                     const int32_t *__restrict__ end, const int32_t *__restrict__ idx,
+                                                     const double *__restrict__ xs, const double *__restrict__ ys,
+                                                     const cx<T> *__restrict__ q, int64_t ns, int nrhs, int P,
+                                                     int nbox, int ncol, int col_lo, double x_lo, double w,
+                                                     cx<T> k1, T invR, int G, int CH, cx<T> *__restrict__ M)
 {
     extern __shared__ unsigned char smem_raw[];
+    __shared__ int bnd[LEAF_GMAX + 1];
     const int nc = 2 * P + 1;
     cx<T> *B = reinterpret_cast<cx<T> *>(smem_raw);  // [CH][nc]
     cx<T> *Q = B + CH * nc;                          // [CH][nrhs]
-    const int box = blockIdx.x, lane = threadIdx.x;
-    const int row = box / ncol, col = col_lo + box % ncol;
-    const double cxp = x_lo + (col + 0.5) * w, cyp = (row + 0.5) * w;
-    const int s = start[box], e = end[box];
-    const int nout = nc * nrhs;
-    cx<T> *Mb = M + (int64_t)box * nout;
-    bool first = true;
-    for (int c0 = s; c0 < e || first; c0 += CH) {
-        int j = c0 + lane;
-        bool act = lane < CH && j < e;
-        if (act) {
-            T X = (T)(xs[j] - cxp), Y = (T)(ys[j] - cyp);
-            bessel_basis<T, PMAX>(k1, X, Y, invR, P, -1, B + lane * nc, 1);
-            int64_t o = idx[j];
-            for (int r = 0; r < nrhs; ++r) Q[lane * nrhs + r] = q[(int64_t)r * ns + o];
+    const int t = threadIdx.x;
+    const int b0 = blockIdx.x * G;
+    const int ng = nbox - b0 < G ? nbox - b0 : G;
+    if (t <= ng) bnd[t] = t < ng ? start[b0 + t] : end[b0 + ng - 1];
+    __syncthreads();
+    const int S = bnd[0], E = bnd[ng];
+    const int nout = nc * nrhs, nitem = ng * nout;
+    cx<T> *Mb = M + (int64_t)b0 * nout;
+    for (int c0 = S; c0 < E || c0 == S; c0 += CH) {
+        const int j = c0 + t;
+        if (t < CH && j < E) {
+            int g = 0;
+            while (j >= bnd[g + 1]) ++g;
+            const int box = b0 + g;
+            const int row = box / ncol, col = col_lo + box % ncol;
+            const double cxp = x_lo + (col + 0.5) * w, cyp = (row + 0.5) * w;
+            const T X = (T)(xs[j] - cxp), Y = (T)(ys[j] - cyp);
+            bessel_basis<T, PMAX>(k1, X, Y, invR, P, -1, B + t * nc, 1);
+            const int64_t o = idx[j];
+            for (int r = 0; r < nrhs; ++r) Q[t * nrhs + r] = q[(int64_t)r * ns + o];
         }
         __syncthreads();
-        int cnt = e - c0 < CH ? e - c0 : CH;
-        if (cnt < 0) cnt = 0;
-        for (int o = lane; o < nout; o += 64) {
-            int t = o % nc, r = o / nc;
+        const int cend = E - c0 < CH ? E : c0 + CH;
+        for (int it = t; it < nitem; it += P2M_THREADS) {
+            const int g = it / nout, o = it - g * nout;
+            const int r = o / nc, c = o - r * nc;
+            const int j0 = bnd[g] > c0 ? bnd[g] : c0, j1 = bnd[g + 1] < cend ? bnd[g + 1] : cend;
             cx<T> acc = mk<T>(0, 0);
-            for (int jj = 0; jj < cnt; ++jj) cfma(acc, B[jj * nc + t], Q[jj * nrhs + r]);
-            Mb[r * nc + t] = first ? acc : Mb[r * nc + t] + acc;
+            for (int jj = j0; jj < j1; ++jj) cfma(acc, B[(jj - c0) * nc + c], Q[(jj - c0) * nrhs + r]);
+            if (c0 == S)
+                Mb[it] = acc;
+            else if (j1 > j0)
+                Mb[it] += acc;
         }
         __syncthreads();
-        first = false;
     }
 }
 
@@ -367,7 +384,136 @@ __device__ inline cx<double> pair_kernel(const Node *__restrict__ nodes, int nmi
 }
 
 // ---------------------------------------------------------------------------
-// Fused L2P + S2T per target leaf; lanes over targets (chunks of 64).
+// L2P (Definition "Local Expansion"): res[r] = sum_p Lhat_p J_p(k2 r)
+// e^{i p theta} at the point (X, Y) relative to the leaf centre, from the
+// scaled expansion Ls[r][2P+1], r < nr.
+// ---------------------------------------------------------------------------
+template <typename T, int PMAX, int RMAX>
+__device__ inline void eval_local(cx<T> k2, T X, T Y, T invR, int P, const cx<T> *Ls, int nr, cx<double> (&res)[RMAX])
+{
+    const int nc = 2 * P + 1;
+    cx<T> tm[PMAX + 1];
+    cx<T> J0;
+    bessel_ratios<T, PMAX>(k2, X, Y, P, tm, J0);
+    cx<T> up = mk<T>(X * invR, Y * invR), dn = mk<T>(-X * invR, Y * invR);
+    cx<T> acc[RMAX];
+    for (int r = 0; r < RMAX; ++r) acc[r] = (r < nr) ? J0 * Ls[r * nc + P] : mk<T>(0, 0);
+    cx<T> vp = J0, vm = J0;
+#pragma unroll
+    for (int p = 1; p <= PMAX; ++p) {
+        if (p <= P) {
+            cx<T> f = T(2 * p) * tm[p];
+            vp = vp * (f * up);
+            vm = vm * (f * dn);
+            for (int r = 0; r < RMAX; ++r)
+                if (r < nr) {
+                    cfma(acc[r], vp, Ls[r * nc + P + p]);
+                    cfma(acc[r], vm, Ls[r * nc + P - p]);
+                }
+        }
+    }
+    for (int r = 0; r < RMAX; ++r) res[r] = {(double)acc[r].re, (double)acc[r].im};
+}
+
+// ---------------------------------------------------------------------------
+// L2P over G consecutive target leaves per block (points contiguous in the
+// sorted order); the near field, if any, comes from the sweep kernel's parts.
+// First the leaves' local expansions go to LDS: by the leaf-level L2L shift of
+// the parent's (Lemma L2L, one leaf per wave at a time), plus the stored M2L
+// result in the interface rows, or copied from the stored expansions.  Then
+// a thread per target evaluates its leaf's expansion and adds the near-field
+// parts in order.  Writes u[r][original index].
+// ---------------------------------------------------------------------------
+constexpr int L2P_THREADS = 256;
+template <typename T, int PMAX, int RMAX>
+__global__ void __launch_bounds__(L2P_THREADS) k_l2p(const int32_t *__restrict__ start,
+                                                     const int32_t *__restrict__ end, const int32_t *__restrict__ idx,
+                                                     const double *__restrict__ xs, const double *__restrict__ ys,
+                                                     int64_t ns, int64_t nt, int nrhs, int P, int nbox, int ncol,
+                                                     int col_lo, double x_lo, double w, cx<T> k2, T invR,
+                                                     const cx<T> *__restrict__ Lc, LeafShift<T> sh, int64_t key_t0,
+                                                     int G, int do_far, const cx<double> *__restrict__ unear,
+                                                     int nparts, cx<T> *__restrict__ u)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ WaveLds<T> wl[L2P_THREADS / 64];
+    __shared__ int bnd[LEAF_GMAX + 1];
+    constexpr int R = Tr<T>::R;
+    const int nc = 2 * P + 1;
+    cx<T> *Ls = reinterpret_cast<cx<T> *>(smem_raw);  // [G][RMAX][nc]
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int b0 = blockIdx.x * G;
+    const int ng = nbox - b0 < G ? nbox - b0 : G;
+    const int r0 = blockIdx.y * RMAX;
+    const int nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
+    if (t <= ng) bnd[t] = t < ng ? start[key_t0 + b0 + t] : end[key_t0 + b0 + ng - 1];
+    __syncthreads();
+    const int S = bnd[0], E = bnd[ng];
+    if (E <= S) return;
+    if (do_far && sh.tab) {
+        for (int g = wv; g < ng; g += L2P_THREADS / 64) {
+            if (bnd[g + 1] <= bnd[g]) continue;  // no targets in this leaf
+            const int box = b0 + g, row = box / ncol, col = col_lo + box % ncol;
+            const int prow = row >> 1, pcl = (col >> 1) - sh.col_lo_p, pos = (col & 1) + 2 * (row & 1);
+            const bool pok = prow < sh.rows_p && pcl >= 0 && pcl < sh.ncol_p;
+            const cx<T> *x = sh.Lp + ((int64_t)prow * sh.ncol_p + pcl) * nrhs * sh.ncp;
+            const bool add = row < sh.add_rows;
+            for (int rr = 0; rr < nr; rr += R) {
+                const int nrr = nr - rr < R ? nr - rr : R;
+                for (int p0 = 0; p0 < nc; p0 += 64) {
+                    cx<T> acc[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+                    if (pok)
+                        item_matvec<T>(sh.tab + (int64_t)pos * sh.ncp * nc, sh.ncp, nc, p0,
+                                       x + (int64_t)(r0 + rr) * sh.ncp, sh.ncp, nrr, wl[wv], acc);
+                    const int p = p0 + lane;
+                    if (p < nc)
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if (r < nrr) {
+                                cx<T> v = acc[r];
+                                if (add) v += Lc[((int64_t)box * nrhs + r0 + rr + r) * nc + p];
+                                Ls[(g * RMAX + rr + r) * nc + p] = v;
+                            }
+                }
+            }
+        }
+    } else if (do_far) {
+        const int per = nr * nc;
+        for (int e = t; e < ng * per; e += L2P_THREADS) {
+            const int g = e / per, o = e - g * per, r = o / nc, c = o - r * nc;
+            Ls[(g * RMAX + r) * nc + c] = Lc[((int64_t)(b0 + g) * nrhs + r0 + r) * nc + c];
+        }
+    }
+    __syncthreads();
+    for (int c0 = S; c0 < E; c0 += L2P_THREADS) {
+        const int i = c0 + t;
+        if (i >= E) break;
+        int g = 0;
+        while (i >= bnd[g + 1]) ++g;
+        const int box = b0 + g, row = box / ncol, col = col_lo + box % ncol;
+        cx<double> res[RMAX];
+        for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
+        if (do_far) {
+            const double cxp = x_lo + (col + 0.5) * w, cyp = -(row + 0.5) * w;
+            eval_local<T, PMAX, RMAX>(k2, (T)(xs[i] - cxp), (T)(ys[i] - cyp), invR, P, Ls + g * RMAX * nc, nr,
+                                      res);
+        }
+        const int64_t o = idx[i] - ns;
+        if (unear && row == 0)
+            for (int pp = 0; pp < nparts; ++pp)
+                for (int r = 0; r < RMAX; ++r)
+                    if (r < nr) res[r] += unear[((int64_t)pp * nrhs + r0 + r) * nt + o];
+        for (int r = 0; r < RMAX; ++r)
+            if (r < nr) u[(int64_t)(r0 + r) * nt + o] = mk<T>((T)res[r].re, (T)res[r].im);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused L2P + S2T per target leaf, the near field by pairs (the alternative
+// to the sweep); lanes over targets (chunks of 64).
 // Writes u[r][original index] (no accumulation across kernels).
 // ---------------------------------------------------------------------------
 template <typename T, int PMAX, int RMAX>
@@ -435,30 +581,7 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
         double x1 = xs[ii], y1 = ys[ii];
         cx<double> res[RMAX];
         for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
-        if (do_far) {
-            cx<T> tm[PMAX + 1];
-            cx<T> J0;
-            T X = (T)(x1 - cxp), Y = (T)(y1 - cyp);
-            bessel_ratios<T, PMAX>(k2, X, Y, P, tm, J0);
-            cx<T> up = mk<T>(X * invR, Y * invR), dn = mk<T>(-X * invR, Y * invR);
-            cx<T> acc[RMAX];
-            for (int r = 0; r < RMAX; ++r) acc[r] = (r < nr) ? J0 * Ls[r * nc + P] : mk<T>(0, 0);
-            cx<T> vp = J0, vm = J0;
-#pragma unroll
-            for (int p = 1; p <= PMAX; ++p) {
-                if (p <= P) {
-                    cx<T> f = T(2 * p) * tm[p];
-                    vp = vp * (f * up);
-                    vm = vm * (f * dn);
-                    for (int r = 0; r < RMAX; ++r)
-                        if (r < nr) {
-                            cfma(acc[r], vp, Ls[r * nc + P + p]);
-                            cfma(acc[r], vm, Ls[r * nc + P - p]);
-                        }
-                }
-            }
-            for (int r = 0; r < RMAX; ++r) res[r] = {(double)acc[r].re, (double)acc[r].im};
-        }
+        if (do_far) eval_local<T, PMAX, RMAX>(k2, (T)(x1 - cxp), (T)(y1 - cyp), invR, P, Ls, nr, res);
         if (do_near && row == 0 && rows_s > 0) {
             if (unear) {
                 // near field computed by the sweep kernel: add its parts in order
@@ -851,6 +974,14 @@ __global__ void __launch_bounds__(256) k_direct_reduce(const cx<double> *__restr
     u[o] = mk<T>((T)v.re, (T)v.im);
 }
 
+// Leaves per block: about 3/4 of the block's threads busy with points at the
+// mean occupancy.
+inline int leaves_per_block(double mean, int threads)
+{
+    int G = (int)std::floor(0.75 * threads / (mean > 0.5 ? mean : 0.5));
+    return G < 1 ? 1 : (G > LEAF_GMAX ? LEAF_GMAX : G);
+}
+
 template <typename T, int PMAX>
 void p2m_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
                   const void *q, int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
@@ -858,22 +989,18 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_s * lv.ncol;
     if (nbox == 0) return;
-    // points per chunk: about 1.5 times the mean leaf occupancy (a multiple of
-    // 16, at most 64), so that the LDS per block stays small and many blocks
-    // share a CU; larger leaves take several chunks
-    const double mean = (double)ns / nbox;
-    int CH = 16 * (int)std::ceil(1.5 * mean / 16.0);
-    CH = CH > 64 ? 64 : (CH < 16 ? 16 : CH);
-    const int chmax = (int)((60 * 1024) / ((size_t)(lv.nc + nrhs) * sizeof(cx<T>)));
-    CH = CH > chmax ? chmax : CH;
-    CH = CH < 1 ? 1 : CH;
-    size_t sh = (size_t)CH * (lv.nc + nrhs) * sizeof(cx<T>);
+    const int G = leaves_per_block((double)ns / nbox, P2M_THREADS);
+    // points per chunk: one per thread, as far as 64 KB of LDS allow
+    const size_t per = (size_t)(lv.nc + nrhs) * sizeof(cx<T>);
+    int CH = (int)((64 * 1024) / per);
+    CH = CH > P2M_THREADS ? P2M_THREADS : (CH < 1 ? 1 : CH);
+    const size_t sh = (size_t)CH * per;
     cx<double> kd = k_src(med);
     cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
-    LMFMM_LAUNCH((k_p2m<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
-                       reinterpret_cast<const cx<T> *>(q), ns, nrhs, lv.P, lv.ncol, lv.col_lo, g.x_lo, lv.w, k1, invR,
-                       CH, M + lv.off_s);
+    LMFMM_LAUNCH((k_p2m<T, PMAX>), dim3((nbox + G - 1) / G), dim3(P2M_THREADS), sh, st, start, end, idx, xs, ys,
+                 reinterpret_cast<const cx<T> *>(q), ns, nrhs, lv.P, nbox, lv.ncol, lv.col_lo, g.x_lo, lv.w, k1, invR,
+                 G, CH, M + lv.off_s);
 }
 
 template <typename T, int PMAX>
@@ -890,7 +1017,28 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     cx<T> k2 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
     int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
-    // one right-hand side: a kernel without the per-rhs loops
+    if (!(do_near && lv.rows_s > 0)) unear = nullptr;
+    if (!do_near || unear || lv.rows_s == 0) {
+        // far field plus, if any, the sweep's near-field parts: G leaves per block
+        const int RM = nrhs == 1 ? 1 : 8;
+        const size_t per_leaf = (size_t)RM * lv.nc * sizeof(cx<T>);
+        int G = leaves_per_block((double)nt / nbox, L2P_THREADS);
+        const int gmax = (int)((48 * 1024) / per_leaf);
+        G = G > gmax ? gmax : G;
+        G = G < 1 ? 1 : G;
+        const dim3 grid((nbox + G - 1) / G, (nrhs + RM - 1) / RM);
+#define LMFMM_L2P_PACKED(RMC)                                                                                      \
+    LMFMM_LAUNCH((k_l2p<T, PMAX, RMC>), grid, dim3(L2P_THREADS), G * per_leaf, st, start, end, idx, xs, ys, ns, nt, \
+                 nrhs, lv.P, nbox, lv.ncol, lv.col_lo, g.x_lo, lv.w, k2, invR, Lc + lv.off_t, shift, key_t0, G,    \
+                 do_far, unear, unear ? nparts : 0, reinterpret_cast<cx<T> *>(u))
+        if (nrhs == 1)
+            LMFMM_L2P_PACKED(1);
+        else
+            LMFMM_L2P_PACKED(8);
+#undef LMFMM_L2P_PACKED
+        return;
+    }
+    // near field by pairs: one leaf per block
 #define LMFMM_L2P_LAUNCH(RM)                                                                                      \
     LMFMM_LAUNCH((k_l2p_near<T, PMAX, RM>), dim3(nbox, (nrhs + RM - 1) / RM), dim3(64), sh, st, start, end, idx, xs, \
                  ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo,  \

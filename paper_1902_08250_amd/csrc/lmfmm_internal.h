@@ -262,26 +262,29 @@ constexpr int NGL = 16;  // Gauss-Legendre points per panel
 // tree.hip
 // sources must satisfy 0 < y < ys_lim, targets yt_lim < y < 0
 // bounding box and bad-point count of both point sets in one launch: the last
-// block writes out[0..6] and then the 64-bit sequence number seq at out + 8
-// (host-mapped memory) and rearms counter (zero between launches)
+// block writes out[0..6] and then the 64-bit sequence number at out + 8
+// (host-mapped memory) and rearms counter (zero between launches).  The
+// sequence number is *dseq + 1, stored back to *dseq (device memory, zero at
+// first), so that launches replayed from a graph still number their results.
 void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
-                 double *partial, unsigned *counter, int nblk, double *out, uint64_t seq, hipStream_t st);
+                 double *partial, unsigned *counter, uint64_t *dseq, int nblk, double *out, hipStream_t st);
 void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st);
 int bbox_blocks(int64_t n);
 // Points grouped by leaf (counting sort; every leaf in increasing original
 // index).  cnt: nbox counts, zero on entry.  Results: start/end[nbox] (leaf
 // ranges in the grouped order), idx[n] (original index, targets offset by
 // n_src), xs/ys[n] (grouped coordinates).  key, perm: n; scratch: 2n.
+// Tree-build buffers.  cnt (one counter per leaf) must be zero when a build
+// starts; each build leaves it zero.  err[0] collects the build's error flag,
+// err[1] receives it at the scan (err[0] is then cleared).
 struct TreeBufs {
     uint32_t *key;
-    int32_t *cnt, *start, *end, *perm, *scratch, *idx;
+    int32_t *rank, *cnt, *start, *end, *perm, *scratch, *idx;
     double *xs, *ys;
 };
 void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
                  int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, const TreeBufs &b, int32_t *err,
                  hipStream_t st);
-// zero three int32 ranges in one launch
-void launch_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb, int32_t *c, int64_t nc, hipStream_t st);
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 
 

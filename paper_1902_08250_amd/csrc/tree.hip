@@ -34,36 +34,53 @@ __device__ inline double wave_sum(double v)
 }
 
 // Per-block partial bounding box: xmin, xmax over all points; source y min/max;
-// target y min/max; count of points outside their layer or not finite.
+// target y min/max; count of points outside their layer or not finite.  The
+// points are taken as one sequence, sources then targets, in chunks of
+// BB_PER * BB_THREADS per block; a thread issues the loads of its BB_PER points
+// before using any of them.
+constexpr int BB_PER = 4;
 __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__restrict__ src, int64_t ns,
                                                              const double *__restrict__ tgt, int64_t nt,
                                                              double ys_lim, double yt_lim, double *partial,
-                                                             unsigned *counter, double *out, uint64_t seq)
+                                                             unsigned *counter, uint64_t *dseq, double *out)
 {
     double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += stride) {
-        double x = src[i], y = src[ns + i];
-        bool ok = isfinite(x) && isfinite(y) && y > 0.0 && y < ys_lim;
-        if (ok) {
-            v[0] = fmin(v[0], x);
-            v[1] = fmax(v[1], x);
-            v[2] = fmin(v[2], y);
-            v[3] = fmax(v[3], y);
-        } else {
-            v[6] += 1.0;
+    const int64_t n = ns + nt, chunk = (int64_t)BB_PER * BB_THREADS;
+    for (int64_t base = (int64_t)blockIdx.x * chunk; base < n; base += (int64_t)gridDim.x * chunk) {
+        double x[BB_PER], y[BB_PER];
+#pragma unroll
+        for (int k = 0; k < BB_PER; ++k) {
+            const int64_t i = base + k * BB_THREADS + threadIdx.x;
+            x[k] = 0.0;
+            y[k] = 0.0;
+            if (i < ns) {
+                x[k] = src[i];
+                y[k] = src[ns + i];
+            } else if (i < n) {
+                x[k] = tgt[i - ns];
+                y[k] = tgt[nt + i - ns];
+            }
         }
-    }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
-        double x = tgt[i], y = tgt[nt + i];
-        bool ok = isfinite(x) && isfinite(y) && y < 0.0 && y > yt_lim;
-        if (ok) {
-            v[0] = fmin(v[0], x);
-            v[1] = fmax(v[1], x);
-            v[4] = fmin(v[4], y);
-            v[5] = fmax(v[5], y);
-        } else {
-            v[6] += 1.0;
+#pragma unroll
+        for (int k = 0; k < BB_PER; ++k) {
+            const int64_t i = base + k * BB_THREADS + threadIdx.x;
+            if (i >= n) continue;
+            const bool tg = i >= ns;
+            const bool ok = isfinite(x[k]) && isfinite(y[k]) && (tg ? (y[k] < 0.0 && y[k] > yt_lim)
+                                                                    : (y[k] > 0.0 && y[k] < ys_lim));
+            if (!ok) {
+                v[6] += 1.0;
+                continue;
+            }
+            v[0] = fmin(v[0], x[k]);
+            v[1] = fmax(v[1], x[k]);
+            if (tg) {
+                v[4] = fmin(v[4], y[k]);
+                v[5] = fmax(v[5], y[k]);
+            } else {
+                v[2] = fmin(v[2], y[k]);
+                v[3] = fmax(v[3], y[k]);
+            }
         }
     }
     __shared__ double red[BB_THREADS / 64][7];
@@ -118,7 +135,10 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
     v2[5] = wave_max(v2[5]);
     v2[6] = wave_sum(v2[6]);
     if (threadIdx.x == 0) {
-        // result, then its sequence number, in host-visible memory; rearm the counter
+        // result, then its sequence number (one more than the last kernel's,
+        // kept in device memory), in host-visible memory; rearm the counter
+        const uint64_t seq = *dseq + 1;
+        *dseq = seq;
         for (int j = 0; j < 7; ++j) __hip_atomic_store(&out[j], v2[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(reinterpret_cast<uint64_t *>(out + 8), seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -129,12 +149,16 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
 // Leaf key of every point.  Sources (y > 0) take row floor(y/w) above the
 // interface, targets row floor(-y/w) below it; columns are relative to
 // col_lo.  Out-of-range rows/columns (points outside a fixed domain) and
-// points in the wrong layer raise the error flag and are clamped.
+// points in the wrong layer raise the error flag and are clamped.  The
+// counter's old value is the point's slot within its leaf (in arrival order;
+// the leaf pass sorts each leaf by original index).  The counters start at
+// zero: the scan of the previous build cleared them.
 __global__ void __launch_bounds__(256) k_tree_count(const double *__restrict__ src, int64_t ns,
                                                     const double *__restrict__ tgt, int64_t nt, double x_lo,
                                                     double invw, int col_lo, int ncol, int rows_s, int rows_t,
                                                     double ys_lim, double yt_lim, uint32_t *__restrict__ key,
-                                                    int32_t *__restrict__ cnt, int32_t *__restrict__ err)
+                                                    int32_t *__restrict__ rank, int32_t *__restrict__ cnt,
+                                                    int32_t *__restrict__ err)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns + nt) return;
@@ -152,19 +176,28 @@ __global__ void __launch_bounds__(256) k_tree_count(const double *__restrict__ s
     uint32_t k = (uint32_t)r * (uint32_t)ncol + (uint32_t)c;
     if (tg) k += (uint32_t)rows_s * (uint32_t)ncol;
     key[i] = k;
-    atomicAdd(&cnt[k], 1);
+    rank[i] = atomicAdd(&cnt[k], 1);
 }
 
 // Exclusive scan of the leaf counts by one block, in LDS tiles of SC_TILE
-// counts (loaded and stored coalesced): start[b], end[b]; the counts become
-// the scatter cursors (= start).
+// counts (loaded and stored coalesced): start[b], end[b].  The counters are
+// cleared for the next build, and the error flag of this build is moved to
+// err[1], where the host reads it (err[0] is cleared).  Counts that do not add
+// up to the number of points (counters not zero at the start) leave every
+// leaf empty and set bit 1 of err[1], so that no later kernel indexes with
+// them.
 constexpr int SC_THREADS = 1024, SC_PER = 8, SC_TILE = SC_THREADS * SC_PER;
-__global__ void __launch_bounds__(SC_THREADS) k_tree_scan(int32_t *__restrict__ cnt, int64_t nbox,
-                                                          int32_t *__restrict__ start, int32_t *__restrict__ end)
+__global__ void __launch_bounds__(SC_THREADS) k_tree_scan(int32_t *__restrict__ cnt, int64_t nbox, int64_t n,
+                                                          int32_t *__restrict__ start, int32_t *__restrict__ end,
+                                                          int32_t *__restrict__ err)
 {
     __shared__ int32_t tile[SC_TILE];
     __shared__ int32_t wsum[SC_THREADS / 64];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) {
+        err[1] = err[0];
+        err[0] = 0;
+    }
     int32_t carry = 0;
     for (int64_t t0 = 0; t0 < nbox; t0 += SC_TILE) {
 #pragma unroll
@@ -211,20 +244,28 @@ __global__ void __launch_bounds__(SC_THREADS) k_tree_scan(int32_t *__restrict__ 
                 int32_t n_b = cnt[b];
                 start[b] = st;
                 end[b] = st + n_b;
-                cnt[b] = st;
+                cnt[b] = 0;
             }
         }
         __syncthreads();
     }
+    if ((int64_t)carry != n) {
+        for (int64_t b = t; b < nbox; b += SC_THREADS) {
+            start[b] = 0;
+            end[b] = 0;
+        }
+        if (t == 0) err[1] |= 2;
+    }
 }
 
-__global__ void __launch_bounds__(256) k_tree_scatter(const uint32_t *__restrict__ key, int64_t n,
-                                                      int32_t *__restrict__ cursor, int32_t *__restrict__ perm)
+__global__ void __launch_bounds__(256) k_tree_scatter(const uint32_t *__restrict__ key,
+                                                      const int32_t *__restrict__ rank, int64_t n,
+                                                      const int32_t *__restrict__ start, int32_t *__restrict__ perm)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int32_t pos = atomicAdd(&cursor[key[i]], 1);
-    perm[pos] = (int32_t)i;
+    const int64_t pos = (int64_t)start[key[i]] + rank[i];
+    if (pos >= 0 && pos < n) perm[pos] = (int32_t)i;
 }
 
 __device__ inline void cswap(int32_t &a, int32_t &b, bool up)
@@ -299,8 +340,6 @@ __global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
     if (i < n) p[i] = 0u;
 }
 
-
-// Leaf ranges [start, end) per key and the sorted coordinates.
 }  // namespace
 
 int bbox_blocks(int64_t n)
@@ -314,10 +353,10 @@ int bbox_blocks(int64_t n)
 }
 
 void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
-                 double *partial, unsigned *counter, int nblk, double *out, uint64_t seq, hipStream_t st)
+                 double *partial, unsigned *counter, uint64_t *dseq, int nblk, double *out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(BB_THREADS), 0, st, src, ns, tgt, nt, ys_lim, yt_lim,
-                       partial, counter, out, seq);
+                       partial, counter, dseq, out);
 }
 
 
@@ -337,26 +376,6 @@ void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st)
 }
 
 
-__global__ void __launch_bounds__(256) k_zero3(int32_t *__restrict__ a, int64_t na, int32_t *__restrict__ b,
-                                               int64_t nb, int32_t *__restrict__ c, int64_t nc)
-{
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < na)
-        a[i] = 0;
-    else if (i < na + nb)
-        b[i - na] = 0;
-    else if (i < na + nb + nc)
-        c[i - na - nb] = 0;
-}
-
-void launch_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb, int32_t *c, int64_t nc, hipStream_t st)
-{
-    int64_t n = na + nb + nc;
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_zero3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, na, b, nb, c, nc);
-}
-
-
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st)
 {
     int64_t n = (int64_t)(nbytes / 4);
@@ -373,9 +392,9 @@ void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, d
     if (n == 0 || nbox == 0) return;
     const unsigned g = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_tree_count, dim3(g), dim3(256), 0, st, src, ns, tgt, nt, x_lo, 1.0 / w, col_lo, ncol, rows_s,
-                       rows_t, ys_lim, yt_lim, b.key, b.cnt, err);
-    hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(SC_THREADS), 0, st, b.cnt, nbox, b.start, b.end);
-    hipLaunchKernelGGL(k_tree_scatter, dim3(g), dim3(256), 0, st, b.key, n, b.cnt, b.perm);
+                       rows_t, ys_lim, yt_lim, b.key, b.rank, b.cnt, err);
+    hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(SC_THREADS), 0, st, b.cnt, nbox, n, b.start, b.end, err);
+    hipLaunchKernelGGL(k_tree_scatter, dim3(g), dim3(256), 0, st, b.key, b.rank, n, b.start, b.perm);
     hipLaunchKernelGGL(k_tree_leaf, dim3((unsigned)nbox), dim3(64), 0, st, b.start, b.end, b.perm, b.scratch, b.idx,
                        src, ns, tgt, nt, b.xs, b.ys);
 }
