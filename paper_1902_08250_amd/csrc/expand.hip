@@ -19,27 +19,29 @@
 // range.  Layout: [box][rhs][2P+1] complex, box = row * ncol + column.
 #include "lmfmm_internal.h"
 
+#include <atomic>
+
 namespace lmfmm {
 
 namespace {
 
 // ---------------------------------------------------------------------------
 // P2M: a block takes G consecutive source leaves, whose points are contiguous
-// in the sorted order, and walks those points in chunks of CH: a thread per
-// point evaluates the point's scaled basis into LDS, then threads over
-// (leaf, right-hand side, coefficient) add the points of their leaf in the
-// chunk, in index order.  The output block of the G leaves is contiguous, and
+// in the grouped order (as are their densities, qs), and walks those points in
+// chunks of CH: a thread per point evaluates the point's scaled basis into
+// LDS, then threads over (leaf, right-hand side, coefficient) add the points
+// of their leaf in the chunk, in index order.  The output block of the G leaves is contiguous, and
 // so are the threads' stores.  Leaves without points get zeros.
 // ---------------------------------------------------------------------------
 constexpr int P2M_THREADS = 256;
 constexpr int LEAF_GMAX = 32;  // leaves per block (P2M and L2P)
 template <typename T, int PMAX>
 __global__ void __launch_bounds__(P2M_THREADS) k_p2m(const int32_t *__restrict__ start,
-                                                     const int32_t *__restrict__ end, const int32_t *__restrict__ idx,
-                                                     const double *__restrict__ xs, const double *__restrict__ ys,
-                                                     const cx<T> *__restrict__ q, int64_t ns, int nrhs, int P,
-                                                     int nbox, int ncol, int col_lo, double x_lo, double w,
-                                                     cx<T> k1, T invR, int G, int CH, cx<T> *__restrict__ M)
+                                                     const int32_t *__restrict__ end, const double *__restrict__ xs,
+                                                     const double *__restrict__ ys, const cx<T> *__restrict__ qs,
+                                                     int64_t ns, int nrhs, int P, int nbox, int ncol, int col_lo,
+                                                     double x_lo, double w, cx<T> k1, T invR, int G, int CH,
+                                                     cx<T> *__restrict__ M)
 {
     extern __shared__ unsigned char smem_raw[];
     __shared__ int bnd[LEAF_GMAX + 1];
@@ -64,8 +66,7 @@ __global__ void __launch_bounds__(P2M_THREADS) k_p2m(const int32_t *__restrict__
             const double cxp = x_lo + (col + 0.5) * w, cyp = (row + 0.5) * w;
             const T X = (T)(xs[j] - cxp), Y = (T)(ys[j] - cyp);
             bessel_basis<T, PMAX>(k1, X, Y, invR, P, -1, B + t * nc, 1);
-            const int64_t o = idx[j];
-            for (int r = 0; r < nrhs; ++r) Q[t * nrhs + r] = q[(int64_t)r * ns + o];
+            for (int r = 0; r < nrhs; ++r) Q[t * nrhs + r] = qs[(int64_t)r * ns + j];
         }
         __syncthreads();
         const int cend = E - c0 < CH ? E : c0 + CH;
@@ -73,8 +74,21 @@ __global__ void __launch_bounds__(P2M_THREADS) k_p2m(const int32_t *__restrict__
             const int g = it / nout, o = it - g * nout;
             const int r = o / nc, c = o - r * nc;
             const int j0 = bnd[g] > c0 ? bnd[g] : c0, j1 = bnd[g + 1] < cend ? bnd[g + 1] : cend;
+            // in increasing point order; four points' LDS reads issued together
+            const cx<T> *bp = B + (j0 - c0) * nc + c, *qp = Q + (j0 - c0) * nrhs + r;
+            const int np = j1 - j0;
             cx<T> acc = mk<T>(0, 0);
-            for (int jj = j0; jj < j1; ++jj) cfma(acc, B[(jj - c0) * nc + c], Q[(jj - c0) * nrhs + r]);
+            int jj = 0;
+            for (; jj + 4 <= np; jj += 4) {
+                const cx<T> b0 = bp[jj * nc], b1 = bp[(jj + 1) * nc], b2 = bp[(jj + 2) * nc], b3 = bp[(jj + 3) * nc];
+                const cx<T> q0 = qp[jj * nrhs], q1 = qp[(jj + 1) * nrhs], q2 = qp[(jj + 2) * nrhs],
+                            q3 = qp[(jj + 3) * nrhs];
+                cfma(acc, b0, q0);
+                cfma(acc, b1, q1);
+                cfma(acc, b2, q2);
+                cfma(acc, b3, q3);
+            }
+            for (; jj < np; ++jj) cfma(acc, bp[jj * nc], qp[jj * nrhs]);
             if (c0 == S)
                 Mb[it] = acc;
             else if (j1 > j0)
@@ -121,17 +135,21 @@ __device__ inline void item_matvec(const cx<T> *__restrict__ A, int nk, int nout
     const int pc = p < nout ? p : nout - 1;
     for (int k0 = 0; k0 < nk; k0 += KC) {
         const int kc = nk - k0 < KC ? nk - k0 : KC;
-        __builtin_amdgcn_wave_barrier();
-        if (lane < KC)
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                lds.x[r][lane] = (r < nr && lane < kc) ? x[r * xstride + k0 + lane] : mk<T>(0, 0);
+        // the table loads first, then the vector's: both round trips overlap
         cx<T> av[KC];
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
             const int k = k0 + (j < kc ? j : kc - 1);
             av[j] = A[(int64_t)k * nout + pc];
         }
+        cx<T> xv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            xv[r] = (lane < kc && r < nr) ? x[r * xstride + k0 + lane] : mk<T>(0, 0);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < KC)
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds.x[r][lane] = xv[r];
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int j0 = 0; j0 < KC; j0 += 8) {
@@ -451,6 +469,15 @@ __global__ void __launch_bounds__(L2P_THREADS) k_l2p(const int32_t *__restrict__
     __syncthreads();
     const int S = bnd[0], E = bnd[ng];
     if (E <= S) return;
+    // the first chunk's points: their loads are in flight while the leaf
+    // expansions are formed
+    double px = 0.0, py = 0.0;
+    int32_t pid = 0;
+    if (S + t < E) {
+        px = xs[S + t];
+        py = ys[S + t];
+        pid = idx[S + t];
+    }
     if (do_far && sh.tab) {
         for (int g = wv; g < ng; g += L2P_THREADS / 64) {
             if (bnd[g + 1] <= bnd[g]) continue;  // no targets in this leaf
@@ -491,6 +518,11 @@ __global__ void __launch_bounds__(L2P_THREADS) k_l2p(const int32_t *__restrict__
     for (int c0 = S; c0 < E; c0 += L2P_THREADS) {
         const int i = c0 + t;
         if (i >= E) break;
+        if (c0 != S) {
+            px = xs[i];
+            py = ys[i];
+            pid = idx[i];
+        }
         int g = 0;
         while (i >= bnd[g + 1]) ++g;
         const int box = b0 + g, row = box / ncol, col = col_lo + box % ncol;
@@ -498,10 +530,9 @@ __global__ void __launch_bounds__(L2P_THREADS) k_l2p(const int32_t *__restrict__
         for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
         if (do_far) {
             const double cxp = x_lo + (col + 0.5) * w, cyp = -(row + 0.5) * w;
-            eval_local<T, PMAX, RMAX>(k2, (T)(xs[i] - cxp), (T)(ys[i] - cyp), invR, P, Ls + g * RMAX * nc, nr,
-                                      res);
+            eval_local<T, PMAX, RMAX>(k2, (T)(px - cxp), (T)(py - cyp), invR, P, Ls + g * RMAX * nc, nr, res);
         }
-        const int64_t o = idx[i] - ns;
+        const int64_t o = pid - ns;
         if (unear && row == 0)
             for (int pp = 0; pp < nparts; ++pp)
                 for (int r = 0; r < RMAX; ++r)
@@ -974,33 +1005,68 @@ __global__ void __launch_bounds__(256) k_direct_reduce(const cx<double> *__restr
     u[o] = mk<T>((T)v.re, (T)v.im);
 }
 
-// Leaves per block: about 3/4 of the block's threads busy with points at the
-// mean occupancy.
-inline int leaves_per_block(double mean, int threads)
+
+// Compute units and LDS bytes per compute unit of the current device.
+struct DeviceShape {
+    int cus = 256;
+    int lds = 160 * 1024;
+};
+DeviceShape device_shape()
 {
-    int G = (int)std::floor(0.75 * threads / (mean > 0.5 ? mean : 0.5));
-    return G < 1 ? 1 : (G > LEAF_GMAX ? LEAF_GMAX : G);
+    static std::atomic<int> cus_cache[64], lds_cache[64];
+    DeviceShape d;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return d;
+    if (!cus_cache[dev].load()) {
+        int v = 0, m = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = d.cus;
+        if (hipDeviceGetAttribute(&m, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+            m <= 0)
+            m = d.lds;
+        lds_cache[dev].store(m);
+        cus_cache[dev].store(v);
+    }
+    d.cus = cus_cache[dev].load();
+    d.lds = lds_cache[dev].load();
+    return d;
+}
+
+// Leaves per block for a kernel of `threads` threads per block over nbox leaves
+// holding npts points: the fewest blocks per compute unit (at most max_per_cu)
+// that keep a block's points within 4/5 of its threads, then as many leaves
+// per block as fill that many blocks on every compute unit.  A grid just
+// under a multiple of the compute units balances the blocks per unit.
+inline int leaves_per_block(int64_t nbox, int64_t npts, int threads, int max_per_cu)
+{
+    const DeviceShape dv = device_shape();
+    int64_t k = (int64_t)std::ceil((double)npts / (0.8 * threads * dv.cus));
+    k = k < 1 ? 1 : (k > max_per_cu ? max_per_cu : k);
+    int64_t G = (nbox + k * dv.cus - 1) / (k * dv.cus);
+    return (int)(G < 1 ? 1 : (G > LEAF_GMAX ? LEAF_GMAX : G));
 }
 
 template <typename T, int PMAX>
-void p2m_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
-                  const void *q, int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
+void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
+                  int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
 {
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_s * lv.ncol;
     if (nbox == 0) return;
-    const int G = leaves_per_block((double)ns / nbox, P2M_THREADS);
-    // points per chunk: one per thread, as far as 64 KB of LDS allow
+    // points per chunk: one per thread, as far as 72 KB of LDS allow (two
+    // blocks per compute unit)
     const size_t per = (size_t)(lv.nc + nrhs) * sizeof(cx<T>);
-    int CH = (int)((64 * 1024) / per);
+    int CH = (int)((72 * 1024) / per);
     CH = CH > P2M_THREADS ? P2M_THREADS : (CH < 1 ? 1 : CH);
     const size_t sh = (size_t)CH * per;
+    int per_cu = (int)(device_shape().lds / (sh > 0 ? sh : 1));
+    per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+    const int G = leaves_per_block(nbox, ns, CH, per_cu);
     cx<double> kd = k_src(med);
     cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
-    LMFMM_LAUNCH((k_p2m<T, PMAX>), dim3((nbox + G - 1) / G), dim3(P2M_THREADS), sh, st, start, end, idx, xs, ys,
-                 reinterpret_cast<const cx<T> *>(q), ns, nrhs, lv.P, nbox, lv.ncol, lv.col_lo, g.x_lo, lv.w, k1, invR,
-                 G, CH, M + lv.off_s);
+    LMFMM_LAUNCH((k_p2m<T, PMAX>), dim3((nbox + G - 1) / G), dim3(P2M_THREADS), sh, st, start, end, xs, ys,
+                 reinterpret_cast<const cx<T> *>(qs), ns, nrhs, lv.P, nbox, lv.ncol, lv.col_lo, g.x_lo, lv.w, k1,
+                 invR, G, CH, M + lv.off_s);
 }
 
 template <typename T, int PMAX>
@@ -1022,7 +1088,7 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
         // far field plus, if any, the sweep's near-field parts: G leaves per block
         const int RM = nrhs == 1 ? 1 : 8;
         const size_t per_leaf = (size_t)RM * lv.nc * sizeof(cx<T>);
-        int G = leaves_per_block((double)nt / nbox, L2P_THREADS);
+        int G = leaves_per_block(nbox, nt, L2P_THREADS, 3);
         const int gmax = (int)((48 * 1024) / per_leaf);
         G = G > gmax ? gmax : G;
         G = G < 1 ? 1 : G;
@@ -1077,18 +1143,18 @@ void grad_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx,
 }  // namespace
 
 template <typename T>
-void launch_p2m(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
-                const void *q, int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
+void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
+                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
 {
     int P = g.lev[g.L].P;
     if (P <= 16)
-        p2m_dispatch<T, 16>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, st);
+        p2m_dispatch<T, 16>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
     else if (P <= 32)
-        p2m_dispatch<T, 32>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, st);
+        p2m_dispatch<T, 32>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
     else if (P <= 64)
-        p2m_dispatch<T, 64>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, st);
+        p2m_dispatch<T, 64>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
     else
-        p2m_dispatch<T, 256>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, st);
+        p2m_dispatch<T, 256>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
 }
 
 template <typename T>
@@ -1261,8 +1327,8 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
 }
 
 #define LMFMM_INST(T)                                                                                               \
-    template void launch_p2m<T>(const int32_t *, const int32_t *, const int32_t *, const double *, const double *,   \
-                                const void *, int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);        \
+    template void launch_p2m<T>(const int32_t *, const int32_t *, const double *, const double *, const void *,      \
+                                int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);                      \
     template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int, hipStream_t);                   \
     template void launch_down<T>(const Geometry &, int, const cx<T> *, const int *, const int *, int, const cx<T> *, \
                                  cx<T> *, int, const cx<T> *, bool, int, hipStream_t);                              \

@@ -261,13 +261,14 @@ constexpr int NGL = 16;  // Gauss-Legendre points per panel
 // ---------------------------------------------------------------------------
 // tree.hip
 // sources must satisfy 0 < y < ys_lim, targets yt_lim < y < 0
-// bounding box and bad-point count of both point sets in one launch: the last
-// block writes out[0..6] and then the 64-bit sequence number at out + 8
-// (host-mapped memory) and rearms counter (zero between launches).  The
-// sequence number is *dseq + 1, stored back to *dseq (device memory, zero at
-// first), so that launches replayed from a graph still number their results.
+// bounding box and bad-point count of both point sets: nblk = bbox_blocks(n)
+// blocks write partials (partial[nblk][8]), one wave reduces them and writes
+// out[0..6] and then the 64-bit sequence number at out + 8 (host-mapped
+// memory).  The sequence number is *dseq + 1, stored back to *dseq (device
+// memory, zero at first), so that launches replayed from a graph still
+// number their results.
 void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
-                 double *partial, unsigned *counter, uint64_t *dseq, int nblk, double *out, hipStream_t st);
+                 double *partial, uint64_t *dseq, int nblk, double *out, hipStream_t st);
 void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st);
 int bbox_blocks(int64_t n);
 // Points grouped by leaf (counting sort; every leaf in increasing original
@@ -276,11 +277,16 @@ int bbox_blocks(int64_t n);
 // n_src), xs/ys[n] (grouped coordinates).  key, perm: n; scratch: 2n.
 // Tree-build buffers.  cnt (one counter per leaf) must be zero when a build
 // starts; each build leaves it zero.  err[0] collects the build's error flag,
-// err[1] receives it at the scan (err[0] is then cleared).
+// err[1] receives it at the scan (err[0] is then cleared).  The densities q
+// ([nrhs][ns] elements of qw 64-bit words) are copied in the sources' grouped
+// order to qs (same layout), unless q is null.
 struct TreeBufs {
     uint32_t *key;
     int32_t *rank, *cnt, *start, *end, *perm, *scratch, *idx;
     double *xs, *ys;
+    const uint64_t *q = nullptr;
+    uint64_t *qs = nullptr;
+    int nrhs = 0, qw = 0;
 };
 void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
                  int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, const TreeBufs &b, int32_t *err,
@@ -290,8 +296,8 @@ void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 
 // expand.hip (T = double or float)
 template <typename T>
-void launch_p2m(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
-                const void *q, int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st);
+void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
+                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st);
 template <typename T>
 void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int nrhs, hipStream_t st);
 // downward pass of level l: M2L (atab non-null; class slots of target row r:

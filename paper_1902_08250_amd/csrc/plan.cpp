@@ -243,7 +243,7 @@ struct lmfmm_plan_s {
     double *h_bbox = nullptr;  // pinned, host-coherent: [0..6] box, [8] sequence number, [12] error copy
     double *d_bbox = nullptr;  // its device address
     uint64_t bbox_seq = 0;
-    DevBuf bbox_dev;           // per-block partials [512][8], then the block counter
+    DevBuf bbox_dev;           // per-block partials [512][8], then the sequence counter (at [512][1])
 
     // cached tables of the forward (0) and transposed (1) operator
     VarTables vt[2];
@@ -910,10 +910,8 @@ static void bbox_launch(lmfmm_plan p, const Medium &med, int64_t ns, const doubl
                         const double *tgt, hipStream_t st)
 {
     double *part = (double *)p->bbox_dev.p;
-    unsigned *counter = (unsigned *)(part + 8 * 512);
     uint64_t *dseq = (uint64_t *)(part + 8 * 512 + 1);
-    launch_bbox(src, ns, tgt, nt, ys_limit(med), yt_limit(med), part, counter, dseq, bbox_blocks(ns + nt),
-                p->d_bbox, st);
+    launch_bbox(src, ns, tgt, nt, ys_limit(med), yt_limit(med), part, dseq, bbox_blocks(ns + nt), p->d_bbox, st);
 }
 
 // Wait for the result of the bbox_seq-th launch: spin on its sequence number
@@ -1150,6 +1148,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     int64_t nbox = (int64_t)(lv.rows_s + lv.rows_t) * lv.ncol;
     size_t need = 0;
     need += 6 * (size_t)n * 4 + 3 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
+    need += (size_t)ns * nrhs * sizeof(cx<T>) + 256;  // densities in grouped order
     need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 20 * 256;
     const int ltop = g.ltop;
     // near-field sweep results: up to 4 node parts x nrhs x targets (FP64)
@@ -1175,6 +1174,10 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     tb.end = cv.take<int32_t>(nbox);
     tb.xs = cv.take<double>(n);
     tb.ys = cv.take<double>(n);
+    tb.q = reinterpret_cast<const uint64_t *>(q);
+    tb.qs = cv.take<uint64_t>((size_t)ns * nrhs * (sizeof(cx<T>) / 8));
+    tb.nrhs = nrhs;
+    tb.qw = (int)(sizeof(cx<T>) / 8);
     int32_t *start = tb.start, *end = tb.end, *idx = tb.idx;
     double *xs = tb.xs, *ys = tb.ys;
     cx<T> *M = cv.take<cx<T>>(g.ncoef_s > 0 ? g.ncoef_s : 1);
@@ -1182,7 +1185,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     p->d_err = err;
     p->err_valid = n > 0 && nbox > 0;
     cx<double> *unear = sweep ? cv.take<cx<double>>(nun) : nullptr;
-    int tree_launches = (have_bb ? 0 : 1) + 4;
+    int tree_launches = (have_bb ? 0 : 2) + 4;
     if (p->tz_gen != p->ws.gen || zero_bytes > p->tz_bytes) {
         launch_zero_bytes(p->ws.p, zero_bytes, st);
         ++tree_launches;
@@ -1204,7 +1207,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         LeafShift<T> shift;
         if (far) {
             timed(LMFMM_K_P2M, 1);
-            launch_p2m<T>(start, end, idx, xs, ys, q, ns, nrhs, g, med, M, sx);
+            launch_p2m<T>(start, end, xs, ys, tb.qs, ns, nrhs, g, med, M, sx);
             timed_done();
             for (int l = L; l >= ltop + 1; --l) {
                 const LevelTables &tb = vt.lt[l];

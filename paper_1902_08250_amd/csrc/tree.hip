@@ -5,10 +5,11 @@
 // every box holds either sources (above) or targets (below).  A leaf key is
 // (row, column) of the level-L box; target keys follow all source keys, so one
 // grouping orders both point sets and the grouped array holds sources first.
-// Grouping is a counting sort: per-leaf counts (atomics), one exclusive scan
-// for the leaf ranges, a scatter (atomic cursors), and a per-leaf sort of the
-// scattered original indices, so that every leaf lists its points in
-// increasing original index whatever order the atomics took.
+// Grouping is a counting sort: per-leaf counts (atomics, whose old values are
+// the points' slots), one exclusive scan for the leaf ranges, a scatter to the
+// slots, and a per-leaf sort of the scattered original indices, so that every
+// leaf lists its points in increasing original index whatever order the
+// atomics took.
 #include "lmfmm_internal.h"
 
 namespace lmfmm {
@@ -41,8 +42,8 @@ __device__ inline double wave_sum(double v)
 constexpr int BB_PER = 4;
 __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__restrict__ src, int64_t ns,
                                                              const double *__restrict__ tgt, int64_t nt,
-                                                             double ys_lim, double yt_lim, double *partial,
-                                                             unsigned *counter, uint64_t *dseq, double *out)
+                                                             double ys_lim, double yt_lim,
+                                                             double *__restrict__ partial)
 {
     double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
     const int64_t n = ns + nt, chunk = (int64_t)BB_PER * BB_THREADS;
@@ -96,7 +97,6 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
     if (lane == 0)
         for (int j = 0; j < 7; ++j) red[wv][j] = r[j];
     __syncthreads();
-    __shared__ int last;
     if (threadIdx.x == 0) {
         for (int w = 1; w < BB_THREADS / 64; ++w) {
             r[0] = fmin(r[0], red[w][0]);
@@ -107,18 +107,21 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
             r[5] = fmax(r[5], red[w][5]);
             r[6] += red[w][6];
         }
-        for (int j = 0; j < 7; ++j)
-            __hip_atomic_store(&partial[blockIdx.x * 8 + j], r[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = t == gridDim.x - 1;
+        for (int j = 0; j < 7; ++j) partial[blockIdx.x * 8 + j] = r[j];
     }
-    __syncthreads();
-    if (!last || threadIdx.x >= 64) return;
-    // the last block to finish: reduce the partials of all blocks
+}
+
+// One wave reduces the nblk partials and writes the box to host-visible
+// memory, then its sequence number: one more than the previous launch's, kept
+// in device memory (*dseq), so that launches replayed from a graph still
+// number their results.
+__global__ void __launch_bounds__(64) k_bbox_final(const double *__restrict__ partial, int nblk,
+                                                   uint64_t *__restrict__ dseq, double *out)
+{
     double v2[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) {
+    for (int b = threadIdx.x; b < nblk; b += 64) {
         double q[7];
-        for (int j = 0; j < 7; ++j) q[j] = __hip_atomic_load(&partial[b * 8 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = 0; j < 7; ++j) q[j] = partial[b * 8 + j];
         v2[0] = fmin(v2[0], q[0]);
         v2[1] = fmax(v2[1], q[1]);
         v2[2] = fmin(v2[2], q[2]);
@@ -135,13 +138,10 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
     v2[5] = wave_max(v2[5]);
     v2[6] = wave_sum(v2[6]);
     if (threadIdx.x == 0) {
-        // result, then its sequence number (one more than the last kernel's,
-        // kept in device memory), in host-visible memory; rearm the counter
         const uint64_t seq = *dseq + 1;
         *dseq = seq;
         for (int j = 0; j < 7; ++j) __hip_atomic_store(&out[j], v2[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(reinterpret_cast<uint64_t *>(out + 8), seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -285,7 +285,9 @@ __global__ void __launch_bounds__(64) k_tree_leaf(const int32_t *__restrict__ st
                                                   const int32_t *__restrict__ perm, int32_t *__restrict__ scratch,
                                                   int32_t *__restrict__ idx, const double *__restrict__ src,
                                                   int64_t ns, const double *__restrict__ tgt, int64_t nt,
-                                                  double *__restrict__ xs, double *__restrict__ ys)
+                                                  double *__restrict__ xs, double *__restrict__ ys,
+                                                  const uint64_t *__restrict__ q, uint64_t *__restrict__ qs,
+                                                  int nrhs, int qw)
 {
     __shared__ int32_t sh[LF_LDS];
     const int b = blockIdx.x, lane = threadIdx.x;
@@ -296,6 +298,10 @@ __global__ void __launch_bounds__(64) k_tree_leaf(const int32_t *__restrict__ st
         if (o < ns) {
             xs[s + k] = src[o];
             ys[s + k] = src[ns + o];
+            if (q)
+                for (int r = 0; r < nrhs; ++r)
+                    for (int w = 0; w < qw; ++w)
+                        qs[((int64_t)r * ns + s + k) * qw + w] = q[((int64_t)r * ns + o) * qw + w];
         } else {
             xs[s + k] = tgt[o - ns];
             ys[s + k] = tgt[nt + o - ns];
@@ -344,8 +350,7 @@ __global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
 
 int bbox_blocks(int64_t n)
 {
-    // about 1024 points per block, at most 256 blocks (the last block's first
-    // wave reduces at most four partials per lane)
+    // about 1024 points per block, at most 256 blocks (partials of 8 doubles)
     int64_t b = (n + 1023) / 1024;
     if (b < 1) b = 1;
     if (b > 256) b = 256;
@@ -353,10 +358,11 @@ int bbox_blocks(int64_t n)
 }
 
 void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
-                 double *partial, unsigned *counter, uint64_t *dseq, int nblk, double *out, hipStream_t st)
+                 double *partial, uint64_t *dseq, int nblk, double *out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(BB_THREADS), 0, st, src, ns, tgt, nt, ys_lim, yt_lim,
-                       partial, counter, dseq, out);
+                       partial);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, partial, nblk, dseq, out);
 }
 
 
@@ -396,7 +402,7 @@ void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, d
     hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(SC_THREADS), 0, st, b.cnt, nbox, n, b.start, b.end, err);
     hipLaunchKernelGGL(k_tree_scatter, dim3(g), dim3(256), 0, st, b.key, b.rank, n, b.start, b.perm);
     hipLaunchKernelGGL(k_tree_leaf, dim3((unsigned)nbox), dim3(64), 0, st, b.start, b.end, b.perm, b.scratch, b.idx,
-                       src, ns, tgt, nt, b.xs, b.ys);
+                       src, ns, tgt, nt, b.xs, b.ys, b.q, b.qs, b.nrhs, b.qw);
 }
 
 }  // namespace lmfmm
