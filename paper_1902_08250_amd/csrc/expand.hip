@@ -34,6 +34,7 @@ namespace {
 // so are the threads' stores.  Leaves without points get zeros.
 // ---------------------------------------------------------------------------
 constexpr int P2M_THREADS = 256;
+constexpr int P2M_CHMAX = 320;  // points per chunk (a thread evaluates up to two)
 constexpr int LEAF_GMAX = 32;  // leaves per block (P2M and L2P)
 template <typename T, int PMAX>
 __global__ void __launch_bounds__(P2M_THREADS) k_p2m(const int32_t *__restrict__ start,
@@ -57,16 +58,17 @@ __global__ void __launch_bounds__(P2M_THREADS) k_p2m(const int32_t *__restrict__
     const int nout = nc * nrhs, nitem = ng * nout;
     cx<T> *Mb = M + (int64_t)b0 * nout;
     for (int c0 = S; c0 < E || c0 == S; c0 += CH) {
-        const int j = c0 + t;
-        if (t < CH && j < E) {
+        for (int jl = t; jl < CH; jl += P2M_THREADS) {
+            const int j = c0 + jl;
+            if (j >= E) break;
             int g = 0;
             while (j >= bnd[g + 1]) ++g;
             const int box = b0 + g;
             const int row = box / ncol, col = col_lo + box % ncol;
             const double cxp = x_lo + (col + 0.5) * w, cyp = (row + 0.5) * w;
             const T X = (T)(xs[j] - cxp), Y = (T)(ys[j] - cyp);
-            bessel_basis<T, PMAX>(k1, X, Y, invR, P, -1, B + t * nc, 1);
-            for (int r = 0; r < nrhs; ++r) Q[t * nrhs + r] = qs[(int64_t)r * ns + j];
+            bessel_basis<T, PMAX>(k1, X, Y, invR, P, -1, B + jl * nc, 1);
+            for (int r = 0; r < nrhs; ++r) Q[jl * nrhs + r] = qs[(int64_t)r * ns + j];
         }
         __syncthreads();
         const int cend = E - c0 < CH ? E : c0 + CH;
@@ -319,12 +321,13 @@ struct M2LLevels {
     const int *row_off[M2L_MAXLEV];
 };
 
+constexpr int M2L_DW = 8;  // waves per target box in the M2L launch
 template <typename T>
-__global__ void __launch_bounds__(64 * DW) k_m2l_all(M2LLevels<T> a, int nrhs, const cx<T> *__restrict__ M,
+__global__ void __launch_bounds__(64 * M2L_DW) k_m2l_all(M2LLevels<T> a, int nrhs, const cx<T> *__restrict__ M,
                                                      cx<T> *__restrict__ Lc)
 {
     constexpr int R = Tr<T>::R;
-    __shared__ WaveLds<T> lds[DW];
+    __shared__ WaveLds<T> lds[M2L_DW];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int li = 0;
     while (li + 1 < a.n && (int)blockIdx.x >= a.blk0[li + 1]) ++li;
@@ -340,7 +343,7 @@ __global__ void __launch_bounds__(64 * DW) k_m2l_all(M2LLevels<T> a, int nrhs, c
             cx<T> acc[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
-            for (int i = w; i < nitems; i += DW) {
+            for (int i = w; i < nitems; i += M2L_DW) {
                 const int slot = s0 + i;
                 const int rs = cls3[3 * slot + 1], dc = cls3[3 * slot + 2];
                 const int cs = col + dc, csl = cs - col_lo, dp = (cs >> 1) - (col >> 1);
@@ -348,7 +351,7 @@ __global__ void __launch_bounds__(64 * DW) k_m2l_all(M2LLevels<T> a, int nrhs, c
                     item_matvec<T>(a.atab[li] + (int64_t)slot * nc * nc, nc, nc, p0,
                                    Ms + (((int64_t)rs * ncol + csl) * nrhs + r0) * nc, nc, nr, lds[w], acc);
             }
-            block_reduce_store<T, DW>(lds, acc, nr, p0, nc, Lc + a.off_t[li] + ((int64_t)box * nrhs + r0) * nc, nc);
+            block_reduce_store<T, M2L_DW>(lds, acc, nr, p0, nc, Lc + a.off_t[li] + ((int64_t)box * nrhs + r0) * nc, nc);
         }
     }
 }
@@ -442,9 +445,9 @@ __device__ inline void eval_local(cx<T> k2, T X, T Y, T invR, int P, const cx<T>
 // a thread per target evaluates its leaf's expansion and adds the near-field
 // parts in order.  Writes u[r][original index].
 // ---------------------------------------------------------------------------
-constexpr int L2P_THREADS = 256;
+constexpr int L2P_THREADS = 512;
 template <typename T, int PMAX, int RMAX>
-__global__ void __launch_bounds__(L2P_THREADS) k_l2p(const int32_t *__restrict__ start,
+__global__ void __launch_bounds__(L2P_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_l2p(const int32_t *__restrict__ start,
                                                      const int32_t *__restrict__ end, const int32_t *__restrict__ idx,
                                                      const double *__restrict__ xs, const double *__restrict__ ys,
                                                      int64_t ns, int64_t nt, int nrhs, int P, int nbox, int ncol,
@@ -1052,15 +1055,15 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_s * lv.ncol;
     if (nbox == 0) return;
-    // points per chunk: one per thread, as far as 72 KB of LDS allow (two
-    // blocks per compute unit)
+    // points per chunk: as many as 78 KB of LDS hold (two blocks per compute
+    // unit), at most P2M_CHMAX
     const size_t per = (size_t)(lv.nc + nrhs) * sizeof(cx<T>);
-    int CH = (int)((72 * 1024) / per);
-    CH = CH > P2M_THREADS ? P2M_THREADS : (CH < 1 ? 1 : CH);
+    int CH = (int)((78 * 1024) / per);
+    CH = CH > P2M_CHMAX ? P2M_CHMAX : (CH < 1 ? 1 : CH);
     const size_t sh = (size_t)CH * per;
     int per_cu = (int)(device_shape().lds / (sh > 0 ? sh : 1));
     per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
-    const int G = leaves_per_block(nbox, ns, CH, per_cu);
+    const int G = leaves_per_block(nbox, ns, CH < P2M_THREADS ? CH : P2M_THREADS, per_cu);
     cx<double> kd = k_src(med);
     cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
@@ -1088,7 +1091,10 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
         // far field plus, if any, the sweep's near-field parts: G leaves per block
         const int RM = nrhs == 1 ? 1 : 8;
         const size_t per_leaf = (size_t)RM * lv.nc * sizeof(cx<T>);
-        int G = leaves_per_block(nbox, nt, L2P_THREADS, 3);
+        // about 0.8 x 256 points per block, two blocks per compute unit: one
+        // leaf per wave in the shift phase
+        int G = leaves_per_block(nbox, nt, 256, 2);
+        G = G > L2P_THREADS / 64 ? L2P_THREADS / 64 : G;
         const int gmax = (int)((48 * 1024) / per_leaf);
         G = G > gmax ? gmax : G;
         G = G < 1 ? 1 : G;
@@ -1221,7 +1227,7 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
     }
     a.blk0[a.n] = blk;
     if (blk == 0) return;
-    LMFMM_LAUNCH((k_m2l_all<T>), dim3(blk), dim3(64 * DW), 0, st, a, nrhs, M, Lc);
+    LMFMM_LAUNCH((k_m2l_all<T>), dim3(blk), dim3(64 * M2L_DW), 0, st, a, nrhs, M, Lc);
 }
 
 template <typename T>
