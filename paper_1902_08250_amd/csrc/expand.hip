@@ -270,6 +270,13 @@ __global__ void __launch_bounds__(64 * DW) k_down(DownArgs a, int nrhs, const cx
             cx<T> acc[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+            cx<T> *out = Lc + (box * nrhs + r0) * a.nc;
+            // the stored value to add, loaded before the shift's own loads
+            const int pp = p0 + (threadIdx.x & 63);
+            const bool addp = !m2l_block && row < a.add_rows && pp < a.nc;
+            cx<T> prev[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) prev[r] = (addp && r < nr) ? out[r * a.nc + pp] : mk<T>(0, 0);
             for (int i = first; i < nitems; i += step) {
                 const cx<T> *A, *x;
                 int nk;
@@ -290,15 +297,12 @@ __global__ void __launch_bounds__(64 * DW) k_down(DownArgs a, int nrhs, const cx
                 }
                 if (ok) item_matvec<T>(A, nk, a.nc, p0, x, nk, nr, lds[w], acc);
             }
-            cx<T> *out = Lc + (box * nrhs + r0) * a.nc;
             if (m2l_block) {
                 block_reduce_store<T, DW>(lds, acc, nr, p0, a.nc, out, a.nc);
-            } else {
-                const int p = p0 + (threadIdx.x & 63);
-                if (p < a.nc)
+            } else if (pp < a.nc) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (r < nr) out[r * a.nc + p] = row < a.add_rows ? acc[r] + out[r * a.nc + p] : acc[r];
+                for (int r = 0; r < R; ++r)
+                    if (r < nr) out[r * a.nc + pp] = addp ? acc[r] + prev[r] : acc[r];
             }
         }
     }
@@ -495,18 +499,20 @@ __global__ void __launch_bounds__(L2P_THREADS) __attribute__((amdgpu_waves_per_e
                     cx<T> acc[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+                    const int p = p0 + lane;
+                    // the stored M2L value, loaded before the shift's own loads
+                    cx<T> prev[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        prev[r] = (add && p < nc && r < nrr) ? Lc[((int64_t)box * nrhs + r0 + rr + r) * nc + p]
+                                                             : mk<T>(0, 0);
                     if (pok)
                         item_matvec<T>(sh.tab + (int64_t)pos * sh.ncp * nc, sh.ncp, nc, p0,
                                        x + (int64_t)(r0 + rr) * sh.ncp, sh.ncp, nrr, wl[wv], acc);
-                    const int p = p0 + lane;
                     if (p < nc)
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            if (r < nrr) {
-                                cx<T> v = acc[r];
-                                if (add) v += Lc[((int64_t)box * nrhs + r0 + rr + r) * nc + p];
-                                Ls[(g * RMAX + rr + r) * nc + p] = v;
-                            }
+                            if (r < nrr) Ls[(g * RMAX + rr + r) * nc + p] = add ? acc[r] + prev[r] : acc[r];
                 }
             }
         }
