@@ -85,6 +85,16 @@ __host__ __device__ inline cx<T> cinv(cx<T> a)
     T s = T(1) / (a.re * a.re + a.im * a.im);
     return {a.re * s, -a.im * s};
 }
+// FP32 on the device: the hardware reciprocal of |a|^2 refined by one Newton
+// step, within about one unit in the last place of the division, in far fewer
+// instructions than the IEEE division sequence.
+__device__ inline cx<float> cinv(cx<float> a)
+{
+    const float d = a.re * a.re + a.im * a.im;
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float s = fmaf(fmaf(-d, r, 1.0f), r, r);
+    return {a.re * s, -a.im * s};
+}
 template <typename T>
 __host__ __device__ inline cx<T> cdiv(cx<T> a, cx<T> b) { return a * cinv(b); }
 template <typename T>
