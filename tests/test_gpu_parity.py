@@ -320,3 +320,41 @@ def test_error_decays_with_order(torch_cuda, plain, golden512):
         if a > 1e-10:
             assert b < 0.6 * a
     assert errs[-1] < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_speculative_replay_follows_moving_points(torch_cuda, mid, precision):
+    """Applies on fixed buffers whose sources are rewritten in place.  A graph
+    replay starts before the bounding box is known: it stands when the box is
+    unchanged (a permutation of the sources) and is redone when the box has
+    changed (the sources shifted and shrunk in x).  Every apply equals, bit for
+    bit, a plan without graphs on the same points."""
+    import torch
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("speculative replay with moving sources", precision)
+    dt = np.complex128 if precision == "c128" else np.complex64
+    tol = 1e-10 if precision == "c128" else 1e-6
+    pl = Plan(mid["k"], mid["d"], order=16, tol=tol, levels=5)
+    ref_pl = Plan(mid["k"], mid["d"], order=16, tol=tol, levels=5)
+    ref_pl.set_option("graph", "0")
+    s_host = mid["src"].copy()
+    src, tgt = dev(s_host), dev(mid["tgt"])
+    q = dev(mid["q"][:2].astype(dt))
+    u = torch.empty((2, tgt.shape[1]), dtype=q.dtype, device="cuda")
+    rng = np.random.default_rng(5)
+    for it in range(9):
+        if it == 4:
+            s_host = np.ascontiguousarray(s_host[:, rng.permutation(s_host.shape[1])])
+        if it == 6:
+            s_host = s_host.copy()
+            s_host[0] = 0.9 * s_host[0] + 0.05
+        if it in (4, 6):
+            src.copy_(torch.from_numpy(s_host).cuda())
+            torch.cuda.synchronize()
+        pl.apply(src, q, tgt, out=u)
+        got = host(u)
+        want = host(ref_pl.apply(dev(s_host), q, tgt))
+        assert np.array_equal(got, want), f"apply {it}"
+    st = pl.stats()
+    say("graph applies", st["graph_applies"])
+    assert st["graph_applies"] >= 6
