@@ -257,17 +257,21 @@ def test_graph_replay_matches_direct(torch_cuda, mid, precision):
 
 def test_large_leaves(torch_cuda, plain):
     """Leaves of about 6000 and 300 points (the per-leaf ordering runs in the
-    scratch array and in LDS) next to small ones: FMM against the direct sum,
-    and two applies bit for bit equal."""
+    scratch array and in LDS; a block's points take several chunks) next to
+    small ones, for sources and for targets: FMM against the direct sum, and two
+    applies bit for bit equal."""
     from paper_1902_08250_amd.lmfmm import Plan
-    say("large leaves: clusters of 6000 and 300 sources, levels 3")
+    say("large leaves: clusters of 6000 and 300 sources and of 3000 and 700 targets, levels 3")
     rng = np.random.default_rng(21)
     k, d = plain["k"], plain["d"]
     sa = np.stack([0.2 + 5e-4 * rng.random(6000), 0.3 + 5e-4 * rng.random(6000)])
     sb = np.stack([0.7 + 1e-3 * rng.random(300), 0.6 + 1e-3 * rng.random(300)])
     su = np.stack([rng.random(500), 0.05 + 0.95 * rng.random(500)])
     src = np.ascontiguousarray(np.concatenate([sa, sb, su], axis=1)[:, rng.permutation(6800)])
-    tgt = np.stack([rng.random(400), -0.05 - 0.9 * rng.random(400)])
+    ta = np.stack([0.4 + 5e-4 * rng.random(3000), -0.5 - 5e-4 * rng.random(3000)])
+    tb = np.stack([0.9 + 1e-3 * rng.random(700), -0.2 - 1e-3 * rng.random(700)])
+    tu = np.stack([rng.random(400), -0.05 - 0.9 * rng.random(400)])
+    tgt = np.ascontiguousarray(np.concatenate([ta, tb, tu], axis=1)[:, rng.permutation(4100)])
     q = rng.standard_normal((2, 6800)) + 1j * rng.standard_normal((2, 6800))
     pl = Plan(k, d, order=20, tol=1e-10, levels=3)
     pl.set_option("graph", "0")
@@ -278,6 +282,12 @@ def test_large_leaves(torch_cuda, plain):
     err = rel(u1, ref)
     say("rel-l2 vs direct", err)
     assert err < 1e-10
+    # one right-hand side in mixed precision (the kernels without per-rhs loops)
+    pl32 = Plan(k, d, order=16, tol=1e-6, levels=3)
+    u32 = host(pl32.apply(dev(src), dev(q[:1].astype(np.complex64)), dev(tgt)))
+    err32 = rel(u32.astype(np.complex128), ref[:1])
+    say("mixed, one rhs: rel-l2 vs direct", err32)
+    assert err32 < 5e-6
 
 
 def test_fixed_domain(torch_cuda, mid, mid_direct):
