@@ -87,7 +87,12 @@ int lmfmm_destroy(lmfmm_plan plan);
  *   "graph"       "1" (default): when two consecutive applies have the same
  *                 geometry, pointers, sizes and tables, the second captures
  *                 its launch sequence in a HIP graph and later ones replay it
- *                 (one launch); "0": always launch kernel by kernel
+ *                 (one launch).  Without a fixed domain the graph starts with
+ *                 the bounding-box kernels: an apply with the same pointers,
+ *                 sizes and options launches it before the box is known, and
+ *                 computes again if the box turns out different from the one
+ *                 the graph was captured for.  "0": always launch kernel by
+ *                 kernel
  *   "near_sweep"  "1" (default): near field by x-ordered sweeps over the node
  *                 table; "0": the pairwise sum (same quadrature)
  *   "near"        "1" (default) / "0": include / skip the near field
@@ -106,9 +111,10 @@ int lmfmm_set_option(lmfmm_plan plan, const char *key, const char *value);
  *   u:     output [nrhs][n_tgt], overwritten.
  *   nrhs:  number of right-hand sides, 1 <= nrhs <= 64.
  *   precision: LMFMM_C128 or LMFMM_C64_MIXED (selects the dtype of q and u).
- * Unless the "domain" option is set, the call reads the points' bounding box
- * back to the host (one stream synchronisation).  Points outside their layer
- * are reported as LMFMM_EDOMAIN by the host check of that bounding box, or by
+ * Unless the "domain" option is set, the call waits for the points' bounding
+ * box, which the device writes to host memory (the host spins on it, and after
+ * 20 ms synchronises the stream).  Points outside their layer are reported as
+ * LMFMM_EDOMAIN by the host check of that bounding box, or by
  * lmfmm_sync_status when a fixed domain is used. */
 int lmfmm_apply(lmfmm_plan plan, int64_t n_src, const double *src_xy, const void *q, int64_t n_tgt,
                 const double *tgt_xy, void *u, int nrhs, int precision, void *stream);
