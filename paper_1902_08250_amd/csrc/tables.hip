@@ -100,44 +100,68 @@ __global__ void __launch_bounds__(256) k_m2l_factors(const double *__restrict__ 
     }
 }
 
-// Ahat[c][q][p] = sum_n T[c][p][n] S[c][n][q]; 16x16 output tile per block,
-// FP64 complex with LDS-staged K tiles; writes FP64 and FP32 copies.
-constexpr int CT = 16, CK = 32;
-__global__ void __launch_bounds__(256) k_m2l_contract(const int *__restrict__ cls_P, const int *__restrict__ cls_Q,
-                                                      const int64_t *__restrict__ cls_toff,
-                                                      const int64_t *__restrict__ cls_aoff,
-                                                      const cx<double> *__restrict__ Tm,
-                                                      const cx<double> *__restrict__ Sm, cx<double> *__restrict__ A,
-                                                      cx<float> *__restrict__ A32)
+// Ahat[c][q][p] = sum_n T[c][p][n] S[c][n][q] (the contraction over the
+// class's quadrature nodes in Lemma M2L) on the FP64 matrix cores: a block of
+// CW waves per 16 x 16 output tile, wave w taking the steps of four nodes
+// w, w + CW, ... (CU steps' operands loaded together), v_mfma_f64_16x16x4f64
+// with the complex product as four real products into two accumulators; the
+// waves' sums are added in wave order through LDS.  Operand layout of that
+// instruction: lane l supplies row l % 16, column l / 16 of the 16 x 4 left
+// factor and row l / 16, column l % 16 of the 4 x 16 right factor; its register
+// v returns entry (l / 16 + 4 v, l % 16) of the product.  Writes FP64 and FP32
+// copies.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int CT = 16, CW = 4, CU = 8;
+__global__ void __launch_bounds__(64 * CW) k_m2l_contract(const int *__restrict__ cls_P,
+                                                          const int *__restrict__ cls_Q,
+                                                          const int64_t *__restrict__ cls_toff,
+                                                          const int64_t *__restrict__ cls_aoff,
+                                                          const cx<double> *__restrict__ Tm,
+                                                          const cx<double> *__restrict__ Sm,
+                                                          cx<double> *__restrict__ A, cx<float> *__restrict__ A32)
 {
-    int c = blockIdx.z;
-    int P = cls_P[c], Q = cls_Q[c], nc = 2 * P + 1;
-    int p0 = blockIdx.x * CT, q0 = blockIdx.y * CT;
-    if (p0 >= nc || q0 >= nc) return;
-    const cx<double> *T = Tm + cls_toff[c];
-    const cx<double> *S = Sm + cls_toff[c];
-    __shared__ cx<double> Ts[CT][CK + 1];
-    __shared__ cx<double> Ss[CK][CT + 1];
-    int tx = threadIdx.x % CT, ty = threadIdx.x / CT;  // tx -> p, ty -> q
-    cx<double> acc = {0.0, 0.0};
-    for (int k0 = 0; k0 < Q; k0 += CK) {
-        for (int t = threadIdx.x; t < CT * CK; t += 256) {
-            int pp = t / CK, kk = t % CK;
-            int p = p0 + pp, k = k0 + kk;
-            Ts[pp][kk] = (p < nc && k < Q) ? T[(int64_t)p * Q + k] : mk(0.0, 0.0);
-            int kk2 = t / CT, qq = t % CT;
-            int q = q0 + qq, k2 = k0 + kk2;
-            Ss[kk2][qq] = (q < nc && k2 < Q) ? S[(int64_t)k2 * nc + q] : mk(0.0, 0.0);
+    __shared__ f64x4 part[CW][2][64];
+    const int c = blockIdx.z;
+    const int P = cls_P[c], Q = cls_Q[c], nc = 2 * P + 1;
+    const int p0 = blockIdx.x * CT, q0 = blockIdx.y * CT;
+    if (p0 >= nc || q0 >= nc) return;  // the whole block
+    const cx<double> *T = Tm + cls_toff[c];  // [nc][Q]
+    const cx<double> *S = Sm + cls_toff[c];  // [Q][nc]
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l % 16, lk = l / 16;
+    const int p = p0 + li, q = q0 + li;
+    f64x4 dr = {0.0, 0.0, 0.0, 0.0}, di = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = w * CU; 4 * s0 < Q; s0 += CW * CU) {
+        cx<double> a[CU], b[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int k = 4 * (s0 + u) + lk;
+            a[u] = (p < nc && k < Q) ? T[(int64_t)p * Q + k] : mk(0.0, 0.0);
+            b[u] = (q < nc && k < Q) ? S[(int64_t)k * nc + q] : mk(0.0, 0.0);
         }
-        __syncthreads();
-        for (int kk = 0; kk < CK; ++kk) cfma(acc, Ts[tx][kk], Ss[kk][ty]);
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            dr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].re, b[u].re, dr, 0, 0, 0);
+            dr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].im, b[u].im, dr, 0, 0, 0);
+            di = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].re, b[u].im, di, 0, 0, 0);
+            di = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].im, b[u].re, di, 0, 0, 0);
+        }
     }
-    int p = p0 + tx, q = q0 + ty;
-    if (p < nc && q < nc) {
-        int64_t o = cls_aoff[c] + (int64_t)q * nc + p;
-        A[o] = acc;
-        A32[o] = mk((float)acc.re, (float)acc.im);
+    part[w][0][l] = dr;
+    part[w][1][l] = di;
+    __syncthreads();
+    if (w != 0) return;
+    for (int x = 1; x < CW; ++x) {
+        dr += part[x][0][l];
+        di += part[x][1][l];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int pp = p0 + lk + 4 * v, qq = q0 + li;
+        if (pp < nc && qq < nc) {
+            const int64_t o = cls_aoff[c] + (int64_t)qq * nc + pp;
+            A[o] = mk(dr[v], di[v]);
+            A32[o] = mk((float)dr[v], (float)di[v]);
+        }
     }
 }
 
@@ -158,8 +182,8 @@ void launch_m2l_tables(const double *lamw, const int *node_cls, const int *node_
     hipLaunchKernelGGL(k_m2l_factors, dim3((ntot + 255) / 256), dim3(256), 0, st, lamw, node_cls, node_local, ntot,
                        cls_geo, med, cls_P, cls_Q, cls_toff, Tm, Sm);
     int tiles = (ncmax + CT - 1) / CT;
-    hipLaunchKernelGGL(k_m2l_contract, dim3(tiles, tiles, ncls), dim3(256), 0, st, cls_P, cls_Q, cls_toff, cls_aoff,
-                       Tm, Sm, A, A32);
+    hipLaunchKernelGGL(k_m2l_contract, dim3(tiles, tiles, ncls), dim3(64 * CW), 0, st, cls_P, cls_Q, cls_toff,
+                       cls_aoff, Tm, Sm, A, A32);
 }
 
 }  // namespace lmfmm
