@@ -2,6 +2,8 @@
 
   python -m paper_1902_08250_amd.prof_summary trace KERNEL_STATS_CSV --command CMD
       per-kernel calls, average / total duration (from --kernel-trace --stats)
+  python -m paper_1902_08250_amd.prof_summary counters COUNTER_CSV --command CMD
+      per-kernel averages of the counters of one --pmc pass
   python -m paper_1902_08250_amd.prof_summary traffic FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV \\
          --copy-bytes N --command CMD
       per-kernel HBM bytes per dispatch from two --pmc passes (FETCH_SIZE,
@@ -95,6 +97,24 @@ def traffic(args):
         print("| %s | %d | %.1f | %.1f | bytes_per_launch=%.0f |" % (k, n, a, b, tot * 1024.0))
 
 
+def counters(args):
+    """Per-kernel averages of the counters of one --pmc pass."""
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(args.csv)):
+        agg[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for d in agg.values() for c in d})
+    print("# Counters per dispatch: %s\n" % args.title)
+    print("source_sha256: %s (kernel sources: %s)\n" % (source_hash(), ", ".join(KERNEL_SOURCES)))
+    print("Command (from the repository root on the GPU machine):\n\n```\n%s\n```\n" % args.command)
+    print("| kernel | dispatches | " + " | ".join(names) + " |")
+    print("|---|---:|" + "---:|" * len(names))
+    rows = sorted(agg.items(), key=lambda kv: -sum(kv[1][names[0]]) if kv[1][names[0]] else 0)
+    for k, d in rows:
+        n = max(len(v) for v in d.values())
+        vals = ["%.0f" % (sum(d[c]) / len(d[c])) if d[c] else "" for c in names]
+        print("| %s | %d | %s |" % (k, n, " | ".join(vals)))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -108,8 +128,12 @@ def main(argv=None):
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--command", required=True)
     c.add_argument("--title", default="")
+    k = sub.add_parser("counters")
+    k.add_argument("csv")
+    k.add_argument("--command", required=True)
+    k.add_argument("--title", default="")
     args = ap.parse_args(argv)
-    (trace if args.cmd == "trace" else traffic)(args)
+    {"trace": trace, "traffic": traffic, "counters": counters}[args.cmd](args)
 
 
 if __name__ == "__main__":
