@@ -110,20 +110,28 @@ __global__ void __launch_bounds__(256) k_m2l_factors(const double *__restrict__ 
 // factor and row l / 16, column l % 16 of the 4 x 16 right factor; its register
 // v returns entry (l / 16 + 4 v, l % 16) of the product.  Writes FP64 and FP32
 // copies.
+//
+// Blocks are numbered so that all tiles of a class go to the same XCD (the
+// dispatcher deals consecutive blocks to the eight XCDs in turn): block b
+// takes class ((b / 8) / tiles^2) * 8 + b % 8 and tile (b / 8) % tiles^2, so
+// the class's factor columns come from HBM into one L2 once.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int CT = 16, CW = 4, CU = 8;
+constexpr int CT = 16, CW = 4, CU = 8, NXCD = 8;
 __global__ void __launch_bounds__(64 * CW) k_m2l_contract(const int *__restrict__ cls_P,
                                                           const int *__restrict__ cls_Q,
                                                           const int64_t *__restrict__ cls_toff,
                                                           const int64_t *__restrict__ cls_aoff,
                                                           const cx<double> *__restrict__ Tm,
                                                           const cx<double> *__restrict__ Sm,
-                                                          cx<double> *__restrict__ A, cx<float> *__restrict__ A32)
+                                                          cx<double> *__restrict__ A, cx<float> *__restrict__ A32,
+                                                          int ncls, int tiles)
 {
     __shared__ f64x4 part[CW][2][64];
-    const int c = blockIdx.z;
+    const int b = blockIdx.x, nt2 = tiles * tiles;
+    const int c = ((b / NXCD) / nt2) * NXCD + b % NXCD, tile = (b / NXCD) % nt2;
+    if (c >= ncls) return;  // the whole block
     const int P = cls_P[c], Q = cls_Q[c], nc = 2 * P + 1;
-    const int p0 = blockIdx.x * CT, q0 = blockIdx.y * CT;
+    const int p0 = (tile % tiles) * CT, q0 = (tile / tiles) * CT;
     if (p0 >= nc || q0 >= nc) return;  // the whole block
     const cx<double> *T = Tm + cls_toff[c];  // [nc][Q]
     const cx<double> *S = Sm + cls_toff[c];  // [Q][nc]
@@ -181,9 +189,10 @@ void launch_m2l_tables(const double *lamw, const int *node_cls, const int *node_
     if (ntot <= 0 || ncls <= 0) return;
     hipLaunchKernelGGL(k_m2l_factors, dim3((ntot + 255) / 256), dim3(256), 0, st, lamw, node_cls, node_local, ntot,
                        cls_geo, med, cls_P, cls_Q, cls_toff, Tm, Sm);
-    int tiles = (ncmax + CT - 1) / CT;
-    hipLaunchKernelGGL(k_m2l_contract, dim3(tiles, tiles, ncls), dim3(64 * CW), 0, st, cls_P, cls_Q, cls_toff,
-                       cls_aoff, Tm, Sm, A, A32);
+    const int tiles = (ncmax + CT - 1) / CT;
+    const int64_t nblk = (int64_t)((ncls + NXCD - 1) / NXCD) * NXCD * tiles * tiles;
+    hipLaunchKernelGGL(k_m2l_contract, dim3((unsigned)nblk), dim3(64 * CW), 0, st, cls_P, cls_Q, cls_toff, cls_aoff,
+                       Tm, Sm, A, A32, ncls, tiles);
 }
 
 }  // namespace lmfmm

@@ -22,7 +22,7 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_1902_08250_amd/csrc/expand.hip", "paper_1902_08250_amd/csrc/lmfmm_internal.h",
-                  "paper_1902_08250_amd/csrc/tree.hip"]
+                  "paper_1902_08250_amd/csrc/tables.hip", "paper_1902_08250_amd/csrc/tree.hip"]
 
 
 def source_hash():

@@ -196,6 +196,17 @@ def test_edge_cases(torch_cuda, plain, orc):
     bad[1, 5] = 0.2
     with pytest.raises(LMFMMError):
         pl.apply(src, q, dev(bad))
+    # the largest number of right-hand sides (64), FP64 and mixed, against the
+    # direct sum (itself checked against the oracle)
+    q64 = rng.standard_normal((64, 512)) + 1j * rng.standard_normal((64, 512))
+    ref = host(pl.direct(src, dev(q64), tgt))
+    u = host(pl.apply(src, dev(q64), tgt))
+    say("64 rhs rel-l2", rel(u, ref))
+    assert rel(u, ref) < 1e-10
+    pl32 = Plan(plain["k"], plain["d"], order=16, tol=1e-6)
+    u32 = host(pl32.apply(src, dev(q64.astype(np.complex64)), tgt))
+    say("64 rhs mixed rel-l2", rel(u32.astype(np.complex128), ref))
+    assert rel(u32.astype(np.complex128), ref) < 1e-5
 
 
 def test_table_cache_follows_row_counts(torch_cuda, plain, orc):
