@@ -672,8 +672,13 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
 // One block per (row-0 target leaf, rhs chunk of 8, node part); results go to
 // unear[part][rhs][target] and the leaf evaluation adds the parts in order.
 // ---------------------------------------------------------------------------
-constexpr int SW_NMAX = 2048;  // points per block held in LDS
-constexpr int SW_TCH = 64;     // targets per sweep chunk
+// points per block held in LDS (with their densities): small enough that many
+// one-wave blocks share a compute unit; larger point sets take the pairwise sum
+template <int RMAX>
+struct SweepCap {
+    static constexpr int N = RMAX == 1 ? 512 : 256;
+};
+constexpr int SW_TCH = 64;  // targets per sweep chunk
 
 __device__ inline double wave_sum_d(double v)
 {
@@ -689,8 +694,10 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
                                                    const Node *__restrict__ nodes, int nnodes, int nmid, int npan,
                                                    double t0, int nparts, cx<double> *__restrict__ unear)
 {
+    constexpr int SW_NMAX = SweepCap<RMAX>::N;
     __shared__ double sx[SW_NMAX], sy[SW_NMAX];
     __shared__ int sord[SW_NMAX];
+    __shared__ cx<double> sq[SW_NMAX][RMAX];  // the sources' densities
     __shared__ double accr[SW_TCH][RMAX], acci[SW_TCH][RMAX];
     const int cl = blockIdx.x, lane = threadIdx.x;
     const int r0 = blockIdx.y * RMAX, nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
@@ -738,10 +745,15 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
     // nodes of this part
     const int nper = (nnodes + nparts - 1) / nparts;
     const int n0 = part * nper, n1 = n0 + nper < nnodes ? n0 + nper : nnodes;
-    // sources into LDS once
+    // sources and their densities into LDS once
     for (int k = lane; k < nS; k += 64) {
         sx[k] = xs[js + k];
         sy[k] = ys[js + k];
+        const int64_t o = idx[js + k];
+        for (int r = 0; r < RMAX; ++r) {
+            const cx<T> qq = r < nr ? q[(int64_t)(r0 + r) * ns + o] : mk<T>(0, 0);
+            sq[k][r] = cx<double>{(double)qq.re, (double)qq.im};
+        }
     }
     for (int tc = ts; tc < te; tc += SW_TCH) {
         const int nT = te - tc < SW_TCH ? te - tc : SW_TCH;
@@ -792,12 +804,8 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
                     if (it < nS) {
                         // source: V += e^{-s_s y} q
                         cx<double> e = cexp_d(cx<double>{-nd.ssr * y, -nd.ssi * y});
-                        int64_t o = idx[js + it];
                         for (int r = 0; r < RMAX; ++r)
-                            if (r < nr) {
-                                cx<T> qq = q[(int64_t)(r0 + r) * ns + o];
-                                cfma(V[r], e, cx<double>{(double)qq.re, (double)qq.im});
-                            }
+                            if (r < nr) cfma(V[r], e, sq[it][r]);
                     } else {
                         // target: add D e^{s_t y} V summed over the wave's nodes
                         cx<double> e = cexp_d(cx<double>{nd.str * y, nd.sti * y}) * cx<double>{nd.dr, nd.di};
