@@ -661,24 +661,37 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
 // Near field by x-ordered sweeps (S2T over adjacent leaves across the
 // interface).  For a fixed node lam_n of the pair-independent contour, the
 // pair term of source j and target i with x_j <= x_i is
-//   D_n e^{s_t y_i} * e^{i lam_n (x_i - x_j)} * e^{-s_s y_j} q_j,
-// so sweeping the block's points in increasing x while carrying
-//   V_n <- e^{i lam_n (x - x_prev)} V_n  (+ e^{-s_s y_j} q_j at a source)
-// gives sum_{j: x_j <= x_i} at every target; a sweep in decreasing x gives the
-// sources with x_j > x_i (|x_i - x_j| enters by evenness).  Every factor is
-// bounded (Re s >= 0, Im lam >= 0 on the rays, |Im lam| <= h on the bump), and
-// each pair's product equals its term in the pairwise sum.  Lanes are nodes;
-// the node sum at each target is a wave reduction in fixed order.
+//   D_n e^{s_t y_i} * e^{i lam_n (x_i - x_j)} * e^{-s_s y_j} q_j.
+// Writing x_i - x_j = (x_i - b) - (x_j - b) for a base point b <= x_j splits
+// the x factor between the two points, so sweeping the block's points in
+// increasing x while carrying
+//   V_n = sum of e^{-i lam_n (x_j - b) - s_s y_j} q_j over the sources passed
+// gives sum_{j: x_j <= x_i} at a target as D_n e^{i lam_n (x_i - b) + s_t y_i} V_n:
+// one complex exponential per point and node.  The source factor grows like
+// e^{Im lam_n (x_j - b)}; before that exceeds e^{SW_RESCALE} for any node of
+// the wave, the base moves to the current point (V_n <- e^{i lam_n (x - b)} V_n,
+// a decaying factor).  A sweep in decreasing x (base to the right) gives the
+// sources with x_j > x_i (|x_i - x_j| enters by evenness).  Every pair's
+// product equals its term in the pairwise sum.  Lanes are nodes; the node sum
+// at each target is a wave reduction in fixed order.
 // One block per (row-0 target leaf, rhs chunk of 8, node part); results go to
 // unear[part][rhs][target] and the leaf evaluation adds the parts in order.
 // ---------------------------------------------------------------------------
-// points per block held in LDS (with their densities): small enough that many
-// one-wave blocks share a compute unit; larger point sets take the pairwise sum
+// points per block held in LDS (with their densities); larger point sets take
+// the pairwise sum
 template <int RMAX>
 struct SweepCap {
     static constexpr int N = RMAX == 1 ? 512 : 256;
 };
 constexpr int SW_TCH = 64;  // targets per sweep chunk
+constexpr int SW_W = 4;     // waves per block: they take the node groups in turn
+constexpr double SW_RESCALE = 300.0;  // largest exponent of a source factor
+
+__device__ inline double wave_max_d(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
 
 __device__ inline double wave_sum_d(double v)
 {
@@ -687,19 +700,23 @@ __device__ inline double wave_sum_d(double v)
 }
 
 template <typename T, int RMAX>
-__global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
-                                                   const int32_t *__restrict__ idx, const double *__restrict__ xs,
-                                                   const double *__restrict__ ys, const cx<T> *__restrict__ q,
-                                                   int64_t ns, int64_t nt, int nrhs, int ncol, int64_t key_t0,
-                                                   const Node *__restrict__ nodes, int nnodes, int nmid, int npan,
-                                                   double t0, int nparts, cx<double> *__restrict__ unear)
+__global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restrict__ start,
+                                                          const int32_t *__restrict__ end,
+                                                          const int32_t *__restrict__ idx, const double *__restrict__ xs,
+                                                          const double *__restrict__ ys, const cx<T> *__restrict__ q,
+                                                          int64_t ns, int64_t nt, int nrhs, int ncol, int64_t key_t0,
+                                                          const Node *__restrict__ nodes, int nnodes, int nmid,
+                                                          int npan, double t0, int nparts,
+                                                          cx<double> *__restrict__ unear)
 {
-    constexpr int SW_NMAX = SweepCap<RMAX>::N;
+    constexpr int SW_NMAX = SweepCap<RMAX>::N, NT = 64 * SW_W;
     __shared__ double sx[SW_NMAX], sy[SW_NMAX];
-    __shared__ int sord[SW_NMAX];
+    __shared__ double ox[SW_NMAX], oy[SW_NMAX];  // positions in sweep order
+    __shared__ int oi[SW_NMAX];                  // point number in sweep order
     __shared__ cx<double> sq[SW_NMAX][RMAX];  // the sources' densities
-    __shared__ double accr[SW_TCH][RMAX], acci[SW_TCH][RMAX];
-    const int cl = blockIdx.x, lane = threadIdx.x;
+    __shared__ double accr[SW_W][SW_TCH][RMAX], acci[SW_W][SW_TCH][RMAX];  // per wave
+    const int cl = blockIdx.x, t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int r0 = blockIdx.y * RMAX, nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
     const int part = blockIdx.z;
     const int ts = start[key_t0 + cl], te = end[key_t0 + cl];
@@ -721,7 +738,7 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
     cx<double> *un = unear + (int64_t)part * nrhs * nt;
     if (nS + SW_TCH > SW_NMAX) {
         // oversized leaves: pairwise sum, lanes over targets (part 0 only)
-        for (int c0 = ts; c0 < te; c0 += 64) {
+        for (int c0 = ts + 64 * wv; c0 < te; c0 += NT) {
             int i = c0 + lane;
             bool act = i < te;
             int ii = act ? i : ts;
@@ -746,7 +763,7 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
     const int nper = (nnodes + nparts - 1) / nparts;
     const int n0 = part * nper, n1 = n0 + nper < nnodes ? n0 + nper : nnodes;
     // sources and their densities into LDS once
-    for (int k = lane; k < nS; k += 64) {
+    for (int k = t; k < nS; k += NT) {
         sx[k] = xs[js + k];
         sy[k] = ys[js + k];
         const int64_t o = idx[js + k];
@@ -758,17 +775,17 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
     for (int tc = ts; tc < te; tc += SW_TCH) {
         const int nT = te - tc < SW_TCH ? te - tc : SW_TCH;
         const int n = nS + nT;
-        for (int k = lane; k < nT; k += 64) {
+        for (int k = t; k < nT; k += NT) {
             sx[nS + k] = xs[tc + k];
             sy[nS + k] = ys[tc + k];
         }
-        for (int k = lane; k < nT * RMAX; k += 64) {
-            accr[k / RMAX][k % RMAX] = 0.0;
-            acci[k / RMAX][k % RMAX] = 0.0;
+        for (int k = t; k < SW_W * SW_TCH * RMAX; k += NT) {
+            (&accr[0][0][0])[k] = 0.0;
+            (&acci[0][0][0])[k] = 0.0;
         }
         __syncthreads();
         // order by (x, sources before targets, index): rank by counting
-        for (int a = lane; a < n; a += 64) {
+        for (int a = t; a < n; a += NT) {
             double xa = sx[a];
             int ta = a >= nS;
             int rank = 0;
@@ -778,45 +795,55 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
                 bool less = xb < xa || (xb == xa && (tb < ta || (tb == ta && b < a)));
                 rank += less ? 1 : 0;
             }
-            sord[rank] = a;
+            ox[rank] = xa;
+            oy[rank] = sy[a];
+            oi[rank] = a;
         }
         __syncthreads();
-        for (int nb = n0; nb < n1; nb += 64) {
+        // the waves take the groups of 64 nodes in turn; each wave's sums go
+        // to its own accumulators
+        for (int nb = n0 + 64 * wv; nb < n1; nb += NT) {
             const int nn = nb + lane;
             const bool act = nn < n1;
             Node nd = nodes[act ? nn : n0];
             if (!act) nd.dr = nd.di = 0.0;  // contributes nothing
+            const double limax = wave_max_d(fabs(nd.li));
             for (int dir = 0; dir < 2; ++dir) {
                 cx<double> V[RMAX];
                 for (int r = 0; r < RMAX; ++r) V[r] = {0.0, 0.0};
-                double xprev = sx[sord[dir == 0 ? 0 : n - 1]];
+                double xb = ox[dir == 0 ? 0 : n - 1];
                 for (int step = 0; step < n; ++step) {
-                    const int it = sord[dir == 0 ? step : n - 1 - step];
-                    const double x = sx[it], y = sy[it];
-                    const double dx = dir == 0 ? x - xprev : xprev - x;
-                    xprev = x;
-                    // V <- e^{i lam dx} V
-                    double m = exp(-nd.li * dx), sn, cs;
-                    sincos(nd.lr * dx, &sn, &cs);
-                    cx<double> f = {m * cs, m * sn};
-                    for (int r = 0; r < RMAX; ++r)
-                        if (r < nr) V[r] = V[r] * f;
+                    const int k = dir == 0 ? step : n - 1 - step;
+                    const double x = ox[k], y = oy[k];
+                    const int it = oi[k];
+                    double u = dir == 0 ? x - xb : xb - x;  // >= 0
+                    if (limax * u > SW_RESCALE) {
+                        // move the base to x: V <- e^{i lam u} V
+                        const cx<double> f = cexp_d(cx<double>{-nd.li * u, nd.lr * u});
+                        for (int r = 0; r < RMAX; ++r)
+                            if (r < nr) V[r] = V[r] * f;
+                        xb = x;
+                        u = 0.0;
+                    }
                     if (it < nS) {
-                        // source: V += e^{-s_s y} q
-                        cx<double> e = cexp_d(cx<double>{-nd.ssr * y, -nd.ssi * y});
+                        // source: V += e^{-i lam u - s_s y} q
+                        const cx<double> e =
+                            cexp_d(cx<double>{fma(nd.li, u, -nd.ssr * y), fma(-nd.lr, u, -nd.ssi * y)});
                         for (int r = 0; r < RMAX; ++r)
                             if (r < nr) cfma(V[r], e, sq[it][r]);
                     } else {
-                        // target: add D e^{s_t y} V summed over the wave's nodes
-                        cx<double> e = cexp_d(cx<double>{nd.str * y, nd.sti * y}) * cx<double>{nd.dr, nd.di};
+                        // target: add D e^{i lam u + s_t y} V summed over the wave's nodes
+                        const cx<double> e =
+                            cexp_d(cx<double>{fma(-nd.li, u, nd.str * y), fma(nd.lr, u, nd.sti * y)}) *
+                            cx<double>{nd.dr, nd.di};
                         const int tl = it - nS;
                         for (int r = 0; r < RMAX; ++r)
                             if (r < nr) {
                                 cx<double> c = e * V[r];
                                 double cr = wave_sum_d(c.re), ci = wave_sum_d(c.im);
                                 if (lane == 0) {
-                                    accr[tl][r] += cr;
-                                    acci[tl][r] += ci;
+                                    accr[wv][tl][r] += cr;
+                                    acci[wv][tl][r] += ci;
                                 }
                             }
                     }
@@ -824,10 +851,16 @@ __global__ void __launch_bounds__(64) k_near_sweep(const int32_t *__restrict__ s
             }
         }
         __syncthreads();
-        for (int k = lane; k < nT * nr; k += 64) {
+        // the waves' sums in wave order
+        for (int k = t; k < nT * nr; k += NT) {
             int tl = k / nr, r = k % nr;
+            double sr = accr[0][tl][r], si = acci[0][tl][r];
+            for (int w = 1; w < SW_W; ++w) {
+                sr += accr[w][tl][r];
+                si += acci[w][tl][r];
+            }
             int64_t o = idx[tc + tl] - ns;
-            un[(int64_t)(r0 + r) * nt + o] = cx<double>{accr[tl][r], acci[tl][r]};
+            un[(int64_t)(r0 + r) * nt + o] = cx<double>{sr, si};
         }
         __syncthreads();
     }
@@ -1255,8 +1288,9 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
     int nparts = lv.ncol >= 1024 ? 1 : (lv.ncol >= 256 ? 2 : 4);
     int nnodes = nmid + 2 * NGL * npan;
 #define LMFMM_SWEEP_LAUNCH(RM)                                                                                     \
-    LMFMM_LAUNCH((k_near_sweep<T, RM>), dim3(lv.ncol, (nrhs + RM - 1) / RM, nparts), dim3(64), 0, st, start, end, idx, \
-                 xs, ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol, (int64_t)lv.rows_s * lv.ncol,     \
+    LMFMM_LAUNCH((k_near_sweep<T, RM>), dim3(lv.ncol, (nrhs + RM - 1) / RM, nparts), dim3(64 * SW_W), 0, st, start,  \
+                 end, idx, xs, ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol,                       \
+                 (int64_t)lv.rows_s * lv.ncol,                                                                        \
                  nodes, nnodes, nmid, npan, t0, nparts, unear)
     if (nrhs == 1)
         LMFMM_SWEEP_LAUNCH(1);
