@@ -663,8 +663,8 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
 // pair term of source j and target i with x_j <= x_i is
 //   D_n e^{s_t y_i} * e^{i lam_n (x_i - x_j)} * e^{-s_s y_j} q_j.
 // Writing x_i - x_j = (x_i - b) - (x_j - b) for a base point b <= x_j splits
-// the x factor between the two points, so sweeping the block's points in
-// increasing x while carrying
+// the x factor between the two points, so sweeping the points in increasing x
+// while carrying
 //   V_n = sum of e^{-i lam_n (x_j - b) - s_s y_j} q_j over the sources passed
 // gives sum_{j: x_j <= x_i} at a target as D_n e^{i lam_n (x_i - b) + s_t y_i} V_n:
 // one complex exponential per point and node.  The source factor grows like
@@ -672,19 +672,32 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
 // the wave, the base moves to the current point (V_n <- e^{i lam_n (x - b)} V_n,
 // a decaying factor).  A sweep in decreasing x (base to the right) gives the
 // sources with x_j > x_i (|x_i - x_j| enters by evenness).  Every pair's
-// product equals its term in the pairwise sum.  Lanes are nodes; the node sum
-// at each target is a wave reduction in fixed order.
-// One block per (row-0 target leaf, rhs chunk of 8, node part); results go to
+// product equals its term in the pairwise sum.
+//
+// Row-0 leaves are x-intervals, so one sweep runs along a segment of
+// consecutive leaf columns.  It keeps two sums: Vp, the complete sum of the
+// previous leaf's sources, and Vc, the running sum of the current leaf's; a
+// target of leaf c takes Vp + Vc, which is exactly its sources in leaves c - 1
+// and c on the sweep's side.  Entering a leaf, Vp <- Vc and Vc <- 0.  The
+// sweep starts one leaf before the segment (sources only), so each source is
+// visited once per direction and segment instead of once per adjacent target
+// leaf.  Lanes are nodes; the node sum at each target is a wave reduction in
+// fixed order, kept per wave in LDS and added in wave order when a piece of
+// SweepCap::T targets is complete; the increasing-x sweep stores the sum and
+// the decreasing-x sweep adds its own (the same thread handles a target in
+// both).
+// One block per (segment, rhs chunk, node part); results go to
 // unear[part][rhs][target] and the leaf evaluation adds the parts in order.
 // ---------------------------------------------------------------------------
-// points per block held in LDS (with their densities); larger point sets take
-// the pairwise sum
+// points of one leaf column (sources and targets) held in LDS with their
+// densities, and targets per accumulator piece; a segment with a larger leaf
+// takes the pairwise sum
 template <int RMAX>
 struct SweepCap {
     static constexpr int N = RMAX == 1 ? 512 : 256;
+    static constexpr int T = RMAX == 1 ? 128 : 64;
 };
-constexpr int SW_TCH = 64;  // targets per sweep chunk
-constexpr int SW_W = 4;     // waves per block: they take the node groups in turn
+constexpr int SW_W = 4;               // waves per block, one node group each
 constexpr double SW_RESCALE = 300.0;  // largest exponent of a source factor
 
 __device__ inline double wave_max_d(double v)
@@ -693,10 +706,49 @@ __device__ inline double wave_max_d(double v)
     return v;
 }
 
-__device__ inline double wave_sum_d(double v)
+// One DPP lane move of a double (both halves); lanes of rows outside ROWMASK
+// read 0.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_d(double v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the wave in a fixed order, complete in lane 63: pairs, quads,
+// half rows and rows by lane permutations within each row of 16, then row 0
+// into row 1, row 2 into row 3, and rows 0-1 into row 3.
+__device__ inline double wave_total_d(double v)
+{
+    v += dpp_d<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_d<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_d<0x141, 0xf>(v);  // row_half_mirror
+    v += dpp_d<0x140, 0xf>(v);  // row_mirror
+    v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return v;
+}
+
+constexpr int SW_KMAX = 32;  // x-slabs per leaf column at most
+
+// x-slabs of a leaf column of n points: one if they fit in LDS, else slabs of
+// about half the capacity each
+__device__ inline int sweep_slabs(int n, int nmax) { return n <= nmax ? 1 : (n + nmax / 2 - 1) / (nmax / 2); }
+
+// slab of position x in a leaf column starting at xl, K slabs of width 1/sc:
+// nondecreasing in x, so slab order is x order
+__device__ inline int slab_of(double x, double xl, double sc, int K)
+{
+    int b = (int)floor((x - xl) * sc);
+    return b < 0 ? 0 : (b >= K ? K - 1 : b);
+}
+
+__device__ inline int leaf_count(const int32_t *start, const int32_t *end, int64_t k)
+{
+    const int a = start[k], b = end[k];
+    return b > a ? b - a : 0;
 }
 
 template <typename T, int RMAX>
@@ -705,164 +757,255 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
                                                           const int32_t *__restrict__ idx, const double *__restrict__ xs,
                                                           const double *__restrict__ ys, const cx<T> *__restrict__ q,
                                                           int64_t ns, int64_t nt, int nrhs, int ncol, int64_t key_t0,
-                                                          const Node *__restrict__ nodes, int nnodes, int nmid,
-                                                          int npan, double t0, int nparts,
+                                                          int seglen, double xl0, double w,
+                                                          const Node *__restrict__ nodes, int nnodes,
+                                                          int nmid, int npan, double t0, int nparts,
                                                           cx<double> *__restrict__ unear)
 {
-    constexpr int SW_NMAX = SweepCap<RMAX>::N, NT = 64 * SW_W;
-    __shared__ double sx[SW_NMAX], sy[SW_NMAX];
-    __shared__ double ox[SW_NMAX], oy[SW_NMAX];  // positions in sweep order
-    __shared__ int oi[SW_NMAX];                  // point number in sweep order
-    __shared__ cx<double> sq[SW_NMAX][RMAX];  // the sources' densities
-    __shared__ double accr[SW_W][SW_TCH][RMAX], acci[SW_W][SW_TCH][RMAX];  // per wave
-    const int cl = blockIdx.x, t = threadIdx.x, lane = t & 63;
+    constexpr int NMAX = SweepCap<RMAX>::N, TCAP = SweepCap<RMAX>::T, NT = 64 * SW_W;
+    static_assert(TCAP <= NT, "a piece's targets map to distinct threads");
+    __shared__ double sx[NMAX], sy[NMAX];
+    __shared__ double ox[NMAX], oy[NMAX];  // positions in increasing-x order
+    __shared__ int oi[NMAX];               // staging index in increasing-x order (targets: -1 - index)
+    __shared__ int tk[NMAX];               // staging index of the slab's target of each rank
+    __shared__ int lid[NMAX];              // leaf index of each staged point (targets after sources)
+    __shared__ int s_cnt[2];               // staged points, of them targets
+    __shared__ int hist[SW_KMAX];
+    __shared__ cx<double> sq[NMAX][RMAX];  // the sources' densities
+    __shared__ double accr[SW_W][TCAP][RMAX], acci[SW_W][TCAP][RMAX];  // per wave
+    __shared__ int s_big;
+    const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int r0 = blockIdx.y * RMAX, nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
     const int part = blockIdx.z;
-    const int ts = start[key_t0 + cl], te = end[key_t0 + cl];
-    if (te <= ts) return;
-    // the three adjacent row-0 source leaves are consecutive keys, so their
-    // sorted points form one contiguous range
-    int js = 0, je = 0;
-    bool any = false;
-    for (int dc = -1; dc <= 1; ++dc) {
-        int cs = cl + dc;
-        if (cs < 0 || cs >= ncol) continue;
-        int a = start[cs], b = end[cs];
-        if (b <= a) continue;
-        if (!any) js = a;
-        je = b;
-        any = true;
-    }
-    const int nS = any ? je - js : 0;
+    const int c0 = blockIdx.x * seglen, c1 = c0 + seglen < ncol ? c0 + seglen : ncol;
     cx<double> *un = unear + (int64_t)part * nrhs * nt;
-    if (nS + SW_TCH > SW_NMAX) {
-        // oversized leaves: pairwise sum, lanes over targets (part 0 only)
-        for (int c0 = ts + 64 * wv; c0 < te; c0 += NT) {
-            int i = c0 + lane;
-            bool act = i < te;
-            int ii = act ? i : ts;
-            double x1 = xs[ii], y1 = ys[ii];
-            cx<double> res[RMAX];
-            for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
-            if (part == 0)
-                for (int j = js; j < je; ++j) {
-                    cx<double> G = pair_kernel(nodes, nmid, npan, t0, y1, ys[j], fabs(x1 - xs[j]), act);
-                    int64_t o = idx[j];
-                    for (int r = 0; r < nr; ++r) {
-                        cx<T> qq = q[(int64_t)(r0 + r) * ns + o];
-                        cfma(res[r], G, cx<double>{(double)qq.re, (double)qq.im});
+
+    // a leaf column of the segment's range whose x-slabs do not fit in LDS
+    // sends the whole segment to the pairwise sum
+    if (t == 0) s_big = 0;
+    for (int c = (c0 > 0 ? c0 - 1 : 0); c < (c1 < ncol ? c1 + 1 : ncol); ++c) {
+        const int nS = leaf_count(start, end, c), nT = c >= c0 && c < c1 ? leaf_count(start, end, key_t0 + c) : 0;
+        const int n = nS + nT, K = sweep_slabs(n, NMAX);
+        if (K == 1) continue;
+        if (K > SW_KMAX) {
+            if (t == 0) s_big = 1;
+            continue;
+        }
+        const double xl = xl0 + c * w, sc = K / w;
+        __syncthreads();
+        for (int k = t; k < K; k += NT) hist[k] = 0;
+        __syncthreads();
+        for (int k = t; k < n; k += NT) {
+            const double x = xs[k < nS ? start[c] + k : start[key_t0 + c] + k - nS];
+            atomicAdd(&hist[slab_of(x, xl, sc, K)], 1);
+        }
+        __syncthreads();
+        for (int k = t; k < K; k += NT)
+            if (hist[k] > NMAX) s_big = 1;
+    }
+    __syncthreads();
+    if (s_big) {
+        // pairwise sum per target leaf, lanes over targets (part 0 only)
+        for (int cl = c0; cl < c1; ++cl) {
+            const int ts = start[key_t0 + cl], te = end[key_t0 + cl];
+            int js = 0, je = 0;
+            bool any = false;
+            for (int dc = -1; dc <= 1; ++dc) {
+                const int cs = cl + dc;
+                if (cs < 0 || cs >= ncol) continue;
+                const int a = start[cs], b = end[cs];
+                if (b <= a) continue;
+                if (!any) js = a;
+                je = b;
+                any = true;
+            }
+            for (int i0 = ts; i0 < te; i0 += NT) {
+                const int i = i0 + t;
+                const bool act = i < te;
+                const int ii = act ? i : ts;
+                const double x1 = xs[ii], y1 = ys[ii];
+                cx<double> res[RMAX];
+                for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
+                if (part == 0 && any)
+                    for (int j = js; j < je; ++j) {
+                        const cx<double> G = pair_kernel(nodes, nmid, npan, t0, y1, ys[j], fabs(x1 - xs[j]), act);
+                        const int64_t o = idx[j];
+                        for (int r = 0; r < nr; ++r) {
+                            const cx<T> qq = q[(int64_t)(r0 + r) * ns + o];
+                            cfma(res[r], G, cx<double>{(double)qq.re, (double)qq.im});
+                        }
                     }
-                }
-            if (act)
-                for (int r = 0; r < nr; ++r) un[(int64_t)(r0 + r) * nt + (idx[i] - ns)] = res[r];
+                if (act)
+                    for (int r = 0; r < nr; ++r) un[(int64_t)(r0 + r) * nt + (idx[i] - ns)] = res[r];
+            }
         }
         return;
     }
-    // nodes of this part
-    const int nper = (nnodes + nparts - 1) / nparts;
-    const int n0 = part * nper, n1 = n0 + nper < nnodes ? n0 + nper : nnodes;
-    // sources and their densities into LDS once
-    for (int k = t; k < nS; k += NT) {
-        sx[k] = xs[js + k];
-        sy[k] = ys[js + k];
-        const int64_t o = idx[js + k];
-        for (int r = 0; r < RMAX; ++r) {
-            const cx<T> qq = r < nr ? q[(int64_t)(r0 + r) * ns + o] : mk<T>(0, 0);
-            sq[k][r] = cx<double>{(double)qq.re, (double)qq.im};
-        }
+
+    const int ngroups = (nnodes + 63) / 64;
+    const int slots = nparts * SW_W, slot = part * SW_W + wv;
+    const int gpw = ngroups > 0 ? (ngroups + slots - 1) / slots : 1;  // at least one pass writes the targets
+    for (int k = t; k < SW_W * TCAP * RMAX; k += NT) {
+        (&accr[0][0][0])[k] = 0.0;
+        (&acci[0][0][0])[k] = 0.0;
     }
-    for (int tc = ts; tc < te; tc += SW_TCH) {
-        const int nT = te - tc < SW_TCH ? te - tc : SW_TCH;
-        const int n = nS + nT;
-        for (int k = t; k < nT; k += NT) {
-            sx[nS + k] = xs[tc + k];
-            sy[nS + k] = ys[tc + k];
-        }
-        for (int k = t; k < SW_W * SW_TCH * RMAX; k += NT) {
-            (&accr[0][0][0])[k] = 0.0;
-            (&acci[0][0][0])[k] = 0.0;
-        }
-        __syncthreads();
-        // order by (x, sources before targets, index): rank by counting
-        for (int a = t; a < n; a += NT) {
-            double xa = sx[a];
-            int ta = a >= nS;
-            int rank = 0;
-            for (int b = 0; b < n; ++b) {
-                double xb = sx[b];
-                int tb = b >= nS;
-                bool less = xb < xa || (xb == xa && (tb < ta || (tb == ta && b < a)));
-                rank += less ? 1 : 0;
-            }
-            ox[rank] = xa;
-            oy[rank] = sy[a];
-            oi[rank] = a;
-        }
-        __syncthreads();
-        // the waves take the groups of 64 nodes in turn; each wave's sums go
-        // to its own accumulators
-        for (int nb = n0 + 64 * wv; nb < n1; nb += NT) {
-            const int nn = nb + lane;
-            const bool act = nn < n1;
-            Node nd = nodes[act ? nn : n0];
-            if (!act) nd.dr = nd.di = 0.0;  // contributes nothing
-            const double limax = wave_max_d(fabs(nd.li));
-            for (int dir = 0; dir < 2; ++dir) {
-                cx<double> V[RMAX];
-                for (int r = 0; r < RMAX; ++r) V[r] = {0.0, 0.0};
-                double xb = ox[dir == 0 ? 0 : n - 1];
-                for (int step = 0; step < n; ++step) {
-                    const int k = dir == 0 ? step : n - 1 - step;
-                    const double x = ox[k], y = oy[k];
-                    const int it = oi[k];
-                    double u = dir == 0 ? x - xb : xb - x;  // >= 0
-                    if (limax * u > SW_RESCALE) {
-                        // move the base to x: V <- e^{i lam u} V
-                        const cx<double> f = cexp_d(cx<double>{-nd.li * u, nd.lr * u});
-                        for (int r = 0; r < RMAX; ++r)
-                            if (r < nr) V[r] = V[r] * f;
-                        xb = x;
-                        u = 0.0;
+    for (int gi = 0; gi < gpw; ++gi) {
+        const int grp = gi * slots + slot;
+        const bool has = grp < ngroups;  // this wave has a node group
+        const int nn = grp * 64 + lane;
+        const bool act = has && nn < nnodes;
+        Node nd = nodes[act ? nn : 0];
+        if (!act) nd.dr = nd.di = 0.0;  // contributes nothing
+        const double limax = wave_max_d(act ? fabs(nd.li) : 0.0);
+        for (int dir = 0; dir < 2; ++dir) {
+            cx<double> Vp[RMAX], Vc[RMAX];
+            for (int r = 0; r < RMAX; ++r) Vp[r] = Vc[r] = {0.0, 0.0};
+            double xb = 0.0;
+            bool based = false;
+            for (int lc = 0; lc <= c1 - c0; ++lc) {
+                const int c = dir == 0 ? c0 - 1 + lc : c1 - lc;
+                if (c < 0 || c >= ncol) continue;
+                const bool warm = dir == 0 ? c < c0 : c >= c1;  // sources only
+                const int ss = start[c], nS = leaf_count(start, end, c);
+                const int ts = start[key_t0 + c], nT = warm ? 0 : leaf_count(start, end, key_t0 + c);
+                const int n = nS + nT;
+                for (int r = 0; r < RMAX; ++r) {
+                    Vp[r] = Vc[r];
+                    Vc[r] = {0.0, 0.0};
+                }
+                // the leaf in x-slabs that fit in LDS, visited in sweep order
+                const int K = sweep_slabs(n, NMAX);
+                const double xl = xl0 + c * w, sc = K / w;
+                int pbase = 0, pcnt = 0;  // targets flushed so far (sweep order); open piece size
+                int tdone = 0;            // targets of the slabs already visited
+                for (int sl = 0; sl < K; ++sl) {
+                    const int sidx = dir == 0 ? sl : K - 1 - sl;
+                    __syncthreads();  // the previous slab's LDS contents are no longer read
+                    if (t == 0) s_cnt[0] = s_cnt[1] = 0;
+                    __syncthreads();
+                    for (int k = t; k < n; k += NT) {
+                        const bool src = k < nS;
+                        const int64_t gp = src ? ss + k : ts + k - nS;
+                        const double x = xs[gp];
+                        int pos = k;
+                        if (K > 1) {
+                            if (slab_of(x, xl, sc, K) != sidx) continue;
+                            pos = atomicAdd(&s_cnt[0], 1);
+                            if (!src) atomicAdd(&s_cnt[1], 1);
+                        }
+                        sx[pos] = x;
+                        sy[pos] = ys[gp];
+                        lid[pos] = k;
+                        if (src) {
+                            const int64_t o = idx[gp];
+                            for (int r = 0; r < RMAX; ++r) {
+                                const cx<T> qq = r < nr ? q[(int64_t)(r0 + r) * ns + o] : mk<T>(0, 0);
+                                sq[pos][r] = cx<double>{(double)qq.re, (double)qq.im};
+                            }
+                        }
                     }
-                    if (it < nS) {
-                        // source: V += e^{-i lam u - s_s y} q
-                        const cx<double> e =
-                            cexp_d(cx<double>{fma(nd.li, u, -nd.ssr * y), fma(-nd.lr, u, -nd.ssi * y)});
-                        for (int r = 0; r < RMAX; ++r)
-                            if (r < nr) cfma(V[r], e, sq[it][r]);
-                    } else {
-                        // target: add D e^{i lam u + s_t y} V summed over the wave's nodes
-                        const cx<double> e =
-                            cexp_d(cx<double>{fma(-nd.li, u, nd.str * y), fma(nd.lr, u, nd.sti * y)}) *
-                            cx<double>{nd.dr, nd.di};
-                        const int tl = it - nS;
-                        for (int r = 0; r < RMAX; ++r)
-                            if (r < nr) {
-                                cx<double> c = e * V[r];
-                                double cr = wave_sum_d(c.re), ci = wave_sum_d(c.im);
-                                if (lane == 0) {
-                                    accr[wv][tl][r] += cr;
-                                    acci[wv][tl][r] += ci;
+                    __syncthreads();
+                    const int m = K > 1 ? s_cnt[0] : n, mt = K > 1 ? s_cnt[1] : nT;
+                    // order by (x, sources before targets, leaf index): rank by
+                    // counting; targets also get their rank among the slab's targets
+                    for (int a = t; a < m; a += NT) {
+                        const double xa = sx[a];
+                        const int la = lid[a], ta = la >= nS;
+                        int rank = 0, trank = 0;
+                        for (int b = 0; b < m; ++b) {
+                            const double xq = sx[b];
+                            const int lb = lid[b], tb = lb >= nS;
+                            const bool less = xq < xa || (xq == xa && (tb < ta || (tb == ta && lb < la)));
+                            rank += less ? 1 : 0;
+                            trank += less && tb ? 1 : 0;
+                        }
+                        ox[rank] = xa;
+                        oy[rank] = sy[a];
+                        oi[rank] = ta ? -1 - a : a;
+                        if (ta) tk[trank] = a;
+                    }
+                    __syncthreads();
+                    for (int step = 0; step < m; ++step) {
+                        const int k = dir == 0 ? step : m - 1 - step;
+                        const int it = oi[k];
+                        if (has) {
+                            const double x = ox[k], y = oy[k];
+                            if (!based) {
+                                xb = x;
+                                based = true;
+                            }
+                            double u = dir == 0 ? x - xb : xb - x;  // >= 0
+                            if (limax * u > SW_RESCALE) {
+                                // move the base to x: V <- e^{i lam u} V
+                                const cx<double> f = cexp_d(cx<double>{-nd.li * u, nd.lr * u});
+                                for (int r = 0; r < RMAX; ++r)
+                                    if (r < nr) {
+                                        Vp[r] = Vp[r] * f;
+                                        Vc[r] = Vc[r] * f;
+                                    }
+                                xb = x;
+                                u = 0.0;
+                            }
+                            if (it >= 0) {
+                                // source: Vc += e^{-i lam u - s_s y} q
+                                const cx<double> e =
+                                    cexp_d(cx<double>{fma(nd.li, u, -nd.ssr * y), fma(-nd.lr, u, -nd.ssi * y)});
+                                for (int r = 0; r < RMAX; ++r)
+                                    if (r < nr) cfma(Vc[r], e, sq[it][r]);
+                            } else {
+                                // target: add D e^{i lam u + s_t y} (Vp + Vc) summed over the wave's nodes
+                                const cx<double> e =
+                                    cexp_d(cx<double>{fma(-nd.li, u, nd.str * y), fma(nd.lr, u, nd.sti * y)}) *
+                                    cx<double>{nd.dr, nd.di};
+                                for (int r = 0; r < RMAX; ++r)
+                                    if (r < nr) {
+                                        const cx<double> cc = e * (Vp[r] + Vc[r]);
+                                        const double cr = wave_total_d(cc.re), ci = wave_total_d(cc.im);
+                                        if (lane == 63) {
+                                            accr[wv][pcnt][r] += cr;
+                                            acci[wv][pcnt][r] += ci;
+                                        }
+                                    }
+                            }
+                        }
+                        if (it < 0) ++pcnt;
+                        if (pcnt > 0 && (pcnt == TCAP || step == m - 1)) {
+                            // the piece is complete: add the waves' sums in wave
+                            // order; target of x-rank tr goes to thread tr mod NT
+                            __syncthreads();
+                            const int j = dir == 0 ? ((t - pbase) % NT + NT) % NT
+                                                   : ((nT - 1 - pbase - t) % NT + NT) % NT;
+                            if (j < pcnt) {
+                                const int tr = dir == 0 ? pbase + j : nT - 1 - (pbase + j);
+                                const int tlo = dir == 0 ? tdone : nT - tdone - mt;  // x-rank of the slab's first target
+                                const int64_t o = idx[ts + lid[tk[tr - tlo]] - nS] - ns;
+                                for (int r = 0; r < nr; ++r) {
+                                    double sr = accr[0][j][r], si = acci[0][j][r];
+                                    for (int w2 = 1; w2 < SW_W; ++w2) {
+                                        sr += accr[w2][j][r];
+                                        si += acci[w2][j][r];
+                                    }
+                                    cx<double> &dst = un[(int64_t)(r0 + r) * nt + o];
+                                    if (dir == 0 && gi == 0)
+                                        dst = cx<double>{sr, si};
+                                    else
+                                        dst = dst + cx<double>{sr, si};
                                 }
                             }
+                            __syncthreads();
+                            for (int kk = t; kk < SW_W * TCAP * RMAX; kk += NT) {
+                                (&accr[0][0][0])[kk] = 0.0;
+                                (&acci[0][0][0])[kk] = 0.0;
+                            }
+                            pbase += pcnt;
+                            pcnt = 0;
+                        }
                     }
+                    tdone += mt;
                 }
             }
         }
-        __syncthreads();
-        // the waves' sums in wave order
-        for (int k = t; k < nT * nr; k += NT) {
-            int tl = k / nr, r = k % nr;
-            double sr = accr[0][tl][r], si = acci[0][tl][r];
-            for (int w = 1; w < SW_W; ++w) {
-                sr += accr[w][tl][r];
-                si += acci[w][tl][r];
-            }
-            int64_t o = idx[tc + tl] - ns;
-            un[(int64_t)(r0 + r) * nt + o] = cx<double>{sr, si};
-        }
-        __syncthreads();
     }
 }
 
@@ -1284,15 +1427,24 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
 {
     const Level &lv = g.lev[g.L];
     if (lv.rows_t == 0 || lv.rows_s == 0 || lv.ncol == 0) return 0;
-    // split the nodes over parts when there are few leaves
-    int nparts = lv.ncol >= 1024 ? 1 : (lv.ncol >= 256 ? 2 : 4);
-    int nnodes = nmid + 2 * NGL * npan;
-#define LMFMM_SWEEP_LAUNCH(RM)                                                                                     \
-    LMFMM_LAUNCH((k_near_sweep<T, RM>), dim3(lv.ncol, (nrhs + RM - 1) / RM, nparts), dim3(64 * SW_W), 0, st, start,  \
-                 end, idx, xs, ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol,                       \
-                 (int64_t)lv.rows_s * lv.ncol,                                                                        \
+    const int nnodes = nmid + 2 * NGL * npan;
+    // node groups of 64 over up to 4 parts of SW_W waves; segments of leaf
+    // columns long enough to share the sources, short enough for about two
+    // thousand blocks
+    const int ngroups = (nnodes + 63) / 64;
+    int nparts = (ngroups + SW_W - 1) / SW_W;
+    nparts = nparts < 1 ? 1 : (nparts > 4 ? 4 : nparts);
+    const int RM = nrhs == 1 ? 1 : 8;
+    const int nrc = (nrhs + RM - 1) / RM;
+    int64_t seg = (int64_t)lv.ncol * nrc * nparts / 2048;
+    const int seglen = seg < 1 ? 1 : (seg > 16 ? 16 : (int)seg);
+    const int nseg = (lv.ncol + seglen - 1) / seglen;
+#define LMFMM_SWEEP_LAUNCH(R)                                                                                     \
+    LMFMM_LAUNCH((k_near_sweep<T, R>), dim3(nseg, nrc, nparts), dim3(64 * SW_W), 0, st, start, end, idx, xs, ys,  \
+                 reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.ncol, (int64_t)lv.rows_s * lv.ncol, seglen, \
+                 g.x_lo + lv.col_lo * lv.w, lv.w,                                                                  \
                  nodes, nnodes, nmid, npan, t0, nparts, unear)
-    if (nrhs == 1)
+    if (RM == 1)
         LMFMM_SWEEP_LAUNCH(1);
     else
         LMFMM_SWEEP_LAUNCH(8);
