@@ -695,7 +695,7 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
 template <int RMAX>
 struct SweepCap {
     static constexpr int N = RMAX == 1 ? 512 : 256;
-    static constexpr int T = RMAX == 1 ? 128 : 64;
+    static constexpr int T = RMAX == 1 ? 96 : 64;
 };
 constexpr int SW_W = 4;               // waves per block, one node group each
 constexpr double SW_RESCALE = 300.0;  // largest exponent of a source factor
@@ -732,6 +732,64 @@ __device__ inline double wave_total_d(double v)
 }
 
 constexpr int SW_KMAX = 32;  // x-slabs per leaf column at most
+
+// Complex exponential e^{a + ib} for the sweep, from small tables in LDS:
+//   e^a  = 2^m 2^{j/64} e^r  with a = (64m + j) ln2/64 + r, |r| <= ln2/128, and
+//          e^r by its Taylor polynomial to r^5 (remainder < 4e-17 relative);
+//   e^ib = e^{i n pi/32} e^{i r'}  with b = n pi/32 + r', |r'| <= pi/64, and
+//          sin r', cos r' by Taylor polynomials to r'^9 and r'^8 (remainder
+//          < 1e-20 relative).
+// The reductions subtract k ln2/64 and n pi/32 in parts whose leading pieces
+// carry 32 significant bits, so that k and n times them are exact below 2^21
+// (ln2/64 in two parts; pi/32 in three; the constants are the binary
+// expansions of ln2/64 and pi/32 cut after 32 bits, the next 32 bits, and the
+// rounded rest).  |b| above 1e5 takes the library sincos.
+struct CexpTab {
+    double t2[64];  // 2^{j/64}
+    double sn[64];  // sin(j pi/32)
+    double cs[64];  // cos(j pi/32)
+};
+
+__device__ inline void cexp_tab_init(CexpTab &tb, int t, int nthreads)
+{
+    for (int j = t; j < 64; j += nthreads) {
+        tb.t2[j] = exp2(j / 64.0);
+        double sv, cv;
+        sincospi(j / 32.0, &sv, &cv);
+        tb.sn[j] = sv;
+        tb.cs[j] = cv;
+    }
+}
+
+__device__ inline cx<double> cexp_tab(double a, double b, const CexpTab &tb)
+{
+    constexpr double INV_LN2_64 = 0x1.71547652b82fep+6, LN2_64_HI = 0x1.62e42fee00000p-7,
+                     LN2_64_LO = 0x1.a39ef35793c76p-39;
+    constexpr double INV_PI32 = 0x1.45f306dc9c883p+3, PI32_1 = 0x1.921fb54400000p-4,
+                     PI32_2 = 0x1.0b4611a600000p-38, PI32_3 = 0x1.3198a2e037073p-73;
+    a = fmin(fmax(a, -2000.0), 2000.0);  // beyond: 0 or inf either way
+    const double kd = rint(a * INV_LN2_64);
+    const double r = fma(-kd, LN2_64_LO, fma(-kd, LN2_64_HI, a));
+    const int k = (int)kd;
+    const double pr = fma(r, fma(r, fma(r, fma(r, fma(r, 1.0 / 120, 1.0 / 24), 1.0 / 6), 0.5), 1.0), 1.0);
+    const double ea = ldexp(tb.t2[k & 63] * pr, k >> 6);
+    double sb, cb;
+    if (fabs(b) <= 1.0e5) {
+        const double nd = rint(b * INV_PI32);
+        const double rr = fma(-nd, PI32_3, fma(-nd, PI32_2, fma(-nd, PI32_1, b)));
+        const int jn = (int)nd & 63;
+        const double z = rr * rr;
+        const double sr =
+            rr * fma(z, fma(z, fma(z, fma(z, 1.0 / 362880, -1.0 / 5040), 1.0 / 120), -1.0 / 6), 1.0);
+        const double cr = fma(z, fma(z, fma(z, fma(z, 1.0 / 40320, -1.0 / 720), 1.0 / 24), -0.5), 1.0);
+        const double S = tb.sn[jn], C = tb.cs[jn];
+        sb = fma(S, cr, C * sr);
+        cb = fma(C, cr, -S * sr);
+    } else {
+        sincos(b, &sb, &cb);
+    }
+    return {ea * cb, ea * sb};
+}
 
 // x-slabs of a leaf column of n points: one if they fit in LDS, else slabs of
 // about half the capacity each
@@ -771,6 +829,7 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
     __shared__ int lid[NMAX];              // leaf index of each staged point (targets after sources)
     __shared__ int s_cnt[2];               // staged points, of them targets
     __shared__ int hist[SW_KMAX];
+    __shared__ CexpTab ctab;
     __shared__ cx<double> sq[NMAX][RMAX];  // the sources' densities
     __shared__ double accr[SW_W][TCAP][RMAX], acci[SW_W][TCAP][RMAX];  // per wave
     __shared__ int s_big;
@@ -784,6 +843,7 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
     // a leaf column of the segment's range whose x-slabs do not fit in LDS
     // sends the whole segment to the pairwise sum
     if (t == 0) s_big = 0;
+    cexp_tab_init(ctab, t, NT);
     for (int c = (c0 > 0 ? c0 - 1 : 0); c < (c1 < ncol ? c1 + 1 : ncol); ++c) {
         const int nS = leaf_count(start, end, c), nT = c >= c0 && c < c1 ? leaf_count(start, end, key_t0 + c) : 0;
         const int n = nS + nT, K = sweep_slabs(n, NMAX);
@@ -938,7 +998,7 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
                             double u = dir == 0 ? x - xb : xb - x;  // >= 0
                             if (limax * u > SW_RESCALE) {
                                 // move the base to x: V <- e^{i lam u} V
-                                const cx<double> f = cexp_d(cx<double>{-nd.li * u, nd.lr * u});
+                                const cx<double> f = cexp_tab(-nd.li * u, nd.lr * u, ctab);
                                 for (int r = 0; r < RMAX; ++r)
                                     if (r < nr) {
                                         Vp[r] = Vp[r] * f;
@@ -950,13 +1010,13 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
                             if (it >= 0) {
                                 // source: Vc += e^{-i lam u - s_s y} q
                                 const cx<double> e =
-                                    cexp_d(cx<double>{fma(nd.li, u, -nd.ssr * y), fma(-nd.lr, u, -nd.ssi * y)});
+                                    cexp_tab(fma(nd.li, u, -nd.ssr * y), fma(-nd.lr, u, -nd.ssi * y), ctab);
                                 for (int r = 0; r < RMAX; ++r)
                                     if (r < nr) cfma(Vc[r], e, sq[it][r]);
                             } else {
                                 // target: add D e^{i lam u + s_t y} (Vp + Vc) summed over the wave's nodes
                                 const cx<double> e =
-                                    cexp_d(cx<double>{fma(-nd.li, u, nd.str * y), fma(nd.lr, u, nd.sti * y)}) *
+                                    cexp_tab(fma(-nd.li, u, nd.str * y), fma(nd.lr, u, nd.sti * y), ctab) *
                                     cx<double>{nd.dr, nd.di};
                                 for (int r = 0; r < RMAX; ++r)
                                     if (r < nr) {
