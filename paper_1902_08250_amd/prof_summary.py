@@ -21,7 +21,8 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_1902_08250_amd/csrc/expand.hip", "paper_1902_08250_amd/csrc/lmfmm_internal.h",
+KERNEL_SOURCES = ["paper_1902_08250_amd/csrc/cexp_tab.h", "paper_1902_08250_amd/csrc/expand.hip",
+                  "paper_1902_08250_amd/csrc/lmfmm_internal.h",
                   "paper_1902_08250_amd/csrc/tables.hip", "paper_1902_08250_amd/csrc/tree.hip"]
 
 
