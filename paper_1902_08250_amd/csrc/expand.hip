@@ -783,6 +783,22 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
     const int c0 = blockIdx.x * seglen, c1 = c0 + seglen < ncol ? c0 + seglen : ncol;
     cx<double> *un = unear + (int64_t)part * nrhs * nt;
 
+    // no targets: nothing to write; no sources: the targets' sums are zero
+    int ntot = 0, nsrc = 0;
+    for (int c = c0 > 0 ? c0 - 1 : 0; c < (c1 < ncol ? c1 + 1 : ncol); ++c) {
+        nsrc += leaf_count(start, end, c);
+        if (c >= c0 && c < c1) ntot += leaf_count(start, end, key_t0 + c);
+    }
+    if (ntot == 0) return;
+    if (nsrc == 0) {
+        for (int c = c0; c < c1; ++c) {
+            const int ts = start[key_t0 + c], nT = leaf_count(start, end, key_t0 + c);
+            for (int k = t; k < nT * nr; k += NT)
+                un[(int64_t)(r0 + k % nr) * nt + (idx[ts + k / nr] - ns)] = cx<double>{0.0, 0.0};
+        }
+        return;
+    }
+
     // a leaf column of the segment's range whose x-slabs do not fit in LDS
     // sends the whole segment to the pairwise sum
     if (t == 0) s_big = 0;

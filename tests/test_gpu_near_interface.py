@@ -74,28 +74,30 @@ def test_near_interface_full_size(orc):
     assert err_d < 1e-10 and err_o < 1e-10 and err_do < 1e-12
 
 
-# (levels, rhs, cluster): leaf columns above the LDS capacity swept in
+# (levels, rhs, layout): leaf columns above the LDS capacity swept in
 # x-slabs (one and eight right-hand sides), several accumulator pieces per
-# leaf, one-leaf segments, and segments of several leaves, one of them holding
-# a cluster of 700 sources in one slab that sends its segment to the pairwise
-# sum
-SWEEP_CASES = [(6, 1, False), (6, 3, False), (7, 1, False), (8, 3, False), (9, 3, False), (11, 1, False),
-               (11, 1, True)]
+# leaf, one-leaf segments, segments of several leaves, one of them holding a
+# cluster of 700 sources in one slab that sends its segment to the pairwise
+# sum, and sources on the left half only (segments without sources)
+SWEEP_CASES = [(6, 1, "uniform"), (6, 3, "uniform"), (7, 1, "uniform"), (8, 3, "uniform"), (9, 3, "uniform"),
+               (11, 1, "uniform"), (11, 1, "cluster"), (11, 1, "left")]
 
 
-@pytest.mark.parametrize("levels,nrhs,cluster", SWEEP_CASES)
-def test_sweep_matches_pairwise(levels, nrhs, cluster):
+@pytest.mark.parametrize("levels,nrhs,layout", SWEEP_CASES)
+def test_sweep_matches_pairwise(levels, nrhs, layout):
     """The x-ordered sweep and the pairwise near-field sum use the same
     quadrature nodes; they agree to rounding."""
     from paper_1902_08250_amd.lmfmm import Plan
-    say("sweep vs pairwise near field, levels", levels, "rhs", nrhs, "cluster", cluster)
+    say("sweep vs pairwise near field, levels", levels, "rhs", nrhs, layout)
     spec = workloads.make(2, n_src=20000, n_tgt=20000)
     rng = np.random.default_rng(8)
     src, tgt, q, _ = workloads.draw_instance(rng, 20000, 20000, (0, 1), (1e-4, 1e-3), (-1e-3, -1e-4), nrhs)
-    if cluster:
+    if layout == "cluster":
         # 700 sources inside one leaf column (x in [0.5, 0.5 + w/4))
         w = 1.0 / 2 ** levels
         src[0, :700] = 0.5 + rng.uniform(0, w / 4, 700)
+    elif layout == "left":
+        src[0] *= 0.5
     pl = Plan(spec["k"], spec["d"], order=20, tol=1e-10, levels=levels)
     pl.set_option("far", "0")
     a = pl.apply(dev(src), dev(q), dev(tgt)).cpu().numpy()
