@@ -8,7 +8,8 @@ one complete apply (bounding box, tree build, upward pass, M2L, downward pass,
 local evaluation and near field) with all inputs resident in HBM.
 
 Prints one JSON line with the throughput in source-target interactions/s,
-the same workload through the plain FP64 FMM, the batched workload (16
+the same workload through the plain FP64 FMM, the near-interface workload
+(FP64, near field by sweeps), the batched workload (16
 instances with their own media, 4 right-hand sides each) as one graph launch
 against the FP64 FMM applied instance by instance, the roofline of the
 dominant kernel (HIP-event durations of its launches in the timed region,
@@ -49,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 FMM leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-near", action="store_true", help="skip the near-interface leg")
+    ap.add_argument("--only-near", action="store_true", help="run only the near-interface leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     return ap.parse_args()
@@ -178,6 +181,24 @@ def batched_leg(torch, steps, warmup):
             "speedup_vs_fp64_sequential": t64 / tb, "rel_l2_max_vs_fp64_fmm": max(errs)}
 
 
+def near_leg(torch, Plan, steps, warmup):
+    """The near-interface workload (2e5 sources and targets within 1e-3 of
+    the interface, medium k = (40, 60, 50) + 0.01i, d = 0.5, FP64, order 20,
+    12 levels): the near field is the x-ordered sweep of the row-0 leaves."""
+    w = workloads.make(2)
+    inter = float(w["n_src"]) * w["n_tgt"] * w["nrhs"]
+    n = max(3, steps // 4)
+    t, _, st = run_gpu(torch, Plan, w, "c128", n, warmup, timing=True)
+    nap = max(1, st["timed_applies"])
+    sweep_ms = st["kernel_ms"]["near_sweep"] / nap
+    return {"workload": w["name"], "n_src": w["n_src"], "n_tgt": w["n_tgt"], "order": w["order"],
+            "levels": w["levels"], "tol": 1e-10, "dtype": "f64", "steps": n, "value": inter / t,
+            "unit": "interactions/s", "ms_per_step": t * 1e3,
+            "kernel_ms_per_apply": {k: v / nap for k, v in st["kernel_ms"].items() if v > 0},
+            "near_sweep": {"kernel": "k_near_sweep<double, 1>", "ms_per_launch": sweep_ms,
+                           "nodes": st["near_nodes_mid"] + 2 * st["near_nodes_ray"]}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -189,6 +210,9 @@ def main():
         copy_probe(torch, args.copy_probe)
         return
     from paper_1902_08250_amd.lmfmm import Plan
+    if args.only_near:
+        print(json.dumps({"near_interface": near_leg(torch, Plan, args.steps, args.warmup)}), flush=True)
+        return
 
     w = workloads.make(1)
     n_src, n_tgt, nrhs = w["n_src"], w["n_tgt"], w["nrhs"]
@@ -232,6 +256,10 @@ def main():
         out["fp64_fmm"] = {"value": inter / t64, "ms_per_step": t64 * 1e3}
         out["mixed_over_fp64"] = t64 / t_mixed
         out["rel_l2_mixed_vs_fp64_fmm"] = float(np.linalg.norm(u_mixed - u64) / np.linalg.norm(u64))
+    if not args.no_near:
+        out["near_interface"] = near_leg(torch, Plan, args.steps, args.warmup)
+        print(f"[bench] near-interface: {out['near_interface']['ms_per_step']:.3f} ms/step", file=sys.stderr,
+              flush=True)
     if not args.no_batched:
         out["batched"] = batched_leg(torch, args.steps, args.warmup)
         print(f"[bench] batched: {out['batched']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
