@@ -865,9 +865,9 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
     const int ngroups = (nnodes + 63) / 64;
     const int slots = nparts * SW_W, slot = part * SW_W + wv;
     const int gpw = ngroups > 0 ? (ngroups + slots - 1) / slots : 1;  // at least one pass writes the targets
-    for (int k = t; k < SW_W * TCAP * RMAX; k += NT) {
-        (&accr[0][0][0])[k] = 0.0;
-        (&acci[0][0][0])[k] = 0.0;
+    for (int k = lane; k < TCAP * RMAX; k += 64) {
+        (&accr[wv][0][0])[k] = 0.0;
+        (&acci[wv][0][0])[k] = 0.0;
     }
     for (int gi = 0; gi < gpw; ++gi) {
         const int grp = gi * slots + slot;
@@ -1013,9 +1013,11 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
                                 }
                             }
                             __syncthreads();
-                            for (int kk = t; kk < SW_W * TCAP * RMAX; kk += NT) {
-                                (&accr[0][0][0])[kk] = 0.0;
-                                (&acci[0][0][0])[kk] = 0.0;
+                            // each wave clears its own sums: its next additions
+                            // follow in its own program order
+                            for (int kk = lane; kk < TCAP * RMAX; kk += 64) {
+                                (&accr[wv][0][0])[kk] = 0.0;
+                                (&acci[wv][0][0])[kk] = 0.0;
                             }
                             pbase += pcnt;
                             pcnt = 0;
