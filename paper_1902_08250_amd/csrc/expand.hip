@@ -697,6 +697,7 @@ template <int RMAX>
 struct SweepCap {
     static constexpr int N = RMAX == 1 ? 512 : 256;
     static constexpr int T = RMAX == 1 ? 96 : 64;
+    static constexpr int G = RMAX == 1 ? 2 : 1;  // node groups per wave (independent chains)
 };
 constexpr int SW_W = 4;               // waves per block, one node group each
 constexpr double SW_RESCALE = 300.0;  // largest exponent of a source factor
@@ -753,7 +754,7 @@ __device__ inline int leaf_count(const int32_t *start, const int32_t *end, int64
 }
 
 template <typename T, int RMAX>
-__global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restrict__ start,
+__global__ void __launch_bounds__(64 * SW_W) __attribute__((amdgpu_waves_per_eu(4))) k_near_sweep(const int32_t *__restrict__ start,
                                                           const int32_t *__restrict__ end,
                                                           const int32_t *__restrict__ idx, const double *__restrict__ xs,
                                                           const double *__restrict__ ys, const cx<T> *__restrict__ q,
@@ -862,25 +863,33 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
         return;
     }
 
-    const int ngroups = (nnodes + 63) / 64;
+    constexpr int G = SweepCap<RMAX>::G;
+    const int ngroups = (nnodes + 63) / 64, nunits = (ngroups + G - 1) / G;  // a unit: G groups of 64 nodes
     const int slots = nparts * SW_W, slot = part * SW_W + wv;
-    const int gpw = ngroups > 0 ? (ngroups + slots - 1) / slots : 1;  // at least one pass writes the targets
+    const int gpw = nunits > 0 ? (nunits + slots - 1) / slots : 1;  // at least one pass writes the targets
     for (int k = lane; k < TCAP * RMAX; k += 64) {
         (&accr[wv][0][0])[k] = 0.0;
         (&acci[wv][0][0])[k] = 0.0;
     }
     for (int gi = 0; gi < gpw; ++gi) {
-        const int grp = gi * slots + slot;
-        const bool has = grp < ngroups;  // this wave has a node group
-        const int nn = grp * 64 + lane;
-        const bool act = has && nn < nnodes;
-        Node nd = nodes[act ? nn : 0];
-        if (!act) nd.dr = nd.di = 0.0;  // contributes nothing
-        const double limax = wave_max_d(act ? fabs(nd.li) : 0.0);
+        const int unit = gi * slots + slot;
+        const bool has = unit < nunits;  // this wave has node groups
+        Node nd[G];
+        double limax[G];
+        for (int g = 0; g < G; ++g) {
+            const int nn = (unit * G + g) * 64 + lane;
+            const bool act = has && nn < nnodes;
+            nd[g] = nodes[act ? nn : 0];
+            if (!act) nd[g].dr = nd[g].di = 0.0;  // contributes nothing
+            limax[g] = wave_max_d(act ? fabs(nd[g].li) : 0.0);
+        }
         for (int dir = 0; dir < 2; ++dir) {
-            cx<double> Vp[RMAX], Vc[RMAX];
-            for (int r = 0; r < RMAX; ++r) Vp[r] = Vc[r] = {0.0, 0.0};
-            double xb = 0.0;
+            cx<double> Vp[G][RMAX], Vc[G][RMAX];
+            double xb[G];
+            for (int g = 0; g < G; ++g) {
+                xb[g] = 0.0;
+                for (int r = 0; r < RMAX; ++r) Vp[g][r] = Vc[g][r] = {0.0, 0.0};
+            }
             bool based = false;
             for (int lc = 0; lc <= c1 - c0; ++lc) {
                 const int c = dir == 0 ? c0 - 1 + lc : c1 - lc;
@@ -889,10 +898,11 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
                 const int ss = start[c], nS = leaf_count(start, end, c);
                 const int ts = start[key_t0 + c], nT = warm ? 0 : leaf_count(start, end, key_t0 + c);
                 const int n = nS + nT;
-                for (int r = 0; r < RMAX; ++r) {
-                    Vp[r] = Vc[r];
-                    Vc[r] = {0.0, 0.0};
-                }
+                for (int g = 0; g < G; ++g)
+                    for (int r = 0; r < RMAX; ++r) {
+                        Vp[g][r] = Vc[g][r];
+                        Vc[g][r] = {0.0, 0.0};
+                    }
                 // the leaf in x-slabs that fit in LDS, visited in sweep order
                 const int K = sweep_slabs(n, NMAX);
                 const double xl = xl0 + c * w, sc = K / w;
@@ -951,35 +961,40 @@ __global__ void __launch_bounds__(64 * SW_W) k_near_sweep(const int32_t *__restr
                         if (has) {
                             const double x = ox[k], y = oy[k];
                             if (!based) {
-                                xb = x;
+                                for (int g = 0; g < G; ++g) xb[g] = x;
                                 based = true;
                             }
-                            double u = dir == 0 ? x - xb : xb - x;  // >= 0
-                            if (limax * u > SW_RESCALE) {
-                                // move the base to x: V <- e^{i lam u} V
-                                const cx<double> f = cexp_tab(-nd.li * u, nd.lr * u, ctab);
-                                for (int r = 0; r < RMAX; ++r)
-                                    if (r < nr) {
-                                        Vp[r] = Vp[r] * f;
-                                        Vc[r] = Vc[r] * f;
-                                    }
-                                xb = x;
-                                u = 0.0;
+                            cx<double> e[G];
+                            for (int g = 0; g < G; ++g) {
+                                const Node &ng = nd[g];
+                                double u = dir == 0 ? x - xb[g] : xb[g] - x;  // >= 0
+                                if (limax[g] * u > SW_RESCALE) {
+                                    // move the base to x: V <- e^{i lam u} V
+                                    const cx<double> f = cexp_tab(-ng.li * u, ng.lr * u, ctab);
+                                    for (int r = 0; r < RMAX; ++r)
+                                        if (r < nr) {
+                                            Vp[g][r] = Vp[g][r] * f;
+                                            Vc[g][r] = Vc[g][r] * f;
+                                        }
+                                    xb[g] = x;
+                                    u = 0.0;
+                                }
+                                // source: e^{-i lam u - s_s y}; target: D e^{i lam u + s_t y}
+                                e[g] = it >= 0 ? cexp_tab(fma(ng.li, u, -ng.ssr * y), fma(-ng.lr, u, -ng.ssi * y), ctab)
+                                               : cexp_tab(fma(-ng.li, u, ng.str * y), fma(ng.lr, u, ng.sti * y), ctab) *
+                                                     cx<double>{ng.dr, ng.di};
                             }
                             if (it >= 0) {
-                                // source: Vc += e^{-i lam u - s_s y} q
-                                const cx<double> e =
-                                    cexp_tab(fma(nd.li, u, -nd.ssr * y), fma(-nd.lr, u, -nd.ssi * y), ctab);
-                                for (int r = 0; r < RMAX; ++r)
-                                    if (r < nr) cfma(Vc[r], e, sq[it][r]);
+                                // source: Vc += e q
+                                for (int g = 0; g < G; ++g)
+                                    for (int r = 0; r < RMAX; ++r)
+                                        if (r < nr) cfma(Vc[g][r], e[g], sq[it][r]);
                             } else {
-                                // target: add D e^{i lam u + s_t y} (Vp + Vc) summed over the wave's nodes
-                                const cx<double> e =
-                                    cexp_tab(fma(-nd.li, u, nd.str * y), fma(nd.lr, u, nd.sti * y), ctab) *
-                                    cx<double>{nd.dr, nd.di};
+                                // target: add e (Vp + Vc) summed over the wave's nodes
                                 for (int r = 0; r < RMAX; ++r)
                                     if (r < nr) {
-                                        const cx<double> cc = e * (Vp[r] + Vc[r]);
+                                        cx<double> cc = e[0] * (Vp[0][r] + Vc[0][r]);
+                                        for (int g = 1; g < G; ++g) cfma(cc, e[g], Vp[g][r] + Vc[g][r]);
                                         const double cr = wave_total_d(cc.re), ci = wave_total_d(cc.im);
                                         if (lane == 63) {
                                             accr[wv][pcnt][r] += cr;
@@ -1452,10 +1467,11 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
     // node groups of 64 over up to 4 parts of SW_W waves; segments of leaf
     // columns long enough to share the sources, short enough for about two
     // thousand blocks
-    const int ngroups = (nnodes + 63) / 64;
-    int nparts = (ngroups + SW_W - 1) / SW_W;
-    nparts = nparts < 1 ? 1 : (nparts > 4 ? 4 : nparts);
     const int RM = nrhs == 1 ? 1 : 8;
+    const int G = RM == 1 ? SweepCap<1>::G : SweepCap<8>::G;
+    const int nunits = ((nnodes + 63) / 64 + G - 1) / G;
+    int nparts = (nunits + SW_W - 1) / SW_W;
+    nparts = nparts < 1 ? 1 : (nparts > 4 ? 4 : nparts);
     const int nrc = (nrhs + RM - 1) / RM;
     int64_t seg = (int64_t)lv.ncol * nrc * nparts / 2048;
     const int seglen = seg < 1 ? 1 : (seg > 16 ? 16 : (int)seg);
