@@ -682,24 +682,27 @@ __global__ void __launch_bounds__(64) k_l2p_near(const int32_t *__restrict__ sta
 // and c on the sweep's side.  Entering a leaf, Vp <- Vc and Vc <- 0.  The
 // sweep starts one leaf before the segment (sources only), so each source is
 // visited once per direction and segment instead of once per adjacent target
-// leaf.  Lanes are nodes; the node sum at each target is a wave reduction in
-// fixed order, kept per wave in LDS and added in wave order when a piece of
-// SweepCap::T targets is complete; the increasing-x sweep stores the sum and
-// the decreasing-x sweep adds its own (the same thread handles a target in
-// both).
+// leaf.  Lanes are nodes; a wave carries SweepCap::G groups of 64 nodes
+// (independent chains) and adds their terms per lane before one wave
+// reduction in fixed order.  Each wave keeps its target sums in LDS (and
+// clears them itself); they are added in wave order when a piece of
+// SweepCap::T targets or an x-slab is complete.  The increasing-x sweep stores
+// the sum and the decreasing-x sweep adds its own (the same thread handles a
+// target in both).
 // One block per (segment, rhs chunk, node part); results go to
 // unear[part][rhs][target] and the leaf evaluation adds the parts in order.
 // ---------------------------------------------------------------------------
 // points of one leaf column (sources and targets) held in LDS with their
-// densities, and targets per accumulator piece; a segment with a larger leaf
-// takes the pairwise sum
+// densities, targets per accumulator piece, node groups per wave; a larger
+// leaf column is swept in x-slabs, and a segment with a slab that still does
+// not fit takes the pairwise sum
 template <int RMAX>
 struct SweepCap {
     static constexpr int N = RMAX == 1 ? 512 : 256;
     static constexpr int T = RMAX == 1 ? 96 : 64;
     static constexpr int G = RMAX == 1 ? 2 : 1;  // node groups per wave (independent chains)
 };
-constexpr int SW_W = 4;               // waves per block, one node group each
+constexpr int SW_W = 4;               // waves per block
 constexpr double SW_RESCALE = 300.0;  // largest exponent of a source factor
 
 __device__ inline double wave_max_d(double v)
