@@ -186,14 +186,33 @@ int lmfmm_sync_status(lmfmm_plan plan, void *stream);
  * lmfmm_batch_create makes one plan per instance; order_set lists candidate
  * order floors (e.g. {12, 16, 20}) and tol the accuracy every candidate must
  * meet (the order rule of lmfmm_create enforces it).  On the first
- * lmfmm_batch_apply, and whenever the descriptors change, each instance's
- * bounding box is read once, an autotuner times each (order floor, levels)
- * candidate with HIP events and keeps the fastest, and all instances are
- * captured into one HIP graph (four parallel branches).  Later calls with the
- * same descriptors are one hipGraphLaunch on `stream` with no host sync.
- * inst: host array of n_inst descriptors with device pointers; all instances
- * use the same nrhs and precision.  Options: "tune" 0/1 (default 1), "graph"
- * 0/1 (default 1); other keys are forwarded to every instance's plan.
+ * lmfmm_batch_apply, and whenever the descriptors, nrhs or precision change,
+ * the batch prepares:
+ *   - each instance's bounding box is read once and pinned (later applies
+ *     queue no host synchronisation);
+ *   - each instance's (order floor, levels) comes from the tuning cache if it
+ *     holds the instance's key (medium, size buckets, tol, nrhs, precision,
+ *     order set), else an autotuner times every candidate with HIP events and
+ *     keeps the fastest, and the choice is added to the cache;
+ *   - every instance's launch sequence is recorded and the launches of each
+ *     stage (tree passes, P2M, M2M per level, M2L, L2L per level, near field,
+ *     local evaluation) are merged into one launch over all instances, captured
+ *     in a HIP graph.
+ * Later calls with the same descriptors are one hipGraphLaunch on `stream`
+ * with no host synchronisation.  Points rewritten in place must stay inside
+ * the pinned bounding boxes: lmfmm_batch_sync_status reports any instance
+ * whose points left it (its results are then invalid) and makes the next
+ * apply prepare again.
+ * inst: host array of n_inst descriptors with device pointers (read during
+ * the call); all instances use the same nrhs and precision, and u must hold
+ * [nrhs][n_tgt] elements of that precision.  Calls that overlap on one batch
+ * are not allowed (a batch is not thread-safe).
+ * Options (lmfmm_batch_set_option): "tune" 0/1 (default 1), "graph" 0/1
+ * (default 1), "tune_cache" path of the tuning cache (one JSON object per
+ * line; default: the environment variable LMFMM_TUNE_CACHE, else none),
+ * "timing" 1/0/reset (launch the merged sequence with start/stop events per
+ * launch and accumulate the durations per kernel class in
+ * lmfmm_batch_stats); other keys are forwarded to every instance's plan.
  * --------------------------------------------------------------------------- */
 typedef struct lmfmm_batch_s *lmfmm_batch;
 typedef struct {
@@ -205,6 +224,21 @@ typedef struct {
     void *u;              /* device [nrhs][n_tgt], overwritten */
 } lmfmm_instance;
 
+typedef struct {
+    int launches;          /* merged kernel launches per apply               */
+    int instances;
+    int tuned_from_cache;  /* instances whose choice came from the cache     */
+    double prepare_seconds;  /* host wall time of the last preparation      */
+    /* by LMFMM_K_* class: algorithmic work of one apply summed over the
+     * instances (as lmfmm_stats.kernel_flops); with "timing", the summed
+     * event-measured durations and launches of the timed applies          */
+    double kernel_flops[8];
+    double kernel_ms[8];
+    int64_t kernel_launches[8];
+    int64_t timed_applies;
+    int64_t graph_applies;
+} lmfmm_batch_stats;
+
 int lmfmm_batch_create(int n_inst, const double *k /* [n_inst][6] */, const double *d /* [n_inst] */,
                        const int *order_set, int n_orders, double tol, lmfmm_batch *out);
 int lmfmm_batch_destroy(lmfmm_batch batch);
@@ -212,6 +246,11 @@ int lmfmm_batch_set_option(lmfmm_batch batch, const char *key, const char *value
 int lmfmm_batch_apply(lmfmm_batch batch, const lmfmm_instance *inst, int nrhs, int precision, void *stream);
 /* The autotuner's choice for instance i and its measured time per apply (us). */
 int lmfmm_batch_get_choice(lmfmm_batch batch, int i, int *order, int *levels, double *us);
+int lmfmm_batch_get_stats(lmfmm_batch batch, lmfmm_batch_stats *stats);
+/* Synchronize the stream; LMFMM_EDOMAIN if any instance's points left the
+ * bounding box the batch was prepared for or their layer (the next apply then
+ * prepares again), else LMFMM_OK. */
+int lmfmm_batch_sync_status(lmfmm_batch batch, void *stream);
 
 const char *lmfmm_status_string(int status);
 const char *lmfmm_last_error(void);

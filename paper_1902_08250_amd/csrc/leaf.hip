@@ -1,0 +1,809 @@
+// Leaf passes of the FMM on the uniform interface-split quadtree (Algorithm 1,
+// Steps 2 and 4):
+//
+//  * P2M  (source-to-multipole, Definition "Multipole Expansion"): per source
+//    leaf, M_q = sum_j q_j J_q(k1 r_j) e^{-i q theta_j}, stored scaled.
+//  * L2P + S2T (Definition "Local Expansion"; direct interactions): per
+//    target leaf, the leaf's L2L shift, then the local expansion evaluated at
+//    the targets, plus the direct interactions of the adjacent source leaves
+//    across the interface (from the sweep's results, or by pairs).
+//  * The coordinate gradient of the local evaluation and of the direct
+//    interactions.
+//
+// Expansions are stored scaled: Mhat_q = s_q M_q and Lhat_p = L_p / s_p with
+// s_q = |q|! (2/(k R))^|q|, R the box half-diagonal, which keeps FP32 in
+// range.  Layout: [box][rhs][2P+1] complex, box = row * ncol + column.
+#include "lmfmm_internal.h"
+#include "expand_common.h"
+
+#include <atomic>
+
+namespace lmfmm {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// P2M: a block takes G consecutive source leaves, whose points are contiguous
+// in the grouped order (as are their densities, qs), and walks those points in
+// chunks of CH: a thread per point evaluates the point's scaled basis into
+// LDS, then threads over (leaf, right-hand side, coefficient) add the points
+// of their leaf in the chunk, in index order.  The output block of the G leaves is contiguous, and
+// so are the threads' stores.  Leaves without points get zeros.
+// ---------------------------------------------------------------------------
+constexpr int P2M_THREADS = 256;
+constexpr int P2M_CHMAX = 320;  // points per chunk (a thread evaluates up to two)
+constexpr int LEAF_GMAX = 32;  // leaves per block (P2M and L2P)
+template <typename T>
+struct P2MArgs {
+    const int32_t *start, *end;
+    const double *xs, *ys;
+    const cx<T> *qs;
+    int64_t ns;
+    int nrhs, P, nbox, ncol, col_lo;
+    double x_lo, w;
+    cx<T> k1;
+    T invR;
+    int G, CH;
+    cx<T> *M;
+};
+template <typename T, int PMAX>
+__device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
+{
+    const int32_t *__restrict__ start = A.start;
+    const int32_t *__restrict__ end = A.end;
+    const double *__restrict__ xs = A.xs;
+    const double *__restrict__ ys = A.ys;
+    const cx<T> *__restrict__ qs = A.qs;
+    cx<T> *__restrict__ M = A.M;
+    const int64_t ns = A.ns;
+    const int nrhs = A.nrhs, P = A.P, nbox = A.nbox, ncol = A.ncol, col_lo = A.col_lo, G = A.G, CH = A.CH;
+    const double x_lo = A.x_lo, w = A.w;
+    const cx<T> k1 = A.k1;
+    const T invR = A.invR;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int bnd[LEAF_GMAX + 1];
+    const int nc = 2 * P + 1;
+    cx<T> *B = reinterpret_cast<cx<T> *>(smem_raw);  // [CH][nc]
+    cx<T> *Q = B + CH * nc;                          // [CH][nrhs]
+    const int t = threadIdx.x;
+    const int b0 = bx * G;
+    const int ng = nbox - b0 < G ? nbox - b0 : G;
+    if (t <= ng) bnd[t] = t < ng ? start[b0 + t] : end[b0 + ng - 1];
+    __syncthreads();
+    const int S = bnd[0], E = bnd[ng];
+    const int nout = nc * nrhs, nitem = ng * nout;
+    cx<T> *Mb = M + (int64_t)b0 * nout;
+    for (int c0 = S; c0 < E || c0 == S; c0 += CH) {
+        for (int jl = t; jl < CH; jl += P2M_THREADS) {
+            const int j = c0 + jl;
+            if (j >= E) break;
+            int g = 0;
+            while (j >= bnd[g + 1]) ++g;
+            const int box = b0 + g;
+            const int row = box / ncol, col = col_lo + box % ncol;
+            const double cxp = x_lo + (col + 0.5) * w, cyp = (row + 0.5) * w;
+            const T X = (T)(xs[j] - cxp), Y = (T)(ys[j] - cyp);
+            bessel_basis<T, PMAX>(k1, X, Y, invR, P, -1, B + jl * nc, 1);
+            for (int r = 0; r < nrhs; ++r) Q[jl * nrhs + r] = qs[(int64_t)r * ns + j];
+        }
+        __syncthreads();
+        const int cend = E - c0 < CH ? E : c0 + CH;
+        for (int it = t; it < nitem; it += P2M_THREADS) {
+            const int g = it / nout, o = it - g * nout;
+            const int r = o / nc, c = o - r * nc;
+            const int j0 = bnd[g] > c0 ? bnd[g] : c0, j1 = bnd[g + 1] < cend ? bnd[g + 1] : cend;
+            // in increasing point order; four points' LDS reads issued together
+            const cx<T> *bp = B + (j0 - c0) * nc + c, *qp = Q + (j0 - c0) * nrhs + r;
+            const int np = j1 - j0;
+            cx<T> acc = mk<T>(0, 0);
+            int jj = 0;
+            for (; jj + 4 <= np; jj += 4) {
+                const cx<T> b0 = bp[jj * nc], b1 = bp[(jj + 1) * nc], b2 = bp[(jj + 2) * nc], b3 = bp[(jj + 3) * nc];
+                const cx<T> q0 = qp[jj * nrhs], q1 = qp[(jj + 1) * nrhs], q2 = qp[(jj + 2) * nrhs],
+                            q3 = qp[(jj + 3) * nrhs];
+                cfma(acc, b0, q0);
+                cfma(acc, b1, q1);
+                cfma(acc, b2, q2);
+                cfma(acc, b3, q3);
+            }
+            for (; jj < np; ++jj) cfma(acc, bp[jj * nc], qp[jj * nrhs]);
+            if (c0 == S)
+                Mb[it] = acc;
+            else if (j1 > j0)
+                Mb[it] += acc;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int PMAX>
+__global__ void __launch_bounds__(P2M_THREADS) k_p2m(P2MArgs<T> a) { p2m_body<T, PMAX>(a, blockIdx.x); }
+template <typename T, int PMAX>
+__global__ void __launch_bounds__(P2M_THREADS) k_p2m_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    p2m_body<T, PMAX>(static_cast<const P2MArgs<T> *>(m.args)[i], bx);
+}
+
+// ---------------------------------------------------------------------------
+// L2P (Definition "Local Expansion"): res[r] = sum_p Lhat_p J_p(k2 r)
+// e^{i p theta} at the point (X, Y) relative to the leaf centre, from the
+// scaled expansion Ls[r][2P+1], r < nr.
+// ---------------------------------------------------------------------------
+template <typename T, int PMAX, int RMAX>
+__device__ inline void eval_local(cx<T> k2, T X, T Y, T invR, int P, const cx<T> *Ls, int nr, cx<double> (&res)[RMAX])
+{
+    const int nc = 2 * P + 1;
+    cx<T> tm[PMAX + 1];
+    cx<T> J0;
+    bessel_ratios<T, PMAX>(k2, X, Y, P, tm, J0);
+    cx<T> up = mk<T>(X * invR, Y * invR), dn = mk<T>(-X * invR, Y * invR);
+    cx<T> acc[RMAX];
+    for (int r = 0; r < RMAX; ++r) acc[r] = (r < nr) ? J0 * Ls[r * nc + P] : mk<T>(0, 0);
+    cx<T> vp = J0, vm = J0;
+#pragma unroll PUnroll<PMAX>::n
+    for (int p = 1; p <= PMAX; ++p) {
+        if (p <= P) {
+            cx<T> f = T(2 * p) * tm[p];
+            vp = vp * (f * up);
+            vm = vm * (f * dn);
+            for (int r = 0; r < RMAX; ++r)
+                if (r < nr) {
+                    cfma(acc[r], vp, Ls[r * nc + P + p]);
+                    cfma(acc[r], vm, Ls[r * nc + P - p]);
+                }
+        }
+    }
+    for (int r = 0; r < RMAX; ++r) res[r] = {(double)acc[r].re, (double)acc[r].im};
+}
+
+// ---------------------------------------------------------------------------
+// L2P over G consecutive target leaves per block (points contiguous in the
+// sorted order); the near field, if any, comes from the sweep kernel's parts.
+// First the leaves' local expansions go to LDS: by the leaf-level L2L shift of
+// the parent's (Lemma L2L, one leaf per wave at a time), plus the stored M2L
+// result in the interface rows, or copied from the stored expansions.  Then
+// a thread per target evaluates its leaf's expansion and adds the near-field
+// parts in order.  Writes u[r][original index].
+// ---------------------------------------------------------------------------
+constexpr int L2P_THREADS = 512;
+template <typename T>
+struct L2PArgs {
+    const int32_t *start, *end, *idx;
+    const double *xs, *ys;
+    int64_t ns, nt;
+    int nrhs, P, nbox, ncol, col_lo;
+    double x_lo, w;
+    cx<T> k2;
+    T invR;
+    const cx<T> *Lc;
+    LeafShift<T> sh;
+    int64_t key_t0;
+    int G, do_far;
+    const cx<double> *unear;
+    int nparts;
+    cx<T> *u;
+};
+template <typename T, int PMAX, int RMAX>
+__device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, const int by)
+{
+    const int32_t *__restrict__ start = A.start;
+    const int32_t *__restrict__ end = A.end;
+    const int32_t *__restrict__ idx = A.idx;
+    const double *__restrict__ xs = A.xs;
+    const double *__restrict__ ys = A.ys;
+    const cx<T> *__restrict__ Lc = A.Lc;
+    const cx<double> *__restrict__ unear = A.unear;
+    cx<T> *__restrict__ u = A.u;
+    const LeafShift<T> &sh = A.sh;
+    const int64_t ns = A.ns, nt = A.nt, key_t0 = A.key_t0;
+    const int nrhs = A.nrhs, P = A.P, nbox = A.nbox, ncol = A.ncol, col_lo = A.col_lo, G = A.G, do_far = A.do_far,
+              nparts = A.nparts;
+    const double x_lo = A.x_lo, w = A.w;
+    const cx<T> k2 = A.k2;
+    const T invR = A.invR;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ WaveLds<T> wl[L2P_THREADS / 64];
+    __shared__ int bnd[LEAF_GMAX + 1];
+    constexpr int R = Tr<T>::R;
+    const int nc = 2 * P + 1;
+    cx<T> *Ls = reinterpret_cast<cx<T> *>(smem_raw);  // [G][RMAX][nc]
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int b0 = bx * G;
+    const int ng = nbox - b0 < G ? nbox - b0 : G;
+    const int r0 = by * RMAX;
+    const int nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
+    if (t <= ng) bnd[t] = t < ng ? start[key_t0 + b0 + t] : end[key_t0 + b0 + ng - 1];
+    __syncthreads();
+    const int S = bnd[0], E = bnd[ng];
+    if (E <= S) return;
+    // the first chunk's points: their loads are in flight while the leaf
+    // expansions are formed
+    double px = 0.0, py = 0.0;
+    int32_t pid = 0;
+    if (S + t < E) {
+        px = xs[S + t];
+        py = ys[S + t];
+        pid = idx[S + t];
+    }
+    if (do_far && sh.tab) {
+        for (int g = wv; g < ng; g += L2P_THREADS / 64) {
+            if (bnd[g + 1] <= bnd[g]) continue;  // no targets in this leaf
+            const int box = b0 + g, row = box / ncol, col = col_lo + box % ncol;
+            const int prow = row >> 1, pcl = (col >> 1) - sh.col_lo_p, pos = (col & 1) + 2 * (row & 1);
+            const bool pok = prow < sh.rows_p && pcl >= 0 && pcl < sh.ncol_p;
+            const cx<T> *x = sh.Lp + ((int64_t)prow * sh.ncol_p + pcl) * nrhs * sh.ncp;
+            const bool add = row < sh.add_rows;
+            for (int rr = 0; rr < nr; rr += R) {
+                const int nrr = nr - rr < R ? nr - rr : R;
+                for (int p0 = 0; p0 < nc; p0 += 64) {
+                    cx<T> acc[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+                    const int p = p0 + lane;
+                    // the stored M2L value, loaded before the shift's own loads
+                    cx<T> prev[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        prev[r] = (add && p < nc && r < nrr) ? Lc[((int64_t)box * nrhs + r0 + rr + r) * nc + p]
+                                                             : mk<T>(0, 0);
+                    if (pok)
+                        item_matvec<T>(sh.tab + (int64_t)pos * sh.ncp * nc, sh.ncp, nc, p0,
+                                       x + (int64_t)(r0 + rr) * sh.ncp, sh.ncp, nrr, wl[wv], acc);
+                    if (p < nc)
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if (r < nrr) Ls[(g * RMAX + rr + r) * nc + p] = add ? acc[r] + prev[r] : acc[r];
+                }
+            }
+        }
+    } else if (do_far) {
+        const int per = nr * nc;
+        for (int e = t; e < ng * per; e += L2P_THREADS) {
+            const int g = e / per, o = e - g * per, r = o / nc, c = o - r * nc;
+            Ls[(g * RMAX + r) * nc + c] = Lc[((int64_t)(b0 + g) * nrhs + r0 + r) * nc + c];
+        }
+    }
+    __syncthreads();
+    for (int c0 = S; c0 < E; c0 += L2P_THREADS) {
+        const int i = c0 + t;
+        if (i >= E) break;
+        if (c0 != S) {
+            px = xs[i];
+            py = ys[i];
+            pid = idx[i];
+        }
+        int g = 0;
+        while (i >= bnd[g + 1]) ++g;
+        const int box = b0 + g, row = box / ncol, col = col_lo + box % ncol;
+        cx<double> res[RMAX];
+        for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
+        if (do_far) {
+            const double cxp = x_lo + (col + 0.5) * w, cyp = -(row + 0.5) * w;
+            eval_local<T, PMAX, RMAX>(k2, (T)(px - cxp), (T)(py - cyp), invR, P, Ls + g * RMAX * nc, nr, res);
+        }
+        const int64_t o = pid - ns;
+        if (unear && row == 0)
+            for (int pp = 0; pp < nparts; ++pp)
+                for (int r = 0; r < RMAX; ++r)
+                    if (r < nr) res[r] += unear[((int64_t)pp * nrhs + r0 + r) * nt + o];
+        for (int r = 0; r < RMAX; ++r)
+            if (r < nr) u[(int64_t)(r0 + r) * nt + o] = mk<T>((T)res[r].re, (T)res[r].im);
+    }
+}
+
+template <typename T, int PMAX, int RMAX>
+__global__ void __launch_bounds__(L2P_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_l2p(L2PArgs<T> a)
+{
+    l2p_body<T, PMAX, RMAX>(a, blockIdx.x, blockIdx.y);
+}
+template <typename T, int PMAX, int RMAX>
+__global__ void __launch_bounds__(L2P_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_l2p_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    l2p_body<T, PMAX, RMAX>(static_cast<const L2PArgs<T> *>(m.args)[i], bx, by);
+}
+
+// ---------------------------------------------------------------------------
+// Fused L2P + S2T per target leaf, the near field by pairs (the alternative
+// to the sweep); lanes over targets (chunks of 64).
+// Writes u[r][original index] (no accumulation across kernels).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct L2PNearArgs {
+    const int32_t *start, *end, *idx;
+    const double *xs, *ys;
+    const cx<T> *q;
+    int64_t ns, nt;
+    int nrhs, P, ncol, col_lo, rows_s;
+    double x_lo, w;
+    cx<T> k2;
+    T invR;
+    const cx<T> *Lc;
+    LeafShift<T> sh;
+    const Node *nodes;
+    int nmid, npan;
+    double t0;
+    int do_far, do_near;
+    int64_t key_t0;
+    const cx<double> *unear;
+    int nparts;
+    cx<T> *u;
+};
+template <typename T, int PMAX, int RMAX>
+__device__ __forceinline__ void l2p_near_body(const L2PNearArgs<T> &A, const int bx, const int by)
+{
+    const int32_t *__restrict__ start = A.start;
+    const int32_t *__restrict__ end = A.end;
+    const int32_t *__restrict__ idx = A.idx;
+    const double *__restrict__ xs = A.xs;
+    const double *__restrict__ ys = A.ys;
+    const cx<T> *__restrict__ q = A.q;
+    const cx<T> *__restrict__ Lc = A.Lc;
+    const Node *__restrict__ nodes = A.nodes;
+    const cx<double> *__restrict__ unear = A.unear;
+    cx<T> *__restrict__ u = A.u;
+    const LeafShift<T> &sh = A.sh;
+    const int64_t ns = A.ns, nt = A.nt, key_t0 = A.key_t0;
+    const int nrhs = A.nrhs, P = A.P, ncol = A.ncol, col_lo = A.col_lo, rows_s = A.rows_s, nmid = A.nmid,
+              npan = A.npan, do_far = A.do_far, do_near = A.do_near, nparts = A.nparts;
+    const double x_lo = A.x_lo, w = A.w, t0 = A.t0;
+    const cx<T> k2 = A.k2;
+    const T invR = A.invR;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ WaveLds<T> wl;
+    const int nc = 2 * P + 1;
+    cx<T> *Ls = reinterpret_cast<cx<T> *>(smem_raw);  // [RMAX][nc]
+    const int box = bx, lane = threadIdx.x;
+    const int r0 = by * RMAX;
+    const int nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
+    const int row = box / ncol, cl = box % ncol, col = col_lo + cl;
+    const double cxp = x_lo + (col + 0.5) * w, cyp = -(row + 0.5) * w;
+    const int s = start[key_t0 + box], e = end[key_t0 + box];
+    if (e <= s) return;
+    if (do_far && sh.tab) {
+        // the leaf's local expansion: L2L shift of the parent's (Lemma L2L),
+        // plus the stored M2L result in the interface rows
+        constexpr int R = Tr<T>::R;
+        const int prow = row >> 1, pcl = (col >> 1) - sh.col_lo_p, pos = (col & 1) + 2 * (row & 1);
+        const bool pok = prow < sh.rows_p && pcl >= 0 && pcl < sh.ncol_p;
+        const cx<T> *x = sh.Lp + ((int64_t)prow * sh.ncol_p + pcl) * nrhs * sh.ncp;
+        const bool add = row < sh.add_rows;
+        for (int rr = 0; rr < nr; rr += R) {
+            const int nrr = nr - rr < R ? nr - rr : R;
+            for (int p0 = 0; p0 < nc; p0 += 64) {
+                cx<T> acc[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+                if (pok)
+                    item_matvec<T>(sh.tab + (int64_t)pos * sh.ncp * nc, sh.ncp, nc, p0,
+                                   x + (int64_t)(r0 + rr) * sh.ncp, sh.ncp, nrr, wl, acc);
+                const int p = p0 + lane;
+                if (p < nc)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r < nrr) {
+                            cx<T> v = acc[r];
+                            if (add) v += Lc[(((int64_t)row * ncol + cl) * nrhs + r0 + rr + r) * nc + p];
+                            Ls[(rr + r) * nc + p] = v;
+                        }
+            }
+        }
+        __syncthreads();
+    } else if (do_far) {
+        for (int r = 0; r < nr; ++r)
+            for (int t = lane; t < nc; t += 64)
+                Ls[r * nc + t] = Lc[(((int64_t)row * ncol + cl) * nrhs + r0 + r) * nc + t];
+        __syncthreads();
+    }
+    for (int c0 = s; c0 < e; c0 += 64) {
+        int i = c0 + lane;
+        bool act = i < e;
+        int ii = act ? i : s;
+        double x1 = xs[ii], y1 = ys[ii];
+        cx<double> res[RMAX];
+        for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
+        if (do_far) eval_local<T, PMAX, RMAX>(k2, (T)(x1 - cxp), (T)(y1 - cyp), invR, P, Ls, nr, res);
+        if (do_near && row == 0 && rows_s > 0) {
+            if (unear) {
+                // near field computed by the sweep kernel: add its parts in order
+                if (act) {
+                    int64_t o = idx[i] - ns;
+                    for (int pp = 0; pp < nparts; ++pp)
+                        for (int r = 0; r < RMAX; ++r)
+                            if (r < nr) res[r] += unear[((int64_t)pp * nrhs + r0 + r) * nt + o];
+                }
+            } else {
+                for (int dc = -1; dc <= 1; ++dc) {
+                    int cs = cl + dc;
+                    if (cs < 0 || cs >= ncol) continue;
+                    int js = start[cs], je = end[cs];  // row-0 source leaf
+                    for (int j = js; j < je; ++j) {
+                        double x0 = xs[j], y0 = ys[j];
+                        cx<double> G = pair_kernel(nodes, nmid, npan, t0, y1, y0, fabs(x1 - x0), act);
+                        int64_t o = idx[j];
+                        for (int r = 0; r < RMAX; ++r)
+                            if (r < nr) {
+                                cx<T> qq = q[(int64_t)(r0 + r) * ns + o];
+                                cfma(res[r], G, cx<double>{(double)qq.re, (double)qq.im});
+                            }
+                    }
+                }
+            }
+        }
+        if (act) {
+            int64_t o = idx[i] - ns;
+            for (int r = 0; r < RMAX; ++r)
+                if (r < nr) u[(int64_t)(r0 + r) * nt + o] = mk<T>((T)res[r].re, (T)res[r].im);
+        }
+    }
+}
+
+template <typename T, int PMAX, int RMAX>
+__global__ void __launch_bounds__(64) k_l2p_near(L2PNearArgs<T> a) { l2p_near_body<T, PMAX, RMAX>(a, blockIdx.x, blockIdx.y); }
+template <typename T, int PMAX, int RMAX>
+__global__ void __launch_bounds__(64) k_l2p_near_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    l2p_near_body<T, PMAX, RMAX>(static_cast<const L2PNearArgs<T> *>(m.args)[i], bx, by);
+}
+
+// Near-field derivative sums for the gradient: returns (sum D e^E lam, sum D e^E s_t)
+// so that d/dx1 = i sgn(x1 - x0) * first and d/dy1 = second.
+__device__ inline void pair_kernel_grad(const Node *__restrict__ nodes, int nmid, int npan, double t0, double y1,
+                                        double y0, double dx, bool act, cx<double> &GL, cx<double> &GS)
+{
+    int need = act ? panels_needed(y0 - y1, dx, t0, npan) : 0;
+    int wneed = wave_max_i(need);
+    GL = {0.0, 0.0};
+    GS = {0.0, 0.0};
+    auto add = [&](const Node &nd, cx<double> &al, cx<double> &as) {
+        cx<double> v = node_term(nd, y1, y0, dx);
+        al += v * cx<double>{nd.lr, nd.li};
+        as += v * cx<double>{nd.str, nd.sti};
+    };
+    for (int n = 0; n < nmid; ++n) add(nodes[n], GL, GS);
+    for (int m = 0; m < wneed; ++m) {
+        const Node *pn = nodes + nmid + m * 2 * NGL;
+        cx<double> al = {0.0, 0.0}, as = {0.0, 0.0};
+        for (int n = 0; n < 2 * NGL; ++n) add(pn[n], al, as);
+        if (m < need) {
+            GL += al;
+            GS += as;
+        }
+    }
+}
+
+// Coordinate gradient at the targets: gout[0][i] = Re sum_r c[r][i] du_r/dx(x_i),
+// gout[1][i] = ysign * Re sum_r c[r][i] du_r/dy(x_i), u = the field of densities q.
+// Far part: the local expansion's gradient is a local expansion of order P+1,
+//   d/dx (J_p e^{ip th}) = (k/2)(J_{p-1} e^{i(p-1)th} - J_{p+1} e^{i(p+1)th}),
+//   d/dy (J_p e^{ip th}) = (ik/2)(J_{p-1} e^{i(p-1)th} + J_{p+1} e^{i(p+1)th}),
+// rewritten for the scaled coefficients.  Near part: the integrand times
+// i lam sgn(x1 - x0) (x) or s_t (y).
+template <typename T, int PMAX>
+__global__ void __launch_bounds__(64) k_l2p_grad(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
+                                                 const int32_t *__restrict__ idx, const double *__restrict__ xs,
+                                                 const double *__restrict__ ys, const cx<T> *__restrict__ q,
+                                                 const cx<T> *__restrict__ cw, int64_t ns, int64_t nt, int nrhs,
+                                                 int r0, int nr, int accumulate,
+                                                 int P, int ncol, int col_lo, int rows_s, double x_lo, double w,
+                                                 cx<T> kt, T invR, const cx<T> *__restrict__ Lc,
+                                                 const Node *__restrict__ nodes, int nmid, int npan, double t0,
+                                                 int do_far, int do_near, int64_t key_t0, double ysign,
+                                                 double *__restrict__ gout)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int ncg = 2 * (P + 1) + 1;           // gradient expansions have order P + 1
+    cx<T> *Gx = reinterpret_cast<cx<T> *>(smem_raw);  // [nr][ncg], right-hand sides r0 .. r0+nr-1
+    cx<T> *Gy = Gx + (size_t)nr * ncg;
+    const int box = blockIdx.x, lane = threadIdx.x;
+    const int row = box / ncol, cl = box % ncol, col = col_lo + cl;
+    const double cxp = x_lo + (col + 0.5) * w, cyp = -(row + 0.5) * w;
+    const int s = start[key_t0 + box], e = end[key_t0 + box];
+    if (e <= s) return;
+    const int nc = 2 * P + 1;
+    if (do_far) {
+        const T R = T(1) / invR;
+        const cx<T> hk2R = T(0.25) * R * (kt * kt);  // k^2 R / 4
+        for (int t = lane; t < nr * ncg; t += 64) {
+            int r = r0 + t / ncg, n = t % ncg - (P + 1);
+            auto Lh = [&](int m) {
+                return (m >= -P && m <= P) ? Lc[(((int64_t)row * ncol + cl) * nrhs + r) * nc + m + P] : mk<T>(0, 0);
+            };
+            cx<T> up = Lh(n + 1), dn = Lh(n - 1);
+            // (k/2) s_{n+1}/s_n and (k/2) s_{n-1}/s_n
+            cx<T> fp = n >= 0 ? mk<T>(T(n + 1) * invR, T(0)) : hk2R * (T(1) / T(-n));
+            cx<T> fm = n > 0 ? hk2R * (T(1) / T(n)) : mk<T>(T(1 - n) * invR, T(0));
+            cx<T> a = fp * up, b = fm * dn;
+            Gx[t] = a - b;
+            cx<T> sum = a + b;
+            Gy[t] = mk<T>(-sum.im, sum.re);
+        }
+        __syncthreads();
+    }
+    for (int c0 = s; c0 < e; c0 += 64) {
+        int i = c0 + lane;
+        bool act = i < e;
+        int ii = act ? i : s;
+        double x1 = xs[ii], y1 = ys[ii];
+        int64_t oi = idx[ii] - ns;
+        double gx = 0.0, gy = 0.0;
+        if (do_far) {
+            cx<T> tm[PMAX + 1];
+            cx<T> J0;
+            T X = (T)(x1 - cxp), Y = (T)(y1 - cyp);
+            const int Pg = P + 1;
+            bessel_ratios<T, PMAX>(kt, X, Y, Pg, tm, J0);
+            cx<T> up = mk<T>(X * invR, Y * invR), dn = mk<T>(-X * invR, Y * invR);
+            for (int rr = 0; rr < nr; ++rr) {
+                const int r = r0 + rr;
+                const cx<T> *gxr = Gx + rr * ncg, *gyr = Gy + rr * ncg;
+                cx<T> ax = J0 * gxr[Pg], ay = J0 * gyr[Pg];
+                cx<T> vp = J0, vm = J0;
+#pragma unroll PUnroll<PMAX>::n
+                for (int p = 1; p <= PMAX; ++p) {
+                    if (p <= Pg) {
+                        cx<T> f = T(2 * p) * tm[p];
+                        vp = vp * (f * up);
+                        vm = vm * (f * dn);
+                        cfma(ax, vp, gxr[Pg + p]);
+                        cfma(ax, vm, gxr[Pg - p]);
+                        cfma(ay, vp, gyr[Pg + p]);
+                        cfma(ay, vm, gyr[Pg - p]);
+                    }
+                }
+                cx<T> cr = act ? cw[(int64_t)r * nt + oi] : mk<T>(0, 0);
+                gx += (double)(cr.re * ax.re - cr.im * ax.im);
+                gy += (double)(cr.re * ay.re - cr.im * ay.im);
+            }
+        }
+        if (do_near && row == 0 && rows_s > 0) {
+            for (int dc = -1; dc <= 1; ++dc) {
+                int cs = cl + dc;
+                if (cs < 0 || cs >= ncol) continue;
+                int js = start[cs], je = end[cs];
+                for (int j = js; j < je; ++j) {
+                    double x0 = xs[j], y0 = ys[j];
+                    cx<double> GL, GS;
+                    pair_kernel_grad(nodes, nmid, npan, t0, y1, y0, fabs(x1 - x0), act, GL, GS);
+                    double sg = x1 > x0 ? 1.0 : (x1 < x0 ? -1.0 : 0.0);
+                    cx<double> GX = {-GL.im * sg, GL.re * sg};  // i sgn * GL
+                    int64_t o = idx[j];
+                    for (int r = r0; r < r0 + nr; ++r) {
+                        cx<T> qq = q[(int64_t)r * ns + o];
+                        cx<T> cr = act ? cw[(int64_t)r * nt + oi] : mk<T>(0, 0);
+                        cx<double> cq = cx<double>{(double)cr.re, (double)cr.im} * cx<double>{(double)qq.re, (double)qq.im};
+                        gx += cq.re * GX.re - cq.im * GX.im;
+                        gy += cq.re * GS.re - cq.im * GS.im;
+                    }
+                }
+            }
+        }
+        if (act) {
+            gout[oi] = accumulate ? gout[oi] + gx : gx;
+            gout[nt + oi] = accumulate ? gout[nt + oi] + ysign * gy : ysign * gy;
+        }
+    }
+}
+
+// Compute units and LDS bytes per compute unit of the current device.
+struct DeviceShape {
+    int cus = 256;
+    int lds = 160 * 1024;
+};
+DeviceShape device_shape()
+{
+    static std::atomic<int> cus_cache[64], lds_cache[64];
+    DeviceShape d;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return d;
+    if (!cus_cache[dev].load()) {
+        int v = 0, m = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = d.cus;
+        if (hipDeviceGetAttribute(&m, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+            m <= 0)
+            m = d.lds;
+        lds_cache[dev].store(m);
+        cus_cache[dev].store(v);
+    }
+    d.cus = cus_cache[dev].load();
+    d.lds = lds_cache[dev].load();
+    return d;
+}
+
+// Leaves per block for a kernel of `threads` threads per block over nbox leaves
+// holding npts points: the fewest blocks per compute unit (at most max_per_cu)
+// that keep a block's points within 4/5 of its threads, then as many leaves
+// per block as fill that many blocks on every compute unit.  A grid just
+// under a multiple of the compute units balances the blocks per unit.
+inline int leaves_per_block(int64_t nbox, int64_t npts, int threads, int max_per_cu)
+{
+    const DeviceShape dv = device_shape();
+    int64_t k = (int64_t)std::ceil((double)npts / (0.8 * threads * dv.cus));
+    k = k < 1 ? 1 : (k > max_per_cu ? max_per_cu : k);
+    int64_t G = (nbox + k * dv.cus - 1) / (k * dv.cus);
+    return (int)(G < 1 ? 1 : (G > LEAF_GMAX ? LEAF_GMAX : G));
+}
+
+template <typename T, int PMAX>
+void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
+                  int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
+{
+    const Level &lv = g.lev[g.L];
+    int nbox = lv.rows_s * lv.ncol;
+    if (nbox == 0) return;
+    // points per chunk: as many as 78 KB of LDS hold (two blocks per compute
+    // unit), at most P2M_CHMAX
+    const size_t per = (size_t)(lv.nc + nrhs) * sizeof(cx<T>);
+    int CH = (int)((78 * 1024) / per);
+    CH = CH > P2M_CHMAX ? P2M_CHMAX : (CH < 1 ? 1 : CH);
+    const size_t sh = (size_t)CH * per;
+    int per_cu = (int)(device_shape().lds / (sh > 0 ? sh : 1));
+    per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+    const int G = leaves_per_block(nbox, ns, CH < P2M_THREADS ? CH : P2M_THREADS, per_cu);
+    cx<double> kd = k_src(med);
+    cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);
+    T invR = (T)(M_SQRT2 / lv.w);
+    const P2MArgs<T> a{start, end, xs, ys, reinterpret_cast<const cx<T> *>(qs), ns, nrhs, lv.P, nbox, lv.ncol,
+                       lv.col_lo, g.x_lo, lv.w, k1, invR, G, CH, M + lv.off_s};
+    emit((const void *)k_p2m<T, PMAX>, (const void *)k_p2m_multi<T, PMAX>, 0, dim3((nbox + G - 1) / G),
+         dim3(P2M_THREADS), sh, st, a);
+}
+
+template <typename T, int PMAX>
+void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
+                  const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med, const cx<T> *Lc,
+                  const LeafShift<T> &shift, const Node *nodes, int nmid, int npan, double t0, int do_far,
+                  int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
+{
+    const Level &lv = g.lev[g.L];
+    int nbox = lv.rows_t * lv.ncol;
+    if (nbox == 0) return;
+    size_t sh = (size_t)lv.nc * 8 * sizeof(cx<T>);
+    cx<double> kd = k_tgt(med);
+    cx<T> k2 = mk<T>((T)kd.re, (T)kd.im);
+    T invR = (T)(M_SQRT2 / lv.w);
+    int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
+    if (!(do_near && lv.rows_s > 0)) unear = nullptr;
+    if (!do_near || unear || lv.rows_s == 0) {
+        // far field plus, if any, the sweep's near-field parts: G leaves per block
+        const int RM = nrhs == 1 ? 1 : 8;
+        const size_t per_leaf = (size_t)RM * lv.nc * sizeof(cx<T>);
+        // about 0.8 x 256 points per block, two blocks per compute unit: one
+        // leaf per wave in the shift phase
+        int G = leaves_per_block(nbox, nt, 256, 2);
+        G = G > L2P_THREADS / 64 ? L2P_THREADS / 64 : G;
+        const int gmax = (int)((48 * 1024) / per_leaf);
+        G = G > gmax ? gmax : G;
+        G = G < 1 ? 1 : G;
+        const dim3 grid((nbox + G - 1) / G, (nrhs + RM - 1) / RM);
+        const L2PArgs<T> a{start, end, idx, xs, ys, ns, nt, nrhs, lv.P, nbox, lv.ncol, lv.col_lo, g.x_lo, lv.w, k2,
+                           invR, Lc + lv.off_t, shift, key_t0, G, do_far, unear, unear ? nparts : 0,
+                           reinterpret_cast<cx<T> *>(u)};
+#define LMFMM_L2P_PACKED(RMC)                                                                              \
+    emit((const void *)k_l2p<T, PMAX, RMC>, (const void *)k_l2p_multi<T, PMAX, RMC>, 0, grid, dim3(L2P_THREADS), \
+         G * per_leaf, st, a)
+        if (nrhs == 1)
+            LMFMM_L2P_PACKED(1);
+        else
+            LMFMM_L2P_PACKED(8);
+#undef LMFMM_L2P_PACKED
+        return;
+    }
+    // near field by pairs: one leaf per block
+    const L2PNearArgs<T> a{start, end, idx, xs, ys, reinterpret_cast<const cx<T> *>(q), ns, nt, nrhs, lv.P,
+                           lv.ncol, lv.col_lo, lv.rows_s, g.x_lo, lv.w, k2, invR, Lc + lv.off_t, shift, nodes, nmid,
+                           npan, t0, do_far, do_near, key_t0, unear, nparts, reinterpret_cast<cx<T> *>(u)};
+#define LMFMM_L2P_LAUNCH(RM)                                                                                 \
+    emit((const void *)k_l2p_near<T, PMAX, RM>, (const void *)k_l2p_near_multi<T, PMAX, RM>, 0,             \
+         dim3(nbox, (nrhs + RM - 1) / RM), dim3(64), sh, st, a)
+    if (nrhs == 1)
+        LMFMM_L2P_LAUNCH(1);
+    else
+        LMFMM_L2P_LAUNCH(8);
+#undef LMFMM_L2P_LAUNCH
+}
+
+template <typename T, int PMAX>
+void grad_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
+                   const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med,
+                   const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0, int do_far, int do_near,
+                   double ysign, double *gout, hipStream_t st)
+{
+    const Level &lv = g.lev[g.L];
+    int nbox = lv.rows_t * lv.ncol;
+    if (nbox == 0) return;
+    cx<double> kd = k_tgt(med);
+    cx<T> kt = mk<T>((T)kd.re, (T)kd.im);
+    T invR = (T)(M_SQRT2 / lv.w);
+    int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
+    for (int r0 = 0; r0 < nrhs; r0 += 8) {
+        int nr = nrhs - r0 < 8 ? nrhs - r0 : 8;
+        size_t sh = (size_t)2 * nr * (2 * (lv.P + 1) + 1) * sizeof(cx<T>);
+        LMFMM_LAUNCH((k_l2p_grad<T, PMAX>), dim3(nbox), dim3(64), sh, st, start, end, idx, xs, ys,
+                           reinterpret_cast<const cx<T> *>(q), reinterpret_cast<const cx<T> *>(cw), ns, nt, nrhs, r0,
+                           nr, r0 > 0 ? 1 : 0, lv.P, lv.ncol, lv.col_lo, lv.rows_s, g.x_lo, lv.w, kt, invR,
+                           Lc + lv.off_t, nodes, nmid, npan, t0, do_far, do_near, key_t0, ysign, gout);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
+                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
+{
+    int P = g.lev[g.L].P;
+    if (P <= 16)
+        p2m_dispatch<T, 16>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
+    else if (P <= 32)
+        p2m_dispatch<T, 32>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
+    else if (P <= 64)
+        p2m_dispatch<T, 64>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
+    else
+        p2m_dispatch<T, 256>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
+}
+
+template <typename T>
+void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
+                     const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
+                     Medium med, const cx<T> *Lc, const LeafShift<T> &shift, const Node *nodes, int nmid, int npan,
+                     double t0, int do_far, int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
+{
+    int P = g.lev[g.L].P;
+    if (!unear) nparts = 0;
+#define LMFMM_L2P(PM)                                                                                          \
+    l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, shift, nodes, nmid, npan, t0, \
+                        do_far, do_near, unear, nparts, u, st)
+    if (P <= 16)
+        LMFMM_L2P(16);
+    else if (P <= 32)
+        LMFMM_L2P(32);
+    else if (P <= 64)
+        LMFMM_L2P(64);
+    else
+        LMFMM_L2P(256);
+#undef LMFMM_L2P
+}
+
+template <typename T>
+void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
+                     const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,
+                     const Geometry &g, Medium med, const cx<T> *Lc, const Node *nodes, int nmid, int npan, double t0,
+                     int do_far, int do_near, double ysign, double *gout, hipStream_t st)
+{
+    int P = g.lev[g.L].P + 1;
+#define LMFMM_GR(PM)                                                                                             \
+    grad_dispatch<T, PM>(start, end, idx, xs, ys, q, cw, ns, nt, nrhs, g, med, Lc, nodes, nmid, npan, t0, do_far, \
+                         do_near, ysign, gout, st)
+    if (P <= 16)
+        LMFMM_GR(16);
+    else if (P <= 32)
+        LMFMM_GR(32);
+    else if (P <= 64)
+        LMFMM_GR(64);
+    else
+        LMFMM_GR(256);
+#undef LMFMM_GR
+}
+
+#define LMFMM_INST(T)                                                                                               \
+    template void launch_p2m<T>(const int32_t *, const int32_t *, const double *, const double *, const void *,      \
+                                int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);                      \
+    template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
+                                     const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
+                                     const cx<T> *, const LeafShift<T> &, const Node *, int, int, double, int, int, \
+                                     const cx<double> *, int, void *, hipStream_t);                                 \
+    template void launch_l2p_grad<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
+                                     const double *, const void *, const void *, int64_t, int64_t, int,             \
+                                     const Geometry &, Medium, const cx<T> *, const Node *, int, int, double, int,  \
+                                     int, double, double *, hipStream_t);
+LMFMM_INST(double)
+LMFMM_INST(float)
+
+}  // namespace lmfmm

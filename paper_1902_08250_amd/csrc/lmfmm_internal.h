@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 #include <vector>
 
 namespace lmfmm {
@@ -39,6 +40,105 @@ inline LaunchTiming &launch_timing()
         }                                                                            \
     } while (0)
 
+
+// ---------------------------------------------------------------------------
+// Launches through a recorder.
+//
+// Every kernel of the apply takes one argument struct by value.  Its launch
+// wrapper calls emit(), which launches the kernel at once (with the start and
+// stop events of launch_timing, if set) or, while a recorder is set for this
+// host thread, appends the launch to it.  The batched apply records every
+// instance's launch sequence and merges the launches of one stage into one
+// launch of the kernel's multi-instance form (MultiArgs below).
+// ---------------------------------------------------------------------------
+enum Stage { S_ZERO = 1, S_TREE, S_P2M, S_M2M, S_ZTOP, S_M2L, S_L2L, S_SWEEP, S_L2P };
+
+struct RecLaunch {
+    int key;             // launch_stage() + sub: position in the merged launch sequence
+    const void *single;  // the kernel, taking the argument struct by value
+    const void *multi;   // its multi-instance form (one MultiArgs argument), or null
+    dim3 grid, block;
+    size_t shmem;
+    size_t align;             // alignment of the argument struct
+    std::vector<char> args;  // the argument struct's bytes
+};
+struct Recorder {
+    std::vector<RecLaunch> v;
+};
+inline Recorder *&launch_recorder()
+{
+    static thread_local Recorder *r = nullptr;
+    return r;
+}
+// key of the launches that follow: stage * 64 + j, j the launch's index among
+// the instance's launches of that stage (the level of a per-level pass); a
+// launcher issuing several kernels adds 0, 1, ... to it
+inline int &launch_stage()
+{
+    static thread_local int s = 0;
+    return s;
+}
+inline void set_stage(Stage s, int j = 0) { launch_stage() = (int)s * 64 + j; }
+
+// Argument of a multi-instance launch: instance i takes the blocks
+// [blk0[i], blk0[i + 1]) of the flat grid, its own grid is grid[3i .. 3i + 2]
+// (x, y, z), and its argument struct is element i of args.
+struct MultiArgs {
+    const int *blk0;
+    const int *grid;
+    const void *args;
+    int n;
+};
+
+template <class A>
+inline void emit(const void *single, const void *multi, int sub, dim3 grid, dim3 block, size_t sh, hipStream_t st,
+                 const A &a)
+{
+    static_assert(std::is_trivially_copyable<A>::value, "kernel arguments are copied as bytes");
+    if (grid.x == 0 || grid.y == 0 || grid.z == 0) return;
+    if (Recorder *r = launch_recorder()) {
+        RecLaunch L;
+        L.key = launch_stage() + sub;
+        L.single = single;
+        L.multi = multi;
+        L.grid = grid;
+        L.block = block;
+        L.shmem = sh;
+        L.align = alignof(A);
+        L.args.assign(reinterpret_cast<const char *>(&a), reinterpret_cast<const char *>(&a) + sizeof(A));
+        r->v.push_back(std::move(L));
+        return;
+    }
+    void *args[] = {const_cast<A *>(&a)};
+    LaunchTiming &lt = launch_timing();
+    if (lt.start) {
+        hipEvent_t a_ = lt.start, b_ = lt.stop;
+        lt.start = lt.stop = nullptr;
+        (void)hipExtLaunchKernel(single, grid, block, args, sh, st, a_, b_, 0);
+    } else {
+        (void)hipLaunchKernel(single, grid, block, args, sh, st);
+    }
+}
+
+// Block of a multi-instance launch: its instance and its block index in the
+// instance's own grid.
+__device__ inline void multi_locate(const MultiArgs &m, int &i, int &bx, int &by, int &bz)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = m.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (m.blk0[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    i = lo;
+    const int loc = b - m.blk0[lo], gx = m.grid[3 * lo], gy = m.grid[3 * lo + 1];
+    bx = loc % gx;
+    by = (loc / gx) % gy;
+    bz = loc / (gx * gy);
+}
 
 // ---------------------------------------------------------------------------
 // Complex arithmetic (device and host)
@@ -166,6 +266,13 @@ __host__ __device__ inline cx<double> sigma2t_d(cx<double> lam, const Medium &m,
 // 1 = J_0 + 2 sum_m J_{2m}.  Then J_q e^{i sign q theta} s_q / (J_{q-1} ...) =
 // 2 q t_q (X + i sign Y) / R.
 // ---------------------------------------------------------------------------
+// Loops over the orders are unrolled up to order 64 (their arrays then stay
+// in registers); the largest-order variants keep the loops.
+template <int PMAX>
+struct PUnroll {
+    static constexpr int n = PMAX <= 64 ? PMAX : 1;
+};
+
 template <typename T, int PMAX>
 __host__ __device__ inline void bessel_ratios(cx<T> k, T X, T Y, int P, cx<T> *tm, cx<T> &J0)
 {
@@ -194,7 +301,7 @@ __host__ __device__ inline void bessel_ratios(cx<T> k, T X, T Y, int P, cx<T> *t
         }
         tprev = t;
     }
-#pragma unroll
+#pragma unroll PUnroll<PMAX>::n
     for (int m = PMAX; m >= 1; --m) {
         if (m <= P) {
             t = cinv(mk<T>(T(2 * m), T(0)) - z2 * t);
@@ -220,7 +327,7 @@ __host__ __device__ inline void bessel_basis(cx<T> k, T X, T Y, T invR, int P, i
     cx<T> up = mk<T>(X * invR, T(sign) * Y * invR);   // (X + i sign Y)/R
     cx<T> dn = mk<T>(-X * invR, T(sign) * Y * invR);  // -(X - i sign Y)/R
     cx<T> vp = J0, vm = J0;
-#pragma unroll
+#pragma unroll PUnroll<PMAX>::n
     for (int q = 1; q <= PMAX; ++q) {
         if (q <= P) {
             cx<T> f = T(2 * q) * tm[q];

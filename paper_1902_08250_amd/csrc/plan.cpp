@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -1187,6 +1188,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     cx<double> *unear = sweep ? cv.take<cx<double>>(nun) : nullptr;
     int tree_launches = (have_bb ? 0 : 2) + 4;
     if (p->tz_gen != p->ws.gen || zero_bytes > p->tz_bytes) {
+        set_stage(S_ZERO);
         launch_zero_bytes(p->ws.p, zero_bytes, st);
         ++tree_launches;
         p->tz_gen = p->ws.gen;
@@ -1199,6 +1201,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     auto launch_all = [&](hipStream_t sx, bool with_bbox) {
         // Step 1: tree (in a graph of the device-computed box, the box first)
         if (with_bbox) bbox_launch(p, med, ns, src, nt, tgt, sx);
+        set_stage(S_TREE);
         launch_tree(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
                     yt_limit(med), tb, err, sx);
         group_end(tree_launches, sx);
@@ -1207,12 +1210,14 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         LeafShift<T> shift;
         if (far) {
             timed(LMFMM_K_P2M, 1);
+            set_stage(S_P2M);
             launch_p2m<T>(start, end, xs, ys, tb.qs, ns, nrhs, g, med, M, sx);
             timed_done();
             for (int l = L; l >= ltop + 1; --l) {
                 const LevelTables &tb = vt.lt[l];
                 const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
                 timed(LMFMM_K_M2M, 1);
+                set_stage(S_M2M, L - l);
                 launch_m2m<T>(g, l, tab, M, nrhs, sx);
                 timed_done();
             }
@@ -1234,9 +1239,11 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             if (!atab[0]) {
                 // coarsest level without translation classes: no far field reaches it
                 const Level &lt = g.lev[ltop];
+                set_stage(S_ZTOP);
                 launch_zero_bytes(Lc + lt.off_t, (size_t)lt.rows_t * lt.ncol * nrhs * lt.nc * sizeof(cx<T>), sx);
             }
             timed(LMFMM_K_DOWN, 1);
+            set_stage(S_M2L);
             launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, sx);
             timed_done();
             // the leaf level's shift is done by the leaf evaluation (forward apply)
@@ -1256,6 +1263,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 const LevelTables &tl = vt.lt[l];
                 const cx<T> *l2l = (const cx<T> *)(sizeof(T) == 8 ? tl.l2l64.p : tl.l2l32.p);
                 timed(LMFMM_K_L2L, 1);
+                set_stage(S_L2L, l - ltop - 1);
                 launch_down<T>(g, l, (const cx<T> *)nullptr, nullptr, nullptr, 0, M, Lc, nrhs, l2l, false,
                                nrt[l - ltop], sx);
                 timed_done();
@@ -1267,11 +1275,13 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         if (!gw) {
             if (sweep) {
                 timed(LMFMM_K_SWEEP, 1);
+                set_stage(S_SWEEP);
                 nparts = launch_near_sweep<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, nnodes, vt.n_nmid, vt.n_npan,
                                               vt.n_t0, unear, sx);
                 timed_done();
             }
             timed(LMFMM_K_L2P, 1);
+            set_stage(S_L2P);
             launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, shift, nnodes, vt.n_nmid, vt.n_npan,
                                vt.n_t0, far ? 1 : 0, near_on ? 1 : 0, nparts ? unear : nullptr, nparts, u, sx);
             timed_done();
@@ -1492,36 +1502,66 @@ int lmfmm_sync_status(lmfmm_plan p, void *stream)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Batched apply: many independent problems in one graph launch.
+// Batched apply: many independent problems, one launch per stage.
 //
 // Preparation (first call, or when the instance descriptors change):
 //   1. each instance's bounding box is read once and pinned in its plan, so
 //      later applies queue no host synchronisation;
-//   2. the autotuner times every (order floor, levels) candidate per instance
-//      with HIP events and keeps the fastest (the tolerance is enforced for
-//      every candidate by the order rule);
-//   3. one apply per instance allocates its tables and workspace, then all
-//      instances are captured into one HIP graph, instance i on branch i % 4
-//      of a fork/join over four streams.
-// Every later call with the same descriptors is a single hipGraphLaunch.
+//   2. each instance's (order floor, levels) comes from the tuning cache when
+//      it holds the instance's key, else the autotuner times every candidate
+//      (order floors of the set x levels around the automatic choice) with HIP
+//      events and keeps the fastest; the tolerance is met by every candidate
+//      (the order rule of the plan enforces it).  New choices are written to
+//      the cache;
+//   3. one apply per instance builds its tables and workspace; then every
+//      instance's launch sequence is recorded instead of launched, and the
+//      launches of one stage (zeroing, the four tree passes, P2M, the M2M of
+//      each level counted from the leaves, M2L, the L2L of each level counted
+//      from the top, near field, local evaluation) become one launch of the
+//      kernel's multi-instance form over all instances (instances whose
+//      kernels differ in template arguments take separate launches of the
+//      stage).  The per-instance arguments go to device memory once;
+//   4. the merged sequence is captured in a HIP graph on one stream.
+// Every later call with the same descriptors is one hipGraphLaunch.
 // ---------------------------------------------------------------------------
+struct BatchLaunch {
+    const void *fn;  // multi-instance kernel
+    dim3 block;
+    size_t shmem;
+    unsigned nblk;
+    int n;
+    int cls;  // LMFMM_K_* class of its stage
+    size_t off_blk0, off_grid, off_args;
+    MultiArgs m;
+};
+
+struct TuneEntry {
+    int order = 0, levels = 0;
+    double us = 0;
+};
+
 struct lmfmm_batch_s {
     int n = 0;
     std::vector<lmfmm_plan_s *> plans;
     std::vector<int> order_set;
     double tol = 1e-6;
     bool tune = true, graph = true;
+    std::string cache_path;  // tuning cache (one JSON object per line); empty: none
     // prepared state
     bool prepared = false;
     std::vector<lmfmm_instance> desc;
     int nrhs = 0, prec = -1;
+    std::vector<BatchLaunch> seq;
+    DevBuf meta;  // blk0, grid and argument arrays of every merged launch
     hipStream_t cap_stream = nullptr;
-    std::vector<hipStream_t> branch;
-    std::vector<hipEvent_t> fork_ev, join_ev;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
-    std::vector<int> chosen_order, chosen_levels;
+    std::vector<int> chosen_order, chosen_levels, from_cache;
     std::vector<double> chosen_us;
+    lmfmm_batch_stats stats;
+    // per-launch timing
+    bool timing = false, ev_pending = false;
+    std::vector<hipEvent_t> ev;
 };
 
 static void batch_drop_graph(lmfmm_batch_s *b)
@@ -1531,6 +1571,36 @@ static void batch_drop_graph(lmfmm_batch_s *b)
     b->ge = nullptr;
     b->g = nullptr;
     b->prepared = false;
+}
+
+static void batch_collect_timing(lmfmm_batch_s *b)
+{
+    if (!b->ev_pending) return;
+    b->ev_pending = false;
+    const size_t n = b->seq.size();
+    if (b->ev.size() < 2 * n || n == 0) return;
+    (void)hipEventSynchronize(b->ev[2 * n - 1]);
+    for (size_t j = 0; j < n; ++j) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b->ev[2 * j], b->ev[2 * j + 1]) == hipSuccess)
+            b->stats.kernel_ms[b->seq[j].cls] += ms;
+        b->stats.kernel_launches[b->seq[j].cls] += 1;
+    }
+    b->stats.timed_applies += 1;
+}
+
+// the merged sequence on stream s (with start/stop events per launch when timed)
+static int batch_launch_seq(lmfmm_batch_s *b, hipStream_t s, bool timed)
+{
+    for (size_t j = 0; j < b->seq.size(); ++j) {
+        BatchLaunch &L = b->seq[j];
+        void *args[] = {&L.m};
+        hipError_t e = timed ? hipExtLaunchKernel(L.fn, dim3(L.nblk), L.block, args, L.shmem, s, b->ev[2 * j],
+                                                  b->ev[2 * j + 1], 0)
+                             : hipLaunchKernel(L.fn, dim3(L.nblk), L.block, args, L.shmem, s);
+        if (e != hipSuccess) return fail(LMFMM_EHIP, std::string("batched launch: ") + hipGetErrorString(e));
+    }
+    return LMFMM_OK;
 }
 
 static int plan_apply_any(lmfmm_plan_s *p, const lmfmm_instance &in, int nrhs, int prec, hipStream_t st)
@@ -1545,14 +1615,175 @@ static bool same_desc(const lmfmm_instance &a, const lmfmm_instance &b)
            a.u == b.u;
 }
 
+// Tuning-cache key of an instance: medium, sizes (in half-octave buckets),
+// tolerance, right-hand sides, precision and the candidate order set.
+static std::string tune_key(const lmfmm_batch_s *b, const lmfmm_plan_s *p, const lmfmm_instance &in, int nrhs,
+                            int prec)
+{
+    char buf[512];
+    auto bucket = [](int64_t n) { return (int)std::floor(2.0 * std::log2((double)std::max<int64_t>(n, 1))); };
+    std::snprintf(buf, sizeof buf, "k=%.9g,%.9g,%.9g,%.9g,%.9g,%.9g d=%.9g ns=%d nt=%d tol=%.3g nrhs=%d prec=%d o=",
+                  p->med.k1.re, p->med.k1.im, p->med.k2.re, p->med.k2.im, p->med.k3.re, p->med.k3.im, p->med.d,
+                  bucket(in.n_src), bucket(in.n_tgt), b->tol, nrhs, prec);
+    std::string k(buf);
+    for (int o : b->order_set) k += std::to_string(o) + ":";
+    return k;
+}
+
+static void read_tune_cache(const std::string &path, std::map<std::string, TuneEntry> &out)
+{
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        // {"key": "<key>", "order": o, "levels": L, "us": t}
+        const char *k0 = std::strstr(line, "\"key\": \"");
+        if (!k0) continue;
+        k0 += 8;
+        const char *k1 = std::strchr(k0, '"');
+        if (!k1) continue;
+        TuneEntry e;
+        const char *o = std::strstr(k1, "\"order\": "), *l = std::strstr(k1, "\"levels\": "), *u = std::strstr(k1, "\"us\": ");
+        if (!o || !l || !u) continue;
+        e.order = std::atoi(o + 9);
+        e.levels = std::atoi(l + 10);
+        e.us = std::atof(u + 6);
+        if (e.order < 1 || e.order > 256 || e.levels < 1 || e.levels > MAXLEV) continue;
+        out[std::string(k0, k1)] = e;
+    }
+    std::fclose(f);
+}
+
+static void write_tune_cache(const std::string &path, const std::map<std::string, TuneEntry> &m)
+{
+    const std::string tmp = path + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto &kv : m)
+        std::fprintf(f, "{\"key\": \"%s\", \"order\": %d, \"levels\": %d, \"us\": %.3f}\n", kv.first.c_str(),
+                     kv.second.order, kv.second.levels, kv.second.us);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), path.c_str());
+}
+
+static int stage_class(int key)
+{
+    switch (key / 64) {
+    case S_ZERO:
+    case S_TREE: return LMFMM_K_TREE;
+    case S_P2M: return LMFMM_K_P2M;
+    case S_M2M: return LMFMM_K_M2M;
+    case S_ZTOP:
+    case S_M2L: return LMFMM_K_DOWN;
+    case S_L2L: return LMFMM_K_L2L;
+    case S_SWEEP: return LMFMM_K_SWEEP;
+    case S_L2P: return LMFMM_K_L2P;
+    default: return LMFMM_K_OTHER;
+    }
+}
+
+// Record every instance's launch sequence and merge it by stage (see above).
+static int batch_record_merge(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs, int prec, hipStream_t st)
+{
+    struct Rec {
+        int inst;
+        RecLaunch L;
+    };
+    std::vector<Rec> all;
+    for (int i = 0; i < b->n; ++i) {
+        lmfmm_plan_s *p = b->plans[i];
+        if (inst[i].n_tgt == 0 || inst[i].n_src == 0) continue;  // (no sources: zeroed by the apply)
+        Recorder rec;
+        const bool timing = p->timing;
+        p->timing = false;
+        p->tz_bytes = 0;  // the recorded sequence clears its own leaf counters
+        launch_recorder() = &rec;
+        int rc = plan_apply_any(p, inst[i], nrhs, prec, st);
+        launch_recorder() = nullptr;
+        p->timing = timing;
+        if (rc) return rc;
+        for (auto &L : rec.v) all.push_back(Rec{i, std::move(L)});
+    }
+    std::stable_sort(all.begin(), all.end(), [](const Rec &a, const Rec &c) {
+        if (a.L.key != c.L.key) return a.L.key < c.L.key;
+        return std::less<const void *>()(a.L.multi, c.L.multi);
+    });
+    b->seq.clear();
+    std::vector<char> host;
+    auto put = [&](const void *src, size_t bytes) {
+        size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + bytes);
+        std::memcpy(host.data() + off, src, bytes);
+        return off;
+    };
+    for (size_t s = 0; s < all.size();) {
+        size_t e = s + 1;
+        const RecLaunch &f = all[s].L;
+        while (e < all.size() && all[e].L.key == f.key && all[e].L.multi == f.multi &&
+               all[e].L.block.x == f.block.x && all[e].L.block.y == f.block.y && all[e].L.block.z == f.block.z)
+            ++e;
+        if (!f.multi) return fail(LMFMM_EINVAL, "a kernel of this apply has no batched form");
+        BatchLaunch BL;
+        BL.fn = f.multi;
+        BL.block = f.block;
+        BL.shmem = 0;
+        BL.n = (int)(e - s);
+        BL.cls = stage_class(f.key);
+        std::vector<int> blk0(BL.n + 1), grid(3 * BL.n);
+        const size_t asz = f.args.size(), stride = (asz + f.align - 1) / f.align * f.align;
+        std::vector<char> args(stride * BL.n, 0);
+        int64_t tot = 0;
+        for (int k = 0; k < BL.n; ++k) {
+            const RecLaunch &L = all[s + k].L;
+            if (L.args.size() != asz) return fail(LMFMM_EINVAL, "batched launch with mixed argument layouts");
+            blk0[k] = (int)tot;
+            tot += (int64_t)L.grid.x * L.grid.y * L.grid.z;
+            grid[3 * k] = (int)L.grid.x;
+            grid[3 * k + 1] = (int)L.grid.y;
+            grid[3 * k + 2] = (int)L.grid.z;
+            std::memcpy(args.data() + stride * k, L.args.data(), asz);
+            BL.shmem = std::max(BL.shmem, L.shmem);
+        }
+        if (tot > INT32_MAX) return fail(LMFMM_EINVAL, "batched launch too large");
+        blk0[BL.n] = (int)tot;
+        BL.nblk = (unsigned)tot;
+        BL.off_blk0 = put(blk0.data(), blk0.size() * sizeof(int));
+        BL.off_grid = put(grid.data(), grid.size() * sizeof(int));
+        BL.off_args = put(args.data(), args.size());
+        b->seq.push_back(BL);
+        s = e;
+    }
+    int rc;
+    if ((rc = upload(b->meta, host.data(), std::max<size_t>(host.size(), 256)))) return rc;
+    char *base = (char *)b->meta.p;
+    for (auto &BL : b->seq)
+        BL.m = MultiArgs{(const int *)(base + BL.off_blk0), (const int *)(base + BL.off_grid),
+                         (const void *)(base + BL.off_args), BL.n};
+    return LMFMM_OK;
+}
+
 static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs, int prec, hipStream_t st)
 {
     batch_drop_graph(b);
+    batch_collect_timing(b);
+    const auto t_start = std::chrono::steady_clock::now();
     int rc;
     b->chosen_order.assign(b->n, 0);
     b->chosen_levels.assign(b->n, 0);
     b->chosen_us.assign(b->n, 0.0);
-    hipEvent_t e0, e1;
+    b->from_cache.assign(b->n, 0);
+    std::map<std::string, TuneEntry> cache;
+    if (b->tune && !b->cache_path.empty()) read_tune_cache(b->cache_path, cache);
+    bool cache_dirty = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct EvGuard {
+        hipEvent_t &a, &c;
+        ~EvGuard()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (c) (void)hipEventDestroy(c);
+        }
+    } guard{e0, e1};
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     for (int i = 0; i < b->n; ++i) {
@@ -1565,92 +1796,97 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
         if ((rc = get_bbox(p, p->med, in.n_src, in.src_xy, in.n_tgt, in.tgt_xy, st, bb))) return rc;
         for (int j = 0; j < 6; ++j) p->box[j] = bb[j];
         p->have_box = true;
-        // 2. autotune (order floor from the set, levels around the automatic choice)
+        // 2. order floor and levels: the cache, else timed candidates
         p->levels_opt = 0;
         Geometry g0;
         if ((rc = make_geometry(p, bb, in.n_src, nrhs, g0))) return rc;
-        std::vector<int> Ls;
-        if (b->tune) {
+        const std::string key = tune_key(b, p, in, nrhs, prec);
+        auto hit = cache.find(key);
+        int bo = b->order_set.front(), bl = g0.L;
+        double best = 0.0;
+        if (b->tune && hit != cache.end()) {
+            bo = hit->second.order;
+            bl = hit->second.levels;
+            best = hit->second.us;
+            b->from_cache[i] = 1;
+        } else if (b->tune) {
+            std::vector<int> Ls;
             for (int dl = -1; dl <= 1; ++dl)
                 if (g0.L + dl >= 1 && g0.L + dl <= MAXLEV) Ls.push_back(g0.L + dl);
-        } else {
-            Ls.push_back(g0.L);
-        }
-        std::vector<int> orders = b->tune ? b->order_set : std::vector<int>{b->order_set.front()};
-        double best = 1e300;
-        int bo = orders.front(), bl = Ls.front();
-        for (int o : orders)
-            for (int L : Ls) {
-                p->order = o;
-                p->levels_opt = L;
-                rc = plan_apply_any(p, in, nrhs, prec, st);  // builds tables
-                if (rc == LMFMM_ETOL) continue;
-                if (rc) return rc;
-                const int reps = 3;
-                HIPCHK(hipEventRecord(e0, st));
-                for (int r = 0; r < reps && rc == LMFMM_OK; ++r) rc = plan_apply_any(p, in, nrhs, prec, st);
-                if (rc) return rc;
-                HIPCHK(hipEventRecord(e1, st));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                double us = 1e3 * ms / reps;
-                if (us < best) {
-                    best = us;
-                    bo = o;
-                    bl = L;
+            best = 1e300;
+            for (int o : b->order_set)
+                for (int L : Ls) {
+                    p->order = o;
+                    p->levels_opt = L;
+                    rc = plan_apply_any(p, in, nrhs, prec, st);  // builds tables
+                    if (rc == LMFMM_ETOL) continue;
+                    if (rc) return rc;
+                    const int reps = 3;
+                    HIPCHK(hipEventRecord(e0, st));
+                    for (int r = 0; r < reps && rc == LMFMM_OK; ++r) rc = plan_apply_any(p, in, nrhs, prec, st);
+                    if (rc) return rc;
+                    HIPCHK(hipEventRecord(e1, st));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    const double us = 1e3 * ms / reps;
+                    if (us < best) {
+                        best = us;
+                        bo = o;
+                        bl = L;
+                    }
                 }
-            }
+            if (best >= 1e300) return fail(LMFMM_ETOL, "no candidate order meets the tolerance");
+            cache[key] = TuneEntry{bo, bl, best};
+            cache_dirty = true;
+        }
         p->order = bo;
-        p->levels_opt = bl;
+        p->levels_opt = b->tune ? bl : 0;
         b->chosen_order[i] = bo;
         b->chosen_levels[i] = bl;
         b->chosen_us[i] = best;
         // 3. warm the chosen configuration (tables, workspace)
         if ((rc = plan_apply_any(p, in, nrhs, prec, st))) return rc;
+        b->chosen_levels[i] = p->geo.L;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (cache_dirty && !b->cache_path.empty()) write_tune_cache(b->cache_path, cache);
     HIPCHK(hipStreamSynchronize(st));
+    if ((rc = batch_record_merge(b, inst, nrhs, prec, st))) return rc;
     b->desc.assign(inst, inst + b->n);
     b->nrhs = nrhs;
     b->prec = prec;
+    // statistics: algorithmic work of every instance's apply (the recording
+    // pass counted it), merged launches per apply
+    for (int k = 0; k < 8; ++k) b->stats.kernel_flops[k] = 0.0;
+    for (int i = 0; i < b->n; ++i)
+        if (inst[i].n_tgt > 0 && inst[i].n_src > 0)
+            for (int k = 0; k < 8; ++k) b->stats.kernel_flops[k] += b->plans[i]->stats.kernel_flops[k];
+    b->stats.launches = (int)b->seq.size();
+    b->stats.instances = b->n;
+    int ncache = 0;
+    for (int v : b->from_cache) ncache += v;
+    b->stats.tuned_from_cache = ncache;
+    if (b->timing && b->ev.size() < 2 * b->seq.size()) {
+        const size_t old = b->ev.size();
+        b->ev.resize(2 * b->seq.size(), nullptr);
+        for (size_t j = old; j < b->ev.size(); ++j) HIPCHK(hipEventCreate(&b->ev[j]));
+    }
     if (b->graph) {
-        // capture all instances on a private stream forked into four branches
-        if (!b->cap_stream) {
-            HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-            b->branch.resize(4);
-            b->fork_ev.resize(1);
-            b->join_ev.resize(4);
-            for (auto &s2 : b->branch) HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&b->fork_ev[0], hipEventDisableTiming));
-            for (auto &e : b->join_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        }
+        if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-        HIPCHK(hipEventRecord(b->fork_ev[0], b->cap_stream));
-        for (int k = 0; k < 4; ++k) HIPCHK(hipStreamWaitEvent(b->branch[k], b->fork_ev[0], 0));
-        int crc = LMFMM_OK;
-        for (int i = 0; i < b->n && crc == LMFMM_OK; ++i) {
-            lmfmm_plan_s *p = b->plans[i];
-            bool timing = p->timing;
-            p->timing = false;
-            crc = plan_apply_any(p, inst[i], nrhs, prec, b->branch[i % 4]);
-            p->timing = timing;
-        }
-        for (int k = 0; k < 4; ++k) {
-            (void)hipEventRecord(b->join_ev[k], b->branch[k]);
-            (void)hipStreamWaitEvent(b->cap_stream, b->join_ev[k], 0);
-        }
+        const int lrc = batch_launch_seq(b, b->cap_stream, false);
         hipGraph_t g = nullptr;
-        hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
-        if (crc) {
+        const hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);  // the capture always ends here
+        if (lrc || ce != hipSuccess || !g) {
             if (g) (void)hipGraphDestroy(g);
-            return crc;
+            if (lrc) return lrc;
+            return fail(LMFMM_EHIP, std::string("graph capture failed: ") + hipGetErrorString(ce));
         }
-        if (ce != hipSuccess) return fail(LMFMM_EHIP, std::string("graph capture failed: ") + hipGetErrorString(ce));
         b->g = g;
         HIPCHK(hipGraphInstantiate(&b->ge, g, nullptr, nullptr, 0));
     }
+    b->stats.prepare_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     b->prepared = true;
     return LMFMM_OK;
 }
@@ -1664,12 +1900,16 @@ int lmfmm_batch_create(int n_inst, const double *k, const double *d, const int *
     *out = nullptr;
     if (n_inst < 1 || n_inst > 4096 || !k || !d) return fail(LMFMM_EINVAL, "bad instance count or media");
     if (!order_set || n_orders < 1 || n_orders > 16) return fail(LMFMM_EINVAL, "bad order set");
+    for (int i = 0; i < n_orders; ++i)
+        if (order_set[i] < 1 || order_set[i] > 256) return fail(LMFMM_EINVAL, "orders must be in [1, 256]");
     lmfmm_batch_s *b = new (std::nothrow) lmfmm_batch_s();
     if (!b) return fail(LMFMM_ENOMEM, "batch allocation failed");
+    std::memset(&b->stats, 0, sizeof b->stats);
     b->n = n_inst;
     b->tol = tol;
     b->order_set.assign(order_set, order_set + n_orders);
     std::sort(b->order_set.begin(), b->order_set.end());
+    if (const char *env = std::getenv("LMFMM_TUNE_CACHE")) b->cache_path = env;
     for (int i = 0; i < n_inst; ++i) {
         lmfmm_plan p = nullptr;
         int rc = lmfmm_create(k + 6 * i, d[i], b->order_set.front(), tol, &p);
@@ -1678,7 +1918,7 @@ int lmfmm_batch_create(int n_inst, const double *k, const double *d, const int *
             delete b;
             return rc;
         }
-        p->use_graph = false;  // the batch captures its instances' launches itself
+        p->use_graph = false;  // the batch launches its instances' kernels itself
         b->plans.push_back(p);
     }
     *out = b;
@@ -1690,11 +1930,11 @@ int lmfmm_batch_destroy(lmfmm_batch b)
     if (!b) return fail(LMFMM_EINVAL, "batch is null");
     (void)hipDeviceSynchronize();
     batch_drop_graph(b);
+    b->meta.release();
     for (auto p : b->plans) lmfmm_destroy(p);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    for (auto s2 : b->branch) (void)hipStreamDestroy(s2);
-    for (auto e : b->fork_ev) (void)hipEventDestroy(e);
-    for (auto e : b->join_ev) (void)hipEventDestroy(e);
+    for (auto e : b->ev)
+        if (e) (void)hipEventDestroy(e);
     delete b;
     return LMFMM_OK;
 }
@@ -1707,6 +1947,31 @@ int lmfmm_batch_set_option(lmfmm_batch b, const char *key, const char *value)
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "tune/graph must be 0 or 1");
         (k == "tune" ? b->tune : b->graph) = v == "1";
         batch_drop_graph(b);
+        return LMFMM_OK;
+    }
+    if (k == "tune_cache") {
+        b->cache_path = v;
+        return LMFMM_OK;
+    }
+    if (k == "timing") {
+        if (v == "reset") {
+            batch_collect_timing(b);
+            for (int i = 0; i < 8; ++i) {
+                b->stats.kernel_ms[i] = 0;
+                b->stats.kernel_launches[i] = 0;
+            }
+            b->stats.timed_applies = 0;
+            return LMFMM_OK;
+        }
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "timing must be 0, 1 or reset");
+        batch_collect_timing(b);
+        b->timing = v == "1";
+        if (b->timing && b->ev.size() < 2 * b->seq.size()) {
+            const size_t old = b->ev.size();
+            b->ev.resize(2 * b->seq.size(), nullptr);
+            for (size_t j = old; j < b->ev.size(); ++j)
+                if (hipEventCreate(&b->ev[j]) != hipSuccess) return fail(LMFMM_EHIP, "hipEventCreate failed");
+        }
         return LMFMM_OK;
     }
     // any other key is forwarded to every instance's plan
@@ -1736,15 +2001,23 @@ int lmfmm_batch_apply(lmfmm_batch b, const lmfmm_instance *inst, int nrhs, int p
             return rc;
         }
     }
-    if (b->ge) {
-        HIPCHK(hipGraphLaunch(b->ge, st));
+    // instances without sources have no recorded launches: zero their outputs
+    for (int i = 0; i < b->n; ++i)
+        if (inst[i].n_src == 0 && inst[i].n_tgt > 0)
+            launch_zero_bytes(inst[i].u, (size_t)inst[i].n_tgt * nrhs * (prec == LMFMM_C128 ? 16 : 8), st);
+    batch_collect_timing(b);
+    if (b->timing && b->ev.size() >= 2 * b->seq.size()) {
+        int rc = batch_launch_seq(b, st, true);
+        if (rc) return rc;
+        b->ev_pending = !b->seq.empty();
         return LMFMM_OK;
     }
-    for (int i = 0; i < b->n; ++i) {
-        int rc = plan_apply_any(b->plans[i], inst[i], nrhs, prec, st);
-        if (rc) return rc;
+    if (b->ge) {
+        HIPCHK(hipGraphLaunch(b->ge, st));
+        b->stats.graph_applies++;
+        return LMFMM_OK;
     }
-    return LMFMM_OK;
+    return batch_launch_seq(b, st, false);
 }
 
 int lmfmm_batch_get_choice(lmfmm_batch b, int i, int *order, int *levels, double *us)
@@ -1754,6 +2027,36 @@ int lmfmm_batch_get_choice(lmfmm_batch b, int i, int *order, int *levels, double
     if (order) *order = b->chosen_order[i];
     if (levels) *levels = b->chosen_levels[i];
     if (us) *us = b->chosen_us[i];
+    return LMFMM_OK;
+}
+
+int lmfmm_batch_get_stats(lmfmm_batch b, lmfmm_batch_stats *s)
+{
+    if (!b || !s) return fail(LMFMM_EINVAL, "null argument");
+    batch_collect_timing(b);
+    *s = b->stats;
+    return LMFMM_OK;
+}
+
+int lmfmm_batch_sync_status(lmfmm_batch b, void *stream)
+{
+    if (!b) return fail(LMFMM_EINVAL, "batch is null");
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    if (!b->prepared) return LMFMM_OK;
+    std::string bad;
+    for (int i = 0; i < b->n; ++i) {
+        lmfmm_plan_s *p = b->plans[i];
+        if (!p->d_err || !p->err_valid) continue;
+        int32_t e = 0;
+        HIPCHK(hipMemcpy(&e, p->d_err + 1, sizeof e, hipMemcpyDeviceToHost));
+        if (e) bad += (bad.empty() ? "" : ", ") + std::to_string(i);
+    }
+    if (!bad.empty()) {
+        batch_drop_graph(b);  // the next apply reads the bounding boxes again
+        return fail(LMFMM_EDOMAIN, "instance(s) " + bad +
+                                       ": points outside the bounding box the batch was prepared for, or outside "
+                                       "their layer (their results are invalid)");
+    }
     return LMFMM_OK;
 }
 

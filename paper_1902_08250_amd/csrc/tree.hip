@@ -153,30 +153,43 @@ __global__ void __launch_bounds__(64) k_bbox_final(const double *__restrict__ pa
 // counter's old value is the point's slot within its leaf (in arrival order;
 // the leaf pass sorts each leaf by original index).  The counters start at
 // zero: the scan of the previous build cleared them.
-__global__ void __launch_bounds__(256) k_tree_count(const double *__restrict__ src, int64_t ns,
-                                                    const double *__restrict__ tgt, int64_t nt, double x_lo,
-                                                    double invw, int col_lo, int ncol, int rows_s, int rows_t,
-                                                    double ys_lim, double yt_lim, uint32_t *__restrict__ key,
-                                                    int32_t *__restrict__ rank, int32_t *__restrict__ cnt,
-                                                    int32_t *__restrict__ err)
+struct TreeCountArgs {
+    const double *src;
+    int64_t ns;
+    const double *tgt;
+    int64_t nt;
+    double x_lo, invw;
+    int col_lo, ncol, rows_s, rows_t;
+    double ys_lim, yt_lim;
+    uint32_t *key;
+    int32_t *rank, *cnt, *err;
+};
+__device__ __forceinline__ void tree_count_body(const TreeCountArgs &a, int bx)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ns + nt) return;
-    bool tg = i >= ns;
-    double x = tg ? tgt[i - ns] : src[i];
-    double y = tg ? tgt[nt + i - ns] : src[ns + i];
-    bool bad = !(isfinite(x) && isfinite(y)) || (tg ? !(y < 0.0 && y > yt_lim) : !(y > 0.0 && y < ys_lim));
-    double fc = floor((x - x_lo) * invw) - (double)col_lo;
-    double fr = floor((tg ? -y : y) * invw);
-    int rows = tg ? rows_t : rows_s;
-    if (!(fc >= 0.0 && fc < (double)ncol && fr >= 0.0 && fr < (double)rows)) bad = true;
-    int c = (int)fmin(fmax(fc, 0.0), (double)(ncol - 1));
+    int64_t i = (int64_t)bx * 256 + threadIdx.x;
+    if (i >= a.ns + a.nt) return;
+    bool tg = i >= a.ns;
+    double x = tg ? a.tgt[i - a.ns] : a.src[i];
+    double y = tg ? a.tgt[a.nt + i - a.ns] : a.src[a.ns + i];
+    bool bad = !(isfinite(x) && isfinite(y)) || (tg ? !(y < 0.0 && y > a.yt_lim) : !(y > 0.0 && y < a.ys_lim));
+    double fc = floor((x - a.x_lo) * a.invw) - (double)a.col_lo;
+    double fr = floor((tg ? -y : y) * a.invw);
+    int rows = tg ? a.rows_t : a.rows_s;
+    if (!(fc >= 0.0 && fc < (double)a.ncol && fr >= 0.0 && fr < (double)rows)) bad = true;
+    int c = (int)fmin(fmax(fc, 0.0), (double)(a.ncol - 1));
     int r = (int)fmin(fmax(fr, 0.0), (double)(rows - 1));
-    if (bad) atomicOr(err, 1);
-    uint32_t k = (uint32_t)r * (uint32_t)ncol + (uint32_t)c;
-    if (tg) k += (uint32_t)rows_s * (uint32_t)ncol;
-    key[i] = k;
-    rank[i] = atomicAdd(&cnt[k], 1);
+    if (bad) atomicOr(a.err, 1);
+    uint32_t k = (uint32_t)r * (uint32_t)a.ncol + (uint32_t)c;
+    if (tg) k += (uint32_t)a.rows_s * (uint32_t)a.ncol;
+    a.key[i] = k;
+    a.rank[i] = atomicAdd(&a.cnt[k], 1);
+}
+__global__ void __launch_bounds__(256) k_tree_count(TreeCountArgs a) { tree_count_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_tree_count_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    tree_count_body(static_cast<const TreeCountArgs *>(m.args)[i], bx);
 }
 
 // Exclusive scan of the leaf counts by one block, in LDS tiles of SC_TILE
@@ -187,10 +200,18 @@ __global__ void __launch_bounds__(256) k_tree_count(const double *__restrict__ s
 // leaf empty and set bit 1 of err[1], so that no later kernel indexes with
 // them.
 constexpr int SC_THREADS = 1024, SC_PER = 8, SC_TILE = SC_THREADS * SC_PER;
-__global__ void __launch_bounds__(SC_THREADS) k_tree_scan(int32_t *__restrict__ cnt, int64_t nbox, int64_t n,
-                                                          int32_t *__restrict__ start, int32_t *__restrict__ end,
-                                                          int32_t *__restrict__ err)
+struct TreeScanArgs {
+    int32_t *cnt;
+    int64_t nbox, n;
+    int32_t *start, *end, *err;
+};
+__device__ __forceinline__ void tree_scan_body(const TreeScanArgs &A)
 {
+    int32_t *__restrict__ cnt = A.cnt;
+    int32_t *__restrict__ start = A.start;
+    int32_t *__restrict__ end = A.end;
+    int32_t *__restrict__ err = A.err;
+    const int64_t nbox = A.nbox, n = A.n;
     __shared__ int32_t tile[SC_TILE];
     __shared__ int32_t wsum[SC_THREADS / 64];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -258,14 +279,34 @@ __global__ void __launch_bounds__(SC_THREADS) k_tree_scan(int32_t *__restrict__ 
     }
 }
 
-__global__ void __launch_bounds__(256) k_tree_scatter(const uint32_t *__restrict__ key,
-                                                      const int32_t *__restrict__ rank, int64_t n,
-                                                      const int32_t *__restrict__ start, int32_t *__restrict__ perm)
+__global__ void __launch_bounds__(SC_THREADS) k_tree_scan(TreeScanArgs a) { tree_scan_body(a); }
+__global__ void __launch_bounds__(SC_THREADS) k_tree_scan_multi(MultiArgs m)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t pos = (int64_t)start[key[i]] + rank[i];
-    if (pos >= 0 && pos < n) perm[pos] = (int32_t)i;
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    tree_scan_body(static_cast<const TreeScanArgs *>(m.args)[i]);
+}
+
+struct TreeScatterArgs {
+    const uint32_t *key;
+    const int32_t *rank;
+    int64_t n;
+    const int32_t *start;
+    int32_t *perm;
+};
+__device__ __forceinline__ void tree_scatter_body(const TreeScatterArgs &a, int bx)
+{
+    int64_t i = (int64_t)bx * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t pos = (int64_t)a.start[a.key[i]] + a.rank[i];
+    if (pos >= 0 && pos < a.n) a.perm[pos] = (int32_t)i;
+}
+__global__ void __launch_bounds__(256) k_tree_scatter(TreeScatterArgs a) { tree_scatter_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_tree_scatter_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    tree_scatter_body(static_cast<const TreeScatterArgs *>(m.args)[i], bx);
 }
 
 __device__ inline void cswap(int32_t &a, int32_t &b, bool up)
@@ -281,16 +322,35 @@ __device__ inline void cswap(int32_t &a, int32_t &b, bool up)
 // registers up to 64 points, in LDS up to LF_LDS, else in the leaf's own
 // slice of the scratch array), then write idx and gather the coordinates.
 constexpr int LF_LDS = 1024;  // small, so that many one-wave blocks fit on a CU
-__global__ void __launch_bounds__(64) k_tree_leaf(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
-                                                  const int32_t *__restrict__ perm, int32_t *__restrict__ scratch,
-                                                  int32_t *__restrict__ idx, const double *__restrict__ src,
-                                                  int64_t ns, const double *__restrict__ tgt, int64_t nt,
-                                                  double *__restrict__ xs, double *__restrict__ ys,
-                                                  const uint64_t *__restrict__ q, uint64_t *__restrict__ qs,
-                                                  int nrhs, int qw)
+struct TreeLeafArgs {
+    const int32_t *start, *end, *perm;
+    int32_t *scratch, *idx;
+    const double *src;
+    int64_t ns;
+    const double *tgt;
+    int64_t nt;
+    double *xs, *ys;
+    const uint64_t *q;
+    uint64_t *qs;
+    int nrhs, qw;
+};
+__device__ __forceinline__ void tree_leaf_body(const TreeLeafArgs &A, int b)
 {
+    const int32_t *__restrict__ start = A.start;
+    const int32_t *__restrict__ end = A.end;
+    const int32_t *__restrict__ perm = A.perm;
+    int32_t *__restrict__ scratch = A.scratch;
+    int32_t *__restrict__ idx = A.idx;
+    const double *__restrict__ src = A.src;
+    const double *__restrict__ tgt = A.tgt;
+    double *__restrict__ xs = A.xs;
+    double *__restrict__ ys = A.ys;
+    const uint64_t *__restrict__ q = A.q;
+    uint64_t *__restrict__ qs = A.qs;
+    const int64_t ns = A.ns, nt = A.nt;
+    const int nrhs = A.nrhs, qw = A.qw;
     __shared__ int32_t sh[LF_LDS];
-    const int b = blockIdx.x, lane = threadIdx.x;
+    const int lane = threadIdx.x;
     const int s = start[b], nb = end[b] - s;
     if (nb <= 0) return;
     auto emit = [&](int k, int32_t o) {
@@ -340,10 +400,29 @@ __global__ void __launch_bounds__(64) k_tree_leaf(const int32_t *__restrict__ st
     for (int i = lane; i < nb; i += 64) emit(i, a[i]);
 }
 
-__global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
+__global__ void __launch_bounds__(64) k_tree_leaf(TreeLeafArgs a) { tree_leaf_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(64) k_tree_leaf_multi(MultiArgs m)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    tree_leaf_body(static_cast<const TreeLeafArgs *>(m.args)[i], bx);
+}
+
+struct ZeroArgs {
+    uint32_t *p;
+    int64_t n;
+};
+__device__ __forceinline__ void zero_body(const ZeroArgs &a, int bx)
+{
+    int64_t i = (int64_t)bx * 256 + threadIdx.x;
+    if (i < a.n) a.p[i] = 0u;
+}
+__global__ void __launch_bounds__(256) k_zero_u32(ZeroArgs a) { zero_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_zero_u32_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    zero_body(static_cast<const ZeroArgs *>(m.args)[i], bx);
 }
 
 }  // namespace
@@ -386,7 +465,9 @@ void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st)
 {
     int64_t n = (int64_t)(nbytes / 4);
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t *)p, n);
+    const ZeroArgs a{(uint32_t *)p, n};
+    emit((const void *)k_zero_u32, (const void *)k_zero_u32_multi, 0, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+         st, a);
 }
 
 void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
@@ -397,12 +478,16 @@ void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, d
     const int64_t nbox = (int64_t)(rows_s + rows_t) * ncol;
     if (n == 0 || nbox == 0) return;
     const unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_tree_count, dim3(g), dim3(256), 0, st, src, ns, tgt, nt, x_lo, 1.0 / w, col_lo, ncol, rows_s,
-                       rows_t, ys_lim, yt_lim, b.key, b.rank, b.cnt, err);
-    hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(SC_THREADS), 0, st, b.cnt, nbox, n, b.start, b.end, err);
-    hipLaunchKernelGGL(k_tree_scatter, dim3(g), dim3(256), 0, st, b.key, b.rank, n, b.start, b.perm);
-    hipLaunchKernelGGL(k_tree_leaf, dim3((unsigned)nbox), dim3(64), 0, st, b.start, b.end, b.perm, b.scratch, b.idx,
-                       src, ns, tgt, nt, b.xs, b.ys, b.q, b.qs, b.nrhs, b.qw);
+    const TreeCountArgs ca{src, ns, tgt, nt, x_lo, 1.0 / w, col_lo, ncol, rows_s, rows_t, ys_lim, yt_lim, b.key, b.rank,
+                           b.cnt, err};
+    emit((const void *)k_tree_count, (const void *)k_tree_count_multi, 0, dim3(g), dim3(256), 0, st, ca);
+    const TreeScanArgs sa{b.cnt, nbox, n, b.start, b.end, err};
+    emit((const void *)k_tree_scan, (const void *)k_tree_scan_multi, 1, dim3(1), dim3(SC_THREADS), 0, st, sa);
+    const TreeScatterArgs xa{b.key, b.rank, n, b.start, b.perm};
+    emit((const void *)k_tree_scatter, (const void *)k_tree_scatter_multi, 2, dim3(g), dim3(256), 0, st, xa);
+    const TreeLeafArgs la{b.start, b.end, b.perm, b.scratch, b.idx, src, ns, tgt, nt, b.xs, b.ys, b.q, b.qs, b.nrhs,
+                          b.qw};
+    emit((const void *)k_tree_leaf, (const void *)k_tree_leaf_multi, 3, dim3((unsigned)nbox), dim3(64), 0, st, la);
 }
 
 }  // namespace lmfmm

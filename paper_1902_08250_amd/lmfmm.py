@@ -42,6 +42,13 @@ class Stats(ctypes.Structure):
 KERNELS = ["tree", "p2m", "m2m", "m2l", "near_sweep", "l2p_near", "l2l", "other"]
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int), ("instances", ctypes.c_int), ("tuned_from_cache", ctypes.c_int),
+                ("prepare_seconds", ctypes.c_double), ("kernel_flops", ctypes.c_double * 8),
+                ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_int64 * 8),
+                ("timed_applies", ctypes.c_int64), ("graph_applies", ctypes.c_int64)]
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("n_src", ctypes.c_int64), ("src_xy", ctypes.c_void_p), ("q", ctypes.c_void_p),
                 ("n_tgt", ctypes.c_int64), ("tgt_xy", ctypes.c_void_p), ("u", ctypes.c_void_p)]
@@ -50,6 +57,7 @@ class Instance(ctypes.Structure):
 EXPORTS = ["lmfmm_create", "lmfmm_destroy", "lmfmm_set_option", "lmfmm_apply", "lmfmm_apply_adjoint",
            "lmfmm_grad_coords", "lmfmm_direct", "lmfmm_get_stats", "lmfmm_sync_status", "lmfmm_batch_create",
            "lmfmm_batch_destroy", "lmfmm_batch_set_option", "lmfmm_batch_apply", "lmfmm_batch_get_choice",
+           "lmfmm_batch_sync_status", "lmfmm_batch_get_stats",
            "lmfmm_status_string", "lmfmm_last_error"]
 
 
@@ -86,6 +94,8 @@ def lib():
     L.lmfmm_batch_set_option.argtypes = [P, ctypes.c_char_p, ctypes.c_char_p]
     L.lmfmm_batch_apply.argtypes = [P, ctypes.POINTER(Instance), I, I, P]
     L.lmfmm_batch_get_choice.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]
+    L.lmfmm_batch_sync_status.argtypes = [P, P]
+    L.lmfmm_batch_get_stats.argtypes = [P, ctypes.POINTER(BatchStats)]
     L.lmfmm_status_string.argtypes = [I]
     L.lmfmm_status_string.restype = ctypes.c_char_p
     L.lmfmm_last_error.argtypes = []
@@ -121,7 +131,7 @@ def _dens(t, n, name):
     import torch
     if t.dim() == 1:
         t = t.unsqueeze(0)
-    if not (t.is_cuda and t.dtype in (torch.complex128, torch.complex64) and t.shape[1] == n):
+    if not (t.dim() == 2 and t.is_cuda and t.dtype in (torch.complex128, torch.complex64) and t.shape[1] == n):
         raise ValueError(f"{name} must be a complex64/complex128 CUDA tensor of shape (nrhs, {n})")
     return t.contiguous()
 
@@ -129,6 +139,16 @@ def _dens(t, n, name):
 def _prec(dtype):
     import torch
     return C128 if dtype == torch.complex128 else C64_MIXED
+
+
+def _out(t, nrhs, n, dtype, device, name):
+    """A caller-supplied output: CUDA, contiguous, shape (nrhs, n), dtype of the densities
+    (the C side cannot know buffer sizes, so a wrong buffer would be written out of bounds)."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous() and t.dtype == dtype
+            and tuple(t.shape) == (nrhs, n) and t.device == device):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape ({nrhs}, {n}) on {device}")
+    return t
 
 
 class Plan:
@@ -168,7 +188,10 @@ class Plan:
         import torch
         src, tgt = _xy(src, "src"), _xy(tgt, "tgt")
         q = _dens(q, src.shape[1], "q")
-        u = out if out is not None else torch.empty((q.shape[0], tgt.shape[1]), dtype=q.dtype, device=q.device)
+        if out is not None:
+            u = _out(out, q.shape[0], tgt.shape[1], q.dtype, q.device, "out")
+        else:
+            u = torch.empty((q.shape[0], tgt.shape[1]), dtype=q.dtype, device=q.device)
         _check(lib().lmfmm_apply(self._h, src.shape[1], src.data_ptr(), q.data_ptr(), tgt.shape[1], tgt.data_ptr(),
                                  u.data_ptr(), q.shape[0], _prec(q.dtype), _stream(stream)))
         return u
@@ -224,7 +247,7 @@ class Batch:
 
     media: list of (k, d); order_set: candidate order floors for the autotuner."""
 
-    def __init__(self, media, order_set=(12, 16, 20), tol=1e-6, tune=True, graph=True):
+    def __init__(self, media, order_set=(12, 16, 20), tol=1e-6, tune=True, graph=True, tune_cache=None):
         L = lib()
         n = len(media)
         karr = (ctypes.c_double * (6 * n))()
@@ -245,34 +268,58 @@ class Batch:
             self.set_option("tune", "0")
         if not graph:
             self.set_option("graph", "0")
+        if tune_cache is not None:
+            self.set_option("tune_cache", tune_cache)
 
     def set_option(self, key, value):
         _check(lib().lmfmm_batch_set_option(self._h, key.encode(), str(value).encode()))
 
     def apply(self, items, outs=None, stream=None):
         """items: list of (src, q, tgt); returns the list of outputs u (reuses outs if given,
-        which keeps the descriptors fixed so that later calls replay the captured graph)."""
+        which keeps the descriptors fixed so that later calls replay the prepared launches).
+        Every instance must have the same number of right-hand sides and the same dtype."""
         import torch
         if len(items) != self.n:
             raise ValueError("one (src, q, tgt) per instance")
-        arr = (Instance * self.n)()
+        if outs is not None and len(outs) != self.n:
+            raise ValueError("one output per instance")
+        checked = []
+        nrhs = dtype = None
+        for i, (src, q, tgt) in enumerate(items):
+            src, tgt = _xy(src, f"src[{i}]"), _xy(tgt, f"tgt[{i}]")
+            q = _dens(q, src.shape[1], f"q[{i}]")
+            if nrhs is None:
+                nrhs, dtype = q.shape[0], q.dtype
+            elif q.shape[0] != nrhs or q.dtype != dtype:
+                raise ValueError(f"instance {i}: densities of shape {tuple(q.shape)} and dtype {q.dtype}; every "
+                                 f"instance must have {nrhs} right-hand sides of dtype {dtype}")
+            checked.append((src, q, tgt))
         if outs is None:
-            outs = []
-            for (src, q, tgt) in items:
-                q2 = q if q.dim() == 2 else q.unsqueeze(0)
-                outs.append(torch.empty((q2.shape[0], tgt.shape[1]), dtype=q.dtype, device=q.device))
-        nrhs, prec = None, None
+            outs = [torch.empty((nrhs, tgt.shape[1]), dtype=dtype, device=q.device) for (_, q, tgt) in checked]
+        else:
+            outs = [_out(u, nrhs, tgt.shape[1], dtype, q.device, f"outs[{i}]")
+                    for i, (u, (_, q, tgt)) in enumerate(zip(outs, checked))]
+        arr = (Instance * self.n)()
         keep = []
-        for i, ((src, q, tgt), u) in enumerate(zip(items, outs)):
-            src, tgt = _xy(src, "src"), _xy(tgt, "tgt")
-            q = _dens(q, src.shape[1], "q")
+        for i, ((src, q, tgt), u) in enumerate(zip(checked, outs)):
             keep += [src, q, tgt, u]
-            nrhs = q.shape[0] if nrhs is None else nrhs
-            prec = _prec(q.dtype) if prec is None else prec
             arr[i] = Instance(src.shape[1], src.data_ptr(), q.data_ptr(), tgt.shape[1], tgt.data_ptr(), u.data_ptr())
-        _check(lib().lmfmm_batch_apply(self._h, arr, nrhs, prec, _stream(stream)))
+        _check(lib().lmfmm_batch_apply(self._h, arr, nrhs, _prec(dtype), _stream(stream)))
         self._keep = keep
         return outs
+
+    def sync_status(self, stream=None):
+        """Synchronise and raise if any instance's points left the bounding box the
+        batch was prepared for (or their layer); the next apply then prepares again."""
+        _check(lib().lmfmm_batch_sync_status(self._h, _stream(stream)))
+
+    def stats(self):
+        s = BatchStats()
+        _check(lib().lmfmm_batch_get_stats(self._h, ctypes.byref(s)))
+        d = {f: getattr(s, f) for f, _ in BatchStats._fields_}
+        for f in ("kernel_flops", "kernel_ms", "kernel_launches"):
+            d[f] = dict(zip(KERNELS, list(getattr(s, f))))
+        return d
 
     def choices(self):
         out = []

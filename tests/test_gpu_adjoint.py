@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from paper_1902_08250_amd import workloads
+from parity_util import TOL, check
 
 pytestmark = pytest.mark.gpu
 K, D = workloads.MEDIUM_A
@@ -83,9 +84,7 @@ def test_adjoint_mixed(cuda):
     pl = Plan(K, D, order=16, tol=1e-6, levels=5)
     v64 = host(pl.apply_adjoint(dev(src), dev(tgt), dev(w)))
     v32 = host(pl.apply_adjoint(dev(src), dev(tgt), dev(w.astype(np.complex64))))
-    err = rel(v32.astype(np.complex128), v64)
-    say("mixed adjoint rel-l2", err)
-    assert err < 5e-6
+    check(v32, v64, TOL["c64"], "mixed adjoint vs fp64", say)
 
 
 @pytest.mark.parametrize("levels", [1, 3])
@@ -134,9 +133,8 @@ def test_grad_mixed_vs_fp64(cuda):
     pl = Plan(K, D, order=16, tol=1e-6, levels=5)
     ds64, dt64 = pl.grad_coords(dev(src), dev(q), dev(tgt), dev(w))
     ds32, dt32 = pl.grad_coords(dev(src), dev(q.astype(np.complex64)), dev(tgt), dev(w.astype(np.complex64)))
-    es, et = rel(host(ds32), host(ds64)), rel(host(dt32), host(dt64))
-    say("mixed grad rel-l2 src", es, "tgt", et)
-    assert es < 2e-5 and et < 2e-5
+    check(host(ds32), host(ds64), TOL["c64"], "mixed source gradient vs fp64", say)
+    check(host(dt32), host(dt64), TOL["c64"], "mixed target gradient vs fp64", say)
 
 
 def test_autograd_function(cuda):

@@ -2,18 +2,23 @@
 slabs, medium k = (10, 20, 15) + 0.01i, d = 1, complex64 densities, order 16
 on a 7-level quadtree (the benchmark configuration).
 
-  * against the FP64 FMM (tol 1e-10) over all targets;
-  * against the FP64 GPU direct sum at 1000 seeded targets over all sources;
-  * the direct sum against the oracle at 3 of those targets.
+  * mixed FMM and FP64 FMM against the oracle at 100 seeded targets, each
+    summed over all 1e5 sources (tests/golden/oracle_mixed_uniform_1e5.npz,
+    written by make_fullsize_goldens.py): 1e-6 (mixed) and 1e-10 (FP64),
+    rel-l2 and worst entry;
+  * mixed FMM against the FP64 FMM over all targets (1e-6).
 """
+import os
 import sys
 
 import numpy as np
 import pytest
 
 from paper_1902_08250_amd import workloads
+from parity_util import TOL, check
 
 pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_mixed_uniform_1e5.npz")
 
 
 def say(*a):
@@ -26,28 +31,18 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
-def test_mixed_uniform_1e5(orc):
+def test_mixed_uniform_1e5():
     from paper_1902_08250_amd.lmfmm import Plan
     w = workloads.make(1)
-    say("mixed-uniform-1e5: mixed FMM, FP64 FMM, direct at 1000 targets")
+    g = np.load(GOLD)
+    sel, ref = g["sel"], g["u"]
+    say("mixed-uniform-1e5: mixed FMM and FP64 FMM vs oracle at", sel.size, "targets")
     src, tgt = dev(w["src"]), dev(w["tgt"])
     pl32 = Plan(w["k"], w["d"], order=w["order"], tol=w["tol"], levels=w["levels"])
     u32 = pl32.apply(src, dev(w["q"].astype(np.complex64)), tgt).cpu().numpy().astype(np.complex128)
-    q64 = w["q"].astype(np.complex128)
     pl64 = Plan(w["k"], w["d"], order=w["order"], tol=1e-10, levels=w["levels"])
-    u64 = pl64.apply(src, dev(q64), tgt).cpu().numpy()
-    rng = np.random.default_rng(1001)
-    sel = np.sort(rng.choice(w["n_tgt"], 1000, replace=False))
-    d = pl64.direct(src, dev(q64), dev(np.ascontiguousarray(w["tgt"][:, sel]))).cpu().numpy()
-    e_mf, e_fd, e_md = rel(u32, u64), rel(u64[:, sel], d), rel(u32[:, sel], d)
-    say("rel-l2 mixed vs fp64 fmm", e_mf, "fp64 fmm vs direct", e_fd, "mixed vs direct", e_md,
-        "orders", pl32.stats()["order"])
-    three = np.array([0, 500, 999])
-    ref = orc.apply(w["src"], q64, w["tgt"][:, sel[three]], w["k"], w["d"])
-    e_do = rel(d[:, three], ref)
-    say("direct vs oracle at 3 targets", e_do)
-    assert e_mf < 1e-6 and e_md < 1e-6 and e_fd < 1e-10 and e_do < 1e-12
+    u64 = pl64.apply(src, dev(w["q"].astype(np.complex128)), tgt).cpu().numpy()
+    say("orders", pl32.stats()["order"], pl64.stats()["order"])
+    check(u32[:, sel], ref, TOL["c64"], "mixed vs oracle", say)
+    check(u64[:, sel], ref, TOL["c128"], "fp64 vs oracle", say)
+    check(u32, u64, TOL["c64"], "mixed vs fp64 fmm (all targets)", say)
