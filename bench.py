@@ -1,20 +1,28 @@
-"""Benchmark of the layered-media FMM apply on one MI355X.
+"""Benchmark of the layered-media FMM on one MI355X.
 
-Workload: the mixed-precision uniform case -- N = M = 100000 sources and
-targets in the slabs x in [0,1], y in (0.05,1) / (-0.95,-0.05) of the medium
-k = (10, 20, 15) + 0.01i, d = 1; complex64 densities; order 16 on a 7-level
-quadtree; FP32 expansions and translations with FP64 sigma tables.  A step is
-one complete apply (bounding box, tree build, upward pass, M2L, downward pass,
-local evaluation and near field) with all inputs resident in HBM.
+Headline workload (the metric's "mixed + batched"): 16 problem instances with
+their own three-layer media (k1 in [5,30], k2 in [10,60], k3 in [5,40], each
++0.01i; d in [0.5, 2]) and log-uniform sizes N = M in [1e3, 2e5], 4 complex64
+right-hand sides each, applied as one batch: every stage of all instances is
+one merged launch, the sequence replayed as one HIP graph, each instance's
+order floor (from {12, 16, 20}) and levels autotuned, tolerance 1e-6.  A step
+is one batched apply of all instances (tree build, upward pass, M2L, downward
+pass, near field, local evaluation) with every input resident in HBM.
+`value` = sum_i N_i M_i nrhs / time per step.
 
-Prints one JSON line with the throughput in source-target interactions/s,
-the same workload through the plain FP64 FMM, the near-interface workload
-(FP64, near field by sweeps), the batched workload (16
-instances with their own media, 4 right-hand sides each) as one graph launch
-against the FP64 FMM applied instance by instance, the roofline of the
-dominant kernel (HIP-event durations of its launches in the timed region,
-algorithmic work from the plan's counts) and the FP64 oracle timed on this
-host's cores on a bounded sample of targets.
+Beside it, on one JSON line:
+  * the same batch through the FP64 path (complex128, tol 1e-10, its own
+    autotuned choices) as one merged graph: the like-for-like FP64 FMM; and
+    the FP64 plans applied instance after instance, for context;
+  * errors against the oracle's stored samples of every instance;
+  * the roofline of the dominant kernel class of the batched apply (event
+    durations of its merged launches, algorithmic flops from the plans'
+    counts) and, for the other legs, of theirs;
+  * the mixed uniform workload (1e5 x 1e5, one right-hand side, order 16,
+    7 levels) with a cold apply (translation tables built in the call);
+  * the near-interface workload (2e5 x 2e5 within 1e-3 of the interface,
+    FP64) with the roofline of its near-field sweep;
+  * the FP64 oracle timed on this host's cores on a bounded sample.
 
 --copy-probe MIB runs only a plain device copy of that size (the calibration
 kernel for the HBM byte counters) and exits.
@@ -24,6 +32,7 @@ import json
 import os
 import re
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -36,10 +45,12 @@ from paper_1902_08250_amd.prof_summary import source_hash  # noqa: E402
 
 # MI355X published peaks
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
-# kernel of each timing class on this workload (FP32 expansions, leaf order 16)
-KERNEL_NAMES = {"p2m": "k_p2m<float, 16>", "m2m": "k_up<float>", "m2l": "k_m2l_all<float>", "l2l": "k_down<float>",
-                "near_sweep": "k_near_sweep<float>", "l2p_near": "k_l2p<float, 16, 1>"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mixed_uniform_1e5.md")
+GOLD = os.path.join(ROOT, "tests", "golden")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batched_16x4.md")
+# algorithmic FP64 flops of the near-field sweep per (point, node, direction):
+# one complex exponential (range reductions and the exp and sin/cos
+# polynomials: 32) and one complex multiply-add (8)
+SWEEP_FLOPS_PER_POINT_NODE_DIR = 40.0
 
 
 def parse():
@@ -48,10 +59,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 FMM leg")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 legs")
+    ap.add_argument("--no-uniform", action="store_true", help="skip the mixed uniform leg")
     ap.add_argument("--no-near", action="store_true", help="skip the near-interface leg")
     ap.add_argument("--only-near", action="store_true", help="run only the near-interface leg")
+    ap.add_argument("--only-batched", action="store_true", help="run only the batched legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     return ap.parse_args()
@@ -82,11 +94,131 @@ def copy_probe(torch, mib):
                                      "write_bytes": 4 * n, "launches": 3}}), flush=True)
 
 
-def run_gpu(torch, Plan, w, precision, steps, warmup, timing=False, domain=None):
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def roofline(st, peak_key, kernel_names, bound="alu"):
+    """Dominant kernel class of the timed applies against its peak:
+    achieved = algorithmic flops per launch / mean launch duration."""
+    nap = max(1, st["timed_applies"])
+    cand = {k: v for k, v in st["kernel_ms"].items() if k in kernel_names and st["kernel_launches"][k] > 0}
+    dom = max(cand, key=cand.get)
+    launches = st["kernel_launches"][dom] / nap
+    avg_s = cand[dom] / nap / launches * 1e-3
+    flops_launch = st["kernel_flops"][dom] / launches
+    achieved = flops_launch / avg_s
+    kname = kernel_names[dom]
+    traffic = recorded_traffic(kname)
+    return {"kernel": kname, "class": dom, "bound": bound, "achieved": achieved / 1e12,
+            "peak": PEAK[peak_key] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[peak_key],
+            "traffic": traffic, "flops_per_launch": flops_launch, "launches_per_apply": launches,
+            "avg_launch_us": avg_s * 1e6, "hbm_GBps_if_traffic": (traffic / avg_s / 1e9) if traffic else None}
+
+
+def time_batch(torch, b, items, outs, steps, warmup):
+    for _ in range(warmup):
+        b.apply(items, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.apply(items, outs=outs)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    # per-class durations: the same merged launches with start/stop events
+    b.set_option("timing", "1")
+    b.apply(items, outs=outs)
+    b.set_option("timing", "reset")
+    for _ in range(steps):
+        b.apply(items, outs=outs)
+    torch.cuda.synchronize()
+    st = b.stats()
+    b.set_option("timing", "0")
+    return t, st
+
+
+BATCH_KERNELS = {"p2m": "k_p2m_multi<float, 16>", "m2m": "k_up_multi<float>", "m2l": "k_m2l_all_multi<float>",
+                 "l2l": "k_down_multi<float>", "near_sweep": "k_near_sweep_multi<float, 4>",
+                 "l2p_near": "k_l2p_multi<float, 16, 4>"}
+
+
+def batched_legs(torch, args):
+    from paper_1902_08250_amd.lmfmm import Batch, Plan
+    inst = workloads.make_batched()
+    inter = float(sum(d["src"].shape[1] * d["tgt"].shape[1] * d["q"].shape[0] for d in inst))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    items = [(dev(d["src"]), dev(d["q"]), dev(d["tgt"])) for d in inst]
+    media = [(d["k"], d["d"]) for d in inst]
+    cache = os.path.join(tempfile.mkdtemp(prefix="lmfmm_tune_"), "tune.jsonl")
+    t0 = time.perf_counter()
+    b = Batch(media, order_set=(12, 16, 20), tol=1e-6, tune_cache=cache)
+    outs = b.apply(items)
+    torch.cuda.synchronize()
+    prep_tuned = time.perf_counter() - t0
+    # a second batch over the same instances takes its choices from the cache
+    t0 = time.perf_counter()
+    b_c = Batch(media, order_set=(12, 16, 20), tol=1e-6, tune_cache=cache)
+    outs_c = b_c.apply(items)
+    torch.cuda.synchronize()
+    prep_cached = time.perf_counter() - t0
+    del b_c, outs_c
+    t, st = time_batch(torch, b, items, outs, args.steps, args.warmup)
+    print(f"[bench] batched mixed: {t * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    u = [o.cpu().numpy().astype(np.complex128) for o in outs]
+    errs = []
+    for i in range(len(inst)):
+        g = np.load(os.path.join(GOLD, f"oracle_batched_inst{i}.npz"))
+        errs.append(rel(u[i][:, g["sel"]], g["u"]))
+    out = {"value": inter / t, "ms_per_step": t * 1e3, "interactions_per_step": inter, "stats": st,
+           "choices": b.choices(), "prepare_s_tuned": prep_tuned, "prepare_s_from_cache": prep_cached,
+           "rel_l2_max_vs_oracle_samples": max(errs), "roofline": roofline(st, "fp32", BATCH_KERNELS)}
+    if not args.no_fp64:
+        items64 = [(s, dev(d["q"].astype(np.complex128)), tt) for (s, _, tt), d in zip(items, inst)]
+        t0 = time.perf_counter()
+        b64 = Batch(media, order_set=(12, 16, 20), tol=1e-10)
+        outs64 = b64.apply(items64)
+        torch.cuda.synchronize()
+        prep64 = time.perf_counter() - t0
+        t64, st64 = time_batch(torch, b64, items64, outs64, max(3, args.steps // 2), 1)
+        print(f"[bench] batched fp64: {t64 * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+        u64 = [o.cpu().numpy() for o in outs64]
+        e64 = []
+        for i in range(len(inst)):
+            g = np.load(os.path.join(GOLD, f"oracle_batched_inst{i}.npz"))
+            e64.append(rel(u64[i][:, g["sel"]], g["u"]))
+        out["fp64_batched"] = {"value": inter / t64, "ms_per_step": t64 * 1e3, "tol": 1e-10,
+                               "prepare_s_tuned": prep64, "choices": b64.choices(),
+                               "rel_l2_max_vs_oracle_samples": max(e64),
+                               "kernel_ms_per_apply": {k: v / max(1, st64["timed_applies"])
+                                                       for k, v in st64["kernel_ms"].items() if v > 0}}
+        out["speedup_mixed_batched_vs_fp64_batched"] = t64 / t
+        out["rel_l2_max_mixed_vs_fp64_batched"] = max(rel(a, c) for a, c in zip(u, u64))
+        # FP64 plans applied one after another (no batching), for context
+        plans = [Plan(d["k"], d["d"], order=16, tol=1e-10) for d in inst]
+        os_ = [p.apply(*it) for p, it in zip(plans, items64)]
+        torch.cuda.synchronize()
+        n64 = max(2, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(n64):
+            for p, it, o in zip(plans, items64, os_):
+                p.apply(*it, out=o)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t0) / n64
+        out["fp64_sequential_plans"] = {"value": inter / ts, "ms_per_step": ts * 1e3}
+        out["speedup_mixed_batched_vs_fp64_sequential"] = ts / t
+    return inst, out
+
+
+UNIFORM_KERNELS = {"p2m": "k_p2m<float, 16>", "m2m": "k_up<float>", "m2l": "k_m2l_all<float>", "l2l": "k_down<float>",
+                   "l2p_near": "k_l2p<float, 16, 1>"}
+
+
+def run_plan(torch, Plan, w, precision, steps, warmup, timing=False, domain=None):
     """Times `steps` applies (the second warm-up apply captures the launch
     sequence as a HIP graph, the timed ones replay it).  With timing, the same
     steps are run again kernel by kernel with HIP start/stop events on every
-    kernel launch of the apply's stream, for the per-kernel durations."""
+    kernel launch of the apply's stream, for the per-kernel durations.  Also
+    returns the time of the plan's first apply, which builds its tables."""
     dt = torch.complex128 if precision == "c128" else torch.complex64
     src = torch.from_numpy(w["src"]).cuda()
     tgt = torch.from_numpy(w["tgt"]).cuda()
@@ -95,6 +227,11 @@ def run_gpu(torch, Plan, w, precision, steps, warmup, timing=False, domain=None)
     pl = Plan(w["k"], w["d"], order=w["order"], tol=w["tol"] if precision == "c64" else 1e-10, levels=w["levels"])
     if domain:
         pl.set_option("domain", domain)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.apply(src, q, tgt, out=u)
+    torch.cuda.synchronize()
+    cold = time.perf_counter() - t0
     for _ in range(max(warmup, 2)):
         pl.apply(src, q, tgt, out=u)
     torch.cuda.synchronize()
@@ -119,84 +256,84 @@ def run_gpu(torch, Plan, w, precision, steps, warmup, timing=False, domain=None)
         st_t["ms_per_step_kernel_by_kernel"] = (time.perf_counter() - t2) / steps * 1e3
         st_t["graph_applies"] = st["graph_applies"]
         st = st_t
-    return (t1 - t0) / steps, out, st
+    return (t1 - t0) / steps, out, st, cold
 
 
-def roofline(st):
-    """Dominant kernel of the timed applies (tree-build group excluded: it is
-    many small kernels) against the FP32 vector peak."""
+def uniform_leg(torch, Plan, args):
+    w = workloads.make(1)
+    inter = float(w["n_src"]) * w["n_tgt"] * w["nrhs"]
+    t, u, st, cold = run_plan(torch, Plan, w, "c64", args.steps, args.warmup, timing=True)
+    print(f"[bench] uniform mixed: {t * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     nap = max(1, st["timed_applies"])
-    cand = {k: v for k, v in st["kernel_ms"].items() if k in KERNEL_NAMES and st["kernel_launches"][k] > 0}
-    dom = max(cand, key=cand.get)
-    ms_apply = cand[dom] / nap
-    launches = st["kernel_launches"][dom] / nap
-    avg_s = ms_apply / launches * 1e-3
-    flops_launch = st["kernel_flops"][dom] / launches
-    achieved = flops_launch / avg_s
-    kname = KERNEL_NAMES[dom]
-    traffic = recorded_traffic(kname)
-    return {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"], "traffic": traffic,
-            "flops_per_launch": flops_launch, "launches_per_apply": launches, "avg_launch_us": avg_s * 1e6,
-            "hbm_GBps_if_traffic": (traffic / avg_s / 1e9) if traffic else None}
+    g = np.load(os.path.join(GOLD, "oracle_mixed_uniform_1e5.npz"))
+    out = {"workload": w["name"], "n_src": w["n_src"], "n_tgt": w["n_tgt"], "nrhs": w["nrhs"], "order": w["order"],
+           "levels": w["levels"], "tol": w["tol"], "dtype": "f32", "value": inter / t, "ms_per_step": t * 1e3,
+           "cold_apply_ms": cold * 1e3, "orders_by_level": st["order"],
+           "kernel_ms_per_apply": {k: v / nap for k, v in st["kernel_ms"].items() if v > 0},
+           "kernel_launches_per_apply": {k: v / nap for k, v in st["kernel_launches"].items() if v > 0},
+           "graph_applies_in_timed_region": st["graph_applies"],
+           "rel_l2_vs_oracle_samples": rel(u[:, g["sel"]].astype(np.complex128), g["u"]),
+           "roofline": roofline(st, "fp32", UNIFORM_KERNELS)}
+    t_dom, u_dom, _, _ = run_plan(torch, Plan, w, "c64", args.steps, args.warmup, domain="0,1,1,-0.95")
+    out["fixed_domain"] = {"value": inter / t_dom, "ms_per_step": t_dom * 1e3,
+                           "max_abs_diff_vs_auto": float(np.max(np.abs(u_dom - u)))}
+    if not args.no_fp64:
+        t64, u64, _, cold64 = run_plan(torch, Plan, w, "c128", max(3, args.steps // 4), 1)
+        out["fp64"] = {"value": inter / t64, "ms_per_step": t64 * 1e3, "cold_apply_ms": cold64 * 1e3,
+                       "rel_l2_vs_oracle_samples": rel(u64[:, g["sel"]], g["u"])}
+        out["rel_l2_mixed_vs_fp64"] = rel(u.astype(np.complex128), u64)
+    return w, out
 
 
-def batched_leg(torch, steps, warmup):
-    from paper_1902_08250_amd.lmfmm import Batch, Plan
-    inst = workloads.make_batched()
-    inter = float(sum(d["src"].shape[1] * d["tgt"].shape[1] * d["q"].shape[0] for d in inst))
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
-    items = [(dev(d["src"]), dev(d["q"]), dev(d["tgt"])) for d in inst]
-    t0 = time.perf_counter()
-    b = Batch([(d["k"], d["d"]) for d in inst], order_set=(12, 16, 20), tol=1e-6)
-    outs = b.apply(items)
-    torch.cuda.synchronize()
-    t_prep = time.perf_counter() - t0
-    for _ in range(warmup):
-        b.apply(items, outs=outs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        b.apply(items, outs=outs)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / steps
-    # plain FP64 FMM, instance after instance
-    items64 = [(s, dev(d["q"].astype(np.complex128)), t) for (s, _, t), d in zip(items, inst)]
-    plans = [Plan(d["k"], d["d"], order=16, tol=1e-10) for d in inst]
-    outs64 = [p.apply(*it) for p, it in zip(plans, items64)]
-    torch.cuda.synchronize()
-    n64 = max(2, steps // 4)
-    t0 = time.perf_counter()
-    for _ in range(n64):
-        for p, it, o in zip(plans, items64, outs64):
-            p.apply(*it, out=o)
-    torch.cuda.synchronize()
-    t64 = (time.perf_counter() - t0) / n64
-    errs = [float(np.linalg.norm(o.cpu().numpy().astype(np.complex128) - r.cpu().numpy()) /
-                  np.linalg.norm(r.cpu().numpy())) for o, r in zip(outs, outs64)]
-    return {"workload": "batched: 16 instances, N log-uniform in [1e3, 2e5], own media, 4 RHS each, c64",
-            "value": inter / tb, "unit": "interactions/s", "ms_per_step": tb * 1e3,
-            "prepare_s": t_prep, "choices": b.choices(),
-            "fp64_fmm_sequential": {"value": inter / t64, "ms_per_step": t64 * 1e3},
-            "speedup_vs_fp64_sequential": t64 / tb, "rel_l2_max_vs_fp64_fmm": max(errs)}
-
-
-def near_leg(torch, Plan, steps, warmup):
+def near_leg(torch, Plan, args):
     """The near-interface workload (2e5 sources and targets within 1e-3 of
     the interface, medium k = (40, 60, 50) + 0.01i, d = 0.5, FP64, order 20,
     12 levels): the near field is the x-ordered sweep of the row-0 leaves."""
     w = workloads.make(2)
     inter = float(w["n_src"]) * w["n_tgt"] * w["nrhs"]
-    n = max(3, steps // 4)
-    t, _, st = run_gpu(torch, Plan, w, "c128", n, warmup, timing=True)
+    n = max(3, args.steps // 4)
+    t, u, st, cold = run_plan(torch, Plan, w, "c128", n, args.warmup, timing=True)
+    print(f"[bench] near-interface: {t * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     nap = max(1, st["timed_applies"])
-    sweep_ms = st["kernel_ms"]["near_sweep"] / nap
+    sweep_s = st["kernel_ms"]["near_sweep"] / nap * 1e-3
+    nodes = st["near_nodes_mid"] + 2 * st["near_nodes_ray"]
+    # every source and target is visited once per direction and node (the
+    # sweep's algorithmic work; all points lie in row-0 leaves here)
+    flops = (w["n_src"] + w["n_tgt"]) * nodes * 2 * SWEEP_FLOPS_PER_POINT_NODE_DIR * w["nrhs"]
+    g = np.load(os.path.join(GOLD, "oracle_near_interface_2e5.npz"))
     return {"workload": w["name"], "n_src": w["n_src"], "n_tgt": w["n_tgt"], "order": w["order"],
             "levels": w["levels"], "tol": 1e-10, "dtype": "f64", "steps": n, "value": inter / t,
-            "unit": "interactions/s", "ms_per_step": t * 1e3,
+            "unit": "interactions/s", "ms_per_step": t * 1e3, "cold_apply_ms": cold * 1e3,
             "kernel_ms_per_apply": {k: v / nap for k, v in st["kernel_ms"].items() if v > 0},
-            "near_sweep": {"kernel": "k_near_sweep<double, 1>", "ms_per_launch": sweep_ms,
-                           "nodes": st["near_nodes_mid"] + 2 * st["near_nodes_ray"]}}
+            "rel_l2_vs_oracle_samples": rel(u[:, g["sel"]], g["u"]),
+            "roofline": {"kernel": "k_near_sweep<double, 1>", "bound": "alu", "achieved": flops / sweep_s / 1e12,
+                         "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s", "frac": flops / sweep_s / PEAK["fp64"],
+                         "traffic": None, "flops_per_launch": flops, "avg_launch_us": sweep_s * 1e6,
+                         "nodes": nodes, "flops_per_point_node_direction": SWEEP_FLOPS_PER_POINT_NODE_DIR}}
+
+
+def cpu_baseline(inst, args):
+    """The oracle on this host's cores on a bounded sample of the batched
+    workload: one seeded target of each instance, summed over all of that
+    instance's sources and all four right-hand sides."""
+    import oracle
+    oracle.build(force=False)
+    cores = oracle.max_threads()
+    rng = np.random.default_rng(123)
+    pairs, t_cpu, done = 0.0, 0.0, 0
+    order = rng.permutation(len(inst))
+    for i in order:
+        d = inst[i]
+        j = int(rng.integers(d["n"]))
+        t0 = time.perf_counter()
+        oracle.apply(d["src"], d["q"].astype(np.complex128), d["tgt"][:, j:j + 1], d["k"], d["d"])
+        t_cpu += time.perf_counter() - t0
+        pairs += float(d["n"]) * d["q"].shape[0]
+        done += 1
+        if t_cpu > args.cpu_seconds:
+            break
+    return {"value": pairs / t_cpu, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 seeded target of each of {done} instances x all their sources x 4 rhs ({t_cpu:.1f} s)"}
 
 
 def main():
@@ -211,80 +348,40 @@ def main():
         return
     from paper_1902_08250_amd.lmfmm import Plan
     if args.only_near:
-        print(json.dumps({"near_interface": near_leg(torch, Plan, args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"near_interface": near_leg(torch, Plan, args)}), flush=True)
         return
-
-    w = workloads.make(1)
-    n_src, n_tgt, nrhs = w["n_src"], w["n_tgt"], w["nrhs"]
-    inter = float(n_src) * n_tgt * nrhs
-
-    print(f"[bench] workload {w['name']}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-    t_mixed, u_mixed, st = run_gpu(torch, Plan, w, "c64", args.steps, args.warmup, timing=True)
-    print(f"[bench] mixed: {t_mixed * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] batched workload: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    inst, b = batched_legs(torch, args)
+    st = b.pop("stats")
     nap = max(1, st["timed_applies"])
     out = {
         "metric": "source-target interactions/s at stated rel-l2 err; mixed+batched vs FP64 FMM",
-        "value": inter / t_mixed,
+        "value": b["value"],
         "unit": "interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t_mixed * 1e3,
+        "ms_per_step": b["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w["name"], "n_src": n_src, "n_tgt": n_tgt, "nrhs": nrhs, "order": w["order"],
-                   "levels": w["levels"], "tol": w["tol"], "orders_by_level": st["order"],
-                   "medium": "k=(10,20,15)+0.01i, d=1"},
-        "kernel_ms_per_apply": {k: v / nap for k, v in st["kernel_ms"].items() if v > 0},
-        "ms_per_step_kernel_by_kernel_with_events": st["ms_per_step_kernel_by_kernel"],
-        "kernel_launches_per_apply": {k: v / nap for k, v in st["kernel_launches"].items() if v > 0},
-        "m2l_pairs": st["m2l_pairs"],
-        "graph_applies_in_timed_region": st["graph_applies"],
-        "roofline": roofline(st),
+        "config": {"workload": "batched-16-instances-4rhs-mixed", "instances": len(inst),
+                   "n_per_instance": [d["n"] for d in inst], "nrhs": 4, "tol": 1e-6, "order_set": [12, 16, 20],
+                   "media": "k1 U[5,30], k2 U[10,60], k3 U[5,40] (+0.01i), d U[0.5,2], seed 3"},
+        "roofline": b.pop("roofline"),
+        "batched": dict(b, merged_launches_per_apply=st["launches"],
+                        kernel_ms_per_apply={k: v / nap for k, v in st["kernel_ms"].items() if v > 0},
+                        kernel_launches_per_apply={k: v / nap for k, v in st["kernel_launches"].items() if v > 0}),
     }
-    # the same applies with the domain given up front: no bounding-box readback,
-    # so consecutive applies are queued without a host round trip in between
-    t_dom, u_dom, _ = run_gpu(torch, Plan, w, "c64", args.steps, args.warmup, domain="0,1,1,-0.95")
-    out["fixed_domain"] = {"value": inter / t_dom, "ms_per_step": t_dom * 1e3, "domain": "x in [0,1], y_s < 1, y_t > -0.95",
-                           "max_abs_diff_vs_auto": float(np.max(np.abs(u_dom - u_mixed)))}
-    if not args.no_fp64:
-        t64, u64, _ = run_gpu(torch, Plan, w, "c128", max(3, args.steps // 4), 1)
-        print(f"[bench] fp64: {t64 * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-        out["fp64_fmm"] = {"value": inter / t64, "ms_per_step": t64 * 1e3}
-        out["mixed_over_fp64"] = t64 / t_mixed
-        out["rel_l2_mixed_vs_fp64_fmm"] = float(np.linalg.norm(u_mixed - u64) / np.linalg.norm(u64))
-    if not args.no_near:
-        out["near_interface"] = near_leg(torch, Plan, args.steps, args.warmup)
-        print(f"[bench] near-interface: {out['near_interface']['ms_per_step']:.3f} ms/step", file=sys.stderr,
-              flush=True)
-    if not args.no_batched:
-        out["batched"] = batched_leg(torch, args.steps, args.warmup)
-        print(f"[bench] batched: {out['batched']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-
+    if not args.only_batched:
+        if not args.no_uniform:
+            _, out["mixed_uniform_1e5"] = uniform_leg(torch, Plan, args)
+        if not args.no_near:
+            out["near_interface"] = near_leg(torch, Plan, args)
     if not args.no_cpu:
-        import oracle
-        oracle.build(force=False)
-        cores = oracle.max_threads()
-        rng = np.random.default_rng(123)
-        # size the sample to about cpu_seconds of oracle work
-        t0 = time.perf_counter()
-        oracle.apply(w["src"], w["q"].astype(np.complex128), w["tgt"][:, :cores], w["k"], w["d"])
-        t_probe = time.perf_counter() - t0
-        n_s = max(cores, int(cores * args.cpu_seconds / max(t_probe, 1e-3)))
-        n_s = min(n_s, n_tgt)
-        sel = np.sort(rng.choice(n_tgt, n_s, replace=False))
-        t0 = time.perf_counter()
-        ref = oracle.apply(w["src"], w["q"].astype(np.complex128), w["tgt"][:, sel], w["k"], w["d"])
-        t_cpu = time.perf_counter() - t0
-        rate = float(n_s) * n_src * nrhs / t_cpu
-        out["cpu_baseline"] = {"value": rate, "unit": "interactions/s", "cores": cores, "kind": "oracle",
-                               "sample": f"{n_s} seeded targets x {n_src} sources ({t_cpu:.1f} s)"}
-        out["rel_l2_mixed_vs_oracle_sample"] = float(np.linalg.norm(u_mixed[:, sel] - ref) / np.linalg.norm(ref))
-        if not args.no_fp64:
-            out["rel_l2_fp64_vs_oracle_sample"] = float(np.linalg.norm(u64[:, sel] - ref) / np.linalg.norm(ref))
+        out["cpu_baseline"] = cpu_baseline(inst, args)
     print(json.dumps(out), flush=True)
 
 

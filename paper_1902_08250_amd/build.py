@@ -2,7 +2,8 @@
 
 Each source in csrc/ is compiled to an object under _build/ in parallel, then
 linked into paper_1902_08250_amd/liblmfmm.so.  Usage: python -m
-paper_1902_08250_amd.build [-j N].
+paper_1902_08250_amd.build [-j N] [--incremental] (--incremental keeps the
+objects that are newer than their source and every header).
 """
 import concurrent.futures as cf
 import os
@@ -24,8 +25,16 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src):
+def _headers_mtime():
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hs.append(os.path.join(ROOT, "include", "lmfmm.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src, incremental=False):
     obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(src), _headers_mtime()):
+        return obj
     cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -33,12 +42,12 @@ def _compile(src):
     return obj
 
 
-def build(jobs=None):
+def build(jobs=None, incremental=False):
     os.makedirs(OUT_DIR, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(8, len(srcs))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,4 +59,4 @@ def build(jobs=None):
 
 if __name__ == "__main__":
     j = int(sys.argv[sys.argv.index("-j") + 1]) if "-j" in sys.argv else None
-    print(build(j))
+    print(build(j, incremental="--incremental" in sys.argv))

@@ -95,22 +95,29 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
             // in increasing point order; four points' LDS reads issued together
             const cx<T> *bp = B + (j0 - c0) * nc + c, *qp = Q + (j0 - c0) * nrhs + r;
             const int np = j1 - j0;
-            cx<T> acc = mk<T>(0, 0);
+            // groups of four points summed plainly, the groups' sums added
+            // with compensation (FP32: the error does not grow with the
+            // leaf's point count)
+            CAcc<T> acc;
+            acc.zero();
             int jj = 0;
             for (; jj + 4 <= np; jj += 4) {
                 const cx<T> b0 = bp[jj * nc], b1 = bp[(jj + 1) * nc], b2 = bp[(jj + 2) * nc], b3 = bp[(jj + 3) * nc];
                 const cx<T> q0 = qp[jj * nrhs], q1 = qp[(jj + 1) * nrhs], q2 = qp[(jj + 2) * nrhs],
                             q3 = qp[(jj + 3) * nrhs];
-                cfma(acc, b0, q0);
-                cfma(acc, b1, q1);
-                cfma(acc, b2, q2);
-                cfma(acc, b3, q3);
+                cx<T> g4 = b0 * q0;
+                cfma(g4, b1, q1);
+                cfma(g4, b2, q2);
+                cfma(g4, b3, q3);
+                acc.add(g4);
             }
-            for (; jj < np; ++jj) cfma(acc, bp[jj * nc], qp[jj * nrhs]);
+            cx<T> g4 = mk<T>(0, 0);
+            for (; jj < np; ++jj) cfma(g4, bp[jj * nc], qp[jj * nrhs]);
+            acc.add(g4);
             if (c0 == S)
-                Mb[it] = acc;
+                Mb[it] = acc.value();
             else if (j1 > j0)
-                Mb[it] += acc;
+                Mb[it] += acc.value();
         }
         __syncthreads();
     }
@@ -637,10 +644,13 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_s * lv.ncol;
     if (nbox == 0) return;
-    // points per chunk: as many as 78 KB of LDS hold (two blocks per compute
-    // unit), at most P2M_CHMAX
+    // points per chunk: as many as the LDS share of a block holds, at most
+    // P2M_CHMAX; the share is 78 KB (two blocks per compute unit) up to about
+    // 0.8 x 256 points per block and compute unit, else 38 KB (four blocks)
     const size_t per = (size_t)(lv.nc + nrhs) * sizeof(cx<T>);
-    int CH = (int)((78 * 1024) / per);
+    const int64_t load = std::max<int64_t>(ns, launch_batch_points());
+    const size_t share = load > (int64_t)(2 * 0.8 * P2M_THREADS * device_shape().cus) ? 38 * 1024 : 78 * 1024;
+    int CH = (int)(share / per);
     CH = CH > P2M_CHMAX ? P2M_CHMAX : (CH < 1 ? 1 : CH);
     const size_t sh = (size_t)CH * per;
     int per_cu = (int)(device_shape().lds / (sh > 0 ? sh : 1));
@@ -672,10 +682,11 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     if (!(do_near && lv.rows_s > 0)) unear = nullptr;
     if (!do_near || unear || lv.rows_s == 0) {
         // far field plus, if any, the sweep's near-field parts: G leaves per block
-        const int RM = nrhs == 1 ? 1 : 8;
+        const int RM = nrhs == 1 ? 1 : (nrhs <= 4 ? 4 : 8);
         const size_t per_leaf = (size_t)RM * lv.nc * sizeof(cx<T>);
         // about 0.8 x 256 points per block, two blocks per compute unit: one
-        // leaf per wave in the shift phase
+        // leaf per wave in the shift phase (larger blocks, whose waves shift
+        // several leaves in turn, were slower)
         int G = leaves_per_block(nbox, nt, 256, 2);
         G = G > L2P_THREADS / 64 ? L2P_THREADS / 64 : G;
         const int gmax = (int)((48 * 1024) / per_leaf);
@@ -688,8 +699,10 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
 #define LMFMM_L2P_PACKED(RMC)                                                                              \
     emit((const void *)k_l2p<T, PMAX, RMC>, (const void *)k_l2p_multi<T, PMAX, RMC>, 0, grid, dim3(L2P_THREADS), \
          G * per_leaf, st, a)
-        if (nrhs == 1)
+        if (RM == 1)
             LMFMM_L2P_PACKED(1);
+        else if (RM == 4)
+            LMFMM_L2P_PACKED(4);
         else
             LMFMM_L2P_PACKED(8);
 #undef LMFMM_L2P_PACKED

@@ -79,6 +79,14 @@ inline int &launch_stage()
     return s;
 }
 inline void set_stage(Stage s, int j = 0) { launch_stage() = (int)s * 64 + j; }
+// While a batch is recorded: the sources of all its instances.  A launcher
+// that sizes its blocks' LDS for occupancy sizes them for this many points
+// (a merged launch runs with the largest LDS size of its instances).
+inline int64_t &launch_batch_points()
+{
+    static thread_local int64_t n = 0;
+    return n;
+}
 
 // Argument of a multi-instance launch: instance i takes the blocks
 // [blk0[i], blk0[i + 1]) of the flat grid, its own grid is grid[3i .. 3i + 2]
@@ -179,6 +187,35 @@ __host__ __device__ inline void cfma(cx<T> &a, cx<T> b, cx<T> c)
     a.re = fma(b.re, c.re, fma(-b.im, c.im, a.re));
     a.im = fma(b.re, c.im, fma(b.im, c.re, a.im));
 }
+// Compensated complex accumulator (Kahan summation): in FP32 the rounding
+// error of each addition is kept in c and taken off the next addend, so the
+// error of a long sum does not grow with the number of terms; FP64 adds
+// plainly.
+template <typename T>
+struct CAcc {
+    cx<T> s, c;
+    __host__ __device__ void zero()
+    {
+        s = {T(0), T(0)};
+        c = {T(0), T(0)};
+    }
+    __host__ __device__ void add(cx<T> x)
+    {
+        if (sizeof(T) == 8) {
+            s.re += x.re;
+            s.im += x.im;
+            return;
+        }
+        const T yr = x.re - c.re, yi = x.im - c.im;
+        const T tr = s.re + yr, ti = s.im + yi;
+        c.re = (tr - s.re) - yr;
+        c.im = (ti - s.im) - yi;
+        s.re = tr;
+        s.im = ti;
+    }
+    __host__ __device__ cx<T> value() const { return {s.re - c.re, s.im - c.im}; }
+};
+
 template <typename T>
 __host__ __device__ inline cx<T> cinv(cx<T> a)
 {

@@ -507,8 +507,8 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
     // node groups of 64 over up to 4 parts of SW_W waves; segments of leaf
     // columns long enough to share the sources, short enough for about two
     // thousand blocks
-    const int RM = nrhs == 1 ? 1 : 8;
-    const int G = RM == 1 ? SweepCap<1>::G : SweepCap<8>::G;
+    const int RM = nrhs == 1 ? 1 : (nrhs <= 4 ? 4 : 8);
+    const int G = RM == 1 ? SweepCap<1>::G : (RM == 4 ? SweepCap<4>::G : SweepCap<8>::G);
     const int nunits = ((nnodes + 63) / 64 + G - 1) / G;
     int nparts = (nunits + SW_W - 1) / SW_W;
     nparts = nparts < 1 ? 1 : (nparts > 4 ? 4 : nparts);
@@ -531,6 +531,8 @@ int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *i
     } while (0)
     if (RM == 1)
         LMFMM_SWEEP_LAUNCH(1);
+    else if (RM == 4)
+        LMFMM_SWEEP_LAUNCH(4);
     else
         LMFMM_SWEEP_LAUNCH(8);
 #undef LMFMM_SWEEP_LAUNCH

@@ -354,13 +354,17 @@ static double kabs_max(const Medium &m)
 
 // Expansion order at a level: max(order, the order the tolerance needs for the
 // worst one-box-separated pair (ratio ~0.4 per term, Theorem 1), the order at
-// which |J_P(|k| R)| falls below tol/100 for the level's box radius R).
+// which |J_P(|k| R)| falls below 1e-4 tol for the level's box radius R).  The
+// Bessel margin covers the slow decay of the expansions' terms for lambda just
+// above the branch point at the high-frequency levels (k R near kr_max): with
+// tol/100 there, an FP64 apply at tol 1e-10 measured 1.7e-10 against the
+// oracle.
 static int order_for_level(const lmfmm_plan_s *p, double w)
 {
     if (p->fixed_order) return p->order;
     double R = w / std::sqrt(2.0);
     int ptol = (int)std::ceil(std::log(p->tol) / std::log(0.4));
-    int pj = bessel_cutoff(kabs_max(p->med) * R, 0.01 * p->tol);
+    int pj = bessel_cutoff(kabs_max(p->med) * R, 1e-4 * p->tol);
     int P = std::max(p->order, std::max(ptol, pj));
     return std::min(P, 480);
 }
@@ -1690,6 +1694,9 @@ static int batch_record_merge(lmfmm_batch_s *b, const lmfmm_instance *inst, int 
         RecLaunch L;
     };
     std::vector<Rec> all;
+    int64_t tot_src = 0;
+    for (int i = 0; i < b->n; ++i) tot_src += inst[i].n_src;
+    launch_batch_points() = tot_src;
     for (int i = 0; i < b->n; ++i) {
         lmfmm_plan_s *p = b->plans[i];
         if (inst[i].n_tgt == 0 || inst[i].n_src == 0) continue;  // (no sources: zeroed by the apply)
@@ -1701,9 +1708,13 @@ static int batch_record_merge(lmfmm_batch_s *b, const lmfmm_instance *inst, int 
         int rc = plan_apply_any(p, inst[i], nrhs, prec, st);
         launch_recorder() = nullptr;
         p->timing = timing;
-        if (rc) return rc;
+        if (rc) {
+            launch_batch_points() = 0;
+            return rc;
+        }
         for (auto &L : rec.v) all.push_back(Rec{i, std::move(L)});
     }
+    launch_batch_points() = 0;
     std::stable_sort(all.begin(), all.end(), [](const Rec &a, const Rec &c) {
         if (a.L.key != c.L.key) return a.L.key < c.L.key;
         return std::less<const void *>()(a.L.multi, c.L.multi);

@@ -21,9 +21,10 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_1902_08250_amd/csrc/cexp_tab.h", "paper_1902_08250_amd/csrc/expand.hip",
-                  "paper_1902_08250_amd/csrc/lmfmm_internal.h",
-                  "paper_1902_08250_amd/csrc/tables.hip", "paper_1902_08250_amd/csrc/tree.hip"]
+KERNEL_SOURCES = ["paper_1902_08250_amd/csrc/cexp_tab.h", "paper_1902_08250_amd/csrc/expand_common.h",
+                  "paper_1902_08250_amd/csrc/leaf.hip", "paper_1902_08250_amd/csrc/lmfmm_internal.h",
+                  "paper_1902_08250_amd/csrc/near.hip", "paper_1902_08250_amd/csrc/tables.hip",
+                  "paper_1902_08250_amd/csrc/translate.hip", "paper_1902_08250_amd/csrc/tree.hip"]
 
 
 def source_hash():
