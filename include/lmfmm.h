@@ -119,6 +119,34 @@ int lmfmm_set_option(lmfmm_plan plan, const char *key, const char *value);
 int lmfmm_apply(lmfmm_plan plan, int64_t n_src, const double *src_xy, const void *q, int64_t n_tgt,
                 const double *tgt_xy, void *u, int nrhs, int precision, void *stream);
 
+/* Size of the fixed device array that lmfmm_apply_noalloc works in. */
+#define LMFMM_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* lmfmm_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and result as lmfmm_apply; the caller passes inputs and outputs.
+ * It allocates no device memory (no hipMalloc, hipFree or other allocating
+ * call): the per-apply workspace (tree arrays, grouped points and densities,
+ * expansions, near-field partial sums, counters and error flags) is one fixed
+ * array of LMFMM_NOALLOC_MAX_BYTES inside the library, one copy per GPU, held
+ * until the process ends.  Its counters are cleared by a kernel at the start
+ * of every call.
+ *   - The plan's translation and near-field tables for the apply's geometry
+ *     must exist: an earlier lmfmm_apply of the plan with the same geometry
+ *     (same bounding box, or the same "domain" option, and the same levels)
+ *     builds them.  Otherwise LMFMM_EINVAL and nothing is queued.
+ *   - An apply whose workspace exceeds LMFMM_NOALLOC_MAX_BYTES returns
+ *     LMFMM_EINVAL (the message states the size needed) before queuing anything.
+ *   - The plan's device must be current.  Kernels are launched one by one (no
+ *     graph); without the "domain" option the call waits for the bounding box
+ *     as lmfmm_apply does.  The plan's statistics are not updated.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap on a
+ *     GPU (other streams, other host threads, other plans) race and give wrong
+ *     results.  lmfmm_sync_status reports the error flag of the last such call
+ *     only until the next one on that GPU. */
+int lmfmm_apply_noalloc(lmfmm_plan plan, int64_t n_src, const double *src_xy, const void *q, int64_t n_tgt,
+                        const double *tgt_xy, void *u, int nrhs, int precision, void *stream);
+
 /* Transposed operator, no conjugation: v[r][j] = sum_i g_2^t(tgt_i, src_j) w[r][i].
  * Same arguments as lmfmm_apply with w: [nrhs][n_tgt] in, v: [nrhs][n_src] out. */
 int lmfmm_apply_adjoint(lmfmm_plan plan, int64_t n_src, const double *src_xy, int64_t n_tgt,

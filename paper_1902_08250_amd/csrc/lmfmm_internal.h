@@ -500,6 +500,13 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
                    const Node *nodes, int nmid, int npan, double t0, int nchunk, cx<double> *part, void *u,
                    hipStream_t st);
 
+// noalloc.hip: the fixed device array of lmfmm_apply_noalloc (its size is
+// LMFMM_NOALLOC_MAX_BYTES of lmfmm.h).  init resolves the address on device
+// dev (which must be current); ptr returns it, or null before init.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+hipError_t noalloc_scratch_init(int dev);
+void *noalloc_scratch_ptr(int dev);
+
 // tables.hip
 void launch_node_table(const double *lamw, int n, Medium med, Node *out, hipStream_t st);
 void launch_m2l_tables(const double *lamw, const int *node_cls, const int *node_local, int ntot,

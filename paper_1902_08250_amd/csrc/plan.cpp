@@ -227,6 +227,7 @@ struct VarTables {
 };
 
 struct lmfmm_plan_s {
+    int device = 0;  // the device current at creation
     Medium med;
     int order = 16;
     double tol = 1e-6;
@@ -680,13 +681,17 @@ static std::vector<int> class_shape(const Geometry &g)
     return k;
 }
 
-static int ensure_far_tables(VarTables &vt, const Medium &med, const Geometry &g)
+// build = false: report LMFMM_EINVAL instead of building (allocation-free apply)
+static int ensure_far_tables(VarTables &vt, const Medium &med, const Geometry &g, bool build = true)
 {
     bool same = vt.t_L == g.L && vt.t_W == g.W && vt.t_top == g.ltop;
     for (int l = 1; same && l <= g.L; ++l) same = vt.t_P[l] == g.lev[l].P;
     std::vector<int> shape = class_shape(g);
     if (same) same = shape == vt.t_shape;
     if (same) return LMFMM_OK;
+    if (!build)
+        return fail(LMFMM_EINVAL, "the plan has no translation tables for this geometry (an lmfmm_apply with the "
+                                  "same geometry builds them)");
     double t_start = (double)clock() / CLOCKS_PER_SEC;
     int rc;
     vt.t_L = -1;
@@ -704,7 +709,7 @@ static int ensure_far_tables(VarTables &vt, const Medium &med, const Geometry &g
     return LMFMM_OK;
 }
 
-static int ensure_near_table(VarTables &vt, const Medium &med, const Geometry &g, double amin)
+static int ensure_near_table(VarTables &vt, const Medium &med, const Geometry &g, double amin, bool build = true)
 {
     double dxmax = 2.0 * g.lev[g.L].w;
     double c = contour_c(med);
@@ -713,6 +718,9 @@ static int ensure_near_table(VarTables &vt, const Medium &med, const Geometry &g
     double ar = std::max(amin, 1e-12) / std::sqrt(2.0);
     int npan = std::min(64, 2 + (int)std::ceil(std::log2(std::max(2.0, 40.0 / (ar * t0)))));
     if (vt.near_nodes.p && vt.n_h == h && vt.n_t0 == t0 && vt.n_npan >= npan) return LMFMM_OK;
+    if (!build)
+        return fail(LMFMM_EINVAL, "the plan has no near-field table for this geometry (an lmfmm_apply with the "
+                                  "same geometry builds it)");
     vt.version++;
     return build_near_table(vt.near_nodes, med, dxmax, amin, vt.n_c, vt.n_h, vt.n_t0, vt.n_nmid, vt.n_npan);
 }
@@ -752,8 +760,15 @@ int lmfmm_create(const double k[6], double d, int order, double tol, lmfmm_plan 
     if (!(tol > 0 && tol < 1)) return fail(LMFMM_EINVAL, "tol must be in (0, 1)");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(LMFMM_ENODEV, "no HIP device available");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(LMFMM_ENODEV, "no current HIP device");
+    // resolve this device's copy of the allocation-free apply's array (a
+    // failure is reported by that entry point, not here)
+    (void)noalloc_scratch_init(dev);
+    (void)hipGetLastError();
     lmfmm_plan_s *p = new (std::nothrow) lmfmm_plan_s();
     if (!p) return fail(LMFMM_ENOMEM, "plan allocation failed");
+    p->device = dev;
     p->med.k1 = {k[0], k[1]};
     p->med.k2 = {k[2], k[3]};
     p->med.k3 = {k[4], k[5]};
@@ -1045,9 +1060,12 @@ static void count_flops(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g,
 }
 
 template <typename T>
+// fixed_ws: the allocation-free form (lmfmm_apply_noalloc): the workspace is
+// that fixed array of NOALLOC_SCRATCH_BYTES, the tables must already exist,
+// every kernel is launched directly, and the statistics are not updated.
 static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, const void *q, int64_t nt,
                       const double *tgt, void *u, int nrhs, hipStream_t st, const void *gw = nullptr,
-                      double *gout = nullptr, double ysign = 1.0)
+                      double *gout = nullptr, double ysign = 1.0, void *fixed_ws = nullptr)
 {
     if (nt == 0) return LMFMM_OK;
     int rc;
@@ -1096,8 +1114,11 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     const bool have_bb = p->have_domain || (p->have_box && !adj);
     // arguments, options, tables and workspace that a captured graph bakes in
     // besides the geometry
+    const bool graph_ok = p->use_graph && !p->timing && !fixed_ws;
+    // (built for every apply but the allocation-free one, which uses no key:
+    // the key code below writes entries 12-14)
     std::vector<uint64_t> prekey;
-    {
+    if (!fixed_ws) {
         auto put = [&](uint64_t v) { prekey.push_back(v); };
         auto putp = [&](const void *ptr) { put((uint64_t)(uintptr_t)ptr); };
         uint64_t ys_bits;
@@ -1119,7 +1140,6 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         put(vt.version);
         put(p->cfg_version);
     }
-    const bool graph_ok = p->use_graph && !p->timing;
     double bb[8];
     bool bb_known = false;
     if (!have_bb && graph_ok && p->gexec && p->g_bbox && prekey == p->g_prekey && p->tz_gen == p->ws.gen &&
@@ -1142,10 +1162,10 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     const int L = g.L;
     if (g.lev[L].P > 255) return fail(LMFMM_EINVAL, "leaf-level expansion order above 255: use more levels");
     bool far = p->do_far && L >= 2;
-    if (far && (rc = ensure_far_tables(vt, med, g))) return rc;
+    if (far && (rc = ensure_far_tables(vt, med, g, !fixed_ws))) return rc;
     double amin = std::max(bb[2], 0.0) + std::max(-bb[5], 0.0);
     if (!(amin > 0)) amin = 1e-9 * g.W;
-    if ((rc = ensure_near_table(vt, med, g, amin))) return rc;
+    if ((rc = ensure_near_table(vt, med, g, amin, !fixed_ws))) return rc;
 
     // workspace
     const Level &lv = g.lev[L];
@@ -1162,8 +1182,15 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     const bool sweep = near_on && p->near_sweep && !gw;
     int64_t nun = sweep ? (int64_t)4 * nrhs * nt : 0;
     need += (size_t)nun * sizeof(cx<double>) + 256;
-    if ((rc = p->ws.ensure(need))) return rc;
-    Carve cv{(char *)p->ws.p};
+    if (fixed_ws) {
+        if (need > NOALLOC_SCRATCH_BYTES)
+            return fail(LMFMM_EINVAL, "this apply needs " + std::to_string(need) +
+                                          " bytes of workspace; the allocation-free apply has " +
+                                          std::to_string(NOALLOC_SCRATCH_BYTES));
+    } else if ((rc = p->ws.ensure(need))) {
+        return rc;
+    }
+    Carve cv{fixed_ws ? (char *)fixed_ws : (char *)p->ws.p};
     TreeBufs tb;
     // error flags and leaf counters first: this prefix must hold zeros when a
     // tree build starts
@@ -1191,15 +1218,23 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     p->err_valid = n > 0 && nbox > 0;
     cx<double> *unear = sweep ? cv.take<cx<double>>(nun) : nullptr;
     int tree_launches = (have_bb ? 0 : 2) + 4;
-    if (p->tz_gen != p->ws.gen || zero_bytes > p->tz_bytes) {
+    if (fixed_ws) {
+        // the fixed array is shared by every plan on this device: clear the
+        // counters every time
         set_stage(S_ZERO);
-        launch_zero_bytes(p->ws.p, zero_bytes, st);
+        launch_zero_bytes(fixed_ws, zero_bytes, st);
         ++tree_launches;
-        p->tz_gen = p->ws.gen;
+    } else {
+        if (p->tz_gen != p->ws.gen || zero_bytes > p->tz_bytes) {
+            set_stage(S_ZERO);
+            launch_zero_bytes(p->ws.p, zero_bytes, st);
+            ++tree_launches;
+            p->tz_gen = p->ws.gen;
+        }
+        // past this apply's counters its other buffers begin: only its own
+        // counter range is known to be zero afterwards
+        p->tz_bytes = zero_bytes;
     }
-    // past this apply's counters its other buffers begin: only its own counter
-    // range is known to be zero afterwards
-    p->tz_bytes = zero_bytes;
 
     // the launch sequence (Steps 1-4) on stream sx
     auto launch_all = [&](hipStream_t sx, bool with_bbox) {
@@ -1296,6 +1331,12 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             timed_done();
         }
     };
+    if (fixed_ws) {
+        launch_all(st, false);
+        HIPCHK(hipGetLastError());
+        if (p->ev_n > 0 && p->timing) p->ev_pending = true;
+        return LMFMM_OK;
+    }
     // key of everything the launch sequence bakes into its kernel arguments
     // (the workspace and tables as they are now)
     prekey[12] = (uint64_t)(uintptr_t)p->ws.p;
@@ -1411,6 +1452,21 @@ int lmfmm_apply(lmfmm_plan p, int64_t ns, const double *src, const void *q, int6
     hipStream_t st = (hipStream_t)stream;
     return prec == LMFMM_C128 ? apply_impl<double>(p, 0, ns, src, q, nt, tgt, u, nrhs, st)
                               : apply_impl<float>(p, 0, ns, src, q, nt, tgt, u, nrhs, st);
+}
+
+int lmfmm_apply_noalloc(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt,
+                        void *u, int nrhs, int prec, void *stream)
+{
+    int rc = check_common(p, ns, src, nt, tgt, q, u, nrhs, prec);
+    if (rc) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(LMFMM_EINVAL, "the plan's device must be current");
+    void *ws = noalloc_scratch_ptr(dev);
+    if (!ws) return fail(LMFMM_EHIP, "the device address of the allocation-free apply's array is not resolved");
+    hipStream_t st = (hipStream_t)stream;
+    return prec == LMFMM_C128 ? apply_impl<double>(p, 0, ns, src, q, nt, tgt, u, nrhs, st, nullptr, nullptr, 1.0, ws)
+                              : apply_impl<float>(p, 0, ns, src, q, nt, tgt, u, nrhs, st, nullptr, nullptr, 1.0, ws);
 }
 
 int lmfmm_direct(lmfmm_plan p, int64_t ns, const double *src, const void *q, int64_t nt, const double *tgt, void *u,

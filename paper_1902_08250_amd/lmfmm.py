@@ -54,7 +54,8 @@ class Instance(ctypes.Structure):
                 ("n_tgt", ctypes.c_int64), ("tgt_xy", ctypes.c_void_p), ("u", ctypes.c_void_p)]
 
 
-EXPORTS = ["lmfmm_create", "lmfmm_destroy", "lmfmm_set_option", "lmfmm_apply", "lmfmm_apply_adjoint",
+EXPORTS = ["lmfmm_create", "lmfmm_destroy", "lmfmm_set_option", "lmfmm_apply", "lmfmm_apply_noalloc",
+           "lmfmm_apply_adjoint",
            "lmfmm_grad_coords", "lmfmm_direct", "lmfmm_get_stats", "lmfmm_sync_status", "lmfmm_batch_create",
            "lmfmm_batch_destroy", "lmfmm_batch_set_option", "lmfmm_batch_apply", "lmfmm_batch_get_choice",
            "lmfmm_batch_sync_status", "lmfmm_batch_get_stats",
@@ -84,6 +85,7 @@ def lib():
     L.lmfmm_set_option.argtypes = [P, ctypes.c_char_p, ctypes.c_char_p]
     L.lmfmm_apply.argtypes = [P, I64, P, P, I64, P, P, I, I, P]
     L.lmfmm_direct.argtypes = [P, I64, P, P, I64, P, P, I, I, P]
+    L.lmfmm_apply_noalloc.argtypes = [P, I64, P, P, I64, P, P, I, I, P]
     L.lmfmm_apply_adjoint.argtypes = [P, I64, P, I64, P, P, P, I, I, P]
     L.lmfmm_grad_coords.argtypes = [P, I64, P, P, I64, P, P, P, P, I, I, P]
     L.lmfmm_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
@@ -194,6 +196,16 @@ class Plan:
             u = torch.empty((q.shape[0], tgt.shape[1]), dtype=q.dtype, device=q.device)
         _check(lib().lmfmm_apply(self._h, src.shape[1], src.data_ptr(), q.data_ptr(), tgt.shape[1], tgt.data_ptr(),
                                  u.data_ptr(), q.shape[0], _prec(q.dtype), _stream(stream)))
+        return u
+
+    def apply_noalloc(self, src, q, tgt, out, stream=None):
+        """lmfmm_apply_noalloc: the apply without device allocation, into the given
+        output (the plan's tables for this geometry must exist)."""
+        src, tgt = _xy(src, "src"), _xy(tgt, "tgt")
+        q = _dens(q, src.shape[1], "q")
+        u = _out(out, q.shape[0], tgt.shape[1], q.dtype, q.device, "out")
+        _check(lib().lmfmm_apply_noalloc(self._h, src.shape[1], src.data_ptr(), q.data_ptr(), tgt.shape[1],
+                                         tgt.data_ptr(), u.data_ptr(), q.shape[0], _prec(q.dtype), _stream(stream)))
         return u
 
     def direct(self, src, q, tgt, stream=None):

@@ -1,0 +1,76 @@
+"""lmfmm_apply_noalloc, the apply that allocates no device memory (its
+workspace is the library's fixed per-GPU array), against lmfmm_apply on the
+same plans and inputs: two calls in a row, the second with a smaller input,
+in both precisions; and its errors: no tables for the geometry, and a
+workspace beyond the array's size."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1902_08250_amd import workloads
+
+pytestmark = pytest.mark.gpu
+DOMAIN = (0.0, 1.0, 1.0, -0.95)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_noalloc_matches_apply(precision):
+    import torch
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("apply_noalloc vs apply,", precision)
+    w = workloads.make(1, n_src=30000, n_tgt=25000, nrhs=2)
+    dt = np.complex64 if precision == "c64" else np.complex128
+    tol = 1e-6 if precision == "c64" else 1e-10
+    k, d = w["k"], w["d"]
+    src, tgt, q = dev(w["src"]), dev(w["tgt"]), dev(w["q"].astype(dt))
+    pl = Plan(k, d, order=16, tol=tol, levels=6, domain=DOMAIN)
+    ref = pl.apply(src, q, tgt)  # builds the plan's tables for this geometry
+    out = torch.empty_like(ref)
+    pl.apply_noalloc(src, q, tgt, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref.cpu().numpy())
+    pl.sync_status()
+    # second call, smaller input (same domain and levels: same tables)
+    s2, t2, q2 = src[:, :12000].contiguous(), tgt[:, :9000].contiguous(), q[:, :12000].contiguous()
+    ref2 = Plan(k, d, order=16, tol=tol, levels=6, domain=DOMAIN).apply(s2, q2, t2)
+    out2 = torch.empty_like(ref2)
+    pl.apply_noalloc(s2, q2, t2, out2)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), ref2.cpu().numpy())
+    say("equal to lmfmm_apply bit for bit, both calls")
+
+
+def test_noalloc_errors():
+    import torch
+    from paper_1902_08250_amd.lmfmm import LMFMMError, Plan
+    say("apply_noalloc errors")
+    w = workloads.make(1, n_src=4000, n_tgt=3000)
+    src, tgt, q = dev(w["src"]), dev(w["tgt"]), dev(w["q"])
+    out = torch.empty((1, 3000), dtype=q.dtype, device="cuda")
+    pl = Plan(w["k"], w["d"], order=16, tol=1e-6, levels=5, domain=DOMAIN)
+    with pytest.raises(LMFMMError, match="tables"):
+        pl.apply_noalloc(src, q, tgt, out)  # no tables for this geometry yet
+    pl.apply(src, q, tgt, out=out)
+    # the same geometry with 1.6e6 points per side needs more than the array holds
+    rng = np.random.default_rng(9)
+    big_s, big_t, big_q, _ = workloads.draw_instance(rng, 1_600_000, 1_600_000, (0, 1), (0.05, 1), (-0.95, -0.05), 1,
+                                                     np.complex64)
+    big_out = torch.empty((1, 1_600_000), dtype=torch.complex64, device="cuda")
+    with pytest.raises(LMFMMError, match="workspace"):
+        pl.apply_noalloc(dev(big_s), dev(big_q), dev(big_t), big_out)
+    # still usable afterwards
+    pl.apply_noalloc(src, q, tgt, out)
+    ref = pl.apply(src, q, tgt)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref.cpu().numpy())
