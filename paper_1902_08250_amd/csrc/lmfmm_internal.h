@@ -464,10 +464,13 @@ void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, c
                  hipStream_t st);
 // M2L of levels l0 .. l1 in one launch (entry l - l0 of each array: class
 // tables, class codes, row slot offsets, number of rows with classes; a null
-// table skips the level); the result is stored as the local expansion
+// table skips the level); the result is stored as the local expansion.
+// mfma: products of the class tables with tiles of boxes on the matrix cores
+// (else per-box matrix-vector products on the vector units)
 template <typename T>
 void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab, const int *const *cls3,
-                    const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, hipStream_t st);
+                    const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, bool mfma,
+                    hipStream_t st);
 // returns the number of node parts written to unear ([part][rhs][target])
 template <typename T>
 int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,

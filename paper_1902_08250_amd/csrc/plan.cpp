@@ -240,6 +240,7 @@ struct lmfmm_plan_s {
     double dom[4] = {0, 0, 0, 0};  // xmin, xmax, ys_max, yt_min
     bool do_near = true, do_far = true;
     bool near_sweep = true;  // near field by x-ordered sweeps (else pairwise)
+    bool m2l_mfma = true;    // M2L on the matrix cores (else vector matrix-vector products)
 
     DevBuf ws;
     double *h_bbox = nullptr;  // pinned, host-coherent: [0..6] box, [8] sequence number, [12] error copy
@@ -847,6 +848,11 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         p->near_sweep = v == "1";
         return LMFMM_OK;
     }
+    if (k == "m2l_mfma") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "m2l_mfma must be 0 or 1");
+        p->m2l_mfma = v == "1";
+        return LMFMM_OK;
+    }
     if (k == "near" || k == "far") {
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "near/far must be 0 or 1");
         (k == "near" ? p->do_near : p->do_far) = v == "1";
@@ -1283,7 +1289,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             }
             timed(LMFMM_K_DOWN, 1);
             set_stage(S_M2L);
-            launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, sx);
+            launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, p->m2l_mfma, sx);
             timed_done();
             // the leaf level's shift is done by the leaf evaluation (forward apply)
             const int l2l_last = (!gw && L > ltop) ? L - 1 : L;

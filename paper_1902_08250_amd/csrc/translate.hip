@@ -256,6 +256,159 @@ __global__ void __launch_bounds__(64 * M2L_DW) k_m2l_all_multi(MultiArgs m)
     m2l_all_body<T>(static_cast<const M2LK<T> *>(m.args)[i], bx);
 }
 
+// ---------------------------------------------------------------------------
+// M2L on the matrix cores (Lemma M2L written as products of matrices).  A
+// translation class (target row, source row, column offset) has one table
+// A_s for every box of its rows, so the local expansions of a tile of
+// neighbouring target boxes in a row are
+//   L[p][(box, rhs)] = sum over the row's class slots s of
+//                      sum_q A_s[q][p] M[source box of (box, s)][rhs][q],
+// a sum of (2P+1) x (2P+1) by (2P+1) x 16 products: 16 columns = NB boxes x
+// RC right-hand sides.  A block of MW waves takes one (level, row, column
+// tile, right-hand-side chunk, 16-row tile of p); its waves take the slots in
+// turn and run each slot's product on v_mfma_f32_16x16x4f32 (FP32 path) or
+// v_mfma_f64_16x16x4f64 (FP64 path), the complex product as four real ones.
+// FP32: every slot's product starts from zero and is added to the wave's sum
+// with compensation (Kahan), so the sum's rounding error does not grow with
+// the number of slots; the waves' sums are then added in wave order (again
+// compensated).  Operand layout of both instructions (checked on the GPU):
+// lane l supplies row l % 16, column l / 16 of the 16 x 4 left factor and row
+// l / 16, column l % 16 of the 4 x 16 right factor; register v of the FP32
+// result holds entry (4 (l / 16) + v, l % 16), of the FP64 result entry
+// (l / 16 + 4 v, l % 16).
+// ---------------------------------------------------------------------------
+constexpr int MW = 4;   // waves per block
+constexpr int MKS = 8;  // k-steps (4 coefficients each) whose operands are loaded together
+template <typename T>
+struct M2LMK {
+    M2LLevels<T> a;  // blk0: first block of each level
+    int nrhs, RC, NB;
+    const cx<T> *M;
+    cx<T> *Lc;
+};
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void mfma_c(mf32x4 &dr, mf32x4 &di, cx<float> x, cx<float> y)
+{
+    dr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, y.re, dr, 0, 0, 0);
+    dr = __builtin_amdgcn_mfma_f32_16x16x4f32(-x.im, y.im, dr, 0, 0, 0);
+    di = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, y.im, di, 0, 0, 0);
+    di = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, y.re, di, 0, 0, 0);
+}
+__device__ inline void mfma_c(mf64x4 &dr, mf64x4 &di, cx<double> x, cx<double> y)
+{
+    dr = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, y.re, dr, 0, 0, 0);
+    dr = __builtin_amdgcn_mfma_f64_16x16x4f64(-x.im, y.im, dr, 0, 0, 0);
+    di = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, y.im, di, 0, 0, 0);
+    di = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, y.re, di, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
+{
+    typedef typename std::conditional<sizeof(T) == 4, mf32x4, mf64x4>::type vx4;
+    constexpr bool F32 = sizeof(T) == 4;
+    const M2LLevels<T> &a = k.a;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+    int li = 0;
+    while (li + 1 < a.n && bx >= a.blk0[li + 1]) ++li;
+    int loc = bx - a.blk0[li];
+    const int nc = a.nc[li], ncol = a.ncol[li], col_lo = a.col_lo[li];
+    const int npt = (nc + 15) >> 4, ntile = (ncol + k.NB - 1) / k.NB, nrc = (k.nrhs + k.RC - 1) / k.RC;
+    const int pt = loc % npt;
+    loc /= npt;
+    const int rcn = loc % nrc;
+    loc /= nrc;
+    const int tile = loc % ntile, row = loc / ntile;
+    const int n = l & 15, kk = l >> 4;
+    const int j = n / k.RC, r = rcn * k.RC + n % k.RC;
+    const int colL = tile * k.NB + j, col = col_lo + colL;
+    const bool nvalid = colL < ncol && r < k.nrhs;
+    const int p = pt * 16 + n;  // output coefficient of this lane's row of the left factor
+    const int *__restrict__ cls3 = a.cls3[li];
+    const int s0 = a.row_off[li][row], s1 = a.row_off[li][row + 1];
+    const cx<T> *__restrict__ Ms = k.M + a.off_s[li];
+    const cx<T> *__restrict__ At = a.atab[li];
+    const int nks = (nc + 3) >> 2;
+    vx4 sr = {0, 0, 0, 0}, si = {0, 0, 0, 0}, cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    for (int s = s0 + w; s < s1; s += MW) {
+        const int rs = cls3[3 * s + 1], dc = cls3[3 * s + 2];
+        const int cs = col + dc, csl = cs - col_lo, dp = (cs >> 1) - (col >> 1);
+        const bool ok = nvalid && rs < a.rows_s[li] && csl >= 0 && csl < ncol && (a.top[li] || (dp >= -1 && dp <= 1));
+        if (!__any(ok)) continue;
+        const cx<T> *__restrict__ As = At + (int64_t)s * nc * nc;
+        const cx<T> *__restrict__ xb = Ms + (((int64_t)rs * ncol + (ok ? csl : 0)) * k.nrhs + (ok ? r : 0)) * nc;
+        vx4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < nks; k0 += MKS) {
+            cx<T> av[MKS], bv[MKS];
+#pragma unroll
+            for (int u = 0; u < MKS; ++u) {
+                const int kq = 4 * (k0 + u) + kk;
+                const bool kin = kq < nc;
+                av[u] = (kin && p < nc) ? As[(int64_t)kq * nc + p] : mk<T>(0, 0);
+                bv[u] = (kin && ok) ? xb[kq] : mk<T>(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < MKS; ++u)
+                if (k0 + u < nks) mfma_c(dr, di, av[u], bv[u]);
+        }
+        if (F32) {
+            // compensated addition of the slot's product to the wave's sum
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const T yr = dr[v] - cr[v], yi = di[v] - ci[v];
+                const T tr = sr[v] + yr, ti = si[v] + yi;
+                cr[v] = (tr - sr[v]) - yr;
+                ci[v] = (ti - si[v]) - yi;
+                sr[v] = tr;
+                si[v] = ti;
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                sr[v] += dr[v];
+                si[v] += di[v];
+            }
+        }
+    }
+    // the waves' sums added in wave order by wave 0
+    __shared__ T red[MW][4][4][64];  // wave, (sr, si, cr, ci), v, lane
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        red[w][0][v][l] = sr[v];
+        red[w][1][v][l] = si[v];
+        red[w][2][v][l] = cr[v];
+        red[w][3][v][l] = ci[v];
+    }
+    __syncthreads();
+    if (w != 0 || !nvalid) return;
+    const int64_t obase = a.off_t[li] + (((int64_t)row * ncol + colL) * k.nrhs + r) * nc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        CAcc<T> re, im;
+        re.zero();
+        im.zero();
+        for (int x = 0; x < MW; ++x) {
+            re.add({red[x][0][v][l], -red[x][2][v][l]});
+            im.add({red[x][1][v][l], -red[x][3][v][l]});
+        }
+        const int prow = F32 ? 4 * kk + v : kk + 4 * v;
+        const int pp = pt * 16 + prow;
+        const cx<T> vr = re.value(), vi = im.value();
+        if (pp < nc) k.Lc[obase + pp] = mk<T>(vr.re + vr.im, vi.re + vi.im);
+    }
+}
+template <typename T>
+__global__ void __launch_bounds__(64 * MW) k_m2l_mfma(M2LMK<T> a) { m2l_mfma_body<T>(a, blockIdx.x); }
+template <typename T>
+__global__ void __launch_bounds__(64 * MW) k_m2l_mfma_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    m2l_mfma_body<T>(static_cast<const M2LMK<T> *>(m.args)[i], bx);
+}
+
 }  // namespace
 
 template <typename T>
@@ -297,11 +450,14 @@ void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, c
 
 template <typename T>
 void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab, const int *const *cls3,
-                    const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, hipStream_t st)
+                    const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, bool mfma,
+                    hipStream_t st)
 {
     M2LLevels<T> a;
     a.n = 0;
     int blk = 0;
+    // matrix-core form: columns of 16 = NB boxes x RC right-hand sides
+    const int RC = nrhs >= 16 ? 16 : (nrhs > 8 ? 16 : (nrhs > 4 ? 8 : (nrhs > 2 ? 4 : nrhs))), NB = 16 / RC;
     for (int l = l0; l <= l1 && a.n < M2L_MAXLEV; ++l) {
         const Level &lv = g.lev[l];
         const int rows = nrt[l - l0] < lv.rows_t ? nrt[l - l0] : lv.rows_t;
@@ -318,10 +474,18 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
         a.atab[i] = atab[l - l0];
         a.cls3[i] = cls3[l - l0];
         a.row_off[i] = row_off[l - l0];
-        blk += rows * lv.ncol;
+        if (mfma)
+            blk += rows * ((lv.ncol + NB - 1) / NB) * ((nrhs + RC - 1) / RC) * ((lv.nc + 15) / 16);
+        else
+            blk += rows * lv.ncol;
     }
     a.blk0[a.n] = blk;
     if (blk == 0) return;
+    if (mfma) {
+        const M2LMK<T> k{a, nrhs, RC, NB, M, Lc};
+        emit((const void *)k_m2l_mfma<T>, (const void *)k_m2l_mfma_multi<T>, 0, dim3(blk), dim3(64 * MW), 0, st, k);
+        return;
+    }
     const M2LK<T> k{a, nrhs, M, Lc};
     emit((const void *)k_m2l_all<T>, (const void *)k_m2l_all_multi<T>, 0, dim3(blk), dim3(64 * M2L_DW), 0, st, k);
 }
@@ -332,7 +496,8 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
     template void launch_down<T>(const Geometry &, int, const cx<T> *, const int *, const int *, int, const cx<T> *, \
                                  cx<T> *, int, const cx<T> *, bool, int, hipStream_t);                              \
     template void launch_m2l_all<T>(const Geometry &, int, int, const cx<T> *const *, const int *const *,           \
-                                    const int *const *, const int *, const cx<T> *, cx<T> *, int, hipStream_t);
+                                    const int *const *, const int *, const cx<T> *, cx<T> *, int, bool,             \
+                                    hipStream_t);
 LMFMM_INST(double)
 LMFMM_INST(float)
 
