@@ -42,13 +42,14 @@ def _load():
     L = ctypes.c_long
     I = ctypes.c_int
     lib.orc_sigma2t.argtypes = [D, I, L, D, D]
+    lib.orc_sigma.argtypes = [D, I, L, D, D]
     lib.orc_entry.argtypes = [D, I, D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, I, D, ctypes.POINTER(I)]
     lib.orc_apply.argtypes = [D, I, D, L, D, D, L, D, D, I, I]
     lib.orc_apply_adjoint.argtypes = [D, I, D, L, D, L, D, D, D, I, I]
     lib.orc_grad_coords.argtypes = [D, I, D, L, D, D, L, D, D, I, D, D, I]
     lib.orc_max_threads.argtypes = []
-    for f in (lib.orc_sigma2t, lib.orc_entry, lib.orc_apply, lib.orc_apply_adjoint,
+    for f in (lib.orc_sigma2t, lib.orc_sigma, lib.orc_entry, lib.orc_apply, lib.orc_apply_adjoint,
               lib.orc_grad_coords, lib.orc_max_threads):
         f.restype = I
     _lib = lib
@@ -63,9 +64,18 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _med(k, d):
+# field components (the target's layer and part; see lmfmm_oracle.c)
+COMP = {"2t": 0, "2b": 1, "1s": 2, "3s": 3, "imp": 4}
+
+
+def _med(k, d, alpha=0.0):
     k1, k2, k3 = (complex(v) for v in k)
-    return np.array([k1.real, k1.imag, k2.real, k2.imag, k3.real, k3.imag, float(d)], dtype=np.float64)
+    return np.array([k1.real, k1.imag, k2.real, k2.imag, k3.real, k3.imag, float(d), float(alpha)],
+                    dtype=np.float64)
+
+
+def _flags(sigma_unity=False, comp="2t"):
+    return int(bool(sigma_unity)) | (COMP[comp] << 1)
 
 
 def _opt(eta=1.0, c_factor=1.5, rep=0, eps=1e-15):
@@ -87,20 +97,33 @@ def sigma2t(lam, k, d, sigma_unity=False):
     lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
     flat = lam.reshape(-1)
     out = np.empty_like(flat)
-    _check(lib.orc_sigma2t(_ptr(_med(k, d)), int(sigma_unity), flat.size,
+    _check(lib.orc_sigma2t(_ptr(_med(k, d)), _flags(sigma_unity), flat.size,
                            _ptr(flat.view(np.float64)), _ptr(out.view(np.float64))), "sigma2t")
     return out.reshape(lam.shape)
 
 
+def sigma(lam, k, d, comp="2t", alpha=0.0):
+    """The density of component comp ("2t", "2b", "1s", "3s" of the three-layer
+    medium; "imp": the impedance half-space with k = k[0]) at complex points lam."""
+    lib = _load()
+    lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
+    flat = lam.reshape(-1)
+    out = np.empty_like(flat)
+    _check(lib.orc_sigma(_ptr(_med(k, d, alpha)), _flags(False, comp), flat.size,
+                         _ptr(flat.view(np.float64)), _ptr(out.view(np.float64))), "sigma")
+    return out.reshape(lam.shape)
+
+
 def entry(x1, y1, x0, y0, k, d, *, derivs=False, sigma_unity=False, rep=0, eta=1.0,
-          c_factor=1.5, eps=1e-15):
-    """g_2^t(x1,y1; x0,y0).  With derivs=True returns (g, dg/dx1, dg/dy1, dg/dx0, dg/dy0).
+          c_factor=1.5, eps=1e-15, comp="2t", alpha=0.0):
+    """g(x1,y1; x0,y0) of component comp (default g_2^t).  With derivs=True returns
+    (g, dg/dx1, dg/dy1, dg/dx0, dg/dy0).
     rep: 0 automatic, 1 north (real-axis tails), 2 east (alternative direction)."""
     lib = _load()
     n = 5 if derivs else 1
     out = np.zeros(n, dtype=np.complex128)
     used = ctypes.c_int(0)
-    rc = lib.orc_entry(_ptr(_med(k, d)), int(sigma_unity), _ptr(_opt(eta, c_factor, rep, eps)),
+    rc = lib.orc_entry(_ptr(_med(k, d, alpha)), _flags(sigma_unity, comp), _ptr(_opt(eta, c_factor, rep, eps)),
                        float(x1), float(y1), float(x0), float(y0), n, _ptr(out.view(np.float64)),
                        ctypes.byref(used))
     _check(rc, "entry")
@@ -125,33 +148,34 @@ def _prep_dens(q, n):
 
 
 def apply(src, q, tgt, k, d, *, sigma_unity=False, rep=0, eta=1.0, c_factor=1.5, eps=1e-15,
-          threads=0):
-    """u[r, i] = sum_j g_2^t(tgt_i, src_j) q[r, j]  (returns shape (nrhs, n_tgt))."""
+          threads=0, comp="2t", alpha=0.0):
+    """u[r, i] = sum_j g(tgt_i, src_j) q[r, j] for component comp (default g_2^t);
+    returns shape (nrhs, n_tgt)."""
     lib = _load()
     src, tgt = _prep_xy(src), _prep_xy(tgt)
     q = _prep_dens(q, src.shape[1])
     u = np.zeros((q.shape[0], tgt.shape[1]), dtype=np.complex128)
-    rc = lib.orc_apply(_ptr(_med(k, d)), int(sigma_unity), _ptr(_opt(eta, c_factor, rep, eps)),
+    rc = lib.orc_apply(_ptr(_med(k, d, alpha)), _flags(sigma_unity, comp), _ptr(_opt(eta, c_factor, rep, eps)),
                        src.shape[1], _ptr(src), _ptr(q.view(np.float64)), tgt.shape[1], _ptr(tgt),
                        _ptr(u.view(np.float64)), q.shape[0], int(threads))
     _check(rc, "apply")
     return u
 
 
-def apply_adjoint(src, tgt, w, k, d, *, sigma_unity=False, eps=1e-15, threads=0):
-    """v[r, j] = sum_i g_2^t(tgt_i, src_j) w[r, i]  (transpose, no conjugation)."""
+def apply_adjoint(src, tgt, w, k, d, *, sigma_unity=False, eps=1e-15, threads=0, comp="2t", alpha=0.0):
+    """v[r, j] = sum_i g(tgt_i, src_j) w[r, i]  (transpose, no conjugation)."""
     lib = _load()
     src, tgt = _prep_xy(src), _prep_xy(tgt)
     w = _prep_dens(w, tgt.shape[1])
     v = np.zeros((w.shape[0], src.shape[1]), dtype=np.complex128)
-    rc = lib.orc_apply_adjoint(_ptr(_med(k, d)), int(sigma_unity), _ptr(_opt(eps=eps)), src.shape[1],
+    rc = lib.orc_apply_adjoint(_ptr(_med(k, d, alpha)), _flags(sigma_unity, comp), _ptr(_opt(eps=eps)), src.shape[1],
                                _ptr(src), tgt.shape[1], _ptr(tgt), _ptr(w.view(np.float64)),
                                _ptr(v.view(np.float64)), w.shape[0], int(threads))
     _check(rc, "apply_adjoint")
     return v
 
 
-def grad_coords(src, q, tgt, w, k, d, *, eps=1e-15, threads=0):
+def grad_coords(src, q, tgt, w, k, d, *, eps=1e-15, threads=0, comp="2t", alpha=0.0):
     """Gradients of L = Re sum w*u with respect to source and target coordinates.
     Returns (dsrc (2, n_src), dtgt (2, n_tgt))."""
     lib = _load()
@@ -162,7 +186,7 @@ def grad_coords(src, q, tgt, w, k, d, *, eps=1e-15, threads=0):
         raise ValueError("q and w must have the same number of right-hand sides")
     dsrc = np.zeros((2, src.shape[1]))
     dtgt = np.zeros((2, tgt.shape[1]))
-    rc = lib.orc_grad_coords(_ptr(_med(k, d)), 0, _ptr(_opt(eps=eps)), src.shape[1], _ptr(src),
+    rc = lib.orc_grad_coords(_ptr(_med(k, d, alpha)), _flags(False, comp), _ptr(_opt(eps=eps)), src.shape[1], _ptr(src),
                              _ptr(q.view(np.float64)), tgt.shape[1], _ptr(tgt),
                              _ptr(w.view(np.float64)), q.shape[0], _ptr(dsrc), _ptr(dtgt), int(threads))
     _check(rc, "grad_coords")

@@ -15,7 +15,11 @@
  *   s_m = sqrt(lam^2 - k_m^2)  (principal branch, Re s_m >= 0),
  *
  * for a source in the top layer (y0 > 0) and a target in the middle layer
- * (-d < y1 < 0).  sigma_2^t is the closed form the paper gives (Section 1,
+ * (-d < y1 < 0).  The other components of the scattered field of Example 4
+ * (g_1^s in the top layer, g_2^b in the middle layer, g_3^s in the bottom
+ * layer) and the impedance half-space of Example 3 are the same kind of
+ * integral with another target factor and density (sigma_comp and
+ * target_exponent below).  sigma_2^t is the closed form the paper gives (Section 1,
  * repeated in Section 3 Example 4 and Section 5); numerator and denominator
  * are both divided by exp(d*s2), which leaves the value unchanged and keeps
  * every factor bounded.
@@ -58,10 +62,21 @@ typedef double complex cplx;
 /* ------------------------------------------------------------------------ */
 /* Medium and options                                                        */
 /* ------------------------------------------------------------------------ */
+/* The field component (which layer the target is in, and which part):
+ *   COMP_2T: middle layer, part from the top interface, g_2^t (the default);
+ *   COMP_2B: middle layer, part from the bottom interface, g_2^b;
+ *   COMP_1S: top layer (reflected field), g_1^s;
+ *   COMP_3S: bottom layer (transmitted field), g_3^s;
+ *   COMP_IMP: the impedance half-space of Section 3 Example 3 (source and
+ *   target above y = 0, wave number k = k1, impedance alpha). */
+enum { COMP_2T = 0, COMP_2B = 1, COMP_1S = 2, COMP_3S = 3, COMP_IMP = 4 };
+
 typedef struct {
     cplx k1, k2, k3;
     double d;
-    int sigma_unity; /* 1: replace sigma_2^t by 1 (free-space closed-form check) */
+    int sigma_unity; /* 1: replace sigma by 1 (free-space closed-form check) */
+    int comp;        /* COMP_*                                              */
+    double alpha;    /* impedance (COMP_IMP)                                */
 } medium_t;
 
 typedef struct {
@@ -78,6 +93,8 @@ static void read_medium(const double *med, int flags, medium_t *m)
     m->k3 = med[4] + I * med[5];
     m->d = med[6];
     m->sigma_unity = flags & 1;
+    m->comp = (flags >> 1) & 7;
+    m->alpha = med[7];
 }
 
 static void read_opts(const double *opt, opts_t *o)
@@ -115,6 +132,61 @@ static cplx sigma2t(cplx lam, const medium_t *m)
     return num / den;
 }
 
+/* The other densities of Section 3 Example 4, from the paper's closed forms
+ * with numerator and denominator divided by exp(d*s2) as for sigma_2^t (the
+ * common denominator D below is that of sigma_2^t):
+ *   sigma_1   = [sinh(d s2)(-l^2 + s1 s3 + k2^2) + s2 (s1 - s3) cosh(d s2)] / D,
+ *   sigma_2^b = -e^{d s2} (-l^2 + s2 s3 + k2^2) / D,
+ *   sigma_3   = 2 s2 s3 e^{d s3} / D.
+ * (The 4x4 interface system's unknowns are sigma_1, sigma_2^t,
+ * e^{-d s2} sigma_2^b and e^{-d s3} sigma_3 of these closed forms.) */
+static cplx sigma_comp(cplx lam, const medium_t *m)
+{
+    if (m->sigma_unity) return 1.0;
+    if (m->comp == COMP_2T) return sigma2t(lam, m);
+    if (m->comp == COMP_IMP) {
+        /* Section 3 Example 3: (s + i k alpha) / (s - i k alpha), s = sqrt(lam^2 - k^2) */
+        cplx s = sroot(lam, m->k1);
+        return (s + I * m->k1 * m->alpha) / (s - I * m->k1 * m->alpha);
+    }
+    cplx s1 = sroot(lam, m->k1), s2 = sroot(lam, m->k2), s3 = sroot(lam, m->k3);
+    cplx e = cexp(-2.0 * m->d * s2);
+    cplx l2 = lam * lam, kk2 = m->k2 * m->k2;
+    cplx den = 0.5 * (1.0 - e) * (l2 + s1 * s3 - kk2) + 0.5 * s2 * (s1 + s3) * (1.0 + e);
+    if (m->comp == COMP_1S) return (0.5 * (1.0 - e) * (-l2 + s1 * s3 + kk2) + 0.5 * s2 * (s1 - s3) * (1.0 + e)) / den;
+    if (m->comp == COMP_2B) return -(-l2 + s2 * s3 + kk2) / den;
+    return 2.0 * s2 * s3 * cexp(m->d * (s3 - s2)) / den; /* COMP_3S */
+}
+
+/* The target factor of each component: exp(tgt_exp(s_t) ...) with the
+ * target-side root s_t, and the density sigma / (4 pi s_t):
+ *   g_2^t: e^{ s2 y},          g_2^b: e^{-s2 (y + 2d)},   g_1^s: e^{-s1 y},
+ *   g_3^s: e^{ s3 y} (read: the printed e^{-s3 (y + 2d)} grows as y -> -inf
+ *          and contradicts the interface system; e^{s3 y} with sigma_3 as
+ *          above satisfies it and gives the free field in a homogeneous
+ *          medium),
+ *   impedance: e^{-s y}.
+ * The source factor is e^{-s1 y0} (e^{-s y0} for the impedance case). */
+static cplx target_root(cplx lam, const medium_t *m)
+{
+    switch (m->comp) {
+    case COMP_1S:
+    case COMP_IMP: return sroot(lam, m->k1);
+    case COMP_3S: return sroot(lam, m->k3);
+    default: return sroot(lam, m->k2);
+    }
+}
+/* exponent of the target factor and its derivative in y */
+static cplx target_exponent(cplx st, double y, const medium_t *m, cplx *dy)
+{
+    switch (m->comp) {
+    case COMP_2B: *dy = -st; return -st * (y + 2.0 * m->d);
+    case COMP_1S:
+    case COMP_IMP: *dy = -st; return -st * y;
+    default: *dy = st; return st * y; /* COMP_2T, COMP_3S */
+    }
+}
+
 /* One pair: geometry and the derivative factor to apply. */
 typedef struct {
     double y1, y0, adx; /* target y, source y, |x1 - x0|            */
@@ -128,12 +200,13 @@ typedef struct {
 static void integrand(cplx lam, const pair_t *p, cplx *out)
 {
     const medium_t *m = p->m;
-    cplx s1 = sroot(lam, m->k1), s2 = sroot(lam, m->k2);
-    cplx f = cexp(s2 * p->y1 - s1 * p->y0 + I * lam * p->adx) * sigma2t(lam, m) / (4.0 * M_PI * s2);
+    cplx s1 = sroot(lam, m->k1), st = target_root(lam, m), dy1;
+    cplx f = cexp(target_exponent(st, p->y1, m, &dy1) - s1 * p->y0 + I * lam * p->adx) * sigma_comp(lam, m) /
+             (4.0 * M_PI * st);
     out[0] = f;
     if (p->nder > 1) {
         out[1] = f * (I * lam * p->sgn);  /* d/dx1 */
-        out[2] = f * s2;                  /* d/dy1 */
+        out[2] = f * dy1;                 /* d/dy1 */
         out[3] = -out[1];                 /* d/dx0 */
         out[4] = f * (-s1);               /* d/dy0 */
     }
@@ -293,7 +366,10 @@ static int entry(double x1, double y1, double x0, double y0, const medium_t *m, 
     p.sgn = (x1 > x0) ? 1.0 : ((x1 < x0) ? -1.0 : 0.0);
     p.m = m;
     p.nder = nder;
-    double a = y0 - y1;
+    /* vertical decay length of the integrand along the real axis */
+    double a = y0 - y1; /* g_2^t, g_3^s */
+    if (m->comp == COMP_2B) a = y0 + y1 + 2.0 * m->d;
+    if (m->comp == COMP_1S || m->comp == COMP_IMP) a = y0 + y1;
     double kmax = max3(creal(m->k1), creal(m->k2), creal(m->k3));
     double c = o->c_factor * kmax;
     if (c < 1.0) c = 1.0;
@@ -365,12 +441,23 @@ static cplx nval(const nsum_t *a) { return (a->sr + a->cr) + I * (a->si + a->ci)
 /* ------------------------------------------------------------------------ */
 /* Exported API                                                              */
 /* ------------------------------------------------------------------------ */
-static int check_layers(long n_src, const double *src, long n_tgt, const double *tgt, double d)
+/* the target's layer of each component */
+static int target_in_layer(double y, const medium_t *m)
+{
+    switch (m->comp) {
+    case COMP_1S:
+    case COMP_IMP: return y > 0;
+    case COMP_3S: return y < -m->d;
+    default: return y < 0 && y > -m->d;
+    }
+}
+
+static int check_layers(long n_src, const double *src, long n_tgt, const double *tgt, const medium_t *m)
 {
     for (long j = 0; j < n_src; ++j)
         if (!(src[n_src + j] > 0) || !isfinite(src[j]) || !isfinite(src[n_src + j])) return ORC_EDOMAIN;
     for (long i = 0; i < n_tgt; ++i)
-        if (!(tgt[n_tgt + i] < 0 && tgt[n_tgt + i] > -d) || !isfinite(tgt[i])) return ORC_EDOMAIN;
+        if (!target_in_layer(tgt[n_tgt + i], m) || !isfinite(tgt[i]) || !isfinite(tgt[n_tgt + i])) return ORC_EDOMAIN;
     return ORC_OK;
 }
 
@@ -405,6 +492,19 @@ int orc_sigma2t(const double *med, int flags, long n, const double *lam, double 
     return ORC_OK;
 }
 
+/* sigma of the medium's component (flags bits 1-3) at n complex points. */
+int orc_sigma(const double *med, int flags, long n, const double *lam, double *out)
+{
+    medium_t m;
+    read_medium(med, flags, &m);
+    for (long i = 0; i < n; ++i) {
+        cplx v = sigma_comp(lam[2 * i] + I * lam[2 * i + 1], &m);
+        out[2 * i] = creal(v);
+        out[2 * i + 1] = cimag(v);
+    }
+    return ORC_OK;
+}
+
 /* One entry g(x1,y1;x0,y0) (nder=1) or g and its derivatives d/dx1, d/dy1,
  * d/dx0, d/dy0 (nder=5); out holds nder interleaved complex values. */
 int orc_entry(const double *med, int flags, const double *opt, double x1, double y1, double x0, double y0, int nder,
@@ -415,7 +515,7 @@ int orc_entry(const double *med, int flags, const double *opt, double x1, double
     opts_t o;
     read_medium(med, flags, &m);
     read_opts(opt, &o);
-    if (!(y0 > 0) || !(y1 < 0 && y1 > -m.d)) return ORC_EDOMAIN;
+    if (!(y0 > 0) || !target_in_layer(y1, &m)) return ORC_EDOMAIN;
     gl_init();
     cplx v[MAXOUT];
     int rc = entry(x1, y1, x0, y0, &m, &o, nder, v, rep_used);
@@ -438,7 +538,7 @@ int orc_apply(const double *med, int flags, const double *opt, long n_src, const
     opts_t o;
     read_medium(med, flags, &m);
     read_opts(opt, &o);
-    int rc = check_layers(n_src, src, n_tgt, tgt, m.d);
+    int rc = check_layers(n_src, src, n_tgt, tgt, &m);
     if (rc) return rc;
     gl_init();
     set_threads(nthreads);
@@ -488,7 +588,7 @@ int orc_apply_adjoint(const double *med, int flags, const double *opt, long n_sr
     opts_t o;
     read_medium(med, flags, &m);
     read_opts(opt, &o);
-    int rc = check_layers(n_src, src, n_tgt, tgt, m.d);
+    int rc = check_layers(n_src, src, n_tgt, tgt, &m);
     if (rc) return rc;
     gl_init();
     set_threads(nthreads);
@@ -527,7 +627,7 @@ int orc_grad_coords(const double *med, int flags, const double *opt, long n_src,
     opts_t o;
     read_medium(med, flags, &m);
     read_opts(opt, &o);
-    int rc = check_layers(n_src, src, n_tgt, tgt, m.d);
+    int rc = check_layers(n_src, src, n_tgt, tgt, &m);
     if (rc) return rc;
     gl_init();
     set_threads(nthreads);
