@@ -14,7 +14,10 @@
  * multipole with the free-space Helmholtz operators for k1, multipole-to-local
  * by Sommerfeld-integral translation matrices (Lemma M2L), local-to-local and
  * local evaluation with the free-space operators for k2, and the near field by
- * direct Sommerfeld quadrature on deformed contours (Section 4.2).
+ * direct Sommerfeld quadrature on deformed contours (Section 4.2).  The
+ * plan option "component" switches the same passes to the other three-layer
+ * components g_2^b, g_1^s, g_3^s or to the impedance half-space (Section 3,
+ * Examples 3 and 4).
  *
  * Conventions shared by every entry point:
  *   - All point and density arrays are DEVICE pointers owned by the caller and
@@ -97,6 +100,27 @@ int lmfmm_destroy(lmfmm_plan plan);
  *                 table; "0": the pairwise sum (same quadrature)
  *   "near"        "1" (default) / "0": include / skip the near field
  *   "far"         "1" (default) / "0": include / skip the far field
+ *   "component"   the field component the plan applies (Section 3), sources
+ *                 always in the top layer (y > 0):
+ *                   "2t" (default) g_2^t, targets -d < y < 0;
+ *                   "2b" g_2^b (Example 4), targets -d < y < 0;
+ *                   "1s" g_1^s (Example 4), targets y > 0;
+ *                   "3s" g_3^s (Example 4), targets y < -d;
+ *                   "impedance" the reflected field of the impedance
+ *                   half-space (Example 3) with wave number k1 (k2, k3 and
+ *                   d unused), targets y > 0.
+ *                 Each is applied by the same passes: targets enter the tree
+ *                 at their image y' = -y (1s, impedance) or y' = -y - 2d
+ *                 (2b), where the component's exponent becomes that of
+ *                 g_2^t; the local expansions use the target layer's wave
+ *                 number.  Setting it discards the plan's tables.
+ *   "alpha"       impedance constant of the "impedance" component (default
+ *                 0): the total field u satisfies u_y + i k1 alpha u = 0 on
+ *                 y = 0 (density (s1 + i k1 alpha) / (s1 - i k1 alpha)).
+ *                 Setting it discards the plan's tables.
+ *   "m2l_mfma"    "1" (default): multipole-to-local as products of the class
+ *                 tables with tiles of boxes x right-hand sides on the matrix
+ *                 cores; "0": one matrix-vector product per box pair list
  *   "timing"      "1": record a HIP event on the apply's stream before every
  *                 kernel (or group of tree-build kernels) of each apply and
  *                 accumulate the durations per kernel in
@@ -107,7 +131,8 @@ int lmfmm_set_option(lmfmm_plan plan, const char *key, const char *value);
 /* Forward apply (Algorithm 1, Steps 1-4): u[r][i] = sum_j g_2^t(tgt_i, src_j) q[r][j].
  *   n_src, src_xy: source count and coordinates [2][n_src] (y > 0).
  *   q:     densities [nrhs][n_src].
- *   n_tgt, tgt_xy: target count and coordinates [2][n_tgt] (-d < y < 0).
+ *   n_tgt, tgt_xy: target count and coordinates [2][n_tgt] (-d < y < 0; the
+ *          layer of the plan's "component" otherwise).
  *   u:     output [nrhs][n_tgt], overwritten.
  *   nrhs:  number of right-hand sides, 1 <= nrhs <= 64.
  *   precision: LMFMM_C128 or LMFMM_C64_MIXED (selects the dtype of q and u).

@@ -261,34 +261,79 @@ __host__ __device__ inline cx<double> csqrt_d(cx<double> z)
 // s_m(lam) = sqrt(lam^2 - k^2), principal branch.
 __host__ __device__ inline cx<double> sroot_d(cx<double> lam, cx<double> k) { return csqrt_d(lam * lam - k * k); }
 
+// Field components (Section 3): the part of the scattered field applied,
+// with its target factor and density.  In the tree's coordinates every one is
+// the same kind of integral,
+//   Int e^{s_t y'} e^{-s_s y0} e^{i lam (x - x0)} sigma(lam) / (4 pi s_t) d lam,
+// with the target's image coordinate y' = a y + b:
+//   COMP_2T  g_2^t (Example 4, middle layer):  y' = y,        s_t = s2
+//   COMP_2B  g_2^b (middle layer):             y' = -y - 2d,  s_t = s2
+//   COMP_1S  g_1^s (top layer):                y' = -y,       s_t = s1
+//   COMP_3S  g_3^s (bottom layer):             y' = y,        s_t = s3
+//   COMP_IMP the impedance half-space (Example 3, wave number k1, impedance
+//            alpha; source and target above y = 0): y' = -y,  s_t = s_s = s1.
+// The source factor is e^{-s1 y0} in every case.
+enum { COMP_2T = 0, COMP_2B = 1, COMP_1S = 2, COMP_3S = 3, COMP_IMP = 4 };
+
 // The medium and the orientation of the operator.  adj = 0: the forward
-// operator (sources in the top layer carry k1, targets in the middle layer
-// k2).  adj = 1: the transposed operator in mirrored coordinates (x, -y):
+// operator (sources in the top layer carry k1, targets the component's wave
+// number).  adj = 1: the transposed operator in mirrored coordinates (x, -y'):
 // substituting lam -> -lam in the Sommerfeld integral shows that G^T acting
-// on middle-layer densities is the same kind of operator with the roles of
-// (k1, s1) and (k2, s2) exchanged and the same density sigma_2^t / (4 pi s2).
+// on target densities is the same kind of operator with the roles of the
+// source and target sides exchanged and the same density sigma / (4 pi s_t).
 struct Medium {
     cx<double> k1, k2, k3;
     double d;
     int adj;
+    int comp = COMP_2T;
+    double alpha = 0.0;  // impedance (COMP_IMP)
 };
-// wave number of the multipole (source) side and of the local (target) side
-__host__ __device__ inline cx<double> k_src(const Medium &m) { return m.adj ? m.k2 : m.k1; }
-__host__ __device__ inline cx<double> k_tgt(const Medium &m) { return m.adj ? m.k1 : m.k2; }
-
-// sigma_2^t(lam) of the three-layer medium (Section 1; Section 3 Example 4),
-// with numerator and denominator divided by exp(d s2) so that every factor
-// stays bounded (Re s2 >= 0).
-__host__ __device__ inline cx<double> sigma2t_d(cx<double> lam, const Medium &m, cx<double> s1, cx<double> s2)
+// the physical target's wave number
+__host__ __device__ inline cx<double> k_target_layer(const Medium &m)
 {
-    cx<double> s3 = sroot_d(lam, m.k3);
-    cx<double> e = cexp_d(mk(-2.0 * m.d * s2.re, -2.0 * m.d * s2.im));
-    cx<double> l2 = lam * lam, kk = m.k2 * m.k2;
-    cx<double> num = l2 + s2 * s3 - kk;
-    cx<double> one = mk(1.0, 0.0);
-    cx<double> den = 0.5 * ((one - e) * (l2 + s1 * s3 - kk)) + 0.5 * (s2 * (s1 + s3) * (one + e));
-    return cdiv(num, den);
+    return (m.comp == COMP_1S || m.comp == COMP_IMP) ? m.k1 : (m.comp == COMP_3S ? m.k3 : m.k2);
 }
+// wave number of the multipole (source) side and of the local (target) side
+__host__ __device__ inline cx<double> k_src(const Medium &m) { return m.adj ? k_target_layer(m) : m.k1; }
+__host__ __device__ inline cx<double> k_tgt(const Medium &m) { return m.adj ? m.k1 : k_target_layer(m); }
+
+// The densities of Section 3 Example 4 from the paper's closed forms, with
+// numerator and denominator divided by exp(d s2) so that every factor stays
+// bounded (Re s2 >= 0); the common denominator is that of sigma_2^t:
+//   sigma_2^t = e^{d s2} (lam^2 + s2 s3 - k2^2) / D,
+//   sigma_2^b = -e^{d s2} (-lam^2 + s2 s3 + k2^2) / D,
+//   sigma_1   = [sinh(d s2)(-lam^2 + s1 s3 + k2^2) + s2 (s1 - s3) cosh(d s2)] / D,
+//   sigma_3   = 2 s2 s3 e^{d s3} / D,
+//   D = sinh(d s2)(lam^2 + s1 s3 - k2^2) + s2 (s1 + s3) cosh(d s2);
+// and the image term of Example 3, (s + i k alpha) / (s - i k alpha).
+__host__ __device__ inline cx<double> sigma_d(cx<double> lam, const Medium &m, cx<double> s1)
+{
+    const cx<double> one = mk(1.0, 0.0);
+    if (m.comp == COMP_IMP) {
+        const cx<double> ika = mk(-m.k1.im * m.alpha, m.k1.re * m.alpha);
+        return cdiv(s1 + ika, s1 - ika);
+    }
+    const cx<double> s2 = sroot_d(lam, m.k2), s3 = sroot_d(lam, m.k3);
+    const cx<double> e = cexp_d(mk(-2.0 * m.d * s2.re, -2.0 * m.d * s2.im));
+    const cx<double> l2 = lam * lam, kk = m.k2 * m.k2;
+    const cx<double> den = 0.5 * ((one - e) * (l2 + s1 * s3 - kk)) + 0.5 * (s2 * (s1 + s3) * (one + e));
+    switch (m.comp) {
+    case COMP_2B: return cdiv(-(s2 * s3 + kk - l2), den);
+    case COMP_1S: return cdiv(0.5 * ((one - e) * (s1 * s3 + kk - l2)) + 0.5 * (s2 * (s1 - s3) * (one + e)), den);
+    case COMP_3S: {
+        const cx<double> g = s3 - s2;
+        return cdiv(2.0 * (s2 * s3) * cexp_d(mk(m.d * g.re, m.d * g.im)), den);
+    }
+    default: return cdiv(l2 + s2 * s3 - kk, den);
+    }
+}
+
+// The layers in the tree's coordinates: sources need ys_lo < y < ys_hi; a
+// target's tree coordinate is ty_a y + ty_b (the component's image map) and
+// needs yt_lo < . < yt_hi.
+struct Layers {
+    double ys_lo, ys_hi, yt_lo, yt_hi, ty_a, ty_b;
+};
 
 // ---------------------------------------------------------------------------
 // Scaled Bessel bases of the expansions.
@@ -414,16 +459,17 @@ constexpr int NGL = 16;  // Gauss-Legendre points per panel
 // Launch wrappers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 // tree.hip
-// sources must satisfy 0 < y < ys_lim, targets yt_lim < y < 0
-// bounding box and bad-point count of both point sets: nblk = bbox_blocks(n)
+// bounding box (targets in their tree coordinates) and the count of points
+// outside their layers (ly) of both point sets: nblk = bbox_blocks(n)
 // blocks write partials (partial[nblk][8]), one wave reduces them and writes
 // out[0..6] and then the 64-bit sequence number at out + 8 (host-mapped
 // memory).  The sequence number is *dseq + 1, stored back to *dseq (device
 // memory, zero at first), so that launches replayed from a graph still
 // number their results.
-void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
+void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, const Layers &ly,
                  double *partial, uint64_t *dseq, int nblk, double *out, hipStream_t st);
-void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st);
+// out = (x, -(a y + b)) of every point
+void launch_mirror(const double *xy, int64_t n, double a, double b, double *out, hipStream_t st);
 int bbox_blocks(int64_t n);
 // Points grouped by leaf (counting sort; every leaf in increasing original
 // index).  cnt: nbox counts, zero on entry.  Results: start/end[nbox] (leaf
@@ -443,7 +489,7 @@ struct TreeBufs {
     int nrhs = 0, qw = 0;
 };
 void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
-                 int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, const TreeBufs &b, int32_t *err,
+                 int ncol, int rows_s, int rows_t, const Layers &ly, const TreeBufs &b, int32_t *err,
                  hipStream_t st);
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 
@@ -499,9 +545,10 @@ void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *id
 // direct sum over all pairs, split into nchunk source chunks (partials in
 // part: nchunk * nrhs * nt, needed when nchunk > 1); direct_chunks picks nchunk
 int direct_chunks(int64_t ns, int64_t nt, int nrhs);
-void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, int nrhs, int prec,
-                   const Node *nodes, int nmid, int npan, double t0, int nchunk, cx<double> *part, void *u,
-                   hipStream_t st);
+// (a target's tree coordinate is ty_a y + ty_b)
+void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, double ty_a,
+                   double ty_b, int nrhs, int prec, const Node *nodes, int nmid, int npan, double t0, int nchunk,
+                   cx<double> *part, void *u, hipStream_t st);
 
 // noalloc.hip: the fixed device array of lmfmm_apply_noalloc (its size is
 // LMFMM_NOALLOC_MAX_BYTES of lmfmm.h).  init resolves the address on device

@@ -450,7 +450,8 @@ __global__ void __launch_bounds__(64 * SW_W) __attribute__((amdgpu_waves_per_eu(
 // chunk order by k_direct_reduce.
 template <typename T>
 __global__ void __launch_bounds__(64) k_direct(const double *__restrict__ src, int64_t ns, const cx<T> *__restrict__ q,
-                                               const double *__restrict__ tgt, int64_t nt, int nrhs,
+                                               const double *__restrict__ tgt, int64_t nt, double ty_a, double ty_b,
+                                               int nrhs,
                                                const Node *__restrict__ nodes, int nmid, int npan, double t0,
                                                int64_t cs, cx<double> *__restrict__ part, cx<T> *__restrict__ u)
 {
@@ -460,7 +461,7 @@ __global__ void __launch_bounds__(64) k_direct(const double *__restrict__ src, i
     const int nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
     const int64_t j0 = (int64_t)blockIdx.z * cs, j1 = j0 + cs < ns ? j0 + cs : ns;
     bool act = i < nt;
-    double x1 = act ? tgt[i] : tgt[0], y1 = act ? tgt[nt + i] : tgt[nt];
+    double x1 = act ? tgt[i] : tgt[0], y1 = fma(ty_a, act ? tgt[nt + i] : tgt[nt], ty_b);
     cx<double> res[RMAX];
     for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
     for (int64_t j = j0; j < j1; ++j) {
@@ -551,9 +552,9 @@ int direct_chunks(int64_t ns, int64_t nt, int nrhs)
     return (int)std::max<int64_t>(1, z);
 }
 
-void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, int nrhs, int prec,
-                   const Node *nodes, int nmid, int npan, double t0, int nchunk, cx<double> *part, void *u,
-                   hipStream_t st)
+void launch_direct(const double *src, int64_t ns, const void *q, const double *tgt, int64_t nt, double ty_a,
+                   double ty_b, int nrhs, int prec, const Node *nodes, int nmid, int npan, double t0, int nchunk,
+                   cx<double> *part, void *u, hipStream_t st)
 {
     if (nt == 0) return;
     int64_t cs = (ns + nchunk - 1) / nchunk;
@@ -562,14 +563,14 @@ void launch_direct(const double *src, int64_t ns, const void *q, const double *t
     const int64_t m = nt * nrhs;
     if (prec == 0) {
         hipLaunchKernelGGL((k_direct<double>), grid, dim3(64), 0, st, src, ns,
-                           reinterpret_cast<const cx<double> *>(q), tgt, nt, nrhs, nodes, nmid, npan, t0, cs, pp,
+                           reinterpret_cast<const cx<double> *>(q), tgt, nt, ty_a, ty_b, nrhs, nodes, nmid, npan, t0, cs, pp,
                            reinterpret_cast<cx<double> *>(u));
         if (pp)
             hipLaunchKernelGGL((k_direct_reduce<double>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, pp,
                                nchunk, m, reinterpret_cast<cx<double> *>(u));
     } else {
         hipLaunchKernelGGL((k_direct<float>), grid, dim3(64), 0, st, src, ns, reinterpret_cast<const cx<float> *>(q),
-                           tgt, nt, nrhs, nodes, nmid, npan, t0, cs, pp, reinterpret_cast<cx<float> *>(u));
+                           tgt, nt, ty_a, ty_b, nrhs, nodes, nmid, npan, t0, cs, pp, reinterpret_cast<cx<float> *>(u));
         if (pp)
             hipLaunchKernelGGL((k_direct_reduce<float>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, pp,
                                nchunk, m, reinterpret_cast<cx<float> *>(u));

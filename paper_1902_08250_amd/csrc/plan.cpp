@@ -324,7 +324,12 @@ static void collect_timing(lmfmm_plan_s *p)
     p->ev_n = 0;
 }
 
-static double kmax_re(const Medium &m) { return std::max(m.k1.re, std::max(m.k2.re, m.k3.re)); }
+// largest real part of the wave numbers the density depends on (the
+// impedance half-space has only k1)
+static double kmax_re(const Medium &m)
+{
+    return m.comp == COMP_IMP ? m.k1.re : std::max(m.k1.re, std::max(m.k2.re, m.k3.re));
+}
 static double contour_c(const Medium &m) { return std::max(1.0, 1.25 * kmax_re(m)); }
 
 // Smallest n with |J_n(z)| <= eps for real z > 0 (n >= z): Miller ratios.
@@ -351,7 +356,8 @@ static int bessel_cutoff(double z, double eps)
 
 static double kabs_max(const Medium &m)
 {
-    return std::max(std::abs(zc(m.k1.re, m.k1.im)), std::abs(zc(m.k2.re, m.k2.im)));
+    const cx<double> kt = k_target_layer(m);
+    return std::max(std::abs(zc(m.k1.re, m.k1.im)), std::abs(zc(kt.re, kt.im)));
 }
 
 // Expansion order at a level: max(order, the order the tolerance needs for the
@@ -563,7 +569,18 @@ static int build_m2l_tables(VarTables &vt, const Medium &med, const Geometry &g,
                 double umax = 2.0 * P + 60.0;
                 double e0 = std::min(c, 2.0 / rho);
                 for (int k = 0; k < 4; ++k) add_ray_panel(nl, c, psi, sgn, e0 * k / 4, e0 * (k + 1) / 4);
-                for (double t = e0; t * rho < umax; t += 2.0 / rho) add_ray_panel(nl, c, psi, sgn, t, t + 2.0 / rho);
+                // Panels of length 2/rho (two e-folds of the ray's decay), but
+                // no longer than their distance from the ray's start: the
+                // branch points +-k and the 1/s2 factor sit within ~c of the
+                // start, and a panel many times longer than that distance
+                // resolves them poorly (for small boxes 2/rho >> c; a 16-node
+                // panel of length 2/rho there left 4e-9 relative error at
+                // k = 20, leaf width 2e-3, and 4e-6 for the impedance density).
+                for (double t = e0; t * rho < umax;) {
+                    double len = std::min(2.0 / rho, std::max(t, c));
+                    add_ray_panel(nl, c, psi, sgn, t, t + len);
+                    t += len;
+                }
                 int Q = nl.count() - start;
                 for (int i = 0; i < Q; ++i) {
                     node_cls.push_back(slot);
@@ -848,6 +865,38 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         p->near_sweep = v == "1";
         return LMFMM_OK;
     }
+    if (k == "component" || k == "alpha") {
+        Medium m = p->med;
+        if (k == "alpha") {
+            char *e = nullptr;
+            const double a = std::strtod(value, &e);
+            if (!e || *e || !std::isfinite(a)) return fail(LMFMM_EINVAL, "alpha must be a finite number");
+            m.alpha = a;
+        } else if (v == "2t") {
+            m.comp = COMP_2T;
+        } else if (v == "2b") {
+            m.comp = COMP_2B;
+        } else if (v == "1s") {
+            m.comp = COMP_1S;
+        } else if (v == "3s") {
+            m.comp = COMP_3S;
+        } else if (v == "impedance") {
+            m.comp = COMP_IMP;
+        } else {
+            return fail(LMFMM_EINVAL, "component must be 2t, 2b, 1s, 3s or impedance");
+        }
+        p->med = m;
+        // every table depends on the component: build them again
+        for (auto &vt : p->vt) {
+            vt.t_L = -1;
+            vt.n_h = -1;
+            vt.version++;
+        }
+        p->d_h = -1;
+        p->last_key.clear();
+        p->g_prekey.clear();
+        return LMFMM_OK;
+    }
     if (k == "m2l_mfma") {
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "m2l_mfma must be 0 or 1");
         p->m2l_mfma = v == "1";
@@ -924,10 +973,40 @@ static int check_common(lmfmm_plan p, int64_t ns, const double *src, int64_t nt,
     return LMFMM_OK;
 }
 
-// Layer bounds of the two point sets: forward, sources 0 < y and targets
-// -d < y < 0; transposed (mirrored coordinates), sources 0 < y < d, targets y < 0.
-static double ys_limit(const Medium &m) { return m.adj ? m.d : INFINITY; }
-static double yt_limit(const Medium &m) { return m.adj ? -INFINITY : -m.d; }
+// The image map of the plan's field component (a target's tree coordinate
+// is a y + b) and its layer in tree coordinates.
+static void image_map(const Medium &m, double &a, double &b)
+{
+    a = 1.0;
+    b = 0.0;
+    if (m.comp == COMP_2B) {
+        a = -1.0;
+        b = -2.0 * m.d;
+    } else if (m.comp == COMP_1S || m.comp == COMP_IMP) {
+        a = -1.0;
+    }
+}
+static void target_layer(const Medium &m, double &lo, double &hi)
+{
+    switch (m.comp) {
+    case COMP_2B: lo = -2.0 * m.d; hi = -m.d; break;  // -d < y < 0
+    case COMP_1S:
+    case COMP_IMP: lo = -INFINITY; hi = 0.0; break;  // y > 0
+    case COMP_3S: lo = -INFINITY; hi = -m.d; break;  // y < -d
+    default: lo = -m.d; hi = 0.0;                    // -d < y < 0
+    }
+}
+// Layers of both point sets in tree coordinates: forward, sources y > 0 and
+// the targets' image layer; transposed (mirrored coordinates), the sources are
+// the mirrored image targets and the targets the mirrored sources (y < 0).
+static Layers layers_of(const Medium &m)
+{
+    double lo, hi, a, b;
+    target_layer(m, lo, hi);
+    image_map(m, a, b);
+    if (m.adj) return Layers{-hi, -lo, -INFINITY, 0.0, 1.0, 0.0};
+    return Layers{0.0, INFINITY, lo, hi, a, b};
+}
 
 // Bounding box of the points (host readback) or the fixed domain.
 // Bounding box on the device: the kernel writes the result into host-coherent
@@ -937,7 +1016,7 @@ static void bbox_launch(lmfmm_plan p, const Medium &med, int64_t ns, const doubl
 {
     double *part = (double *)p->bbox_dev.p;
     uint64_t *dseq = (uint64_t *)(part + 8 * 512 + 1);
-    launch_bbox(src, ns, tgt, nt, ys_limit(med), yt_limit(med), part, dseq, bbox_blocks(ns + nt), p->d_bbox, st);
+    launch_bbox(src, ns, tgt, nt, layers_of(med), part, dseq, bbox_blocks(ns + nt), p->d_bbox, st);
 }
 
 // Wait for the result of the bbox_seq-th launch: spin on its sequence number
@@ -1247,8 +1326,8 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         // Step 1: tree (in a graph of the device-computed box, the box first)
         if (with_bbox) bbox_launch(p, med, ns, src, nt, tgt, sx);
         set_stage(S_TREE);
-        launch_tree(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, ys_limit(med),
-                    yt_limit(med), tb, err, sx);
+        launch_tree(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, layers_of(med), tb,
+                    err, sx);
         group_end(tree_launches, sx);
 
         // Step 2: upward pass
@@ -1441,9 +1520,11 @@ static int mirror_points(lmfmm_plan p, int64_t ns, const double *src, int64_t nt
     int rc = p->mirror.ensure((size_t)2 * (ns + nt) * sizeof(double) + 512);
     if (rc) return rc;
     mtgt = (double *)p->mirror.p;             // mirrored original sources: targets of G^T
-    msrc = mtgt + 2 * ns;                     // mirrored original targets: sources of G^T
-    launch_mirror(src, ns, mtgt, st);
-    launch_mirror(tgt, nt, msrc, st);
+    msrc = mtgt + 2 * ns;                     // mirrored image targets: sources of G^T
+    double a, b;
+    image_map(p->med, a, b);
+    launch_mirror(src, ns, 1.0, 0.0, mtgt, st);
+    launch_mirror(tgt, nt, a, b, msrc, st);
     HIPCHK(hipGetLastError());
     return LMFMM_OK;
 }
@@ -1508,8 +1589,10 @@ int lmfmm_direct(lmfmm_plan p, int64_t ns, const double *src, const void *q, int
     }
     const int nchunk = direct_chunks(ns, nt, nrhs);
     if (nchunk > 1 && (rc = p->dir_part.ensure((size_t)nchunk * nt * nrhs * sizeof(cx<double>)))) return rc;
-    launch_direct(src, ns, q, tgt, nt, nrhs, prec, (const Node *)p->dir_nodes.p, p->d_nmid, p->d_npan, p->d_t0,
-                  nchunk, (cx<double> *)p->dir_part.p, u, st);
+    double ty_a, ty_b;
+    image_map(p->med, ty_a, ty_b);
+    launch_direct(src, ns, q, tgt, nt, ty_a, ty_b, nrhs, prec, (const Node *)p->dir_nodes.p, p->d_nmid, p->d_npan,
+                  p->d_t0, nchunk, (cx<double> *)p->dir_part.p, u, st);
     HIPCHK(hipGetLastError());
     return LMFMM_OK;
 }
@@ -1535,9 +1618,12 @@ int lmfmm_grad_coords(lmfmm_plan p, int64_t ns, const double *src, const void *q
     if (rc) return rc;
     if ((ns > 0 && !dsrc) || (nt > 0 && !dtgt)) return fail(LMFMM_EINVAL, "null gradient output");
     hipStream_t st = (hipStream_t)stream;
-    // target coordinates: gradient of the field of q contracted with w
-    rc = prec == LMFMM_C128 ? apply_impl<double>(p, 0, ns, src, q, nt, tgt, nullptr, nrhs, st, w, dtgt, 1.0)
-                            : apply_impl<float>(p, 0, ns, src, q, nt, tgt, nullptr, nrhs, st, w, dtgt, 1.0);
+    // target coordinates: gradient of the field of q contracted with w (the
+    // y derivative in tree coordinates times the image map's slope)
+    double ty_a, ty_b;
+    image_map(p->med, ty_a, ty_b);
+    rc = prec == LMFMM_C128 ? apply_impl<double>(p, 0, ns, src, q, nt, tgt, nullptr, nrhs, st, w, dtgt, ty_a)
+                            : apply_impl<float>(p, 0, ns, src, q, nt, tgt, nullptr, nrhs, st, w, dtgt, ty_a);
     if (rc) return rc;
     if (ns == 0) return LMFMM_OK;
     // source coordinates: gradient of the transposed field of w contracted with q,

@@ -1,7 +1,9 @@
 // Quadrature-node tables (Algorithm 1, Step 1: "precompute necessary tables").
 //
 //  * Near-field table: on a contour fixed per plan and tree, the FP64 values
-//    lambda_n, s1(lambda_n), s2(lambda_n) and D_n = weight_n sigma_2^t / (4 pi s2).
+//    lambda_n, s1(lambda_n), s2(lambda_n) and D_n = weight_n sigma / (4 pi s2)
+//    (sigma and s2 = the target layer's root of the plan's field component;
+//    sigma_2^t and the middle layer's root by default).
 //  * M2L translation matrices (Lemma M2L, the remark on precomputing A per
 //    level): for a translation class with target centre (x_t, y_t) and source
 //    centre (x_s, y_s),
@@ -25,8 +27,8 @@ __global__ void __launch_bounds__(256) k_node_table(const double *__restrict__ l
     if (i >= n) return;
     cx<double> lam = {lamw[4 * i], lamw[4 * i + 1]};
     cx<double> wt = {lamw[4 * i + 2], lamw[4 * i + 3]};
-    cx<double> s1 = sroot_d(lam, med.k1), s2 = sroot_d(lam, med.k2);
-    cx<double> sg = sigma2t_d(lam, med, s1, s2);
+    cx<double> s1 = sroot_d(lam, med.k1), s2 = sroot_d(lam, k_target_layer(med));
+    cx<double> sg = sigma_d(lam, med, s1);
     cx<double> D = cdiv(wt * sg, (4.0 * M_PI) * s2);
     cx<double> ss = med.adj ? s2 : s1, stt = med.adj ? s1 : s2;
     Node nd;
@@ -69,9 +71,10 @@ __global__ void __launch_bounds__(256) k_m2l_factors(const double *__restrict__ 
     double dxc = cls_geo[4 * c], yt = cls_geo[4 * c + 1], ys = cls_geo[4 * c + 2], R = cls_geo[4 * c + 3];
     cx<double> lam = {lamw[4 * i], lamw[4 * i + 1]};
     cx<double> wt = {lamw[4 * i + 2], lamw[4 * i + 3]};
-    cx<double> s1 = sroot_d(lam, med.k1), s2 = sroot_d(lam, med.k2);
-    cx<double> sg = sigma2t_d(lam, med, s1, s2);
-    // source side (multipole, Shat) and target side (local, That)
+    cx<double> s1 = sroot_d(lam, med.k1), s2 = sroot_d(lam, k_target_layer(med));
+    cx<double> sg = sigma_d(lam, med, s1);
+    // source side (multipole, Shat) and target side (local, That); s2 is the
+    // target layer's root (k2 for the middle layer)
     cx<double> ss = med.adj ? s2 : s1, stt = med.adj ? s1 : s2;
     cx<double> E = cexp_d(stt * yt - ss * ys + mk(-lam.im * dxc, lam.re * dxc));
     cx<double> D = cdiv(wt * E * sg, (4.0 * M_PI) * s2);

@@ -41,8 +41,7 @@ __device__ inline double wave_sum(double v)
 // before using any of them.
 constexpr int BB_PER = 4;
 __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__restrict__ src, int64_t ns,
-                                                             const double *__restrict__ tgt, int64_t nt,
-                                                             double ys_lim, double yt_lim,
+                                                             const double *__restrict__ tgt, int64_t nt, Layers ly,
                                                              double *__restrict__ partial)
 {
     double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
@@ -59,7 +58,7 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
                 y[k] = src[ns + i];
             } else if (i < n) {
                 x[k] = tgt[i - ns];
-                y[k] = tgt[nt + i - ns];
+                y[k] = fma(ly.ty_a, tgt[nt + i - ns], ly.ty_b);
             }
         }
 #pragma unroll
@@ -67,8 +66,8 @@ __global__ void __launch_bounds__(BB_THREADS) k_bbox_partial(const double *__res
             const int64_t i = base + k * BB_THREADS + threadIdx.x;
             if (i >= n) continue;
             const bool tg = i >= ns;
-            const bool ok = isfinite(x[k]) && isfinite(y[k]) && (tg ? (y[k] < 0.0 && y[k] > yt_lim)
-                                                                    : (y[k] > 0.0 && y[k] < ys_lim));
+            const bool ok = isfinite(x[k]) && isfinite(y[k]) && (tg ? (y[k] < ly.yt_hi && y[k] > ly.yt_lo)
+                                                                    : (y[k] > ly.ys_lo && y[k] < ly.ys_hi));
             if (!ok) {
                 v[6] += 1.0;
                 continue;
@@ -160,7 +159,7 @@ struct TreeCountArgs {
     int64_t nt;
     double x_lo, invw;
     int col_lo, ncol, rows_s, rows_t;
-    double ys_lim, yt_lim;
+    Layers ly;
     uint32_t *key;
     int32_t *rank, *cnt, *err;
 };
@@ -170,8 +169,9 @@ __device__ __forceinline__ void tree_count_body(const TreeCountArgs &a, int bx)
     if (i >= a.ns + a.nt) return;
     bool tg = i >= a.ns;
     double x = tg ? a.tgt[i - a.ns] : a.src[i];
-    double y = tg ? a.tgt[a.nt + i - a.ns] : a.src[a.ns + i];
-    bool bad = !(isfinite(x) && isfinite(y)) || (tg ? !(y < 0.0 && y > a.yt_lim) : !(y > 0.0 && y < a.ys_lim));
+    double y = tg ? fma(a.ly.ty_a, a.tgt[a.nt + i - a.ns], a.ly.ty_b) : a.src[a.ns + i];
+    bool bad = !(isfinite(x) && isfinite(y)) ||
+               (tg ? !(y < a.ly.yt_hi && y > a.ly.yt_lo) : !(y > a.ly.ys_lo && y < a.ly.ys_hi));
     double fc = floor((x - a.x_lo) * a.invw) - (double)a.col_lo;
     double fr = floor((tg ? -y : y) * a.invw);
     int rows = tg ? a.rows_t : a.rows_s;
@@ -333,6 +333,7 @@ struct TreeLeafArgs {
     const uint64_t *q;
     uint64_t *qs;
     int nrhs, qw;
+    double ty_a, ty_b;  // tree coordinate of a target: ty_a y + ty_b
 };
 __device__ __forceinline__ void tree_leaf_body(const TreeLeafArgs &A, int b)
 {
@@ -364,7 +365,7 @@ __device__ __forceinline__ void tree_leaf_body(const TreeLeafArgs &A, int b)
                         qs[((int64_t)r * ns + s + k) * qw + w] = q[((int64_t)r * ns + o) * qw + w];
         } else {
             xs[s + k] = tgt[o - ns];
-            ys[s + k] = tgt[nt + o - ns];
+            ys[s + k] = fma(A.ty_a, tgt[nt + o - ns], A.ty_b);
         }
     };
     if (nb <= 64) {
@@ -436,28 +437,27 @@ int bbox_blocks(int64_t n)
     return (int)b;
 }
 
-void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, double ys_lim, double yt_lim,
-                 double *partial, uint64_t *dseq, int nblk, double *out, hipStream_t st)
+void launch_bbox(const double *src, int64_t ns, const double *tgt, int64_t nt, const Layers &ly, double *partial,
+                 uint64_t *dseq, int nblk, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(BB_THREADS), 0, st, src, ns, tgt, nt, ys_lim, yt_lim,
-                       partial);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(BB_THREADS), 0, st, src, ns, tgt, nt, ly, partial);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, partial, nblk, dseq, out);
 }
 
 
-__global__ void k_mirror(const double *__restrict__ xy, int64_t n, double *__restrict__ out)
+__global__ void k_mirror(const double *__restrict__ xy, int64_t n, double a, double b, double *__restrict__ out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         out[i] = xy[i];
-        out[n + i] = -xy[n + i];
+        out[n + i] = -fma(a, xy[n + i], b);
     }
 }
 
-void launch_mirror(const double *xy, int64_t n, double *out, hipStream_t st)
+void launch_mirror(const double *xy, int64_t n, double a, double b, double *out, hipStream_t st)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_mirror, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xy, n, out);
+    hipLaunchKernelGGL(k_mirror, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xy, n, a, b, out);
 }
 
 
@@ -471,22 +471,21 @@ void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st)
 }
 
 void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
-                 int ncol, int rows_s, int rows_t, double ys_lim, double yt_lim, const TreeBufs &b, int32_t *err,
+                 int ncol, int rows_s, int rows_t, const Layers &ly, const TreeBufs &b, int32_t *err,
                  hipStream_t st)
 {
     const int64_t n = ns + nt;
     const int64_t nbox = (int64_t)(rows_s + rows_t) * ncol;
     if (n == 0 || nbox == 0) return;
     const unsigned g = (unsigned)((n + 255) / 256);
-    const TreeCountArgs ca{src, ns, tgt, nt, x_lo, 1.0 / w, col_lo, ncol, rows_s, rows_t, ys_lim, yt_lim, b.key, b.rank,
-                           b.cnt, err};
+    const TreeCountArgs ca{src, ns, tgt, nt, x_lo, 1.0 / w, col_lo, ncol, rows_s, rows_t, ly, b.key, b.rank, b.cnt, err};
     emit((const void *)k_tree_count, (const void *)k_tree_count_multi, 0, dim3(g), dim3(256), 0, st, ca);
     const TreeScanArgs sa{b.cnt, nbox, n, b.start, b.end, err};
     emit((const void *)k_tree_scan, (const void *)k_tree_scan_multi, 1, dim3(1), dim3(SC_THREADS), 0, st, sa);
     const TreeScatterArgs xa{b.key, b.rank, n, b.start, b.perm};
     emit((const void *)k_tree_scatter, (const void *)k_tree_scatter_multi, 2, dim3(g), dim3(256), 0, st, xa);
     const TreeLeafArgs la{b.start, b.end, b.perm, b.scratch, b.idx, src, ns, tgt, nt, b.xs, b.ys, b.q, b.qs, b.nrhs,
-                          b.qw};
+                          b.qw, ly.ty_a, ly.ty_b};
     emit((const void *)k_tree_leaf, (const void *)k_tree_leaf_multi, 3, dim3((unsigned)nbox), dim3(64), 0, st, la);
 }
 

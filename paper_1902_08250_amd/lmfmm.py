@@ -154,9 +154,16 @@ def _out(t, nrhs, n, dtype, device, name):
 
 
 class Plan:
-    """A plan for one three-layer medium: k = (k1, k2, k3) complex, d > 0."""
+    """A plan for one three-layer medium: k = (k1, k2, k3) complex, d > 0.
 
-    def __init__(self, k, d, order=16, tol=1e-6, levels=None, fixed_order=False, domain=None):
+    component: the part of the scattered field applied (Section 3): "2t"
+    (default, g_2^t: targets in the middle layer), "2b" (g_2^b, middle layer),
+    "1s" (g_1^s, top layer), "3s" (g_3^s, bottom layer) or "impedance" (the
+    impedance half-space of wave number k[0] with impedance alpha; targets
+    above y = 0)."""
+
+    def __init__(self, k, d, order=16, tol=1e-6, levels=None, fixed_order=False, domain=None, component=None,
+                 alpha=None):
         L = lib()
         kk = [complex(v) for v in k]
         arr = (ctypes.c_double * 6)(kk[0].real, kk[0].imag, kk[1].real, kk[1].imag, kk[2].real, kk[2].imag)
@@ -170,6 +177,10 @@ class Plan:
             self.set_option("fixed_order", "1")
         if domain is not None:
             self.set_option("domain", ",".join(repr(float(v)) for v in domain))
+        if alpha is not None:
+            self.set_option("alpha", repr(float(alpha)))
+        if component is not None:
+            self.set_option("component", component)
 
     def set_option(self, key, value):
         _check(lib().lmfmm_set_option(self._h, key.encode(), str(value).encode()))
