@@ -246,7 +246,9 @@ int lmfmm_sync_status(lmfmm_plan plan, void *stream);
  *   - each instance's (order floor, levels) comes from the tuning cache if it
  *     holds the instance's key (medium, size buckets, tol, nrhs, precision,
  *     order set), else an autotuner times every candidate with HIP events and
- *     keeps the fastest, and the choice is added to the cache;
+ *     keeps the fastest, then times the other near-field form (sweep or
+ *     pairwise sum, plan option "near_sweep") at that choice, and the choice
+ *     is added to the cache;
  *   - every instance's launch sequence is recorded and the launches of each
  *     stage (tree passes, P2M, M2M per level, M2L, L2L per level, near field,
  *     local evaluation) are merged into one launch over all instances, captured
@@ -265,7 +267,8 @@ int lmfmm_sync_status(lmfmm_plan plan, void *stream);
  * line; default: the environment variable LMFMM_TUNE_CACHE, else none),
  * "timing" 1/0/reset (launch the merged sequence with start/stop events per
  * launch and accumulate the durations per kernel class in
- * lmfmm_batch_stats); other keys are forwarded to every instance's plan.
+ * lmfmm_batch_stats); other keys are forwarded to every instance's plan
+ * ("near_sweep" set this way also stops the tuner choosing the form).
  * --------------------------------------------------------------------------- */
 typedef struct lmfmm_batch_s *lmfmm_batch;
 typedef struct {
@@ -297,8 +300,10 @@ int lmfmm_batch_create(int n_inst, const double *k /* [n_inst][6] */, const doub
 int lmfmm_batch_destroy(lmfmm_batch batch);
 int lmfmm_batch_set_option(lmfmm_batch batch, const char *key, const char *value);
 int lmfmm_batch_apply(lmfmm_batch batch, const lmfmm_instance *inst, int nrhs, int precision, void *stream);
-/* The autotuner's choice for instance i and its measured time per apply (us). */
-int lmfmm_batch_get_choice(lmfmm_batch batch, int i, int *order, int *levels, double *us);
+/* The autotuner's choice for instance i: order floor, levels, near-field form
+ * (1: the x-ordered sweep, 0: the pairwise sum) and its measured time per
+ * apply (us).  Null out-pointers are skipped. */
+int lmfmm_batch_get_choice(lmfmm_batch batch, int i, int *order, int *levels, double *us, int *near_sweep);
 int lmfmm_batch_get_stats(lmfmm_batch batch, lmfmm_batch_stats *stats);
 /* Synchronize the stream; LMFMM_EDOMAIN if any instance's points left the
  * bounding box the batch was prepared for or their layer (the next apply then

@@ -1,5 +1,13 @@
 // Complex exponential from small tables, for the near-field sweep (host and
 // device, so that its accuracy can be checked on the host).
+//
+// Method: table-driven reduction in the manner of Tang's exponential (P. T. P.
+// Tang, "Table-driven implementation of the exponential function in IEEE
+// floating-point arithmetic", ACM TOMS 15(2), 1989: a 2^{j/32}-type table plus
+// a short polynomial on the reduced argument), applied here with 64 entries to
+// e^a and, with a table of sin and cos at multiples of pi/32, to e^{ib}; the
+// argument reductions subtract the multiple of the step in several parts
+// (Cody and Waite, "Software Manual for the Elementary Functions", 1980).
 #pragma once
 #include <hip/hip_runtime.h>
 

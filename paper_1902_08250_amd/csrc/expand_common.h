@@ -27,8 +27,11 @@ struct Tr {
 
 // Per-wave LDS: x chunk [R][KC] and the wave's partial sums [R][64].
 template <typename T>
-struct WaveLds {
+struct WaveX {
     cx<T> x[Tr<T>::R][Tr<T>::KC];
+};
+template <typename T>
+struct WaveLds : WaveX<T> {
     cx<T> out[Tr<T>::R][64];
 };
 
@@ -36,7 +39,7 @@ struct WaveLds {
 // r < nr.  Every lane of the wave calls this with the same arguments.
 template <typename T>
 __device__ inline void item_matvec(const cx<T> *__restrict__ A, int nk, int nout, int p0,
-                                   const cx<T> *__restrict__ x, int64_t xstride, int nr, WaveLds<T> &lds,
+                                   const cx<T> *__restrict__ x, int64_t xstride, int nr, WaveX<T> &lds,
                                    cx<T> (&acc)[Tr<T>::R])
 {
     constexpr int R = Tr<T>::R, KC = Tr<T>::KC;

@@ -138,43 +138,58 @@ __global__ void __launch_bounds__(P2M_THREADS) k_p2m_multi(MultiArgs m)
 // e^{i p theta} at the point (X, Y) relative to the leaf centre, from the
 // scaled expansion Ls[r][2P+1], r < nr.
 // ---------------------------------------------------------------------------
+// The local expansion of order P at offset (X, Y) from its centre, for nr
+// right-hand sides (Ls[r * (2P + 1) + P + p], p = -P..P): sum_p Lhat_p B_p.
+// The basis ratios g_p = B_p / B_{p-1} come out of the backward recurrence in
+// decreasing p, so the sums are formed there by Horner's rule,
+// sum_{p >= 1} Lhat_p B_p = B_0 g_1 (Lhat_1 + g_2 (Lhat_2 + ...)), and no
+// table of ratios is kept (B_0 = J_0 is known only at the end).
 template <typename T, int PMAX, int RMAX>
 __device__ inline void eval_local(cx<T> k2, T X, T Y, T invR, int P, const cx<T> *Ls, int nr, cx<double> (&res)[RMAX])
 {
     const int nc = 2 * P + 1;
-    cx<T> tm[PMAX + 1];
-    cx<T> J0;
-    bessel_ratios<T, PMAX>(k2, X, Y, P, tm, J0);
-    cx<T> up = mk<T>(X * invR, Y * invR), dn = mk<T>(-X * invR, Y * invR);
-    cx<T> acc[RMAX];
-    for (int r = 0; r < RMAX; ++r) acc[r] = (r < nr) ? J0 * Ls[r * nc + P] : mk<T>(0, 0);
-    cx<T> vp = J0, vm = J0;
-#pragma unroll PUnroll<PMAX>::n
-    for (int p = 1; p <= PMAX; ++p) {
-        if (p <= P) {
-            cx<T> f = T(2 * p) * tm[p];
-            vp = vp * (f * up);
-            vm = vm * (f * dn);
-            for (int r = 0; r < RMAX; ++r)
-                if (r < nr) {
-                    cfma(acc[r], vp, Ls[r * nc + P + p]);
-                    cfma(acc[r], vm, Ls[r * nc + P - p]);
-                }
-        }
+    const cx<T> z2 = (k2 * k2) * (X * X + Y * Y);
+    const int N = miller_start<T>(z2, P);
+    cx<T> t = mk<T>(0, 0), tprev = mk<T>(0, 0), U = mk<T>(0, 0);
+    for (int m = N; m > P; --m) miller_step<T>(z2, m, t, tprev, U);
+    const cx<T> up = mk<T>(X * invR, Y * invR), dn = mk<T>(-X * invR, Y * invR);
+    cx<T> hp[RMAX], hm[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) hp[r] = hm[r] = mk<T>(0, 0);
+    for (int m = P; m >= 1; --m) {
+        miller_step<T>(z2, m, t, tprev, U);
+        const cx<T> f = T(2 * m) * t;
+        const cx<T> gp = f * up, gm = f * dn;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+            if (r < nr) {
+                hp[r] = gp * (Ls[r * nc + P + m] + hp[r]);
+                hm[r] = gm * (Ls[r * nc + P - m] + hm[r]);
+            }
     }
-    for (int r = 0; r < RMAX; ++r) res[r] = {(double)acc[r].re, (double)acc[r].im};
+    const cx<T> J0 = cinv(mk<T>(T(1), T(0)) + U);
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        const cx<T> v = r < nr ? J0 * (Ls[r * nc + P] + hp[r] + hm[r]) : mk<T>(0, 0);
+        res[r] = {(double)v.re, (double)v.im};
+    }
 }
 
 // ---------------------------------------------------------------------------
-// L2P over G consecutive target leaves per block (points contiguous in the
-// sorted order); the near field, if any, comes from the sweep kernel's parts.
-// First the leaves' local expansions go to LDS: by the leaf-level L2L shift of
-// the parent's (Lemma L2L, one leaf per wave at a time), plus the stored M2L
-// result in the interface rows, or copied from the stored expansions.  Then
-// a thread per target evaluates its leaf's expansion and adds the near-field
+// L2P over consecutive target leaves (points contiguous in the sorted order);
+// the near field, if any, comes from the sweep kernel's parts.  Blocks below
+// nb_if take G_if leaves each from the first n_if leaves (the interface rows),
+// the others G leaves each from the rest.  Each leaf evaluates one local
+// expansion (EvalLevels): its own, or its ancestor's at the level where the
+// far field was complete.  Leaves with the same expansion share a slot in LDS.
+// Slots are filled first: by the leaf-level L2L shift of the parent's
+// expansion (Lemma L2L, one slot per wave at a time) plus the stored M2L
+// result in the interface rows, or copied from the stored expansions.  Then a
+// thread per target evaluates its slot's expansion and adds the near-field
 // parts in order.  Writes u[r][original index].
 // ---------------------------------------------------------------------------
 constexpr int L2P_THREADS = 512;
+constexpr int L2P_GMAX = 64;  // leaves per block (at most one wave's lanes)
 template <typename T>
 struct L2PArgs {
     const int32_t *start, *end, *idx;
@@ -184,13 +199,14 @@ struct L2PArgs {
     double x_lo, w;
     cx<T> k2;
     T invR;
-    const cx<T> *Lc;
+    const cx<T> *Lc;  // local expansions of every level (ev.off[l]: level l)
     LeafShift<T> sh;
     int64_t key_t0;
-    int G, do_far;
+    int G, G_if, n_if, nb_if, ncmax, do_far;
     const cx<double> *unear;
     int nparts;
     cx<T> *u;
+    EvalLevels ev;
 };
 template <typename T, int PMAX, int RMAX>
 __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, const int by)
@@ -200,34 +216,65 @@ __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, cons
     const int32_t *__restrict__ idx = A.idx;
     const double *__restrict__ xs = A.xs;
     const double *__restrict__ ys = A.ys;
-    const cx<T> *__restrict__ Lc = A.Lc;
     const cx<double> *__restrict__ unear = A.unear;
     cx<T> *__restrict__ u = A.u;
     const LeafShift<T> &sh = A.sh;
+    const EvalLevels &ev = A.ev;
     const int64_t ns = A.ns, nt = A.nt, key_t0 = A.key_t0;
-    const int nrhs = A.nrhs, P = A.P, nbox = A.nbox, ncol = A.ncol, col_lo = A.col_lo, G = A.G, do_far = A.do_far,
-              nparts = A.nparts;
+    const int nrhs = A.nrhs, P = A.P, nbox = A.nbox, ncol = A.ncol, col_lo = A.col_lo, do_far = A.do_far,
+              nparts = A.nparts, ncmax = A.ncmax, L = ev.L;
     const double x_lo = A.x_lo, w = A.w;
     const cx<T> k2 = A.k2;
     const T invR = A.invR;
+    const cx<T> *__restrict__ LcL = A.Lc + ev.off[L];
     extern __shared__ unsigned char smem_raw[];
-    __shared__ WaveLds<T> wl[L2P_THREADS / 64];
-    __shared__ int bnd[LEAF_GMAX + 1];
+    __shared__ WaveX<T> wl[L2P_THREADS / 64];
+    __shared__ int bnd[L2P_GMAX + 1];
+    __shared__ int s_slot[L2P_GMAX], s_leaf[L2P_GMAX + 1], s_lev[L2P_GMAX], s_P[L2P_GMAX];
+    __shared__ int s_nslot;
     constexpr int R = Tr<T>::R;
     const int nc = 2 * P + 1;
-    cx<T> *Ls = reinterpret_cast<cx<T> *>(smem_raw);  // [G][RMAX][nc]
+    cx<T> *Ls = reinterpret_cast<cx<T> *>(smem_raw);  // [slot][RMAX][nc of the slot's level]
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int b0 = bx * G;
-    const int ng = nbox - b0 < G ? nbox - b0 : G;
+    const int b0 = bx < A.nb_if ? bx * A.G_if : A.n_if + (bx - A.nb_if) * A.G;
+    const int Gb = bx < A.nb_if ? A.G_if : A.G;
+    const int lim = bx < A.nb_if ? A.n_if : nbox;
+    const int ng = lim - b0 < Gb ? lim - b0 : Gb;
     const int r0 = by * RMAX;
     const int nr = nrhs - r0 < RMAX ? nrhs - r0 : RMAX;
     if (t <= ng) bnd[t] = t < ng ? start[key_t0 + b0 + t] : end[key_t0 + b0 + ng - 1];
+    if (wv == 0) {
+        // the expansion each leaf evaluates: consecutive leaves with the same
+        // (level, ancestor box) share a slot
+        int e = L, khi = -1, klo = -1;
+        if (lane < ng) {
+            const int box = b0 + lane, row = box / ncol, col = col_lo + box % ncol;
+            e = eval_level(ev, row);
+            khi = (e << 24) | (row >> (L - e));
+            klo = col >> (L - e);
+        }
+        const int phi = __shfl_up(khi, 1), plo = __shfl_up(klo, 1);
+        const bool isnew = lane < ng && (lane == 0 || khi != phi || klo != plo);
+        const unsigned long long m = __ballot(isnew);
+        const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const int slot = __popcll(m & le) - 1;
+        if (lane < ng) s_slot[lane] = slot;
+        if (isnew) {
+            s_leaf[slot] = lane;
+            s_lev[slot] = e;
+            s_P[slot] = ev.on ? ev.P[e] : P;
+        }
+        if (lane == 0) {
+            s_nslot = __popcll(m);
+            s_leaf[__popcll(m)] = ng;
+        }
+    }
     __syncthreads();
     const int S = bnd[0], E = bnd[ng];
     if (E <= S) return;
-    // the first chunk's points: their loads are in flight while the leaf
-    // expansions are formed
+    // the first chunk's points: their loads are in flight while the slots
+    // are filled
     double px = 0.0, py = 0.0;
     int32_t pid = 0;
     if (S + t < E) {
@@ -235,42 +282,50 @@ __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, cons
         py = ys[S + t];
         pid = idx[S + t];
     }
-    if (do_far && sh.tab) {
-        for (int g = wv; g < ng; g += L2P_THREADS / 64) {
-            if (bnd[g + 1] <= bnd[g]) continue;  // no targets in this leaf
+    const int nslot = s_nslot;
+    if (do_far) {
+        for (int s = wv; s < nslot; s += L2P_THREADS / 64) {
+            const int g = s_leaf[s], e = s_lev[s];
+            if (bnd[s_leaf[s + 1]] <= bnd[g]) continue;  // no targets in the slot's leaves
             const int box = b0 + g, row = box / ncol, col = col_lo + box % ncol;
-            const int prow = row >> 1, pcl = (col >> 1) - sh.col_lo_p, pos = (col & 1) + 2 * (row & 1);
-            const bool pok = prow < sh.rows_p && pcl >= 0 && pcl < sh.ncol_p;
-            const cx<T> *x = sh.Lp + ((int64_t)prow * sh.ncol_p + pcl) * nrhs * sh.ncp;
-            const bool add = row < sh.add_rows;
-            for (int rr = 0; rr < nr; rr += R) {
-                const int nrr = nr - rr < R ? nr - rr : R;
-                for (int p0 = 0; p0 < nc; p0 += 64) {
-                    cx<T> acc[R];
+            cx<T> *Lslot = Ls + (int64_t)s * RMAX * ncmax;
+            if (sh.tab && e == L) {
+                const int prow = row >> 1, pcl = (col >> 1) - sh.col_lo_p, pos = (col & 1) + 2 * (row & 1);
+                const bool pok = prow < sh.rows_p && pcl >= 0 && pcl < sh.ncol_p;
+                const cx<T> *x = sh.Lp + ((int64_t)prow * sh.ncol_p + pcl) * nrhs * sh.ncp;
+                const bool add = row < sh.add_rows;
+                for (int rr = 0; rr < nr; rr += R) {
+                    const int nrr = nr - rr < R ? nr - rr : R;
+                    for (int p0 = 0; p0 < nc; p0 += 64) {
+                        cx<T> acc[R];
 #pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
-                    const int p = p0 + lane;
-                    // the stored M2L value, loaded before the shift's own loads
-                    cx<T> prev[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        prev[r] = (add && p < nc && r < nrr) ? Lc[((int64_t)box * nrhs + r0 + rr + r) * nc + p]
-                                                             : mk<T>(0, 0);
-                    if (pok)
-                        item_matvec<T>(sh.tab + (int64_t)pos * sh.ncp * nc, sh.ncp, nc, p0,
-                                       x + (int64_t)(r0 + rr) * sh.ncp, sh.ncp, nrr, wl[wv], acc);
-                    if (p < nc)
+                        for (int r = 0; r < R; ++r) acc[r] = mk<T>(0, 0);
+                        const int p = p0 + lane;
+                        // the stored M2L value, loaded before the shift's own loads
+                        cx<T> prev[R];
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            if (r < nrr) Ls[(g * RMAX + rr + r) * nc + p] = add ? acc[r] + prev[r] : acc[r];
+                            prev[r] = (add && p < nc && r < nrr)
+                                          ? LcL[((int64_t)box * nrhs + r0 + rr + r) * nc + p]
+                                          : mk<T>(0, 0);
+                        if (pok)
+                            item_matvec<T>(sh.tab + (int64_t)pos * sh.ncp * nc, sh.ncp, nc, p0,
+                                           x + (int64_t)(r0 + rr) * sh.ncp, sh.ncp, nrr, wl[wv], acc);
+                        if (p < nc)
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+                                if (r < nrr) Lslot[(rr + r) * nc + p] = add ? acc[r] + prev[r] : acc[r];
+                    }
                 }
+            } else {
+                // the stored expansion of the slot's box at level e
+                const int she = L - e, nce = 2 * s_P[s] + 1;
+                const int64_t be = (int64_t)(row >> she) * (ev.on ? ev.ncol[e] : ncol) + (col >> she) -
+                                   (col_lo >> she);
+                const cx<T> *src = A.Lc + ev.off[e] + (be * nrhs + r0) * nce;
+                for (int r = 0; r < nr; ++r)
+                    for (int c = lane; c < nce; c += 64) Lslot[r * nce + c] = src[(int64_t)r * nce + c];
             }
-        }
-    } else if (do_far) {
-        const int per = nr * nc;
-        for (int e = t; e < ng * per; e += L2P_THREADS) {
-            const int g = e / per, o = e - g * per, r = o / nc, c = o - r * nc;
-            Ls[(g * RMAX + r) * nc + c] = Lc[((int64_t)(b0 + g) * nrhs + r0 + r) * nc + c];
         }
     }
     __syncthreads();
@@ -288,8 +343,11 @@ __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, cons
         cx<double> res[RMAX];
         for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
         if (do_far) {
-            const double cxp = x_lo + (col + 0.5) * w, cyp = -(row + 0.5) * w;
-            eval_local<T, PMAX, RMAX>(k2, (T)(px - cxp), (T)(py - cyp), invR, P, Ls + g * RMAX * nc, nr, res);
+            const int s = s_slot[g], she = L - s_lev[s];
+            const double we = ldexp(w, she);
+            const double cxp = x_lo + ((col >> she) + 0.5) * we, cyp = -((row >> she) + 0.5) * we;
+            eval_local<T, PMAX, RMAX>(k2, (T)(px - cxp), (T)(py - cyp), invR / (T)(1 << she), s_P[s],
+                                      Ls + (int64_t)s * RMAX * ncmax, nr, res);
         }
         const int64_t o = pid - ns;
         if (unear && row == 0)
@@ -668,8 +726,8 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
 template <typename T, int PMAX>
 void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs, const double *ys,
                   const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g, Medium med, const cx<T> *Lc,
-                  const LeafShift<T> &shift, const Node *nodes, int nmid, int npan, double t0, int do_far,
-                  int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
+                  const LeafShift<T> &shift, const EvalLevels &ev_in, const Node *nodes, int nmid, int npan,
+                  double t0, int do_far, int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
 {
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_t * lv.ncol;
@@ -681,24 +739,47 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
     int64_t key_t0 = (int64_t)lv.rows_s * lv.ncol;
     if (!(do_near && lv.rows_s > 0)) unear = nullptr;
     if (!do_near || unear || lv.rows_s == 0) {
-        // far field plus, if any, the sweep's near-field parts: G leaves per block
+        // far field plus, if any, the sweep's near-field parts
+        EvalLevels ev = ev_in;
+        ev.L = g.L;
+        ev.P[g.L] = lv.P;
+        ev.ncol[g.L] = lv.ncol;
+        ev.off[g.L] = lv.off_t;
+        int ncmax = lv.nc;
+        if (ev.on)
+            for (int l = ev.lc; l < g.L; ++l) ncmax = std::max(ncmax, 2 * ev.P[l] + 1);
         const int RM = nrhs == 1 ? 1 : (nrhs <= 4 ? 4 : 8);
-        const size_t per_leaf = (size_t)RM * lv.nc * sizeof(cx<T>);
-        // about 0.8 x 256 points per block, two blocks per compute unit: one
-        // leaf per wave in the shift phase (larger blocks, whose waves shift
-        // several leaves in turn, were slower)
-        int G = leaves_per_block(nbox, nt, 256, 2);
-        G = G > L2P_THREADS / 64 ? L2P_THREADS / 64 : G;
-        const int gmax = (int)((48 * 1024) / per_leaf);
-        G = G > gmax ? gmax : G;
-        G = G < 1 ? 1 : G;
-        const dim3 grid((nbox + G - 1) / G, (nrhs + RM - 1) / RM);
-        const L2PArgs<T> a{start, end, idx, xs, ys, ns, nt, nrhs, lv.P, nbox, lv.ncol, lv.col_lo, g.x_lo, lv.w, k2,
-                           invR, Lc + lv.off_t, shift, key_t0, G, do_far, unear, unear ? nparts : 0,
-                           reinterpret_cast<cx<T> *>(u)};
+        const size_t per_leaf = (size_t)RM * ncmax * sizeof(cx<T>);
+        // Leaves that shift (evaluation at the leaf level): about 0.8 x 256
+        // points per block, two blocks per compute unit, one leaf per wave
+        // (larger blocks, whose waves shift several leaves in turn, were
+        // slower).  The other leaves only copy a stored expansion, shared by
+        // neighbouring leaves: up to L2P_GMAX leaves and about 0.8 x 512
+        // points per block.  Without evaluation levels every leaf shifts.
+        const int gmax = std::max(1, (int)((48 * 1024) / per_leaf));
+        const int gmax_deep = gmax;
+        int n_if = nbox;
+        if (ev.on && ev.lc < g.L) n_if = std::min(nbox, shift.tab ? shift.add_rows * lv.ncol : 0);
+        int G_if = leaves_per_block(nbox, nt, 256, 2);
+        G_if = std::max(1, std::min(std::min(G_if, L2P_THREADS / 64), gmax));
+        int G = G_if;
+        if (n_if < nbox) {
+            const DeviceShape dv = device_shape();
+            int64_t k = (int64_t)std::ceil((double)nt / (0.8 * L2P_THREADS * dv.cus));
+            k = k < 1 ? 1 : (k > 2 ? 2 : k);
+            const int64_t gd = ((int64_t)(nbox - n_if) + k * dv.cus - 1) / (k * dv.cus);
+            G = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(gd, L2P_GMAX), gmax_deep));
+        }
+        const int nb_if = (n_if + G_if - 1) / G_if;
+        const int nblk = nb_if + (nbox - n_if + G - 1) / G;
+        const dim3 grid(nblk, (nrhs + RM - 1) / RM);
+        L2PArgs<T> a{start, end, idx, xs, ys, ns, nt, nrhs, lv.P, nbox, lv.ncol, lv.col_lo, g.x_lo, lv.w, k2,
+                     invR, Lc, shift, key_t0, G, G_if, n_if, nb_if, ncmax, do_far, unear, unear ? nparts : 0,
+                     reinterpret_cast<cx<T> *>(u), ev};
+        const size_t shmem = (size_t)std::max(G, G_if) * per_leaf;
 #define LMFMM_L2P_PACKED(RMC)                                                                              \
     emit((const void *)k_l2p<T, PMAX, RMC>, (const void *)k_l2p_multi<T, PMAX, RMC>, 0, grid, dim3(L2P_THREADS), \
-         G * per_leaf, st, a)
+         shmem, st, a)
         if (RM == 1)
             LMFMM_L2P_PACKED(1);
         else if (RM == 4)
@@ -765,13 +846,16 @@ void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, cons
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
-                     Medium med, const cx<T> *Lc, const LeafShift<T> &shift, const Node *nodes, int nmid, int npan,
-                     double t0, int do_far, int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st)
+                     Medium med, const cx<T> *Lc, const LeafShift<T> &shift, const EvalLevels &ev, const Node *nodes,
+                     int nmid, int npan, double t0, int do_far, int do_near, const cx<double> *unear, int nparts,
+                     void *u, hipStream_t st)
 {
     int P = g.lev[g.L].P;
+    if (ev.on)
+        for (int l = ev.lc; l < g.L; ++l) P = std::max(P, ev.P[l]);
     if (!unear) nparts = 0;
-#define LMFMM_L2P(PM)                                                                                          \
-    l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, shift, nodes, nmid, npan, t0, \
+#define LMFMM_L2P(PM)                                                                                               \
+    l2p_dispatch<T, PM>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, shift, ev, nodes, nmid, npan, t0, \
                         do_far, do_near, unear, nparts, u, st)
     if (P <= 16)
         LMFMM_L2P(16);
@@ -810,8 +894,8 @@ void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *id
                                 int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);                      \
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
-                                     const cx<T> *, const LeafShift<T> &, const Node *, int, int, double, int, int, \
-                                     const cx<double> *, int, void *, hipStream_t);                                 \
+                                     const cx<T> *, const LeafShift<T> &, const EvalLevels &, const Node *, int,    \
+                                     int, double, int, int, const cx<double> *, int, void *, hipStream_t);          \
     template void launch_l2p_grad<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, const void *, int64_t, int64_t, int,             \
                                      const Geometry &, Medium, const cx<T> *, const Node *, int, int, double, int,  \

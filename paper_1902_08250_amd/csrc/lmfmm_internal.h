@@ -355,13 +355,12 @@ struct PUnroll {
     static constexpr int n = PMAX <= 64 ? PMAX : 1;
 };
 
-template <typename T, int PMAX>
-__host__ __device__ inline void bessel_ratios(cx<T> k, T X, T Y, int P, cx<T> *tm, cx<T> &J0)
+// Start of the backward recurrence: starting at N with t_{N+1} = 0 perturbs
+// t_m by about prod_{j=m+1}^{N} |z|^2 / (4 j^2); take N so that this is below
+// the working precision at m = P.
+template <typename T>
+__host__ __device__ inline int miller_start(cx<T> z2, int P)
 {
-    cx<T> z2 = (k * k) * (X * X + Y * Y);
-    // Start of the backward recurrence: starting at N with t_{N+1} = 0 perturbs
-    // t_m by about prod_{j=m+1}^{N} |z|^2 / (4 j^2); take N so that this is
-    // below the working precision at m = P.
     const T a2 = sqrt(cabs2(z2)) * T(0.25);
     const T eps = sizeof(T) == 8 ? T(1e-17) : T(1e-8);
     int N = P;
@@ -371,28 +370,34 @@ __host__ __device__ inline void bessel_ratios(cx<T> k, T X, T Y, int P, cx<T> *t
         T f = a2 / T(N * N);
         prod *= f < T(1) ? f : T(1);
     }
-    cx<T> t = mk<T>(0, 0), tprev = mk<T>(0, 0);
-    // U = 2 sum_{even j >= max(m,2)} J_j / J_m, updated at every odd m:
-    // U_{m-1} = 2 [m-1 >= 2] + U_{m+1} z^2 t_{m+1} t_m.
-    cx<T> U = mk<T>(0, 0);
-    for (int m = N; m > P; --m) {
-        t = cinv(mk<T>(T(2 * m), T(0)) - z2 * t);
-        if (m & 1) {
-            U = U * (z2 * (tprev * t));
-            if (m - 1 >= 2) U.re += T(2);
-        }
-        tprev = t;
+    return N;
+}
+// One step m of the recurrence: t <- t_m, and U = 2 sum_{even j >= max(m,2)}
+// J_j / J_m updated at every odd m: U_{m-1} = 2 [m-1 >= 2] + U_{m+1} z^2
+// t_{m+1} t_m.  J_0 = 1 / (1 + U) after the step m = 1.
+template <typename T>
+__host__ __device__ inline void miller_step(cx<T> z2, int m, cx<T> &t, cx<T> &tprev, cx<T> &U)
+{
+    t = cinv(mk<T>(T(2 * m), T(0)) - z2 * t);
+    if (m & 1) {
+        U = U * (z2 * (tprev * t));
+        if (m - 1 >= 2) U.re += T(2);
     }
+    tprev = t;
+}
+
+template <typename T, int PMAX>
+__host__ __device__ inline void bessel_ratios(cx<T> k, T X, T Y, int P, cx<T> *tm, cx<T> &J0)
+{
+    cx<T> z2 = (k * k) * (X * X + Y * Y);
+    const int N = miller_start<T>(z2, P);
+    cx<T> t = mk<T>(0, 0), tprev = mk<T>(0, 0), U = mk<T>(0, 0);
+    for (int m = N; m > P; --m) miller_step<T>(z2, m, t, tprev, U);
 #pragma unroll PUnroll<PMAX>::n
     for (int m = PMAX; m >= 1; --m) {
         if (m <= P) {
-            t = cinv(mk<T>(T(2 * m), T(0)) - z2 * t);
+            miller_step<T>(z2, m, t, tprev, U);
             tm[m] = t;
-            if (m & 1) {
-                U = U * (z2 * (tprev * t));
-                if (m - 1 >= 2) U.re += T(2);
-            }
-            tprev = t;
         }
     }
     J0 = cinv(mk<T>(T(1), T(0)) + U);
@@ -503,11 +508,12 @@ void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int n
 // downward pass of level l: M2L (atab non-null; class slots of target row r:
 // row_off[r] .. row_off[r + 1], rows < nrt) and/or L2L from level l - 1
 // (l2l_tab non-null); add_rows: rows whose stored local expansion (M2L of an
-// earlier launch) is added to the L2L shift
+// earlier launch) is added to the L2L shift; rows_l2l: the L2L shift covers
+// rows below it only (-1: every row)
 template <typename T>
 void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, const int *row_off, int nrt,
                  const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, int add_rows,
-                 hipStream_t st);
+                 hipStream_t st, int rows_l2l = -1);
 // M2L of levels l0 .. l1 in one launch (entry l - l0 of each array: class
 // tables, class codes, row slot offsets, number of rows with classes; a null
 // table skips the level); the result is stored as the local expansion.
@@ -532,11 +538,36 @@ struct LeafShift {
     const cx<T> *Lp = nullptr;
     int ncp = 0, ncol_p = 0, col_lo_p = 0, rows_p = 0, add_rows = 0;
 };
+// The local expansions that the leaf evaluation reads.  on = 0: every leaf
+// evaluates its own expansion (level L).  on = 1: the downward pass shifts
+// every row down to level lc and, below it, only the rows with M2L classes
+// (row < nrt[l]) and their ancestors; a leaf evaluates the expansion of its
+// ancestor at the finest level e >= lc at which that ancestor has M2L
+// classes, else at lc.  Below e the downward pass adds nothing to the leaf's
+// ancestors, so that expansion holds the leaf's whole far field, and the L2L
+// shifts of the other rows are not needed.  Per level: the order, the columns
+// and the offset of its block of local expansions.
+struct EvalLevels {
+    int on = 0, lc = 0, L = 0;
+    int nrt[MAXLEV + 1] = {};
+    int P[MAXLEV + 1] = {};
+    int ncol[MAXLEV + 1] = {};
+    int64_t off[MAXLEV + 1] = {};
+};
+__host__ __device__ inline int eval_level(const EvalLevels &ev, int row)
+{
+    if (!ev.on) return ev.L;
+    for (int l = ev.L; l > ev.lc; --l)
+        if ((row >> (ev.L - l)) < ev.nrt[l]) return l;
+    return ev.lc;
+}
+// Lc: the local expansions of every level (ev.off[l] is level l's block)
 template <typename T>
 void launch_l2p_near(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, int64_t ns, int64_t nt, int nrhs, const Geometry &g,
-                     Medium med, const cx<T> *Lc, const LeafShift<T> &shift, const Node *nodes, int nmid, int npan,
-                     double t0, int do_far, int do_near, const cx<double> *unear, int nparts, void *u, hipStream_t st);
+                     Medium med, const cx<T> *Lc, const LeafShift<T> &shift, const EvalLevels &ev, const Node *nodes,
+                     int nmid, int npan, double t0, int do_far, int do_near, const cx<double> *unear, int nparts,
+                     void *u, hipStream_t st);
 template <typename T>
 void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,
                      const double *ys, const void *q, const void *cw, int64_t ns, int64_t nt, int nrhs,

@@ -241,6 +241,7 @@ struct lmfmm_plan_s {
     bool do_near = true, do_far = true;
     bool near_sweep = true;  // near field by x-ordered sweeps (else pairwise)
     bool m2l_mfma = true;    // M2L on the matrix cores (else vector matrix-vector products)
+    bool eval_levels = true; // leaves evaluate the expansion of the level where their far field is complete
 
     DevBuf ws;
     double *h_bbox = nullptr;  // pinned, host-coherent: [0..6] box, [8] sequence number, [12] error copy
@@ -902,6 +903,11 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         p->m2l_mfma = v == "1";
         return LMFMM_OK;
     }
+    if (k == "eval_levels") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "eval_levels must be 0 or 1");
+        p->eval_levels = v == "1";
+        return LMFMM_OK;
+    }
     if (k == "near" || k == "far") {
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "near/far must be 0 or 1");
         (k == "near" ? p->do_near : p->do_far) = v == "1";
@@ -1332,6 +1338,13 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
 
         // Step 2: upward pass
         LeafShift<T> shift;
+        // The leaf evaluation reads each leaf's expansion at the level where
+        // its far field is complete (the sweep or no near field: the packed
+        // evaluation kernel); the gradient and pairwise forms read the leaves'
+        // own expansions.
+        EvalLevels ev;
+        int rows_l2l[MAXLEV + 1] = {};
+        const bool eval_on = far && !gw && (sweep || !near_on || lv.rows_s == 0) && p->eval_levels;
         if (far) {
             timed(LMFMM_K_P2M, 1);
             set_stage(S_P2M);
@@ -1372,6 +1385,33 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             timed_done();
             // the leaf level's shift is done by the leaf evaluation (forward apply)
             const int l2l_last = (!gw && L > ltop) ? L - 1 : L;
+            if (eval_on) {
+                // Levels down to lc (the coarsest whose order is within two of
+                // the leaves') are shifted in every row; below it only the
+                // rows whose expansion is read: those with M2L classes, and
+                // the parents of the rows shifted one level finer.  A leaf
+                // evaluates at lc or at the finest level where its ancestor
+                // has M2L classes, if finer.
+                int lc = L;
+                for (int l = ltop; l <= L; ++l)
+                    if (g.lev[l].P <= g.lev[L].P + 2) {
+                        lc = l;
+                        break;
+                    }
+                ev.on = 1;
+                ev.lc = lc;
+                ev.L = L;
+                int need = L > ltop ? nrt[L - ltop] : 0;
+                for (int l = L; l >= ltop; --l) {
+                    const Level &lv2 = g.lev[l];
+                    ev.nrt[l] = l <= lc ? lv2.rows_t : nrt[l - ltop];
+                    ev.P[l] = lv2.P;
+                    ev.ncol[l] = lv2.ncol;
+                    ev.off[l] = lv2.off_t;
+                    if (l < L) need = std::max(ev.nrt[l], (need + 1) >> 1);
+                    rows_l2l[l] = l <= lc ? -1 : (l == L ? nrt[L - ltop] : need);
+                }
+            }
             if (l2l_last < L) {
                 const LevelTables &tl = vt.lt[L];
                 const Level &pv = g.lev[L - 1];
@@ -1389,7 +1429,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 timed(LMFMM_K_L2L, 1);
                 set_stage(S_L2L, l - ltop - 1);
                 launch_down<T>(g, l, (const cx<T> *)nullptr, nullptr, nullptr, 0, M, Lc, nrhs, l2l, false,
-                               nrt[l - ltop], sx);
+                               nrt[l - ltop], sx, eval_on ? rows_l2l[l] : -1);
                 timed_done();
             }
         }
@@ -1406,8 +1446,9 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             }
             timed(LMFMM_K_L2P, 1);
             set_stage(S_L2P);
-            launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, shift, nnodes, vt.n_nmid, vt.n_npan,
-                               vt.n_t0, far ? 1 : 0, near_on ? 1 : 0, nparts ? unear : nullptr, nparts, u, sx);
+            launch_l2p_near<T>(start, end, idx, xs, ys, q, ns, nt, nrhs, g, med, Lc, shift, ev, nnodes, vt.n_nmid,
+                               vt.n_npan, vt.n_t0, far ? 1 : 0, near_on ? 1 : 0, nparts ? unear : nullptr, nparts, u,
+                               sx);
             timed_done();
         } else {
             timed(LMFMM_K_L2P, 1);  // the first right-hand-side chunk
@@ -1688,7 +1729,7 @@ struct BatchLaunch {
 };
 
 struct TuneEntry {
-    int order = 0, levels = 0;
+    int order = 0, levels = 0, sweep = 1;
     double us = 0;
 };
 
@@ -1698,6 +1739,7 @@ struct lmfmm_batch_s {
     std::vector<int> order_set;
     double tol = 1e-6;
     bool tune = true, graph = true;
+    bool tune_near = true;  // the tuner also picks the near-field form (cleared when the caller sets it)
     std::string cache_path;  // tuning cache (one JSON object per line); empty: none
     // prepared state
     bool prepared = false;
@@ -1788,7 +1830,7 @@ static void read_tune_cache(const std::string &path, std::map<std::string, TuneE
     if (!f) return;
     char line[1024];
     while (std::fgets(line, sizeof line, f)) {
-        // {"key": "<key>", "order": o, "levels": L, "us": t}
+        // {"key": "<key>", "order": o, "levels": L, "us": t, "sweep": 0/1 (optional, default 1)}
         const char *k0 = std::strstr(line, "\"key\": \"");
         if (!k0) continue;
         k0 += 8;
@@ -1800,6 +1842,7 @@ static void read_tune_cache(const std::string &path, std::map<std::string, TuneE
         e.order = std::atoi(o + 9);
         e.levels = std::atoi(l + 10);
         e.us = std::atof(u + 6);
+        if (const char *sw = std::strstr(k1, "\"sweep\": ")) e.sweep = std::atoi(sw + 10) != 0;
         if (e.order < 1 || e.order > 256 || e.levels < 1 || e.levels > MAXLEV) continue;
         out[std::string(k0, k1)] = e;
     }
@@ -1812,8 +1855,8 @@ static void write_tune_cache(const std::string &path, const std::map<std::string
     FILE *f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
     for (const auto &kv : m)
-        std::fprintf(f, "{\"key\": \"%s\", \"order\": %d, \"levels\": %d, \"us\": %.3f}\n", kv.first.c_str(),
-                     kv.second.order, kv.second.levels, kv.second.us);
+        std::fprintf(f, "{\"key\": \"%s\", \"order\": %d, \"levels\": %d, \"us\": %.3f, \"sweep\": %d}\n",
+                     kv.first.c_str(), kv.second.order, kv.second.levels, kv.second.us, kv.second.sweep);
     const bool ok = std::fclose(f) == 0;
     if (ok) std::rename(tmp.c_str(), path.c_str());
 }
@@ -1961,11 +2004,12 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
         if ((rc = make_geometry(p, bb, in.n_src, nrhs, g0))) return rc;
         const std::string key = tune_key(b, p, in, nrhs, prec);
         auto hit = cache.find(key);
-        int bo = b->order_set.front(), bl = g0.L;
+        int bo = b->order_set.front(), bl = g0.L, bs = p->near_sweep ? 1 : 0;
         double best = 0.0;
         if (b->tune && hit != cache.end()) {
             bo = hit->second.order;
             bl = hit->second.levels;
+            if (b->tune_near) bs = hit->second.sweep;
             best = hit->second.us;
             b->from_cache[i] = 1;
         } else if (b->tune) {
@@ -1996,11 +2040,36 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
                     }
                 }
             if (best >= 1e300) return fail(LMFMM_ETOL, "no candidate order meets the tolerance");
-            cache[key] = TuneEntry{bo, bl, best};
+            if (b->tune_near) {
+                // the other near-field form at the chosen order and depth: the
+                // sweep is serial along x within a segment of leaf columns, so
+                // an instance with few, full interface columns can take longer
+                // than its pairwise sum
+                p->order = bo;
+                p->levels_opt = bl;
+                p->near_sweep = !bs;
+                rc = plan_apply_any(p, in, nrhs, prec, st);
+                if (rc) return rc;
+                const int reps = 3;
+                HIPCHK(hipEventRecord(e0, st));
+                for (int r = 0; r < reps && rc == LMFMM_OK; ++r) rc = plan_apply_any(p, in, nrhs, prec, st);
+                if (rc) return rc;
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                const double us = 1e3 * ms / reps;
+                if (us < best) {
+                    best = us;
+                    bs = !bs;
+                }
+            }
+            cache[key] = TuneEntry{bo, bl, bs, best};
             cache_dirty = true;
         }
         p->order = bo;
         p->levels_opt = b->tune ? bl : 0;
+        p->near_sweep = bs != 0;
         b->chosen_order[i] = bo;
         b->chosen_levels[i] = bl;
         b->chosen_us[i] = best;
@@ -2134,6 +2203,7 @@ int lmfmm_batch_set_option(lmfmm_batch b, const char *key, const char *value)
         return LMFMM_OK;
     }
     // any other key is forwarded to every instance's plan
+    if (k == "near_sweep") b->tune_near = false;
     for (auto p : b->plans) {
         int rc = lmfmm_set_option(p, key, value);
         if (rc) return rc;
@@ -2179,13 +2249,14 @@ int lmfmm_batch_apply(lmfmm_batch b, const lmfmm_instance *inst, int nrhs, int p
     return batch_launch_seq(b, st, false);
 }
 
-int lmfmm_batch_get_choice(lmfmm_batch b, int i, int *order, int *levels, double *us)
+int lmfmm_batch_get_choice(lmfmm_batch b, int i, int *order, int *levels, double *us, int *near_sweep)
 {
     if (!b || i < 0 || i >= b->n) return fail(LMFMM_EINVAL, "bad batch or index");
     if (!b->prepared) return fail(LMFMM_EINVAL, "batch not prepared yet");
     if (order) *order = b->chosen_order[i];
     if (levels) *levels = b->chosen_levels[i];
     if (us) *us = b->chosen_us[i];
+    if (near_sweep) *near_sweep = b->plans[i]->near_sweep ? 1 : 0;
     return LMFMM_OK;
 }
 

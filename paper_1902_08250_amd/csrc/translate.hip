@@ -75,6 +75,7 @@ struct DownArgs {
     int ncp, ncol_p, col_lo_p, rows_t_p;
     int has_l2l;
     int add_rows;  // rows whose stored local expansion (M2L of an earlier launch) is added to the L2L shift
+    int rows_l2l;  // the L2L shift covers rows below this one (the rest are never read)
 };
 
 // Downward pass of one level: L_box = L2L(parent's L) + sum over the box's
@@ -122,7 +123,7 @@ __device__ __forceinline__ void down_body(const DownK<T> &k, const int bx)
         step = DW;
     } else {
         box = (int64_t)a.nrt * a.ncol + (int64_t)(bx - a.nb_m2l) * DW + w;
-        if (box >= (int64_t)a.rows_t * a.ncol) return;  // whole wave; no block barrier on this path
+        if (box >= (int64_t)a.rows_l2l * a.ncol) return;  // whole wave; no block barrier on this path
         nitems = a.has_l2l;
         first = 0;
         step = 1;
@@ -423,7 +424,8 @@ void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int nrhs,
 
 template <typename T>
 void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, const int *row_off, int nrt,
-                 const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, int add_rows, hipStream_t st)
+                 const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, int add_rows, hipStream_t st,
+                 int rows_l2l)
 {
     const Level &lv = g.lev[l], &pv = g.lev[l - 1];
     DownArgs a;
@@ -441,7 +443,8 @@ void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, c
     a.rows_t_p = pv.rows_t;
     a.has_l2l = l2l_tab != nullptr;
     a.add_rows = add_rows;
-    int64_t rest = (int64_t)(lv.rows_t - a.nrt) * lv.ncol;
+    a.rows_l2l = rows_l2l < 0 || rows_l2l > lv.rows_t ? lv.rows_t : rows_l2l;
+    int64_t rest = (int64_t)(a.rows_l2l > a.nrt ? a.rows_l2l - a.nrt : 0) * lv.ncol;
     int64_t nblk = a.nb_m2l + (a.has_l2l ? (rest + DW - 1) / DW : 0);
     if (nblk == 0) return;
     const DownK<T> k{a, nrhs, Lc + pv.off_t, l2l_tab, Lc + lv.off_t, M + lv.off_s, atab, cls3, row_off};
@@ -494,7 +497,7 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
 #define LMFMM_INST(T)                                                                                               \
     template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int, hipStream_t);                   \
     template void launch_down<T>(const Geometry &, int, const cx<T> *, const int *, const int *, int, const cx<T> *, \
-                                 cx<T> *, int, const cx<T> *, bool, int, hipStream_t);                              \
+                                 cx<T> *, int, const cx<T> *, bool, int, hipStream_t, int);                         \
     template void launch_m2l_all<T>(const Geometry &, int, int, const cx<T> *const *, const int *const *,           \
                                     const int *const *, const int *, const cx<T> *, cx<T> *, int, bool,             \
                                     hipStream_t);

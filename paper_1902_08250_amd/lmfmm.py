@@ -95,7 +95,8 @@ def lib():
     L.lmfmm_batch_destroy.argtypes = [P]
     L.lmfmm_batch_set_option.argtypes = [P, ctypes.c_char_p, ctypes.c_char_p]
     L.lmfmm_batch_apply.argtypes = [P, ctypes.POINTER(Instance), I, I, P]
-    L.lmfmm_batch_get_choice.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]
+    L.lmfmm_batch_get_choice.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D),
+                                         ctypes.POINTER(I)]
     L.lmfmm_batch_sync_status.argtypes = [P, P]
     L.lmfmm_batch_get_stats.argtypes = [P, ctypes.POINTER(BatchStats)]
     L.lmfmm_status_string.argtypes = [I]
@@ -347,9 +348,10 @@ class Batch:
     def choices(self):
         out = []
         for i in range(self.n):
-            o, L_, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-            _check(lib().lmfmm_batch_get_choice(self._h, i, ctypes.byref(o), ctypes.byref(L_), ctypes.byref(us)))
-            out.append(dict(order=o.value, levels=L_.value, us=us.value))
+            o, L_, us, sw = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+            _check(lib().lmfmm_batch_get_choice(self._h, i, ctypes.byref(o), ctypes.byref(L_), ctypes.byref(us),
+                                                ctypes.byref(sw)))
+            out.append(dict(order=o.value, levels=L_.value, us=us.value, near_sweep=sw.value))
         return out
 
     def close(self):
