@@ -47,6 +47,7 @@ from paper_1902_08250_amd.prof_summary import source_hash  # noqa: E402
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
 GOLD = os.path.join(ROOT, "tests", "golden")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batched_16x4.md")
+UNIFORM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mixed_uniform_1e5.md")
 # algorithmic FP64 flops of the near-field sweep per (point, node, direction):
 # one complex exponential (range reductions and the exp and sin/cos
 # polynomials: 32) and one complex multiply-add (8)
@@ -64,23 +65,29 @@ def parse():
     ap.add_argument("--no-near", action="store_true", help="skip the near-interface leg")
     ap.add_argument("--only-near", action="store_true", help="run only the near-interface leg")
     ap.add_argument("--only-batched", action="store_true", help="run only the batched legs")
+    ap.add_argument("--only-uniform", action="store_true", help="run only the mixed uniform leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     return ap.parse_args()
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on the current kernel sources (else None)."""
+def recorded_traffic(prefix, path=TRAFFIC_FILE):
+    """HBM bytes per launch of the kernels whose names start with `prefix`
+    (averaged over their dispatches) from a committed counter summary, if it
+    was taken on the current kernel sources (else None)."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     m = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
     if not m or m.group(1) != source_hash():
         return None
-    m = re.search(r"^\|\s*%s\s*\|[^\n]*?\|\s*bytes_per_launch=([0-9.eE+]+)" % re.escape(kernel), text, re.M)
-    return float(m.group(1)) if m else None
+    tot, n = 0.0, 0
+    for m in re.finditer(r"^\|\s*%s[^|]*\|\s*(\d+)\s*\|[^\n]*?\|\s*bytes_per_launch=([0-9.eE+]+)" % re.escape(prefix),
+                         text, re.M):
+        tot += float(m.group(2)) * int(m.group(1))
+        n += int(m.group(1))
+    return tot / n if n else None
 
 
 def copy_probe(torch, mib):
@@ -98,9 +105,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def roofline(st, peak_key, kernel_names, bound="alu"):
+def roofline(st, peak_key, kernel_names, bound="alu", traffic_file=TRAFFIC_FILE):
     """Dominant kernel class of the timed applies against its peak:
-    achieved = algorithmic flops per launch / mean launch duration."""
+    achieved = algorithmic flops per launch / mean launch duration.  The tree
+    group (bounding box and tree build, HBM-bound) is reported apart
+    (tree_roofline)."""
     nap = max(1, st["timed_applies"])
     cand = {k: v for k, v in st["kernel_ms"].items() if k in kernel_names and st["kernel_launches"][k] > 0}
     dom = max(cand, key=cand.get)
@@ -109,11 +118,31 @@ def roofline(st, peak_key, kernel_names, bound="alu"):
     flops_launch = st["kernel_flops"][dom] / launches
     achieved = flops_launch / avg_s
     kname = kernel_names[dom]
-    traffic = recorded_traffic(kname)
+    traffic = recorded_traffic(kname, traffic_file)
     return {"kernel": kname, "class": dom, "bound": bound, "achieved": achieved / 1e12,
             "peak": PEAK[peak_key] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[peak_key],
             "traffic": traffic, "flops_per_launch": flops_launch, "launches_per_apply": launches,
             "avg_launch_us": avg_s * 1e6, "hbm_GBps_if_traffic": (traffic / avg_s / 1e9) if traffic else None}
+
+
+# algorithmic HBM bytes of the tree build per point (count: coordinates in,
+# leaf key and slot out; scatter: key and slot in, index out; leaf order:
+# index and coordinates in, grouped coordinates and index out), plus the
+# bounding box (coordinates in) when it is computed, plus each source's
+# densities read and written in grouped order
+TREE_BYTES_PER_POINT = (16 + 8) + (8 + 4) + (4 + 16 + 16 + 4)
+BBOX_BYTES_PER_POINT = 16
+
+
+def tree_roofline(st, n_points, n_sources, density_bytes, bbox):
+    nap = max(1, st["timed_applies"])
+    t = st["kernel_ms"]["tree"] / nap * 1e-3
+    if t <= 0:
+        return None
+    by = n_points * (TREE_BYTES_PER_POINT + (BBOX_BYTES_PER_POINT if bbox else 0)) + 2 * n_sources * density_bytes
+    return {"kernels": "bounding box and tree build (one group)", "bound": "hbm", "achieved": by / t / 1e9,
+            "peak": PEAK["hbm"] / 1e9, "unit": "GB/s", "frac": by / t / PEAK["hbm"], "bytes_per_apply": by,
+            "us_per_apply": t * 1e6}
 
 
 def time_batch(torch, b, items, outs, steps, warmup):
@@ -137,9 +166,10 @@ def time_batch(torch, b, items, outs, steps, warmup):
     return t, st
 
 
-BATCH_KERNELS = {"p2m": "k_p2m_multi<float, 16>", "m2m": "k_up_multi<float>", "m2l": "k_m2l_all_multi<float>",
-                 "l2l": "k_down_multi<float>", "near_sweep": "k_near_sweep_multi<float, 4>",
-                 "l2p_near": "k_l2p_multi<float, 16, 4>"}
+# kernel class -> name prefix of its merged kernels (every template instance)
+BATCH_KERNELS = {"p2m": "k_p2m_multi<float", "m2m": "k_up_multi<float", "m2l": "k_m2l_mfma_multi<float",
+                 "l2l": "k_down_multi<float", "near_sweep": "k_near_sweep_multi<float",
+                 "l2p_near": "k_l2p_multi<float"}
 
 
 def batched_legs(torch, args):
@@ -171,7 +201,9 @@ def batched_legs(torch, args):
         errs.append(rel(u[i][:, g["sel"]], g["u"]))
     out = {"value": inter / t, "ms_per_step": t * 1e3, "interactions_per_step": inter, "stats": st,
            "choices": b.choices(), "prepare_s_tuned": prep_tuned, "prepare_s_from_cache": prep_cached,
-           "rel_l2_max_vs_oracle_samples": max(errs), "roofline": roofline(st, "fp32", BATCH_KERNELS)}
+           "rel_l2_max_vs_oracle_samples": max(errs), "roofline": roofline(st, "fp32", BATCH_KERNELS),
+           "tree_roofline": tree_roofline(st, sum(d["src"].shape[1] + d["tgt"].shape[1] for d in inst),
+                                          sum(d["src"].shape[1] for d in inst), 8 * inst[0]["q"].shape[0], False)}
     if not args.no_fp64:
         items64 = [(s, dev(d["q"].astype(np.complex128)), tt) for (s, _, tt), d in zip(items, inst)]
         t0 = time.perf_counter()
@@ -209,8 +241,8 @@ def batched_legs(torch, args):
     return inst, out
 
 
-UNIFORM_KERNELS = {"p2m": "k_p2m<float, 16>", "m2m": "k_up<float>", "m2l": "k_m2l_all<float>", "l2l": "k_down<float>",
-                   "l2p_near": "k_l2p<float, 16, 1>"}
+UNIFORM_KERNELS = {"p2m": "k_p2m<float", "m2m": "k_up<float", "m2l": "k_m2l_mfma<float", "l2l": "k_down<float",
+                   "l2p_near": "k_l2p<float"}
 
 
 def run_plan(torch, Plan, w, precision, steps, warmup, timing=False, domain=None):
@@ -273,7 +305,8 @@ def uniform_leg(torch, Plan, args):
            "kernel_launches_per_apply": {k: v / nap for k, v in st["kernel_launches"].items() if v > 0},
            "graph_applies_in_timed_region": st["graph_applies"],
            "rel_l2_vs_oracle_samples": rel(u[:, g["sel"]].astype(np.complex128), g["u"]),
-           "roofline": roofline(st, "fp32", UNIFORM_KERNELS)}
+           "roofline": roofline(st, "fp32", UNIFORM_KERNELS, traffic_file=UNIFORM_TRAFFIC_FILE),
+           "tree_roofline": tree_roofline(st, w["n_src"] + w["n_tgt"], w["n_src"], 8 * w["nrhs"], True)}
     t_dom, u_dom, _, _ = run_plan(torch, Plan, w, "c64", args.steps, args.warmup, domain="0,1,1,-0.95")
     out["fixed_domain"] = {"value": inter / t_dom, "ms_per_step": t_dom * 1e3,
                            "max_abs_diff_vs_auto": float(np.max(np.abs(u_dom - u)))}
@@ -297,9 +330,9 @@ def near_leg(torch, Plan, args):
     nap = max(1, st["timed_applies"])
     sweep_s = st["kernel_ms"]["near_sweep"] / nap * 1e-3
     nodes = st["near_nodes_mid"] + 2 * st["near_nodes_ray"]
-    # every source and target is visited once per direction and node (the
-    # sweep's algorithmic work; all points lie in row-0 leaves here)
-    flops = (w["n_src"] + w["n_tgt"]) * nodes * 2 * SWEEP_FLOPS_PER_POINT_NODE_DIR * w["nrhs"]
+    # the plan's count: every point of the row-0 leaves once per direction and
+    # node (here all points)
+    flops = st["kernel_flops"]["near_sweep"]
     g = np.load(os.path.join(GOLD, "oracle_near_interface_2e5.npz"))
     return {"workload": w["name"], "n_src": w["n_src"], "n_tgt": w["n_tgt"], "order": w["order"],
             "levels": w["levels"], "tol": 1e-10, "dtype": "f64", "steps": n, "value": inter / t,
@@ -349,6 +382,9 @@ def main():
     from paper_1902_08250_amd.lmfmm import Plan
     if args.only_near:
         print(json.dumps({"near_interface": near_leg(torch, Plan, args)}), flush=True)
+        return
+    if args.only_uniform:
+        print(json.dumps({"mixed_uniform_1e5": uniform_leg(torch, Plan, args)[1]}), flush=True)
         return
     print(f"[bench] batched workload: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     inst, b = batched_legs(torch, args)

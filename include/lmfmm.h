@@ -209,7 +209,11 @@ typedef struct {
      *   kernel_flops: algorithmic real floating-point operations of the last
      *   apply (complex multiply-add = 8; translation and accumulation
      *   contractions counted over the box pairs and points the method
-     *   defines, basis evaluations at 60 P per point);
+     *   defines, basis evaluations at 60 P per point; the near-field sweep
+     *   at 32 per complex exponential plus 8 per right-hand side for every
+     *   point of the interface leaves, node and sweep direction).  The leaf
+     *   evaluation and sweep counts depend on the leaves' populations:
+     *   lmfmm_get_stats reads them back and then synchronizes the device;
      * with the "timing" option, summed over the timed applies:
      *   kernel_ms: event-measured duration, kernel_launches: launches.     */
     double kernel_flops[8];

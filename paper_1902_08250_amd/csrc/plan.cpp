@@ -261,6 +261,21 @@ struct lmfmm_plan_s {
 
     Geometry geo;
     lmfmm_stats stats;
+    // Work counts that depend on how the points fall into the leaves (the
+    // leaf evaluation at its levels, the near-field sweep over the row-0
+    // leaves): the last apply's leaf ranges are read back when the
+    // statistics are asked for.
+    struct DeferredWork {
+        bool pending = false;
+        const int32_t *start = nullptr, *end = nullptr;
+        int64_t key_t0 = 0;
+        int ncol = 0, rows_t = 0, nrhs = 0, nodes = 0;
+        bool sweep = false, eval = false;
+        EvalLevels ev;
+        int nc_shift = 0;  // parent order of the leaf-level shift (0: none)
+    } dw;
+    EvalLevels last_ev;           // evaluation levels of the last launch sequence
+    int last_rows_l2l[MAXLEV + 1] = {};
     int32_t *d_err = nullptr;  // device error flags of the last apply (in the workspace)
     bool err_valid = false;    // the last apply built a tree (and so wrote d_err[1])
     // the workspace prefix holding the error flags and leaf counters, zeroed
@@ -747,6 +762,8 @@ static int ensure_near_table(VarTables &vt, const Medium &med, const Geometry &g
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+static void resolve_work(lmfmm_plan_s *p);
+
 extern "C" {
 
 const char *lmfmm_status_string(int s)
@@ -957,6 +974,7 @@ int lmfmm_get_stats(lmfmm_plan p, lmfmm_stats *s)
 {
     if (!p || !s) return fail(LMFMM_EINVAL, "null argument");
     collect_timing(p);
+    resolve_work(p);
     *s = p->stats;
     return LMFMM_OK;
 }
@@ -1112,41 +1130,108 @@ static void m2l_pair_counts(lmfmm_plan_s *p, const VarTables &vt, const Geometry
 
 // Algorithmic floating-point work of one apply per kernel (complex
 // multiply-add = 8 real operations; Bessel/exponential basis of order P at
-// 60 P per point).
+// 60 P per point; the near-field sweep at 32 per complex exponential plus 8
+// per right-hand side, for every point of the row-0 leaves, node and
+// direction).  The parts that depend on how the points fall into the leaves
+// are completed by resolve_work (the statistics call).
 static void count_flops(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g, bool far, int64_t ns, int64_t nt,
-                        int nrhs, bool grad)
+                        int nrhs, bool grad, bool sweep, const int32_t *start, const int32_t *end)
 {
     double *f = p->stats.kernel_flops;
     for (int i = 0; i < 8; ++i) f[i] = 0;
     p->stats.m2l_pairs = 0;
+    auto &dw = p->dw;
+    dw = lmfmm_plan_s::DeferredWork();
+    const int L = g.L, ltop = g.ltop;
+    const Level &lf = g.lev[L];
+    dw.start = start;
+    dw.end = end;
+    dw.key_t0 = (int64_t)lf.rows_s * lf.ncol;
+    dw.ncol = lf.ncol;
+    dw.rows_t = lf.rows_t;
+    dw.nrhs = nrhs;
+    dw.sweep = sweep && !grad;
+    dw.nodes = vt.n_nmid + 2 * NGL * vt.n_npan;
+    dw.pending = dw.sweep;
     if (!far) return;
     m2l_pair_counts(p, vt, g);
-    const int L = g.L, ltop = g.ltop;
     const double R = nrhs;
-    const Level &lf = g.lev[L];
     f[LMFMM_K_P2M] = (double)ns * (60.0 * lf.P + 8.0 * lf.nc * R);
     for (int l = L; l >= ltop + 1; --l) {
         const Level &c = g.lev[l], &pa = g.lev[l - 1];
         f[LMFMM_K_M2M] += (double)pa.rows_s * pa.ncol * 4.0 * c.nc * pa.nc * 8.0 * R;
     }
     int64_t pairs = 0;
+    const EvalLevels &ev = p->last_ev;
+    const bool eval = ev.on && !grad;
     for (int l = ltop; l <= L; ++l) {
         const Level &lv = g.lev[l], &pa = g.lev[l - 1];
         pairs += p->pair_count[l];
         f[LMFMM_K_DOWN] += 8.0 * R * (double)p->pair_count[l] * lv.nc * lv.nc;
-        if (l > ltop) f[LMFMM_K_L2L] += 8.0 * R * (double)pa.rows_t * pa.ncol * 4.0 * pa.nc * lv.nc;
+        if (l > ltop && l < L) {
+            // boxes shifted at level l: every row, or with evaluation levels
+            // the rows whose expansions are read
+            const int rows = eval && p->last_rows_l2l[l] >= 0 ? std::min(p->last_rows_l2l[l], lv.rows_t) : lv.rows_t;
+            f[LMFMM_K_L2L] += 8.0 * R * (double)rows * lv.ncol * pa.nc * lv.nc;
+        }
     }
     p->stats.m2l_pairs = pairs;
     if (grad) {
+        if (L > ltop) f[LMFMM_K_L2L] += 8.0 * R * (double)lf.rows_t * lf.ncol * g.lev[L - 1].nc * lf.nc;
         f[LMFMM_K_L2P] = (double)nt * (60.0 * (lf.P + 1) + 3.0 * 8.0 * (lf.nc + 2) * R);
-    } else {
-        f[LMFMM_K_L2P] = (double)nt * (60.0 * lf.P + 8.0 * lf.nc * R);
-        if (L > ltop) {  // the leaf level's L2L runs inside the leaf evaluation
-            const Level &pa = g.lev[L - 1];
-            const double wl = 8.0 * R * (double)pa.rows_t * pa.ncol * 4.0 * pa.nc * lf.nc;
-            f[LMFMM_K_L2L] -= wl;
-            f[LMFMM_K_L2P] += wl;
+        return;
+    }
+    // the leaf evaluation (with the leaf-level shift inside it): per target,
+    // the basis and contraction of the expansion it evaluates
+    dw.eval = true;
+    dw.ev = ev;
+    if (!ev.on) {
+        dw.ev.L = L;
+        dw.ev.P[L] = lf.P;
+    }
+    dw.nc_shift = L > ltop ? g.lev[L - 1].nc : 0;
+    dw.pending = true;
+}
+
+// Completes the leaf-count-dependent work counts of the last apply (reads the
+// leaf ranges back; synchronizes the device).
+static void resolve_work(lmfmm_plan_s *p)
+{
+    auto &dw = p->dw;
+    if (!dw.pending) return;
+    dw.pending = false;
+    const int64_t nb = (int64_t)dw.rows_t * dw.ncol;
+    if (nb <= 0 || !dw.start || !dw.end) return;
+    std::vector<int32_t> st(nb), en(nb);
+    if (hipDeviceSynchronize() != hipSuccess) return;
+    if (hipMemcpy(st.data(), dw.start + dw.key_t0, nb * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+    if (hipMemcpy(en.data(), dw.end + dw.key_t0, nb * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+    double *f = p->stats.kernel_flops;
+    const double R = dw.nrhs;
+    if (dw.eval) {
+        const EvalLevels &ev = dw.ev;
+        const int L = ev.L;
+        double fl = 0.0;
+        for (int r = 0; r < dw.rows_t; ++r) {
+            const int e = eval_level(ev, r), P = ev.P[e], ncl = 2 * ev.P[L] + 1;
+            for (int c = 0; c < dw.ncol; ++c) {
+                const int64_t b = (int64_t)r * dw.ncol + c;
+                const int64_t n = en[b] - st[b];
+                if (n <= 0) continue;
+                fl += (double)n * (60.0 * P + 8.0 * (2 * P + 1) * R);
+                if (e == L && dw.nc_shift) fl += 8.0 * R * dw.nc_shift * ncl;  // the leaf's shift
+            }
         }
+        f[LMFMM_K_L2P] = fl;
+    }
+    if (dw.sweep) {
+        // points of the row-0 leaves: targets from these ranges, sources from
+        // the source keys 0 .. ncol - 1 (the ranges are contiguous in key order)
+        int32_t s0 = 0, s1 = 0;
+        if (hipMemcpy(&s0, dw.start, 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+        if (hipMemcpy(&s1, dw.end + dw.ncol - 1, 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+        const int64_t n0 = (int64_t)(s1 - s0) + (en[dw.ncol - 1] - st[0]);
+        f[LMFMM_K_SWEEP] = (double)n0 * dw.nodes * 2.0 * (32.0 + 8.0 * R);
     }
 }
 
@@ -1433,6 +1518,8 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 timed_done();
             }
         }
+        p->last_ev = ev;
+        for (int l = 0; l <= MAXLEV; ++l) p->last_rows_l2l[l] = rows_l2l[l];
         // Step 4: local evaluation and direct interactions
         const Node *nnodes = (const Node *)vt.near_nodes.p;
         int nparts = 0;
@@ -1549,7 +1636,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     s.m2l_classes = ncls;
     s.m2l_nodes = nn;
     s.table_seconds = vt.table_seconds;
-    count_flops(p, vt, g, far, ns, nt, nrhs, gw != nullptr);
+    count_flops(p, vt, g, far, ns, nt, nrhs, gw != nullptr, sweep, start, end);
     return LMFMM_OK;
 }
 
@@ -2013,52 +2100,70 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
             best = hit->second.us;
             b->from_cache[i] = 1;
         } else if (b->tune) {
-            std::vector<int> Ls;
-            for (int dl = -1; dl <= 1; ++dl)
-                if (g0.L + dl >= 1 && g0.L + dl <= MAXLEV) Ls.push_back(g0.L + dl);
-            best = 1e300;
-            for (int o : b->order_set)
-                for (int L : Ls) {
-                    p->order = o;
-                    p->levels_opt = L;
-                    rc = plan_apply_any(p, in, nrhs, prec, st);  // builds tables
-                    if (rc == LMFMM_ETOL) continue;
-                    if (rc) return rc;
-                    const int reps = 3;
-                    HIPCHK(hipEventRecord(e0, st));
-                    for (int r = 0; r < reps && rc == LMFMM_OK; ++r) rc = plan_apply_any(p, in, nrhs, prec, st);
-                    if (rc) return rc;
-                    HIPCHK(hipEventRecord(e1, st));
-                    HIPCHK(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                    const double us = 1e3 * ms / reps;
-                    if (us < best) {
-                        best = us;
-                        bo = o;
-                        bl = L;
-                    }
-                }
-            if (best >= 1e300) return fail(LMFMM_ETOL, "no candidate order meets the tolerance");
-            if (b->tune_near) {
-                // the other near-field form at the chosen order and depth: the
-                // sweep is serial along x within a segment of leaf columns, so
-                // an instance with few, full interface columns can take longer
-                // than its pairwise sum
-                p->order = bo;
-                p->levels_opt = bl;
-                p->near_sweep = !bs;
-                rc = plan_apply_any(p, in, nrhs, prec, st);
-                if (rc) return rc;
+            // time one candidate: a first apply builds its tables, a second
+            // captures its launch sequence, then the replays are timed
+            auto time_candidate = [&](double &us) -> int {
+                int r = plan_apply_any(p, in, nrhs, prec, st);
+                if (r) return r;
+                if ((r = plan_apply_any(p, in, nrhs, prec, st))) return r;
                 const int reps = 3;
                 HIPCHK(hipEventRecord(e0, st));
-                for (int r = 0; r < reps && rc == LMFMM_OK; ++r) rc = plan_apply_any(p, in, nrhs, prec, st);
-                if (rc) return rc;
+                for (int k = 0; k < reps && r == LMFMM_OK; ++k) r = plan_apply_any(p, in, nrhs, prec, st);
+                if (r) return r;
                 HIPCHK(hipEventRecord(e1, st));
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                const double us = 1e3 * ms / reps;
+                us = 1e3 * ms / reps;
+                return LMFMM_OK;
+            };
+            // per order floor, the depth by descent from the automatic one:
+            // deeper while that is faster, else shallower while faster
+            best = 1e300;
+            for (int o : b->order_set) {
+                p->order = o;
+                std::map<int, double> seen;
+                auto at = [&](int L, double &us) -> int {
+                    auto it = seen.find(L);
+                    if (it != seen.end()) {
+                        us = it->second;
+                        return LMFMM_OK;
+                    }
+                    p->levels_opt = L;
+                    int r = time_candidate(us);
+                    if (r == LMFMM_ETOL) us = 1e300, r = LMFMM_OK;
+                    if (!r) seen[L] = us;
+                    return r;
+                };
+                int Lb = g0.L;
+                double ub = 0.0;
+                if ((rc = at(Lb, ub))) return rc;
+                for (int dir = 1; dir >= -1; dir -= 2) {
+                    bool moved = false;
+                    while (Lb + dir >= 1 && Lb + dir <= std::min(MAXLEV, g0.L + 6)) {
+                        double un = 0.0;
+                        if ((rc = at(Lb + dir, un))) return rc;
+                        if (!(un < ub)) break;
+                        Lb += dir;
+                        ub = un;
+                        moved = true;
+                    }
+                    if (moved) break;
+                }
+                if (ub < best) {
+                    best = ub;
+                    bo = o;
+                    bl = Lb;
+                }
+            }
+            if (best >= 1e300) return fail(LMFMM_ETOL, "no candidate order meets the tolerance");
+            if (b->tune_near) {
+                // the other near-field form at the chosen order and depth
+                p->order = bo;
+                p->levels_opt = bl;
+                p->near_sweep = !bs;
+                double us = 0.0;
+                if ((rc = time_candidate(us))) return rc;
                 if (us < best) {
                     best = us;
                     bs = !bs;
@@ -2087,8 +2192,10 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
     // pass counted it), merged launches per apply
     for (int k = 0; k < 8; ++k) b->stats.kernel_flops[k] = 0.0;
     for (int i = 0; i < b->n; ++i)
-        if (inst[i].n_tgt > 0 && inst[i].n_src > 0)
+        if (inst[i].n_tgt > 0 && inst[i].n_src > 0) {
+            resolve_work(b->plans[i]);  // the leaf ranges of the warm apply (the recording launched nothing)
             for (int k = 0; k < 8; ++k) b->stats.kernel_flops[k] += b->plans[i]->stats.kernel_flops[k];
+        }
     b->stats.launches = (int)b->seq.size();
     b->stats.instances = b->n;
     int ncache = 0;
