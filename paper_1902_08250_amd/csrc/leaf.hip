@@ -88,36 +88,67 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
         }
         __syncthreads();
         const int cend = E - c0 < CH ? E : c0 + CH;
-        for (int it = t; it < nitem; it += P2M_THREADS) {
-            const int g = it / nout, o = it - g * nout;
-            const int r = o / nc, c = o - r * nc;
+        // the chunk's leaves: those ending after c0 or starting at or after
+        // it, up to the last starting before cend (every remaining leaf for
+        // the last chunk); a leaf starting in the chunk (empty leaves
+        // included) is written, one continuing into it is added to
+        int glo = 0;
+        while (glo < ng && bnd[glo + 1] <= c0 && bnd[glo] < c0) ++glo;
+        int ghi = ng - 1;
+        if (cend < E)
+            while (ghi >= glo && bnd[ghi] >= cend) --ghi;
+        // items (leaf, chunk of up to four right-hand sides, coefficient):
+        // one basis value read per point serves every right-hand side of the
+        // chunk
+        const int nrc = (nrhs + 3) >> 2, nout4 = nrc * nc;
+        const int nit = (ghi - glo + 1) * nout4;
+        for (int it0 = t; it0 < nit; it0 += P2M_THREADS) {
+            const int it = glo * nout4 + it0;
+            const int g = it / nout4, o = it - g * nout4;
+            const int rc = o / nc, c = o - rc * nc;
+            const int r0 = rc * 4, nr = nrhs - r0 < 4 ? nrhs - r0 : 4;
             const int j0 = bnd[g] > c0 ? bnd[g] : c0, j1 = bnd[g + 1] < cend ? bnd[g + 1] : cend;
             // in increasing point order; four points' LDS reads issued together
-            const cx<T> *bp = B + (j0 - c0) * nc + c, *qp = Q + (j0 - c0) * nrhs + r;
+            const cx<T> *bp = B + (j0 - c0) * nc + c, *qp = Q + (j0 - c0) * nrhs + r0;
             const int np = j1 - j0;
             // groups of four points summed plainly, the groups' sums added
             // with compensation (FP32: the error does not grow with the
             // leaf's point count)
-            CAcc<T> acc;
-            acc.zero();
+            CAcc<T> acc[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r].zero();
             int jj = 0;
             for (; jj + 4 <= np; jj += 4) {
                 const cx<T> b0 = bp[jj * nc], b1 = bp[(jj + 1) * nc], b2 = bp[(jj + 2) * nc], b3 = bp[(jj + 3) * nc];
-                const cx<T> q0 = qp[jj * nrhs], q1 = qp[(jj + 1) * nrhs], q2 = qp[(jj + 2) * nrhs],
-                            q3 = qp[(jj + 3) * nrhs];
-                cx<T> g4 = b0 * q0;
-                cfma(g4, b1, q1);
-                cfma(g4, b2, q2);
-                cfma(g4, b3, q3);
-                acc.add(g4);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < nr) {
+                        cx<T> g4 = b0 * qp[jj * nrhs + r];
+                        cfma(g4, b1, qp[(jj + 1) * nrhs + r]);
+                        cfma(g4, b2, qp[(jj + 2) * nrhs + r]);
+                        cfma(g4, b3, qp[(jj + 3) * nrhs + r]);
+                        acc[r].add(g4);
+                    }
             }
-            cx<T> g4 = mk<T>(0, 0);
-            for (; jj < np; ++jj) cfma(g4, bp[jj * nc], qp[jj * nrhs]);
-            acc.add(g4);
-            if (c0 == S)
-                Mb[it] = acc.value();
-            else if (j1 > j0)
-                Mb[it] += acc.value();
+            cx<T> g4[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g4[r] = mk<T>(0, 0);
+            for (; jj < np; ++jj) {
+                const cx<T> bj = bp[jj * nc];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < nr) cfma(g4[r], bj, qp[jj * nrhs + r]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < nr) {
+                    acc[r].add(g4[r]);
+                    cx<T> &dst = Mb[(int64_t)g * nout + (r0 + r) * nc + c];
+                    if (bnd[g] >= c0)
+                        dst = acc[r].value();
+                    else if (j1 > j0)
+                        dst += acc[r].value();
+                }
         }
         __syncthreads();
     }

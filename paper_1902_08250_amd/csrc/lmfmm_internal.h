@@ -232,6 +232,22 @@ __device__ inline cx<float> cinv(cx<float> a)
     const float s = fmaf(fmaf(-d, r, 1.0f), r, r);
     return {a.re * s, -a.im * s};
 }
+// FP64: on the device the hardware reciprocal refined by two Newton steps
+// (each about doubles the correct bits), without the IEEE division's scaling
+// and fix-up steps (|a|^2 here stays far from the overflow and underflow
+// thresholds); on the host the division.
+__host__ __device__ inline cx<double> cinv(cx<double> a)
+{
+    const double d = a.re * a.re + a.im * a.im;
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+#else
+    const double r = 1.0 / d;
+#endif
+    return {a.re * r, -a.im * r};
+}
 template <typename T>
 __host__ __device__ inline cx<T> cdiv(cx<T> a, cx<T> b) { return a * cinv(b); }
 template <typename T>
