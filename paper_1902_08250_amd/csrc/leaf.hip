@@ -45,6 +45,7 @@ struct P2MArgs {
     T invR;
     int G, CH;
     cx<T> *M;
+    int32_t *occ;  // the leaves' occupancy flags
 };
 template <typename T, int PMAX>
 __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
@@ -70,8 +71,9 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
     const int ng = nbox - b0 < G ? nbox - b0 : G;
     if (t <= ng) bnd[t] = t < ng ? start[b0 + t] : end[b0 + ng - 1];
     __syncthreads();
+    if (t < ng) A.occ[b0 + t] = bnd[t + 1] > bnd[t] ? 1 : 0;
     const int S = bnd[0], E = bnd[ng];
-    const int nout = nc * nrhs, nitem = ng * nout;
+    const int nout = nc * nrhs;
     cx<T> *Mb = M + (int64_t)b0 * nout;
     for (int c0 = S; c0 < E || c0 == S; c0 += CH) {
         for (int jl = t; jl < CH; jl += P2M_THREADS) {
@@ -728,7 +730,7 @@ inline int leaves_per_block(int64_t nbox, int64_t npts, int threads, int max_per
 
 template <typename T, int PMAX>
 void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
-                  int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
+                  int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, hipStream_t st)
 {
     const Level &lv = g.lev[g.L];
     int nbox = lv.rows_s * lv.ncol;
@@ -749,7 +751,7 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
     cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
     const P2MArgs<T> a{start, end, xs, ys, reinterpret_cast<const cx<T> *>(qs), ns, nrhs, lv.P, nbox, lv.ncol,
-                       lv.col_lo, g.x_lo, lv.w, k1, invR, G, CH, M + lv.off_s};
+                       lv.col_lo, g.x_lo, lv.w, k1, invR, G, CH, M + lv.off_s, occ + lv.off_occ};
     emit((const void *)k_p2m<T, PMAX>, (const void *)k_p2m_multi<T, PMAX>, 0, dim3((nbox + G - 1) / G),
          dim3(P2M_THREADS), sh, st, a);
 }
@@ -861,17 +863,17 @@ void grad_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx,
 
 template <typename T>
 void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
-                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st)
+                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, hipStream_t st)
 {
     int P = g.lev[g.L].P;
     if (P <= 16)
-        p2m_dispatch<T, 16>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
+        p2m_dispatch<T, 16>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
     else if (P <= 32)
-        p2m_dispatch<T, 32>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
+        p2m_dispatch<T, 32>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
     else if (P <= 64)
-        p2m_dispatch<T, 64>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
+        p2m_dispatch<T, 64>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
     else
-        p2m_dispatch<T, 256>(start, end, xs, ys, qs, ns, nrhs, g, med, M, st);
+        p2m_dispatch<T, 256>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
 }
 
 template <typename T>
@@ -922,7 +924,7 @@ void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *id
 
 #define LMFMM_INST(T)                                                                                               \
     template void launch_p2m<T>(const int32_t *, const int32_t *, const double *, const double *, const void *,      \
-                                int64_t, int, const Geometry &, Medium, cx<T> *, hipStream_t);                      \
+                                int64_t, int, const Geometry &, Medium, cx<T> *, int32_t *, hipStream_t);           \
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
                                      const cx<T> *, const LeafShift<T> &, const EvalLevels &, const Node *, int,    \

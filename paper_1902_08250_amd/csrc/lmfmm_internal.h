@@ -457,6 +457,7 @@ struct Level {
     double w;        // box width
     int64_t off_s;   // offset (in complex elements) of this level's multipole block
     int64_t off_t;   // offset of this level's local block
+    int64_t off_occ; // offset of this level's source-box occupancy flags
 };
 
 struct Geometry {
@@ -465,6 +466,7 @@ struct Geometry {
     int ltop;  // coarsest level carrying expansions (M2L among all its non-adjacent boxes)
     Level lev[MAXLEV + 1];
     int64_t ncoef_s, ncoef_t;  // total complex coefficients (times nrhs)
+    int64_t nocc_s;            // source boxes over all levels (one occupancy flag each)
 };
 
 // Near-field node record (FP64): lambda, the source-side and target-side
@@ -517,10 +519,12 @@ void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 
 // expand.hip (T = double or float)
 template <typename T>
+// (occ: the source-box occupancy flags of every level, Level::off_occ; P2M
+// writes the leaves', M2M the parents')
 void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
-                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, hipStream_t st);
+                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, hipStream_t st);
 template <typename T>
-void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int nrhs, hipStream_t st);
+void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int32_t *occ, int nrhs, hipStream_t st);
 // downward pass of level l: M2L (atab non-null; class slots of target row r:
 // row_off[r] .. row_off[r + 1], rows < nrt) and/or L2L from level l - 1
 // (l2l_tab non-null); add_rows: rows whose stored local expansion (M2L of an
@@ -538,7 +542,7 @@ void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, c
 template <typename T>
 void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab, const int *const *cls3,
                     const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, bool mfma,
-                    hipStream_t st);
+                    const int32_t *occ, hipStream_t st);
 // returns the number of node parts written to unear ([part][rhs][target])
 template <typename T>
 int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,

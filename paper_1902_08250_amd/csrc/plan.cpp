@@ -266,13 +266,13 @@ struct lmfmm_plan_s {
     // leaves): the last apply's leaf ranges are read back when the
     // statistics are asked for.
     struct DeferredWork {
-        bool pending = false;
-        const int32_t *start = nullptr, *end = nullptr;
-        int64_t key_t0 = 0;
-        int ncol = 0, rows_t = 0, nrhs = 0, nodes = 0;
-        bool sweep = false, eval = false;
+        bool pending = false, far = false, grad = false, sweep = false;
+        const int32_t *start = nullptr, *end = nullptr;  // leaf ranges (source keys, then target keys)
+        Geometry g;
+        std::vector<std::vector<int>> cls;  // class codes per level
         EvalLevels ev;
-        int nc_shift = 0;  // parent order of the leaf-level shift (0: none)
+        int rows_l2l[MAXLEV + 1] = {};
+        int nrhs = 0, nodes = 0;
     } dw;
     EvalLevels last_ev;           // evaluation levels of the last launch sequence
     int last_rows_l2l[MAXLEV + 1] = {};
@@ -316,8 +316,6 @@ struct lmfmm_plan_s {
     uint64_t cfg_version = 0;  // bumped by every set_option call
 
     // cached M2L pair counts per level for the last geometry
-    std::vector<int64_t> pair_key;
-    int64_t pair_count[MAXLEV + 1] = {0};
 };
 
 // Fold the events of the previous timed apply into the statistics.
@@ -456,6 +454,13 @@ static int make_geometry(lmfmm_plan_s *p, const double *bb, int64_t ns, int nrhs
     }
     g.ncoef_s = offs;
     g.ncoef_t = offt;
+    int64_t nocc = 0;
+    for (int l = 1; l <= L; ++l) {
+        g.lev[l].off_occ = nocc;
+        nocc += (int64_t)g.lev[l].rows_s * g.lev[l].ncol;
+    }
+    g.lev[0].off_occ = 0;
+    g.nocc_s = nocc;
     return LMFMM_OK;
 }
 
@@ -1092,48 +1097,13 @@ static int get_bbox(lmfmm_plan p, const Medium &med, int64_t ns, const double *s
     return bbox_wait(p, st, bb);
 }
 
-// One pass of Algorithm 1 for the operator of orientation adj (0: forward,
-// 1: transposed in mirrored coordinates).  With gw == nullptr the field of the
-// densities q is written to u; otherwise the target-side coordinate gradient of
-// Re sum gw * field is written to gout ([2][nt], y component times ysign).
-// Box pairs that M2L translates at level l: for each class slot (target row,
-// source row, column offset), the target columns whose source box exists and,
-// below the coarsest expansion level, whose parents are adjacent (the
-// interaction list).  Cached for the last geometry.
-static void m2l_pair_counts(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g)
-{
-    std::vector<int64_t> key = {g.L, g.ltop};
-    for (int l = g.ltop; l <= g.L; ++l) {
-        const Level &lv = g.lev[l];
-        key.insert(key.end(), {lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, vt.lt[l].nslots});
-    }
-    if (key == p->pair_key) return;
-    p->pair_key = key;
-    for (int l = 0; l <= MAXLEV; ++l) p->pair_count[l] = 0;
-    for (int l = g.ltop; l <= g.L; ++l) {
-        const Level &lv = g.lev[l];
-        const std::vector<int> &c3 = vt.lt[l].clsof_host;
-        int64_t cnt = 0;
-        for (int sl = 0; sl < vt.lt[l].nslots; ++sl) {
-            int rt = c3[3 * sl], rs = c3[3 * sl + 1], dc = c3[3 * sl + 2];
-            if (rt >= lv.rows_t || rs >= lv.rows_s) continue;
-            for (int b = 0; b < lv.ncol; ++b) {
-                int col = lv.col_lo + b, cs = col + dc, csl = cs - lv.col_lo;
-                if (csl < 0 || csl >= lv.ncol) continue;
-                int dp = (cs >> 1) - (col >> 1);
-                if (l == g.ltop || (dp >= -1 && dp <= 1)) ++cnt;
-            }
-        }
-        p->pair_count[l] = cnt;
-    }
-}
-
 // Algorithmic floating-point work of one apply per kernel (complex
 // multiply-add = 8 real operations; Bessel/exponential basis of order P at
 // 60 P per point; the near-field sweep at 32 per complex exponential plus 8
 // per right-hand side, for every point of the row-0 leaves, node and
-// direction).  The parts that depend on how the points fall into the leaves
-// are completed by resolve_work (the statistics call).
+// direction).  Translations count only boxes that hold points (source boxes
+// with sources, target boxes with targets): the statistics call completes
+// the counts from the leaf populations of the apply (resolve_work).
 static void count_flops(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g, bool far, int64_t ns, int64_t nt,
                         int nrhs, bool grad, bool sweep, const int32_t *start, const int32_t *end)
 {
@@ -1142,99 +1112,140 @@ static void count_flops(lmfmm_plan_s *p, const VarTables &vt, const Geometry &g,
     p->stats.m2l_pairs = 0;
     auto &dw = p->dw;
     dw = lmfmm_plan_s::DeferredWork();
-    const int L = g.L, ltop = g.ltop;
-    const Level &lf = g.lev[L];
+    const Level &lf = g.lev[g.L];
     dw.start = start;
     dw.end = end;
-    dw.key_t0 = (int64_t)lf.rows_s * lf.ncol;
-    dw.ncol = lf.ncol;
-    dw.rows_t = lf.rows_t;
+    dw.g = g;
+    dw.far = far;
+    dw.grad = grad;
     dw.nrhs = nrhs;
     dw.sweep = sweep && !grad;
     dw.nodes = vt.n_nmid + 2 * NGL * vt.n_npan;
-    dw.pending = dw.sweep;
+    dw.pending = dw.sweep || far;
     if (!far) return;
-    m2l_pair_counts(p, vt, g);
-    const double R = nrhs;
-    f[LMFMM_K_P2M] = (double)ns * (60.0 * lf.P + 8.0 * lf.nc * R);
-    for (int l = L; l >= ltop + 1; --l) {
-        const Level &c = g.lev[l], &pa = g.lev[l - 1];
-        f[LMFMM_K_M2M] += (double)pa.rows_s * pa.ncol * 4.0 * c.nc * pa.nc * 8.0 * R;
+    f[LMFMM_K_P2M] = (double)ns * (60.0 * lf.P + 8.0 * lf.nc * nrhs);
+    if (grad) f[LMFMM_K_L2P] = (double)nt * (60.0 * (lf.P + 1) + 3.0 * 8.0 * (lf.nc + 2) * nrhs);
+    dw.cls.assign(MAXLEV + 1, std::vector<int>());
+    for (int l = g.ltop; l <= g.L; ++l) dw.cls[l] = vt.lt[l].clsof_host;
+    dw.ev = p->last_ev;
+    if (!dw.ev.on || grad) {
+        dw.ev = EvalLevels();
+        dw.ev.L = g.L;
+        dw.ev.P[g.L] = lf.P;
     }
-    int64_t pairs = 0;
-    const EvalLevels &ev = p->last_ev;
-    const bool eval = ev.on && !grad;
-    for (int l = ltop; l <= L; ++l) {
-        const Level &lv = g.lev[l], &pa = g.lev[l - 1];
-        pairs += p->pair_count[l];
-        f[LMFMM_K_DOWN] += 8.0 * R * (double)p->pair_count[l] * lv.nc * lv.nc;
-        if (l > ltop && l < L) {
-            // boxes shifted at level l: every row, or with evaluation levels
-            // the rows whose expansions are read
-            const int rows = eval && p->last_rows_l2l[l] >= 0 ? std::min(p->last_rows_l2l[l], lv.rows_t) : lv.rows_t;
-            f[LMFMM_K_L2L] += 8.0 * R * (double)rows * lv.ncol * pa.nc * lv.nc;
-        }
-    }
-    p->stats.m2l_pairs = pairs;
-    if (grad) {
-        if (L > ltop) f[LMFMM_K_L2L] += 8.0 * R * (double)lf.rows_t * lf.ncol * g.lev[L - 1].nc * lf.nc;
-        f[LMFMM_K_L2P] = (double)nt * (60.0 * (lf.P + 1) + 3.0 * 8.0 * (lf.nc + 2) * R);
-        return;
-    }
-    // the leaf evaluation (with the leaf-level shift inside it): per target,
-    // the basis and contraction of the expansion it evaluates
-    dw.eval = true;
-    dw.ev = ev;
-    if (!ev.on) {
-        dw.ev.L = L;
-        dw.ev.P[L] = lf.P;
-    }
-    dw.nc_shift = L > ltop ? g.lev[L - 1].nc : 0;
-    dw.pending = true;
+    for (int l = 0; l <= MAXLEV; ++l) dw.rows_l2l[l] = p->last_ev.on && !grad ? p->last_rows_l2l[l] : -1;
 }
 
-// Completes the leaf-count-dependent work counts of the last apply (reads the
-// leaf ranges back; synchronizes the device).
+// Completes the work counts of the last apply from its leaf populations
+// (reads the leaf ranges back; synchronizes the device).
 static void resolve_work(lmfmm_plan_s *p)
 {
     auto &dw = p->dw;
     if (!dw.pending) return;
     dw.pending = false;
-    const int64_t nb = (int64_t)dw.rows_t * dw.ncol;
-    if (nb <= 0 || !dw.start || !dw.end) return;
-    std::vector<int32_t> st(nb), en(nb);
+    const Geometry &g = dw.g;
+    const int L = g.L, ltop = g.ltop;
+    const Level &lf = g.lev[L];
+    const int64_t nbs = (int64_t)lf.rows_s * lf.ncol, nbt = (int64_t)lf.rows_t * lf.ncol;
+    if (nbs + nbt <= 0 || !dw.start || !dw.end) return;
+    std::vector<int32_t> st(nbs + nbt), en(nbs + nbt);
     if (hipDeviceSynchronize() != hipSuccess) return;
-    if (hipMemcpy(st.data(), dw.start + dw.key_t0, nb * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
-    if (hipMemcpy(en.data(), dw.end + dw.key_t0, nb * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+    if (hipMemcpy(st.data(), dw.start, (nbs + nbt) * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+    if (hipMemcpy(en.data(), dw.end, (nbs + nbt) * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+    auto cnt_s = [&](int64_t b) { return (int64_t)en[b] - st[b]; };
+    auto cnt_t = [&](int64_t b) { return (int64_t)en[nbs + b] - st[nbs + b]; };
     double *f = p->stats.kernel_flops;
     const double R = dw.nrhs;
-    if (dw.eval) {
-        const EvalLevels &ev = dw.ev;
-        const int L = ev.L;
-        double fl = 0.0;
-        for (int r = 0; r < dw.rows_t; ++r) {
-            const int e = eval_level(ev, r), P = ev.P[e], ncl = 2 * ev.P[L] + 1;
-            for (int c = 0; c < dw.ncol; ++c) {
-                const int64_t b = (int64_t)r * dw.ncol + c;
-                const int64_t n = en[b] - st[b];
-                if (n <= 0) continue;
-                fl += (double)n * (60.0 * P + 8.0 * (2 * P + 1) * R);
-                if (e == L && dw.nc_shift) fl += 8.0 * R * dw.nc_shift * ncl;  // the leaf's shift
-            }
+    if (dw.sweep && lf.ncol > 0) {
+        // points of the row-0 leaves of both sides
+        int64_t n0 = 0;
+        for (int c = 0; c < lf.ncol; ++c) {
+            if (lf.rows_s > 0) n0 += cnt_s(c);
+            if (lf.rows_t > 0) n0 += cnt_t(c);
         }
-        f[LMFMM_K_L2P] = fl;
-    }
-    if (dw.sweep) {
-        // points of the row-0 leaves: targets from these ranges, sources from
-        // the source keys 0 .. ncol - 1 (the ranges are contiguous in key order)
-        int32_t s0 = 0, s1 = 0;
-        if (hipMemcpy(&s0, dw.start, 4, hipMemcpyDeviceToHost) != hipSuccess) return;
-        if (hipMemcpy(&s1, dw.end + dw.ncol - 1, 4, hipMemcpyDeviceToHost) != hipSuccess) return;
-        const int64_t n0 = (int64_t)(s1 - s0) + (en[dw.ncol - 1] - st[0]);
         f[LMFMM_K_SWEEP] = (double)n0 * dw.nodes * 2.0 * (32.0 + 8.0 * R);
     }
+    if (!dw.far) return;
+    // occupancy of every box of the expansion levels (row-major, rows from
+    // the interface; a parent holds points if any child does)
+    std::vector<std::vector<char>> os(MAXLEV + 1), ot(MAXLEV + 1);
+    os[L].resize(nbs);
+    ot[L].resize(nbt);
+    for (int64_t b = 0; b < nbs; ++b) os[L][b] = cnt_s(b) > 0;
+    for (int64_t b = 0; b < nbt; ++b) ot[L][b] = cnt_t(b) > 0;
+    for (int l = L - 1; l >= ltop; --l) {
+        const Level &c = g.lev[l + 1], &pa = g.lev[l];
+        os[l].assign((size_t)pa.rows_s * pa.ncol, 0);
+        ot[l].assign((size_t)pa.rows_t * pa.ncol, 0);
+        for (int r = 0; r < c.rows_s; ++r)
+            for (int b = 0; b < c.ncol; ++b)
+                if (os[l + 1][(size_t)r * c.ncol + b]) os[l][(size_t)(r >> 1) * pa.ncol + ((c.col_lo + b) >> 1) - pa.col_lo] = 1;
+        for (int r = 0; r < c.rows_t; ++r)
+            for (int b = 0; b < c.ncol; ++b)
+                if (ot[l + 1][(size_t)r * c.ncol + b]) ot[l][(size_t)(r >> 1) * pa.ncol + ((c.col_lo + b) >> 1) - pa.col_lo] = 1;
+    }
+    f[LMFMM_K_M2M] = 0;
+    for (int l = L; l >= ltop + 1; --l) {
+        const Level &c = g.lev[l], &pa = g.lev[l - 1];
+        int64_t n = 0;
+        for (char v : os[l]) n += v;
+        f[LMFMM_K_M2M] += 8.0 * R * (double)n * c.nc * pa.nc;
+    }
+    f[LMFMM_K_DOWN] = 0;
+    int64_t pairs = 0;
+    for (int l = ltop; l <= L; ++l) {
+        const Level &lv = g.lev[l];
+        const std::vector<int> &c3 = dw.cls[l];
+        int64_t cnt = 0;
+        for (size_t sl = 0; sl + 2 < c3.size(); sl += 3) {
+            const int rt = c3[sl], rs = c3[sl + 1], dc = c3[sl + 2];
+            if (rt >= lv.rows_t || rs >= lv.rows_s) continue;
+            for (int b = 0; b < lv.ncol; ++b) {
+                const int col = lv.col_lo + b, cs = col + dc, csl = cs - lv.col_lo;
+                if (csl < 0 || csl >= lv.ncol) continue;
+                const int dp = (cs >> 1) - (col >> 1);
+                if (l != ltop && (dp < -1 || dp > 1)) continue;
+                if (ot[l][(size_t)rt * lv.ncol + b] && os[l][(size_t)rs * lv.ncol + csl]) ++cnt;
+            }
+        }
+        pairs += cnt;
+        f[LMFMM_K_DOWN] += 8.0 * R * (double)cnt * lv.nc * lv.nc;
+    }
+    p->stats.m2l_pairs = pairs;
+    // L2L: the target boxes shifted (levels below ltop; the leaf level's
+    // shift is counted with the leaf evaluation, except in the gradient form)
+    f[LMFMM_K_L2L] = 0;
+    for (int l = ltop + 1; l <= L; ++l) {
+        if (l == L && !dw.grad) break;
+        const Level &lv = g.lev[l], &pa = g.lev[l - 1];
+        const int rows = dw.rows_l2l[l] >= 0 ? std::min(dw.rows_l2l[l], lv.rows_t) : lv.rows_t;
+        int64_t n = 0;
+        for (int64_t b = 0; b < (int64_t)rows * lv.ncol; ++b) n += ot[l][b];
+        f[LMFMM_K_L2L] += 8.0 * R * (double)n * pa.nc * lv.nc;
+    }
+    if (dw.grad) return;
+    // the leaf evaluation: per target, the basis and contraction of the
+    // expansion it evaluates, plus the shift of each occupied leaf that
+    // evaluates its own expansion
+    const EvalLevels &ev = dw.ev;
+    const int ncs = L > ltop ? g.lev[L - 1].nc : 0;
+    double fl = 0.0;
+    for (int r = 0; r < lf.rows_t; ++r) {
+        const int e = eval_level(ev, r), P = ev.P[e];
+        for (int c = 0; c < lf.ncol; ++c) {
+            const int64_t n = cnt_t((int64_t)r * lf.ncol + c);
+            if (n <= 0) continue;
+            fl += (double)n * (60.0 * P + 8.0 * (2 * P + 1) * R);
+            if (e == L && ncs) fl += 8.0 * R * ncs * lf.nc;
+        }
+    }
+    f[LMFMM_K_L2P] = fl;
 }
 
+// One pass of Algorithm 1 for the operator of orientation adj (0: forward,
+// 1: transposed in mirrored coordinates).  With gw == nullptr the field of the
+// densities q is written to u; otherwise the target-side coordinate gradient of
+// Re sum gw * field is written to gout ([2][nt], y component times ysign).
 template <typename T>
 // fixed_ws: the allocation-free form (lmfmm_apply_noalloc): the workspace is
 // that fixed array of NOALLOC_SCRATCH_BYTES, the tables must already exist,
@@ -1351,6 +1362,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     need += 6 * (size_t)n * 4 + 3 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
     need += (size_t)ns * nrhs * sizeof(cx<T>) + 256;  // densities in grouped order
     need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 20 * 256;
+    need += (size_t)g.nocc_s * 4 + 256;
     const int ltop = g.ltop;
     // near-field sweep results: up to 4 node parts x nrhs x targets (FP64)
     // direct interactions exist only between row-0 leaves on both sides
@@ -1390,6 +1402,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     double *xs = tb.xs, *ys = tb.ys;
     cx<T> *M = cv.take<cx<T>>(g.ncoef_s > 0 ? g.ncoef_s : 1);
     cx<T> *Lc = cv.take<cx<T>>(g.ncoef_t > 0 ? g.ncoef_t : 1);
+    int32_t *occ = cv.take<int32_t>(g.nocc_s > 0 ? g.nocc_s : 1);
     p->d_err = err;
     p->err_valid = n > 0 && nbox > 0;
     cx<double> *unear = sweep ? cv.take<cx<double>>(nun) : nullptr;
@@ -1433,14 +1446,14 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         if (far) {
             timed(LMFMM_K_P2M, 1);
             set_stage(S_P2M);
-            launch_p2m<T>(start, end, xs, ys, tb.qs, ns, nrhs, g, med, M, sx);
+            launch_p2m<T>(start, end, xs, ys, tb.qs, ns, nrhs, g, med, M, occ, sx);
             timed_done();
             for (int l = L; l >= ltop + 1; --l) {
                 const LevelTables &tb = vt.lt[l];
                 const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
                 timed(LMFMM_K_M2M, 1);
                 set_stage(S_M2M, L - l);
-                launch_m2m<T>(g, l, tab, M, nrhs, sx);
+                launch_m2m<T>(g, l, tab, M, occ, nrhs, sx);
                 timed_done();
             }
             // Step 3: downward pass.  M2L of every level in one launch (the
@@ -1466,7 +1479,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             }
             timed(LMFMM_K_DOWN, 1);
             set_stage(S_M2L);
-            launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, p->m2l_mfma, sx);
+            launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, p->m2l_mfma, occ, sx);
             timed_done();
             // the leaf level's shift is done by the leaf evaluation (forward apply)
             const int l2l_last = (!gw && L > ltop) ? L - 1 : L;

@@ -27,6 +27,8 @@ struct UpArgs {
     cx<T> *Mp;
     const cx<T> *tab;
     int nrhs, ncc, ncp, ncol_c, col_lo_c, rows_c, ncol_p, col_lo_p;
+    const int32_t *occ_c;  // occupancy flags of the children's level
+    int32_t *occ_p;        // ... of the parents' level (written: any child occupied)
 };
 template <typename T>
 __device__ __forceinline__ void up_body(const UpArgs<T> &ua, int b)
@@ -44,6 +46,14 @@ __device__ __forceinline__ void up_body(const UpArgs<T> &ua, int b)
     const bool ok = crow < rows_c && ccl >= 0 && ccl < ncol_c;
     const cx<T> *x = Mc + ((int64_t)crow * ncol_c + ccl) * nrhs * ncc;
     const cx<T> *A = tab + (int64_t)w * ncc * ncp;
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int c = 0; c < 4; ++c) {
+            const int cr = 2 * prow + (c >> 1), cc = 2 * pcol + (c & 1) - col_lo_c;
+            if (cr < rows_c && cc >= 0 && cc < ncol_c) any |= ua.occ_c[(int64_t)cr * ncol_c + cc];
+        }
+        ua.occ_p[b] = any;
+    }
     for (int r0 = 0; r0 < nrhs; r0 += R) {
         const int nr = nrhs - r0 < R ? nrhs - r0 : R;
         for (int p0 = 0; p0 < ncp; p0 += 64) {
@@ -197,6 +207,7 @@ struct M2LLevels {
     int blk0[M2L_MAXLEV + 1];  // first block of each listed level; blk0[n] = total
     int nc[M2L_MAXLEV], ncol[M2L_MAXLEV], col_lo[M2L_MAXLEV], rows_s[M2L_MAXLEV], top[M2L_MAXLEV];
     int64_t off_s[M2L_MAXLEV], off_t[M2L_MAXLEV];
+    const int32_t *occ[M2L_MAXLEV];  // source-box occupancy flags (null: not used)
     const cx<T> *atab[M2L_MAXLEV];
     const int *cls3[M2L_MAXLEV];
     const int *row_off[M2L_MAXLEV];
@@ -336,7 +347,9 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
     for (int s = s0 + w; s < s1; s += MW) {
         const int rs = cls3[3 * s + 1], dc = cls3[3 * s + 2];
         const int cs = col + dc, csl = cs - col_lo, dp = (cs >> 1) - (col >> 1);
-        const bool ok = nvalid && rs < a.rows_s[li] && csl >= 0 && csl < ncol && (a.top[li] || (dp >= -1 && dp <= 1));
+        bool ok = nvalid && rs < a.rows_s[li] && csl >= 0 && csl < ncol && (a.top[li] || (dp >= -1 && dp <= 1));
+        // an empty source box has a zero expansion: nothing to translate
+        if (ok && a.occ[li]) ok = a.occ[li][(int64_t)rs * ncol + csl] != 0;
         if (!__any(ok)) continue;
         const cx<T> *__restrict__ As = At + (int64_t)s * nc * nc;
         const cx<T> *__restrict__ xb = Ms + (((int64_t)rs * ncol + (ok ? csl : 0)) * k.nrhs + (ok ? r : 0)) * nc;
@@ -413,12 +426,13 @@ __global__ void __launch_bounds__(64 * MW) k_m2l_mfma_multi(MultiArgs m)
 }  // namespace
 
 template <typename T>
-void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int nrhs, hipStream_t st)
+void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int32_t *occ, int nrhs, hipStream_t st)
 {
     const Level &c = g.lev[lc], &p = g.lev[lc - 1];
     int nbox = p.rows_s * p.ncol;
     if (nbox == 0) return;
-    const UpArgs<T> a{M + c.off_s, M + p.off_s, tab, nrhs, c.nc, p.nc, c.ncol, c.col_lo, c.rows_s, p.ncol, p.col_lo};
+    const UpArgs<T> a{M + c.off_s, M + p.off_s, tab, nrhs, c.nc, p.nc, c.ncol, c.col_lo, c.rows_s, p.ncol, p.col_lo,
+                      occ + c.off_occ, occ + p.off_occ};
     emit((const void *)k_up<T>, (const void *)k_up_multi<T>, 0, dim3(nbox), dim3(256), 0, st, a);
 }
 
@@ -454,7 +468,7 @@ void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, c
 template <typename T>
 void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab, const int *const *cls3,
                     const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, bool mfma,
-                    hipStream_t st)
+                    const int32_t *occ, hipStream_t st)
 {
     M2LLevels<T> a;
     a.n = 0;
@@ -474,6 +488,7 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
         a.top[i] = l == g.ltop;
         a.off_s[i] = lv.off_s;
         a.off_t[i] = lv.off_t;
+        a.occ[i] = occ ? occ + lv.off_occ : nullptr;
         a.atab[i] = atab[l - l0];
         a.cls3[i] = cls3[l - l0];
         a.row_off[i] = row_off[l - l0];
@@ -495,12 +510,12 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
 
 
 #define LMFMM_INST(T)                                                                                               \
-    template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int, hipStream_t);                   \
+    template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int32_t *, int, hipStream_t);        \
     template void launch_down<T>(const Geometry &, int, const cx<T> *, const int *, const int *, int, const cx<T> *, \
                                  cx<T> *, int, const cx<T> *, bool, int, hipStream_t, int);                         \
     template void launch_m2l_all<T>(const Geometry &, int, int, const cx<T> *const *, const int *const *,           \
                                     const int *const *, const int *, const cx<T> *, cx<T> *, int, bool,             \
-                                    hipStream_t);
+                                    const int32_t *, hipStream_t);
 LMFMM_INST(double)
 LMFMM_INST(float)
 
