@@ -121,6 +121,13 @@ int lmfmm_destroy(lmfmm_plan plan);
  *   "m2l_mfma"    "1" (default): multipole-to-local as products of the class
  *                 tables with tiles of boxes x right-hand sides on the matrix
  *                 cores; "0": one matrix-vector product per box pair list
+ *   "shift_mfma"  "1" (default): M2M and L2L as products of the shift tables
+ *                 with tiles of boxes x right-hand sides on the matrix cores;
+ *                 "0": one matrix-vector product per box
+ *   "eval_levels" "1" (default): each leaf evaluates the local expansion of
+ *                 the level where its far field is complete (its ancestor's),
+ *                 and only the expansions read are shifted down; "0": every
+ *                 leaf evaluates its own, shifted down level by level
  *   "timing"      "1": record a HIP event on the apply's stream before every
  *                 kernel (or group of tree-build kernels) of each apply and
  *                 accumulate the durations per kernel in

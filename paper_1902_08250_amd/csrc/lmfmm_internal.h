@@ -524,25 +524,29 @@ template <typename T>
 void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
                 int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, hipStream_t st);
 template <typename T>
-void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int32_t *occ, int nrhs, hipStream_t st);
+// (mfma: on the matrix cores)
+void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int32_t *occ, int nrhs, bool mfma,
+                hipStream_t st);
 // downward pass of level l: M2L (atab non-null; class slots of target row r:
 // row_off[r] .. row_off[r + 1], rows < nrt) and/or L2L from level l - 1
 // (l2l_tab non-null); add_rows: rows whose stored local expansion (M2L of an
 // earlier launch) is added to the L2L shift; rows_l2l: the L2L shift covers
-// rows below it only (-1: every row)
+// rows below it only (-1: every row); mfma: the L2L form on the matrix cores
 template <typename T>
 void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, const int *row_off, int nrt,
                  const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, int add_rows,
-                 hipStream_t st, int rows_l2l = -1);
-// M2L of levels l0 .. l1 in one launch (entry l - l0 of each array: class
-// tables, class codes, row slot offsets, number of rows with classes; a null
-// table skips the level); the result is stored as the local expansion.
-// mfma: products of the class tables with tiles of boxes on the matrix cores
-// (else per-box matrix-vector products on the vector units)
+                 hipStream_t st, int rows_l2l = -1, bool mfma = false);
+// M2L of levels l0 .. l1 (entry l - l0 of each array: class tables, class
+// codes, row slot offsets, number of rows with classes; a null table skips
+// the level); the result is stored as the local expansion.  mfma: products of
+// the class tables with tiles of boxes on the matrix cores, the coarsest level
+// (part 1) and the others (part 2) in a launch each (part 0: both); else
+// per-box matrix-vector products on the vector units, every level in one
+// launch (part 1 launches nothing).  occ: source-box occupancy flags.
 template <typename T>
 void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab, const int *const *cls3,
                     const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, bool mfma,
-                    const int32_t *occ, hipStream_t st);
+                    const int32_t *occ, int part, hipStream_t st);
 // returns the number of node parts written to unear ([part][rhs][target])
 template <typename T>
 int launch_near_sweep(const int32_t *start, const int32_t *end, const int32_t *idx, const double *xs,

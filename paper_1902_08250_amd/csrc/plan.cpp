@@ -242,6 +242,7 @@ struct lmfmm_plan_s {
     bool near_sweep = true;  // near field by x-ordered sweeps (else pairwise)
     bool m2l_mfma = true;    // M2L on the matrix cores (else vector matrix-vector products)
     bool eval_levels = true; // leaves evaluate the expansion of the level where their far field is complete
+    bool shift_mfma = true;  // M2M and L2L on the matrix cores (else vector matrix-vector products)
 
     DevBuf ws;
     double *h_bbox = nullptr;  // pinned, host-coherent: [0..6] box, [8] sequence number, [12] error copy
@@ -925,6 +926,11 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         p->m2l_mfma = v == "1";
         return LMFMM_OK;
     }
+    if (k == "shift_mfma") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "shift_mfma must be 0 or 1");
+        p->shift_mfma = v == "1";
+        return LMFMM_OK;
+    }
     if (k == "eval_levels") {
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "eval_levels must be 0 or 1");
         p->eval_levels = v == "1";
@@ -1453,7 +1459,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 const cx<T> *tab = (const cx<T> *)(sizeof(T) == 8 ? tb.m2m64.p : tb.m2m32.p);
                 timed(LMFMM_K_M2M, 1);
                 set_stage(S_M2M, L - l);
-                launch_m2m<T>(g, l, tab, M, occ, nrhs, sx);
+                launch_m2m<T>(g, l, tab, M, occ, nrhs, p->shift_mfma, sx);
                 timed_done();
             }
             // Step 3: downward pass.  M2L of every level in one launch (the
@@ -1477,10 +1483,12 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 set_stage(S_ZTOP);
                 launch_zero_bytes(Lc + lt.off_t, (size_t)lt.rows_t * lt.ncol * nrhs * lt.nc * sizeof(cx<T>), sx);
             }
-            timed(LMFMM_K_DOWN, 1);
-            set_stage(S_M2L);
-            launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, p->m2l_mfma, occ, sx);
-            timed_done();
+            for (int part = 1; part <= 2; ++part) {
+                timed(LMFMM_K_DOWN, 1);
+                set_stage(S_M2L, part);
+                launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, p->m2l_mfma, occ, part, sx);
+                timed_done();
+            }
             // the leaf level's shift is done by the leaf evaluation (forward apply)
             const int l2l_last = (!gw && L > ltop) ? L - 1 : L;
             if (eval_on) {
@@ -1527,7 +1535,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
                 timed(LMFMM_K_L2L, 1);
                 set_stage(S_L2L, l - ltop - 1);
                 launch_down<T>(g, l, (const cx<T> *)nullptr, nullptr, nullptr, 0, M, Lc, nrhs, l2l, false,
-                               nrt[l - ltop], sx, eval_on ? rows_l2l[l] : -1);
+                               nrt[l - ltop], sx, eval_on ? rows_l2l[l] : -1, p->shift_mfma);
                 timed_done();
             }
         }

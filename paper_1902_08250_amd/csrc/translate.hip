@@ -289,8 +289,9 @@ __global__ void __launch_bounds__(64 * M2L_DW) k_m2l_all_multi(MultiArgs m)
 // result holds entry (4 (l / 16) + v, l % 16), of the FP64 result entry
 // (l / 16 + 4 v, l % 16).
 // ---------------------------------------------------------------------------
-constexpr int MW = 4;   // waves per block
-constexpr int MKS = 8;  // k-steps (4 coefficients each) whose operands are loaded together
+constexpr int MW = 4;       // waves per block
+constexpr int MW_TOP = 16;  // waves per block at the coarsest level (every non-adjacent pair: long slot lists)
+constexpr int MKS = 8;      // k-steps (4 coefficients each) whose operands are loaded together
 template <typename T>
 struct M2LMK {
     M2LLevels<T> a;  // blk0: first block of each level
@@ -316,7 +317,7 @@ __device__ inline void mfma_c(mf64x4 &dr, mf64x4 &di, cx<double> x, cx<double> y
     di = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, y.re, di, 0, 0, 0);
 }
 
-template <typename T>
+template <typename T, int NW>
 __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
 {
     typedef typename std::conditional<sizeof(T) == 4, mf32x4, mf64x4>::type vx4;
@@ -344,7 +345,7 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
     const cx<T> *__restrict__ At = a.atab[li];
     const int nks = (nc + 3) >> 2;
     vx4 sr = {0, 0, 0, 0}, si = {0, 0, 0, 0}, cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-    for (int s = s0 + w; s < s1; s += MW) {
+    for (int s = s0 + w; s < s1; s += NW) {
         const int rs = cls3[3 * s + 1], dc = cls3[3 * s + 2];
         const int cs = col + dc, csl = cs - col_lo, dp = (cs >> 1) - (col >> 1);
         bool ok = nvalid && rs < a.rows_s[li] && csl >= 0 && csl < ncol && (a.top[li] || (dp >= -1 && dp <= 1));
@@ -386,51 +387,207 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
             }
         }
     }
-    // the waves' sums added in wave order by wave 0
-    __shared__ T red[MW][4][4][64];  // wave, (sr, si, cr, ci), v, lane
+    // the waves' sums added in wave order by wave 0, four waves per round
+    __shared__ T red[4][4][4][64];  // wave of the round, (sr, si, cr, ci), v, lane
+    CAcc<T> are[4], aim[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        red[w][0][v][l] = sr[v];
-        red[w][1][v][l] = si[v];
-        red[w][2][v][l] = cr[v];
-        red[w][3][v][l] = ci[v];
+        are[v].zero();
+        aim[v].zero();
     }
-    __syncthreads();
+    for (int r0 = 0; r0 < NW; r0 += 4) {
+        if (w >= r0 && w < r0 + 4) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                red[w - r0][0][v][l] = sr[v];
+                red[w - r0][1][v][l] = si[v];
+                red[w - r0][2][v][l] = cr[v];
+                red[w - r0][3][v][l] = ci[v];
+            }
+        }
+        __syncthreads();
+        if (w == 0)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                for (int x = 0; x < 4; ++x) {
+                    are[v].add({red[x][0][v][l], -red[x][2][v][l]});
+                    aim[v].add({red[x][1][v][l], -red[x][3][v][l]});
+                }
+        __syncthreads();
+    }
     if (w != 0 || !nvalid) return;
     const int64_t obase = a.off_t[li] + (((int64_t)row * ncol + colL) * k.nrhs + r) * nc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        CAcc<T> re, im;
-        re.zero();
-        im.zero();
-        for (int x = 0; x < MW; ++x) {
-            re.add({red[x][0][v][l], -red[x][2][v][l]});
-            im.add({red[x][1][v][l], -red[x][3][v][l]});
-        }
         const int prow = F32 ? 4 * kk + v : kk + 4 * v;
         const int pp = pt * 16 + prow;
-        const cx<T> vr = re.value(), vi = im.value();
+        const cx<T> vr = are[v].value(), vi = aim[v].value();
         if (pp < nc) k.Lc[obase + pp] = mk<T>(vr.re + vr.im, vi.re + vi.im);
     }
 }
-template <typename T>
-__global__ void __launch_bounds__(64 * MW) k_m2l_mfma(M2LMK<T> a) { m2l_mfma_body<T>(a, blockIdx.x); }
-template <typename T>
-__global__ void __launch_bounds__(64 * MW) k_m2l_mfma_multi(MultiArgs m)
+template <typename T, int NW>
+__global__ void __launch_bounds__(64 * NW) k_m2l_mfma(M2LMK<T> a) { m2l_mfma_body<T, NW>(a, blockIdx.x); }
+template <typename T, int NW>
+__global__ void __launch_bounds__(64 * NW) k_m2l_mfma_multi(MultiArgs m)
 {
     int i, bx, by, bz;
     multi_locate(m, i, bx, by, bz);
-    m2l_mfma_body<T>(static_cast<const M2LMK<T> *>(m.args)[i], bx);
+    m2l_mfma_body<T, NW>(static_cast<const M2LMK<T> *>(m.args)[i], bx);
+}
+
+// ---------------------------------------------------------------------------
+// M2M and L2L on the matrix cores (Lemma M2M, Lemma L2L): per child position
+// the shift table (in x out) times the expansions of a tile of NB output
+// boxes x RC right-hand sides, v_mfma_f32_16x16x4f32 (FP64: ..._f64_...) with
+// the lane layouts of the M2L kernel above.
+//   M2M (UP = true): a block takes one tile of parent boxes and one tile of 16
+//   output coefficients; wave w takes child position w; the four products
+//   are added in wave order through LDS.  It also writes the parents'
+//   occupancy flags.
+//   L2L (UP = false): a block takes one tile of child boxes of one column
+//   parity (so that they share the position and the table) and four tiles of
+//   output coefficients, one per wave; rows below add_rows add their stored
+//   M2L result.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ShiftMK {
+    const cx<T> *X;  // input expansions (children for M2M, parents for L2L)
+    cx<T> *Y;        // output expansions
+    const cx<T> *tab;  // [4][nc_in][nc_out]
+    int nc_in, ncol_in, col_lo_in, rows_in;
+    int nc_out, ncol_out, col_lo_out, rows_out;  // rows_out: output rows computed
+    int nrhs, RC, NB, add_rows;
+    const int32_t *occ_in;  // M2M: children's occupancy flags
+    int32_t *occ_out;       // M2M: parents'
+};
+template <typename T, bool UP>
+__device__ __forceinline__ void shift_mfma_body(const ShiftMK<T> &k, const int bx)
+{
+    typedef typename std::conditional<sizeof(T) == 4, mf32x4, mf64x4>::type vx4;
+    constexpr bool F32 = sizeof(T) == 4;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+    const int nin = k.nc_in, nout = k.nc_out;
+    const int npt = (nout + 15) >> 4, npb = UP ? npt : (npt + 3) >> 2;  // p-tile blocks
+    // L2L: tiles of boxes of one column parity: half-tiles 0 .. nth-1 take
+    // the columns colL = c0 + 2 m (c0 = 0 or 1), m in the tile
+    const int nhalf = (k.ncol_out + 1) >> 1, nth = (nhalf + k.NB - 1) / k.NB;
+    const int ntile = UP ? (k.ncol_out + k.NB - 1) / k.NB : 2 * nth, nrc = (k.nrhs + k.RC - 1) / k.RC;
+    int loc = bx;
+    const int ptb = loc % npb;
+    loc /= npb;
+    const int rcn = loc % nrc;
+    loc /= nrc;
+    const int tile = loc % ntile, row = loc / ntile;
+    const int pt = UP ? ptb : 4 * ptb + w;  // this wave's tile of output coefficients
+    const int n = l & 15, kk = l >> 4;
+    const int j = n / k.RC, r = rcn * k.RC + n % k.RC;
+    const int colL = UP ? tile * k.NB + j : (tile & 1) + 2 * ((tile >> 1) * k.NB + j);
+    const int col = k.col_lo_out + colL;
+    const bool nvalid = colL < k.ncol_out && r < k.nrhs && row < k.rows_out;
+    const int p = pt * 16 + n;  // this lane's row of the left factor (output coefficient)
+    // the input box and the child position
+    int irow, icl, pos;
+    if (UP) {
+        pos = w;
+        irow = 2 * row + (w >> 1);
+        icl = 2 * col + (w & 1) - k.col_lo_in;
+    } else {
+        pos = (col & 1) + 2 * (row & 1);
+        irow = row >> 1;
+        icl = (col >> 1) - k.col_lo_in;
+    }
+    bool ok = nvalid && irow < k.rows_in && icl >= 0 && icl < k.ncol_in;
+    if (UP && ok && k.occ_in) ok = k.occ_in[(int64_t)irow * k.ncol_in + icl] != 0;
+    if (UP && rcn == 0 && ptb == 0 && threadIdx.x < k.NB) {
+        // parents' occupancy: any child holds sources
+        const int cL = tile * k.NB + threadIdx.x, pc = k.col_lo_out + cL;
+        if (cL < k.ncol_out && row < k.rows_out) {
+            int any = 0;
+            for (int c = 0; c < 4; ++c) {
+                const int cr = 2 * row + (c >> 1), cc = 2 * pc + (c & 1) - k.col_lo_in;
+                if (cr < k.rows_in && cc >= 0 && cc < k.ncol_in) any |= k.occ_in[(int64_t)cr * k.ncol_in + cc];
+            }
+            k.occ_out[(int64_t)row * k.ncol_out + cL] = any;
+        }
+    }
+    vx4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+    if (__any(ok) && (UP || pt < npt)) {
+        const cx<T> *__restrict__ A = k.tab + (int64_t)pos * nin * nout;
+        const cx<T> *__restrict__ xb =
+            k.X + (((int64_t)(ok ? irow : 0) * k.ncol_in + (ok ? icl : 0)) * k.nrhs + (ok ? r : 0)) * nin;
+        const int nks = (nin + 3) >> 2;
+        for (int k0 = 0; k0 < nks; k0 += MKS) {
+            cx<T> av[MKS], bv[MKS];
+#pragma unroll
+            for (int u = 0; u < MKS; ++u) {
+                const int kq = 4 * (k0 + u) + kk;
+                const bool kin = kq < nin;
+                av[u] = (kin && p < nout) ? A[(int64_t)kq * nout + p] : mk<T>(0, 0);
+                bv[u] = (kin && ok) ? xb[kq] : mk<T>(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < MKS; ++u)
+                if (k0 + u < nks) mfma_c(dr, di, av[u], bv[u]);
+        }
+    }
+    if (UP) {
+        // the four positions' products added in wave order by wave 0
+        __shared__ T red[4][2][4][64];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            red[w][0][v][l] = dr[v];
+            red[w][1][v][l] = di[v];
+        }
+        __syncthreads();
+        if (w != 0 || !nvalid) return;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            dr[v] = red[0][0][v][l] + red[1][0][v][l] + red[2][0][v][l] + red[3][0][v][l];
+            di[v] = red[0][1][v][l] + red[1][1][v][l] + red[2][1][v][l] + red[3][1][v][l];
+        }
+    }
+    if (!nvalid || pt >= npt) return;
+    cx<T> *__restrict__ out = k.Y + (((int64_t)row * k.ncol_out + colL) * k.nrhs + r) * nout;
+    const bool add = !UP && row < k.add_rows;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int prow = F32 ? 4 * kk + v : kk + 4 * v;
+        const int pp = pt * 16 + prow;
+        if (pp < nout) {
+            cx<T> val = mk<T>(dr[v], di[v]);
+            if (add) val += out[pp];
+            out[pp] = val;
+        }
+    }
+}
+template <typename T, bool UP>
+__global__ void __launch_bounds__(256) k_shift_mfma(ShiftMK<T> a) { shift_mfma_body<T, UP>(a, blockIdx.x); }
+template <typename T, bool UP>
+__global__ void __launch_bounds__(256) k_shift_mfma_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    shift_mfma_body<T, UP>(static_cast<const ShiftMK<T> *>(m.args)[i], bx);
 }
 
 }  // namespace
 
 template <typename T>
-void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int32_t *occ, int nrhs, hipStream_t st)
+void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int32_t *occ, int nrhs, bool mfma,
+                hipStream_t st)
 {
     const Level &c = g.lev[lc], &p = g.lev[lc - 1];
     int nbox = p.rows_s * p.ncol;
     if (nbox == 0) return;
+    if (mfma) {
+        const int RC = nrhs >= 16 ? 16 : (nrhs > 8 ? 16 : (nrhs > 4 ? 8 : (nrhs > 2 ? 4 : nrhs))), NB = 16 / RC;
+        const ShiftMK<T> a{M + c.off_s, M + p.off_s, tab, c.nc, c.ncol, c.col_lo, c.rows_s, p.nc, p.ncol, p.col_lo,
+                           p.rows_s, nrhs, RC, NB, 0, occ + c.off_occ, occ + p.off_occ};
+        const int64_t nblk = (int64_t)p.rows_s * ((p.ncol + NB - 1) / NB) * ((nrhs + RC - 1) / RC) * ((p.nc + 15) / 16);
+        emit((const void *)k_shift_mfma<T, true>, (const void *)k_shift_mfma_multi<T, true>, 0, dim3((unsigned)nblk),
+             dim3(256), 0, st, a);
+        return;
+    }
     const UpArgs<T> a{M + c.off_s, M + p.off_s, tab, nrhs, c.nc, p.nc, c.ncol, c.col_lo, c.rows_s, p.ncol, p.col_lo,
                       occ + c.off_occ, occ + p.off_occ};
     emit((const void *)k_up<T>, (const void *)k_up_multi<T>, 0, dim3(nbox), dim3(256), 0, st, a);
@@ -439,7 +596,7 @@ void launch_m2m(const Geometry &g, int lc, const cx<T> *tab, cx<T> *M, int32_t *
 template <typename T>
 void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, const int *row_off, int nrt,
                  const cx<T> *M, cx<T> *Lc, int nrhs, const cx<T> *l2l_tab, bool top, int add_rows, hipStream_t st,
-                 int rows_l2l)
+                 int rows_l2l, bool mfma)
 {
     const Level &lv = g.lev[l], &pv = g.lev[l - 1];
     DownArgs a;
@@ -458,6 +615,19 @@ void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, c
     a.has_l2l = l2l_tab != nullptr;
     a.add_rows = add_rows;
     a.rows_l2l = rows_l2l < 0 || rows_l2l > lv.rows_t ? lv.rows_t : rows_l2l;
+    if (mfma && !atab && l2l_tab) {
+        // the L2L form on the matrix cores
+        const int RC = nrhs >= 16 ? 16 : (nrhs > 8 ? 16 : (nrhs > 4 ? 8 : (nrhs > 2 ? 4 : nrhs))), NB = 16 / RC;
+        const ShiftMK<T> s{Lc + pv.off_t, Lc + lv.off_t, l2l_tab, pv.nc, pv.ncol, pv.col_lo, pv.rows_t, lv.nc, lv.ncol,
+                           lv.col_lo, a.rows_l2l, nrhs, RC, NB, add_rows, nullptr, nullptr};
+        const int nth = (((lv.ncol + 1) >> 1) + NB - 1) / NB;
+        const int64_t nblk =
+            (int64_t)a.rows_l2l * 2 * nth * ((nrhs + RC - 1) / RC) * ((((lv.nc + 15) / 16) + 3) / 4);
+        if (nblk == 0) return;
+        emit((const void *)k_shift_mfma<T, false>, (const void *)k_shift_mfma_multi<T, false>, 0,
+             dim3((unsigned)nblk), dim3(256), 0, st, s);
+        return;
+    }
     int64_t rest = (int64_t)(a.rows_l2l > a.nrt ? a.rows_l2l - a.nrt : 0) * lv.ncol;
     int64_t nblk = a.nb_m2l + (a.has_l2l ? (rest + DW - 1) / DW : 0);
     if (nblk == 0) return;
@@ -468,54 +638,69 @@ void launch_down(const Geometry &g, int l, const cx<T> *atab, const int *cls3, c
 template <typename T>
 void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab, const int *const *cls3,
                     const int *const *row_off, const int *nrt, const cx<T> *M, cx<T> *Lc, int nrhs, bool mfma,
-                    const int32_t *occ, hipStream_t st)
+                    const int32_t *occ, int part, hipStream_t st)
 {
-    M2LLevels<T> a;
-    a.n = 0;
-    int blk = 0;
     // matrix-core form: columns of 16 = NB boxes x RC right-hand sides
     const int RC = nrhs >= 16 ? 16 : (nrhs > 8 ? 16 : (nrhs > 4 ? 8 : (nrhs > 2 ? 4 : nrhs))), NB = 16 / RC;
-    for (int l = l0; l <= l1 && a.n < M2L_MAXLEV; ++l) {
-        const Level &lv = g.lev[l];
-        const int rows = nrt[l - l0] < lv.rows_t ? nrt[l - l0] : lv.rows_t;
-        if (!atab[l - l0] || rows <= 0 || lv.ncol <= 0) continue;
-        const int i = a.n++;
-        a.blk0[i] = blk;
-        a.nc[i] = lv.nc;
-        a.ncol[i] = lv.ncol;
-        a.col_lo[i] = lv.col_lo;
-        a.rows_s[i] = lv.rows_s;
-        a.top[i] = l == g.ltop;
-        a.off_s[i] = lv.off_s;
-        a.off_t[i] = lv.off_t;
-        a.occ[i] = occ ? occ + lv.off_occ : nullptr;
-        a.atab[i] = atab[l - l0];
-        a.cls3[i] = cls3[l - l0];
-        a.row_off[i] = row_off[l - l0];
-        if (mfma)
-            blk += rows * ((lv.ncol + NB - 1) / NB) * ((nrhs + RC - 1) / RC) * ((lv.nc + 15) / 16);
-        else
-            blk += rows * lv.ncol;
-    }
-    a.blk0[a.n] = blk;
-    if (blk == 0) return;
+    // the levels of one launch: the coarsest level alone (its rows list every
+    // non-adjacent pair, so its blocks take more waves) or all the others
+    auto levels = [&](bool top, M2LLevels<T> &a) {
+        a.n = 0;
+        int blk = 0;
+        for (int l = l0; l <= l1 && a.n < M2L_MAXLEV; ++l) {
+            if (mfma && (l == g.ltop) != top) continue;
+            const Level &lv = g.lev[l];
+            const int rows = nrt[l - l0] < lv.rows_t ? nrt[l - l0] : lv.rows_t;
+            if (!atab[l - l0] || rows <= 0 || lv.ncol <= 0) continue;
+            const int i = a.n++;
+            a.blk0[i] = blk;
+            a.nc[i] = lv.nc;
+            a.ncol[i] = lv.ncol;
+            a.col_lo[i] = lv.col_lo;
+            a.rows_s[i] = lv.rows_s;
+            a.top[i] = l == g.ltop;
+            a.off_s[i] = lv.off_s;
+            a.off_t[i] = lv.off_t;
+            a.occ[i] = occ ? occ + lv.off_occ : nullptr;
+            a.atab[i] = atab[l - l0];
+            a.cls3[i] = cls3[l - l0];
+            a.row_off[i] = row_off[l - l0];
+            if (mfma)
+                blk += rows * ((lv.ncol + NB - 1) / NB) * ((nrhs + RC - 1) / RC) * ((lv.nc + 15) / 16);
+            else
+                blk += rows * lv.ncol;
+        }
+        a.blk0[a.n] = blk;
+        return blk;
+    };
+    M2LLevels<T> a;
     if (mfma) {
-        const M2LMK<T> k{a, nrhs, RC, NB, M, Lc};
-        emit((const void *)k_m2l_mfma<T>, (const void *)k_m2l_mfma_multi<T>, 0, dim3(blk), dim3(64 * MW), 0, st, k);
+        if (part != 2 && levels(true, a) > 0) {
+            const M2LMK<T> k{a, nrhs, RC, NB, M, Lc};
+            emit((const void *)k_m2l_mfma<T, MW_TOP>, (const void *)k_m2l_mfma_multi<T, MW_TOP>, 0,
+                 dim3(a.blk0[a.n]), dim3(64 * MW_TOP), 0, st, k);
+        }
+        if (part != 1 && levels(false, a) > 0) {
+            const M2LMK<T> k{a, nrhs, RC, NB, M, Lc};
+            emit((const void *)k_m2l_mfma<T, MW>, (const void *)k_m2l_mfma_multi<T, MW>, 0, dim3(a.blk0[a.n]),
+                 dim3(64 * MW), 0, st, k);
+        }
         return;
     }
+    if (part == 2 || levels(false, a) == 0) return;
     const M2LK<T> k{a, nrhs, M, Lc};
-    emit((const void *)k_m2l_all<T>, (const void *)k_m2l_all_multi<T>, 0, dim3(blk), dim3(64 * M2L_DW), 0, st, k);
+    emit((const void *)k_m2l_all<T>, (const void *)k_m2l_all_multi<T>, 0, dim3(a.blk0[a.n]), dim3(64 * M2L_DW), 0, st,
+         k);
 }
 
 
 #define LMFMM_INST(T)                                                                                               \
-    template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int32_t *, int, hipStream_t);        \
+    template void launch_m2m<T>(const Geometry &, int, const cx<T> *, cx<T> *, int32_t *, int, bool, hipStream_t);  \
     template void launch_down<T>(const Geometry &, int, const cx<T> *, const int *, const int *, int, const cx<T> *, \
-                                 cx<T> *, int, const cx<T> *, bool, int, hipStream_t, int);                         \
+                                 cx<T> *, int, const cx<T> *, bool, int, hipStream_t, int, bool);                   \
     template void launch_m2l_all<T>(const Geometry &, int, int, const cx<T> *const *, const int *const *,           \
                                     const int *const *, const int *, const cx<T> *, cx<T> *, int, bool,             \
-                                    const int32_t *, hipStream_t);
+                                    const int32_t *, int, hipStream_t);
 LMFMM_INST(double)
 LMFMM_INST(float)
 

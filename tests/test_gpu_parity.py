@@ -150,19 +150,20 @@ def test_mid_fmm_vs_direct(torch_cuda, mid, mid_direct, levels):
 def test_eval_levels_match_leaf_evaluation(torch_cuda, mid, mid_direct, levels):
     """Leaves evaluating the expansion of the level where their far field is
     complete (default) against every leaf evaluating its own shifted expansion
-    (option eval_levels = 0), FP64 and mixed, 11 right-hand sides; both
-    against the GPU direct sum."""
+    (option eval_levels = 0), with M2M and L2L on the matrix cores (default)
+    and on the vector units (shift_mfma = 0), FP64 and mixed, 11 right-hand
+    sides; each against the GPU direct sum."""
     from paper_1902_08250_amd.lmfmm import Plan
-    say("eval levels on/off 4000x3000 nrhs=11 levels", levels)
+    say("eval levels on/off, shifts on matrix cores/vector units, 4000x3000 nrhs=11 levels", levels)
     for prec, tol in (("c128", 1e-10), ("c64", TOL["c64"])):
         q = mid["q"] if prec == "c128" else mid["q"].astype(np.complex64)
-        pl = Plan(mid["k"], mid["d"], order=20 if prec == "c128" else 16, tol=1e-10 if prec == "c128" else 1e-6,
-                  levels=levels)
-        u_on = host(pl.apply(dev(mid["src"]), dev(q), dev(mid["tgt"])))
-        pl.set_option("eval_levels", "0")
-        u_off = host(pl.apply(dev(mid["src"]), dev(q), dev(mid["tgt"])))
-        check(u_on, mid_direct, tol, f"{prec} L={levels} evaluation levels vs direct", say)
-        check(u_off, mid_direct, tol, f"{prec} L={levels} leaf evaluation vs direct", say)
+        for ev, sm in (("1", "1"), ("0", "1"), ("1", "0"), ("0", "0")):
+            pl = Plan(mid["k"], mid["d"], order=20 if prec == "c128" else 16, tol=1e-10 if prec == "c128" else 1e-6,
+                      levels=levels)
+            pl.set_option("eval_levels", ev)
+            pl.set_option("shift_mfma", sm)
+            u = host(pl.apply(dev(mid["src"]), dev(q), dev(mid["tgt"])))
+            check(u, mid_direct, tol, f"{prec} L={levels} eval_levels={ev} shift_mfma={sm} vs direct", say)
 
 
 def test_mid_mixed_vs_fp64(torch_cuda, mid, mid_direct):
