@@ -8,6 +8,33 @@ namespace lmfmm {
 
 namespace {
 
+// One DPP lane move of a double (both halves); lanes of rows outside ROWMASK
+// read 0.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_d(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each aligned group of S adjacent lanes (S = 1, 2, 4, ..., 64), in
+// a fixed order, complete in the group's last lane: pairs, quads, half rows
+// and rows of 16 by lane permutations (then the sum is in every lane of the
+// row), then row 0 into row 1 and row 2 into row 3, then rows 0-1 into row 3.
+// Every lane of the wave must be active.
+__device__ inline double group_sum_d(double v, int S)
+{
+    if (S >= 2) v += dpp_d<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    if (S >= 4) v += dpp_d<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    if (S >= 8) v += dpp_d<0x141, 0xf>(v);  // row_half_mirror
+    if (S >= 16) v += dpp_d<0x140, 0xf>(v); // row_mirror
+    if (S >= 32) v += dpp_d<0x142, 0xa>(v); // row_bcast:15 into rows 1 and 3
+    if (S >= 64) v += dpp_d<0x143, 0xc>(v); // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Translations (Lemma M2M, Lemma M2L, Lemma L2L) as one matrix-vector product
 // per (table, vector) item: out[p] += sum_k A[k][p] x[k], A a per-level table

@@ -23,16 +23,19 @@ namespace lmfmm {
 namespace {
 
 // ---------------------------------------------------------------------------
-// P2M: a block takes G consecutive source leaves, whose points are contiguous
-// in the grouped order (as are their densities, qs), and walks those points in
-// chunks of CH: a thread per point evaluates the point's scaled basis into
-// LDS, then threads over (leaf, right-hand side, coefficient) add the points
-// of their leaf in the chunk, in index order.  The output block of the G leaves is contiguous, and
-// so are the threads' stores.  Leaves without points get zeros.
+// P2M by the recurrence form: a block takes G consecutive source leaves, whose
+// points are contiguous in the grouped order (as are their densities, qs),
+// and walks those points in chunks of CH: a thread per point evaluates the
+// point's scaled basis into LDS, with the point's densities padded with zeros
+// to a multiple of four right-hand sides, then threads over (leaf, chunk of
+// four right-hand sides, coefficient) add the points of their leaf in the
+// chunk, in index order; the padding keeps that loop free of per-lane
+// branches.  The output block of the G leaves is contiguous, and so are the
+// threads' stores.  Leaves without points get zeros.
 // ---------------------------------------------------------------------------
 constexpr int P2M_THREADS = 256;
 constexpr int P2M_CHMAX = 320;  // points per chunk (a thread evaluates up to two)
-constexpr int LEAF_GMAX = 32;  // leaves per block (P2M and L2P)
+constexpr int LEAF_GMAX = 32;   // leaves per block (P2M and L2P)
 template <typename T>
 struct P2MArgs {
     const int32_t *start, *end;
@@ -47,7 +50,7 @@ struct P2MArgs {
     cx<T> *M;
     int32_t *occ;  // the leaves' occupancy flags
 };
-template <typename T, int PMAX>
+template <typename T>
 __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
 {
     const int32_t *__restrict__ start = A.start;
@@ -64,8 +67,9 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
     extern __shared__ unsigned char smem_raw[];
     __shared__ int bnd[LEAF_GMAX + 1];
     const int nc = 2 * P + 1;
+    const int nrc = (nrhs + 3) >> 2, nq = 4 * nrc;
     cx<T> *B = reinterpret_cast<cx<T> *>(smem_raw);  // [CH][nc]
-    cx<T> *Q = B + CH * nc;                          // [CH][nrhs]
+    cx<T> *Q = B + CH * nc;                          // [CH][nq]
     const int t = threadIdx.x;
     const int b0 = bx * G;
     const int ng = nbox - b0 < G ? nbox - b0 : G;
@@ -85,8 +89,8 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
             const int row = box / ncol, col = col_lo + box % ncol;
             const double cxp = x_lo + (col + 0.5) * w, cyp = (row + 0.5) * w;
             const T X = (T)(xs[j] - cxp), Y = (T)(ys[j] - cyp);
-            bessel_basis<T, PMAX>(k1, X, Y, invR, P, -1, B + jl * nc, 1);
-            for (int r = 0; r < nrhs; ++r) Q[jl * nrhs + r] = qs[(int64_t)r * ns + j];
+            bessel_basis<T>(k1, X, Y, invR, P, -1, B + jl * nc, 1);
+            for (int r = 0; r < nq; ++r) Q[jl * nq + r] = r < nrhs ? qs[(int64_t)r * ns + j] : mk<T>(0, 0);
         }
         __syncthreads();
         const int cend = E - c0 < CH ? E : c0 + CH;
@@ -102,7 +106,7 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
         // items (leaf, chunk of up to four right-hand sides, coefficient):
         // one basis value read per point serves every right-hand side of the
         // chunk
-        const int nrc = (nrhs + 3) >> 2, nout4 = nrc * nc;
+        const int nout4 = nrc * nc;
         const int nit = (ghi - glo + 1) * nout4;
         for (int it0 = t; it0 < nit; it0 += P2M_THREADS) {
             const int it = glo * nout4 + it0;
@@ -111,7 +115,7 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
             const int r0 = rc * 4, nr = nrhs - r0 < 4 ? nrhs - r0 : 4;
             const int j0 = bnd[g] > c0 ? bnd[g] : c0, j1 = bnd[g + 1] < cend ? bnd[g + 1] : cend;
             // in increasing point order; four points' LDS reads issued together
-            const cx<T> *bp = B + (j0 - c0) * nc + c, *qp = Q + (j0 - c0) * nrhs + r0;
+            const cx<T> *bp = B + (j0 - c0) * nc + c, *qp = Q + (j0 - c0) * nq + r0;
             const int np = j1 - j0;
             // groups of four points summed plainly, the groups' sums added
             // with compensation (FP32: the error does not grow with the
@@ -121,16 +125,21 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
             for (int r = 0; r < 4; ++r) acc[r].zero();
             int jj = 0;
             for (; jj + 4 <= np; jj += 4) {
-                const cx<T> b0 = bp[jj * nc], b1 = bp[(jj + 1) * nc], b2 = bp[(jj + 2) * nc], b3 = bp[(jj + 3) * nc];
+                cx<T> b[4], qv[4][4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (r < nr) {
-                        cx<T> g4 = b0 * qp[jj * nrhs + r];
-                        cfma(g4, b1, qp[(jj + 1) * nrhs + r]);
-                        cfma(g4, b2, qp[(jj + 2) * nrhs + r]);
-                        cfma(g4, b3, qp[(jj + 3) * nrhs + r]);
-                        acc[r].add(g4);
-                    }
+                for (int i = 0; i < 4; ++i) {
+                    b[i] = bp[(jj + i) * nc];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) qv[i][r] = qp[(jj + i) * nq + r];
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    cx<T> g4 = b[0] * qv[0][r];
+                    cfma(g4, b[1], qv[1][r]);
+                    cfma(g4, b[2], qv[2][r]);
+                    cfma(g4, b[3], qv[3][r]);
+                    acc[r].add(g4);
+                }
             }
             cx<T> g4[4];
 #pragma unroll
@@ -138,8 +147,7 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
             for (; jj < np; ++jj) {
                 const cx<T> bj = bp[jj * nc];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (r < nr) cfma(g4[r], bj, qp[jj * nrhs + r]);
+                for (int r = 0; r < 4; ++r) cfma(g4[r], bj, qp[jj * nq + r]);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -156,14 +164,159 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
     }
 }
 
-template <typename T, int PMAX>
-__global__ void __launch_bounds__(P2M_THREADS) k_p2m(P2MArgs<T> a) { p2m_body<T, PMAX>(a, blockIdx.x); }
-template <typename T, int PMAX>
+template <typename T>
+__global__ void __launch_bounds__(P2M_THREADS) k_p2m(P2MArgs<T> a) { p2m_body<T>(a, blockIdx.x); }
+template <typename T>
 __global__ void __launch_bounds__(P2M_THREADS) k_p2m_multi(MultiArgs m)
 {
     int i, bx, by, bz;
     multi_locate(m, i, bx, by, bz);
-    p2m_body<T, PMAX>(static_cast<const P2MArgs<T> *>(m.args)[i], bx);
+    p2m_body<T>(static_cast<const P2MArgs<T> *>(m.args)[i], bx);
+}
+
+// ---------------------------------------------------------------------------
+// P2M by the ascending series of J (DLMF 10.2.2), for leaves whose k1 R is
+// small.  With z = k1 r, the scaled basis value of order +-a is
+//     s_a J_a(z) e^{-+ i a theta} = S_a(zeta) up^a   and   S_a(zeta) dn^a,
+//     S_a(zeta) = sum_m a! zeta^m / (m! (m + a)!),   zeta = -z^2 / 4,
+// with up = (X - iY)/R and dn = -conj(up), so that no recurrence over the
+// order and no division is needed.  S_a is summed by Horner's rule from the
+// term ratios zeta / (m (m + a)); the reciprocals 1/(m (m + a)) come from a
+// constant table.  A wave owns two magnitudes a, a + 1 (four coefficients)
+// of 64 / S leaves, a lane one leaf and a slice of its points (offsets s,
+// s + S, ...); the slices are added by lane permutations at the end, into the
+// group's last lane, which stores the sums.  No LDS,
+// no barrier: every wave is independent.  Everything is computed in FP64
+// (FP64 and FP32 issue at the same rate on the vector units) and stored in
+// the expansion's precision.
+// ---------------------------------------------------------------------------
+constexpr int P2MS_MMAX = 24;   // series terms at most
+constexpr int P2M_SERIES_MIN_PER_LEAF = 40;  // FP32: mean points per leaf for the series form
+constexpr int P2MS_AMAX = 258;  // magnitudes 0..257 (orders up to 256, and one more)
+struct P2MSeriesTable {
+    double v[P2MS_AMAX][P2MS_MMAX];  // v[a][m-1] = 1 / (m (m + a))
+    constexpr P2MSeriesTable() : v()
+    {
+        for (int a = 0; a < P2MS_AMAX; ++a)
+            for (int m = 1; m <= P2MS_MMAX; ++m) v[a][m - 1] = 1.0 / ((double)m * (double)(m + a));
+    }
+};
+__constant__ const P2MSeriesTable p2ms_tab = P2MSeriesTable();
+
+template <typename T>
+struct P2MSArgs {
+    const int32_t *start, *end;
+    const double *xs, *ys;
+    const cx<T> *qs;
+    int64_t ns;
+    int nrhs, P, nbox, ncol, col_lo;
+    double x_lo, w;
+    cx<double> kappa;  // -k1^2 / 4
+    double invR;
+    int S, LB;         // slices per leaf (adjacent lanes), leaves per wave
+    int npair, ncpg;   // magnitude pairs, groups of four pairs (one per block)
+    int nterm;         // series terms
+    cx<T> *M;
+    int32_t *occ;
+};
+template <typename T>
+__device__ __forceinline__ void p2ms_body(const P2MSArgs<T> &A, const int bx, const int rc)
+{
+    const int lg = bx / A.ncpg, cpg = bx - lg * A.ncpg;
+    const int cp = __builtin_amdgcn_readfirstlane(cpg * 4 + (int)(threadIdx.x >> 6));
+    if (cp >= A.npair) return;  // the whole wave: no barrier follows
+    const int lane = threadIdx.x & 63, S = A.S, P = A.P, nc = 2 * P + 1;
+    const int leaf = lg * A.LB + lane / S, s = lane & (S - 1);
+    const bool act = leaf < A.nbox;
+    int j0 = 0, j1 = 0;
+    if (act) {
+        j0 = A.start[leaf];
+        j1 = A.end[leaf];
+    }
+    const int row = leaf / A.ncol, col = A.col_lo + leaf % A.ncol;
+    const double cxp = A.x_lo + (col + 0.5) * A.w, cyp = (row + 0.5) * A.w;
+    const int a = 2 * cp;
+    const bool two = a + 1 <= P;
+    const int r0 = 4 * rc, nr = A.nrhs - r0 < 4 ? A.nrhs - r0 : 4;
+    const cx<double> kappa = A.kappa;
+    const double invR = A.invR;
+    const double *__restrict__ ta = p2ms_tab.v[a];
+    const double *__restrict__ tb = p2ms_tab.v[a + 1];
+    cx<double> acc[4][4];  // coefficients +a, -a, +(a+1), -(a+1); right-hand sides
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][r] = mk<double>(0, 0);
+    for (int j = j0 + s; j < j1; j += S) {
+        const double X = A.xs[j] - cxp, Y = A.ys[j] - cyp;
+        cx<double> qv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r < nr) {
+                const cx<T> q = A.qs[(int64_t)(r0 + r) * A.ns + j];
+                qv[r] = mk<double>(q.re, q.im);
+            } else {
+                qv[r] = mk<double>(0, 0);
+            }
+        }
+        const cx<double> zeta = kappa * (X * X + Y * Y);
+        const cx<double> up = mk<double>(X * invR, -Y * invR);
+        cx<double> pa = mk<double>(1, 0), bb = up;
+        for (int e = a; e; e >>= 1) {
+            if (e & 1) pa = pa * bb;
+            bb = bb * bb;
+        }
+        cx<double> Sa = mk<double>(1, 0), Sb = mk<double>(1, 0);
+        for (int m = A.nterm; m >= 1; --m) {
+            const cx<double> za = zeta * Sa, zb = zeta * Sb;
+            Sa = mk<double>(fma(za.re, ta[m - 1], 1.0), za.im * ta[m - 1]);
+            Sb = mk<double>(fma(zb.re, tb[m - 1], 1.0), zb.im * tb[m - 1]);
+        }
+        const cx<double> pb = pa * up;
+        const double sa = (a & 1) ? -1.0 : 1.0;
+        const cx<double> B0 = pa * Sa;
+        const cx<double> B1 = mk<double>(sa * pa.re, -sa * pa.im) * Sa;
+        const cx<double> B2 = pb * Sb;
+        const cx<double> B3 = mk<double>(-sa * pb.re, sa * pb.im) * Sb;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            cfma(acc[0][r], B0, qv[r]);
+            cfma(acc[1][r], B1, qv[r]);
+            cfma(acc[2][r], B2, qv[r]);
+            cfma(acc[3][r], B3, qv[r]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            acc[i][r].re = group_sum_d(acc[i][r].re, S);
+            acc[i][r].im = group_sum_d(acc[i][r].im, S);
+        }
+    if (!act || s != S - 1) return;
+    cx<T> *Mb = A.M + (int64_t)leaf * nc * A.nrhs;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r >= nr) break;
+        cx<T> *m = Mb + (int64_t)(r0 + r) * nc + P;
+        m[a] = mk<T>((T)acc[0][r].re, (T)acc[0][r].im);
+        if (a > 0) m[-a] = mk<T>((T)acc[1][r].re, (T)acc[1][r].im);
+        if (two) {
+            m[a + 1] = mk<T>((T)acc[2][r].re, (T)acc[2][r].im);
+            m[-a - 1] = mk<T>((T)acc[3][r].re, (T)acc[3][r].im);
+        }
+    }
+    if (cp == 0 && rc == 0) A.occ[leaf] = j1 > j0 ? 1 : 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2m_series(P2MSArgs<T> a) { p2ms_body<T>(a, blockIdx.x, blockIdx.y); }
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2m_series_multi(MultiArgs m)
+{
+    int i, bx, by, bz;
+    multi_locate(m, i, bx, by, bz);
+    p2ms_body<T>(static_cast<const P2MSArgs<T> *>(m.args)[i], bx, by);
 }
 
 // ---------------------------------------------------------------------------
@@ -728,7 +881,7 @@ inline int leaves_per_block(int64_t nbox, int64_t npts, int threads, int max_per
     return (int)(G < 1 ? 1 : (G > LEAF_GMAX ? LEAF_GMAX : G));
 }
 
-template <typename T, int PMAX>
+template <typename T>
 void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
                   int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, hipStream_t st)
 {
@@ -738,7 +891,7 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
     // points per chunk: as many as the LDS share of a block holds, at most
     // P2M_CHMAX; the share is 78 KB (two blocks per compute unit) up to about
     // 0.8 x 256 points per block and compute unit, else 38 KB (four blocks)
-    const size_t per = (size_t)(lv.nc + nrhs) * sizeof(cx<T>);
+    const size_t per = (size_t)(lv.nc + 4 * ((nrhs + 3) / 4)) * sizeof(cx<T>);
     const int64_t load = std::max<int64_t>(ns, launch_batch_points());
     const size_t share = load > (int64_t)(2 * 0.8 * P2M_THREADS * device_shape().cus) ? 38 * 1024 : 78 * 1024;
     int CH = (int)(share / per);
@@ -752,8 +905,55 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
     T invR = (T)(M_SQRT2 / lv.w);
     const P2MArgs<T> a{start, end, xs, ys, reinterpret_cast<const cx<T> *>(qs), ns, nrhs, lv.P, nbox, lv.ncol,
                        lv.col_lo, g.x_lo, lv.w, k1, invR, G, CH, M + lv.off_s, occ + lv.off_occ};
-    emit((const void *)k_p2m<T, PMAX>, (const void *)k_p2m_multi<T, PMAX>, 0, dim3((nbox + G - 1) / G),
+    emit((const void *)k_p2m<T>, (const void *)k_p2m_multi<T>, 0, dim3((nbox + G - 1) / G),
          dim3(P2M_THREADS), sh, st, a);
+}
+
+// Terms of the series P2M for the leaf level, or 0 where its k1 R is too
+// large for the series (then the recurrence form is used).  The terms left
+// out are below 1e-18 (FP64) or 1e-10 (FP32 expansions) of the leading one:
+// |zeta| <= (|k1| R)^2 / 4 and the m-th term is at most |zeta|^m / (m!)^2.
+// Up to k1 R = 3 the terms' sum exceeds the result by a factor I_0(3) < 5 at
+// most, which bounds the rounding error.
+int p2m_series_terms(const Geometry &g, Medium med, bool fp64)
+{
+    const Level &lv = g.lev[g.L];
+    const cx<double> k = k_src(med);
+    const double kr = std::sqrt(k.re * k.re + k.im * k.im) * lv.w * M_SQRT1_2;
+    if (!(kr <= 3.0) || lv.P + 1 >= P2MS_AMAX) return 0;
+    const double z = kr * kr / 4, eps = fp64 ? 1e-18 : 1e-10;
+    double term = 1.0;
+    for (int m = 1; m <= P2MS_MMAX; ++m) {
+        term *= z / ((double)m * m);
+        if (term < eps) return m;
+    }
+    return 0;
+}
+
+template <typename T>
+void p2m_series_dispatch(const int32_t *start, const int32_t *end, const double *xs, const double *ys,
+                         const void *qs, int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M,
+                         int32_t *occ, int nterm, hipStream_t st)
+{
+    const Level &lv = g.lev[g.L];
+    const int nbox = lv.rows_s * lv.ncol;
+    if (nbox == 0) return;
+    // slices per leaf: a power of two up to 64, about an eighth of the mean
+    // points per leaf
+    const double per_leaf = (double)ns / nbox;
+    int S = 1;
+    while (S < 64 && 8.0 * S <= per_leaf) S <<= 1;
+    const int LB = 64 / S;
+    const int npair = (lv.P + 2) / 2;
+    const int ncpg = (npair + 3) / 4;
+    const int nlg = (nbox + LB - 1) / LB;
+    const cx<double> k = k_src(med);
+    const cx<double> kappa = mk<double>(-(k.re * k.re - k.im * k.im) / 4, -(2 * k.re * k.im) / 4);
+    const P2MSArgs<T> a{start, end, xs, ys, reinterpret_cast<const cx<T> *>(qs), ns, nrhs, lv.P, nbox, lv.ncol,
+                        lv.col_lo, g.x_lo, lv.w, kappa, M_SQRT2 / lv.w, S, LB, npair, ncpg, nterm,
+                        M + lv.off_s, occ + lv.off_occ};
+    emit((const void *)k_p2m_series<T>, (const void *)k_p2m_series_multi<T>, 1, dim3(nlg * ncpg, (nrhs + 3) / 4),
+         dim3(256), 0, st, a);
 }
 
 template <typename T, int PMAX>
@@ -863,17 +1063,21 @@ void grad_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx,
 
 template <typename T>
 void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
-                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, hipStream_t st)
+                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, bool series,
+                hipStream_t st)
 {
-    int P = g.lev[g.L].P;
-    if (P <= 16)
-        p2m_dispatch<T, 16>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
-    else if (P <= 32)
-        p2m_dispatch<T, 32>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
-    else if (P <= 64)
-        p2m_dispatch<T, 64>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
+    // the series form wherever its terms allow, except for FP32 expansions of
+    // leaves with few points, where evaluating each point's basis once (the
+    // recurrence form) costs less than the series' per-point work, which is
+    // repeated for every pair of orders
+    const Level &lv = g.lev[g.L];
+    const int64_t nbox = (int64_t)lv.rows_s * lv.ncol;
+    const bool few = sizeof(T) == 4 && nbox > 0 && ns < P2M_SERIES_MIN_PER_LEAF * nbox;
+    const int nterm = series && !few ? p2m_series_terms(g, med, sizeof(T) == 8) : 0;
+    if (nterm > 0)
+        p2m_series_dispatch<T>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, nterm, st);
     else
-        p2m_dispatch<T, 256>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
+        p2m_dispatch<T>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, st);
 }
 
 template <typename T>
@@ -924,7 +1128,7 @@ void launch_l2p_grad(const int32_t *start, const int32_t *end, const int32_t *id
 
 #define LMFMM_INST(T)                                                                                               \
     template void launch_p2m<T>(const int32_t *, const int32_t *, const double *, const double *, const void *,      \
-                                int64_t, int, const Geometry &, Medium, cx<T> *, int32_t *, hipStream_t);           \
+                                int64_t, int, const Geometry &, Medium, cx<T> *, int32_t *, bool, hipStream_t);     \
     template void launch_l2p_near<T>(const int32_t *, const int32_t *, const int32_t *, const double *,             \
                                      const double *, const void *, int64_t, int64_t, int, const Geometry &, Medium, \
                                      const cx<T> *, const LeafShift<T> &, const EvalLevels &, const Node *, int,    \

@@ -419,26 +419,32 @@ __host__ __device__ inline void bessel_ratios(cx<T> k, T X, T Y, int P, cx<T> *t
     J0 = cinv(mk<T>(T(1), T(0)) + U);
 }
 
-// Scaled basis values written to out[(P+q)*stride], q = -P..P.
-template <typename T, int PMAX>
+// Scaled basis values written to out[(P+q)*stride], q = -P..P.  The ratios
+// t_m = J_m / J_{m-1} of the downward recurrence are parked in the slots of
+// q = m and turned into basis values in increasing q, so that no per-thread
+// array of P values is needed.
+template <typename T>
 __host__ __device__ inline void bessel_basis(cx<T> k, T X, T Y, T invR, int P, int sign, cx<T> *out, int stride)
 {
-    cx<T> tm[PMAX + 1];
-    cx<T> J0;
-    bessel_ratios<T, PMAX>(k, X, Y, P, tm, J0);
+    const cx<T> z2 = (k * k) * (X * X + Y * Y);
+    const int N = miller_start<T>(z2, P);
+    cx<T> t = mk<T>(0, 0), tprev = mk<T>(0, 0), U = mk<T>(0, 0);
+    for (int m = N; m > P; --m) miller_step<T>(z2, m, t, tprev, U);
+    for (int m = P; m >= 1; --m) {
+        miller_step<T>(z2, m, t, tprev, U);
+        out[(P + m) * stride] = t;
+    }
+    const cx<T> J0 = cinv(mk<T>(T(1), T(0)) + U);
     out[P * stride] = J0;
-    cx<T> up = mk<T>(X * invR, T(sign) * Y * invR);   // (X + i sign Y)/R
-    cx<T> dn = mk<T>(-X * invR, T(sign) * Y * invR);  // -(X - i sign Y)/R
+    const cx<T> up = mk<T>(X * invR, T(sign) * Y * invR);   // (X + i sign Y)/R
+    const cx<T> dn = mk<T>(-X * invR, T(sign) * Y * invR);  // -(X - i sign Y)/R
     cx<T> vp = J0, vm = J0;
-#pragma unroll PUnroll<PMAX>::n
-    for (int q = 1; q <= PMAX; ++q) {
-        if (q <= P) {
-            cx<T> f = T(2 * q) * tm[q];
-            vp = vp * (f * up);
-            vm = vm * (f * dn);
-            out[(P + q) * stride] = vp;
-            out[(P - q) * stride] = vm;
-        }
+    for (int q = 1; q <= P; ++q) {
+        const cx<T> f = T(2 * q) * out[(P + q) * stride];
+        vp = vp * (f * up);
+        vm = vm * (f * dn);
+        out[(P + q) * stride] = vp;
+        out[(P - q) * stride] = vm;
     }
 }
 
@@ -517,12 +523,14 @@ void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, d
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 
 
-// expand.hip (T = double or float)
-template <typename T>
+// leaf.hip and translate.hip (T = double or float)
 // (occ: the source-box occupancy flags of every level, Level::off_occ; P2M
-// writes the leaves', M2M the parents')
+// writes the leaves', M2M the parents; series: P2M by the ascending series
+// where the leaves' k1 R allows it)
+template <typename T>
 void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, const double *ys, const void *qs,
-                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, hipStream_t st);
+                int64_t ns, int nrhs, const Geometry &g, Medium med, cx<T> *M, int32_t *occ, bool series,
+                hipStream_t st);
 template <typename T>
 // (mfma: on the matrix cores)
 void launch_m2m(const Geometry &g, int lchild, const cx<T> *tab, cx<T> *M, int32_t *occ, int nrhs, bool mfma,

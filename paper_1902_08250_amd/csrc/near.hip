@@ -63,17 +63,6 @@ __device__ inline double wave_max_d(double v)
     return v;
 }
 
-// One DPP lane move of a double (both halves); lanes of rows outside ROWMASK
-// read 0.
-template <int CTRL, int ROWMASK>
-__device__ inline double dpp_d(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
 // Sum over the wave in a fixed order, complete in lane 63: pairs, quads,
 // half rows and rows by lane permutations within each row of 16, then row 0
 // into row 1, row 2 into row 3, and rows 0-1 into row 3.

@@ -243,6 +243,7 @@ struct lmfmm_plan_s {
     bool m2l_mfma = true;    // M2L on the matrix cores (else vector matrix-vector products)
     bool eval_levels = true; // leaves evaluate the expansion of the level where their far field is complete
     bool shift_mfma = true;  // M2M and L2L on the matrix cores (else vector matrix-vector products)
+    bool p2m_series = true;  // P2M by the ascending series where k1 R is small (else the recurrence form)
 
     DevBuf ws;
     double *h_bbox = nullptr;  // pinned, host-coherent: [0..6] box, [8] sequence number, [12] error copy
@@ -931,6 +932,11 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         p->shift_mfma = v == "1";
         return LMFMM_OK;
     }
+    if (k == "p2m_series") {
+        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "p2m_series must be 0 or 1");
+        p->p2m_series = v == "1";
+        return LMFMM_OK;
+    }
     if (k == "eval_levels") {
         if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "eval_levels must be 0 or 1");
         p->eval_levels = v == "1";
@@ -1452,7 +1458,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         if (far) {
             timed(LMFMM_K_P2M, 1);
             set_stage(S_P2M);
-            launch_p2m<T>(start, end, xs, ys, tb.qs, ns, nrhs, g, med, M, occ, sx);
+            launch_p2m<T>(start, end, xs, ys, tb.qs, ns, nrhs, g, med, M, occ, p->p2m_series, sx);
             timed_done();
             for (int l = L; l >= ltop + 1; --l) {
                 const LevelTables &tb = vt.lt[l];
