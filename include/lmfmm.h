@@ -124,6 +124,10 @@ int lmfmm_destroy(lmfmm_plan plan);
  *   "shift_mfma"  "1" (default): M2M and L2L as products of the shift tables
  *                 with tiles of boxes x right-hand sides on the matrix cores;
  *                 "0": one matrix-vector product per box
+ *   "p2m_series"  "1" (default): P2M by the ascending series of J_q where the
+ *                 leaves' k1 R <= 3 (for FP32 expansions only where leaves hold
+ *                 40 points or more on average); "0": the recurrence form
+ *                 everywhere
  *   "eval_levels" "1" (default): each leaf evaluates the local expansion of
  *                 the level where its far field is complete (its ancestor's),
  *                 and only the expansions read are shifted down; "0": every

@@ -146,6 +146,43 @@ def test_mid_fmm_vs_direct(torch_cuda, mid, mid_direct, levels):
         assert rel(u[r], mid_direct[r]) < 1e-10
 
 
+@pytest.mark.parametrize("levels", [2, 4, 7])
+def test_p2m_forms_match_direct(torch_cuda, mid, mid_direct, levels):
+    """P2M by the ascending series (default where k1 R allows it) and by the
+    recurrence form (option p2m_series = 0), FP64 and mixed, 11 right-hand
+    sides (three chunks of four), against the GPU direct sum.  Level 2 puts
+    hundreds of points in a leaf (64 lanes per leaf in the series form), level
+    7 about one."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    say("P2M series / recurrence, 4000x3000 nrhs=11 levels", levels)
+    for prec, tol in (("c128", 1e-10), ("c64", TOL["c64"])):
+        q = mid["q"] if prec == "c128" else mid["q"].astype(np.complex64)
+        for ser in ("1", "0"):
+            pl = Plan(mid["k"], mid["d"], order=20 if prec == "c128" else 16, tol=1e-10 if prec == "c128" else 1e-6,
+                      levels=levels)
+            pl.set_option("p2m_series", ser)
+            u = host(pl.apply(dev(mid["src"]), dev(q), dev(mid["tgt"])))
+            check(u, mid_direct, tol, f"{prec} L={levels} p2m_series={ser} vs direct", say)
+
+
+def test_p2m_large_k1r_uses_recurrence_form(torch_cuda):
+    """A top layer with k1 = 60: at three levels the leaves' k1 R is about
+    5.3, beyond the series form, so P2M takes the recurrence form whatever the
+    option says; FP64 and mixed FMM against the GPU direct sum."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    rng = np.random.default_rng(78)
+    src, tgt, q, _ = workloads.draw_instance(rng, 3000, 2000, (0, 1), (0.05, 1), (-0.95, -0.05), 2)
+    k = (60 + 0.01j, 40 + 0.01j, 30 + 0.01j)
+    say("k1 = 60, 3000x2000, levels 3")
+    ref = host(Plan(k, 1.0, order=20, tol=1e-10).direct(dev(src), dev(q), dev(tgt)))
+    for prec, tol in (("c128", 1e-10), ("c64", TOL["c64"])):
+        qq = q if prec == "c128" else q.astype(np.complex64)
+        pl = Plan(k, 1.0, order=20 if prec == "c128" else 16, tol=1e-10 if prec == "c128" else 1e-6, levels=3)
+        u = host(pl.apply(dev(src), dev(qq), dev(tgt)))
+        say("orders", pl.stats()["order"])
+        check(u, ref, tol, f"{prec} k1=60 L=3 vs direct", say)
+
+
 @pytest.mark.parametrize("levels", [2, 5, 7])
 def test_eval_levels_match_leaf_evaluation(torch_cuda, mid, mid_direct, levels):
     """Leaves evaluating the expansion of the level where their far field is
