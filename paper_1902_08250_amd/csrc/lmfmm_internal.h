@@ -61,10 +61,17 @@ struct RecLaunch {
     size_t shmem;
     size_t align;             // alignment of the argument struct
     std::vector<char> args;  // the argument struct's bytes
+    double cost = 0;         // estimated work per block (merged launches start the costliest instances first)
 };
 struct Recorder {
     std::vector<RecLaunch> v;
 };
+// Estimated work per block of the next recorded launches (0: none).
+inline double &launch_cost()
+{
+    static thread_local double c = 0;
+    return c;
+}
 inline Recorder *&launch_recorder()
 {
     static thread_local Recorder *r = nullptr;
@@ -113,6 +120,7 @@ inline void emit(const void *single, const void *multi, int sub, dim3 grid, dim3
         L.block = block;
         L.shmem = sh;
         L.align = alignof(A);
+        L.cost = launch_cost();
         L.args.assign(reinterpret_cast<const char *>(&a), reinterpret_cast<const char *>(&a) + sizeof(A));
         r->v.push_back(std::move(L));
         return;

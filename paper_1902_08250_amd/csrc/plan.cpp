@@ -2039,6 +2039,10 @@ static int batch_record_merge(lmfmm_batch_s *b, const lmfmm_instance *inst, int 
                all[e].L.block.x == f.block.x && all[e].L.block.y == f.block.y && all[e].L.block.z == f.block.z)
             ++e;
         if (!f.multi) return fail(LMFMM_EINVAL, "a kernel of this apply has no batched form");
+        // instances with the costliest blocks first: the dispatcher hands out
+        // blocks in index order, so their long blocks do not start last
+        std::stable_sort(all.begin() + s, all.begin() + e,
+                         [](const Rec &a, const Rec &c) { return a.L.cost > c.L.cost; });
         BatchLaunch BL;
         BL.fn = f.multi;
         BL.block = f.block;

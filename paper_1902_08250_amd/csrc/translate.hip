@@ -345,12 +345,27 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
     const cx<T> *__restrict__ At = a.atab[li];
     const int nks = (nc + 3) >> 2;
     vx4 sr = {0, 0, 0, 0}, si = {0, 0, 0, 0}, cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    const int rows_s = a.rows_s[li];
+    const bool top = a.top[li];
+    const int32_t *__restrict__ occ = a.occ[li];
+    // a slot's source box for this lane's column, and whether it is in range
+    // (adjacent parents at the levels below the coarsest); an empty source box
+    // has a zero expansion, so its flag is read too.  The next slot's entry and
+    // flag are read while the current slot computes.
+    auto probe = [&](int ss, int &rs_, int &csl_, int &flag_) {
+        rs_ = cls3[3 * ss + 1];
+        const int cs = col + cls3[3 * ss + 2];
+        csl_ = cs - col_lo;
+        const int dp = (cs >> 1) - (col >> 1);
+        const bool in = nvalid && rs_ < rows_s && csl_ >= 0 && csl_ < ncol && (top || (dp >= -1 && dp <= 1));
+        flag_ = in ? (occ ? occ[(int64_t)rs_ * ncol + csl_] : 1) : 0;
+    };
+    int rsN = 0, cslN = 0, flagN = 0;
+    if (s0 + w < s1) probe(s0 + w, rsN, cslN, flagN);
     for (int s = s0 + w; s < s1; s += NW) {
-        const int rs = cls3[3 * s + 1], dc = cls3[3 * s + 2];
-        const int cs = col + dc, csl = cs - col_lo, dp = (cs >> 1) - (col >> 1);
-        bool ok = nvalid && rs < a.rows_s[li] && csl >= 0 && csl < ncol && (a.top[li] || (dp >= -1 && dp <= 1));
-        // an empty source box has a zero expansion: nothing to translate
-        if (ok && a.occ[li]) ok = a.occ[li][(int64_t)rs * ncol + csl] != 0;
+        const int rs = rsN, csl = cslN;
+        const bool ok = flagN != 0;
+        if (s + NW < s1) probe(s + NW, rsN, cslN, flagN);
         if (!__any(ok)) continue;
         const cx<T> *__restrict__ As = At + (int64_t)s * nc * nc;
         const cx<T> *__restrict__ xb = Ms + (((int64_t)rs * ncol + (ok ? csl : 0)) * k.nrhs + (ok ? r : 0)) * nc;
@@ -677,8 +692,13 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
     if (mfma) {
         if (part != 2 && levels(true, a) > 0) {
             const M2LMK<T> k{a, nrhs, RC, NB, M, Lc};
+            // a block's slots run over every source box of the level, each a
+            // product of about nc^2 / 4 steps
+            const Level &lt = g.lev[g.ltop];
+            launch_cost() = (double)lt.rows_s * lt.ncol * lt.nc * lt.nc;
             emit((const void *)k_m2l_mfma<T, MW_TOP>, (const void *)k_m2l_mfma_multi<T, MW_TOP>, 0,
                  dim3(a.blk0[a.n]), dim3(64 * MW_TOP), 0, st, k);
+            launch_cost() = 0;
         }
         if (part != 1 && levels(false, a) > 0) {
             const M2LMK<T> k{a, nrhs, RC, NB, M, Lc};
