@@ -508,9 +508,23 @@ __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, cons
                 const int she = L - e, nce = 2 * s_P[s] + 1;
                 const int64_t be = (int64_t)(row >> she) * (ev.on ? ev.ncol[e] : ncol) + (col >> she) -
                                    (col_lo >> she);
+                // nr rows of nce coefficients, contiguous in both: every load of
+                // the copy is issued before the first store
                 const cx<T> *src = A.Lc + ev.off[e] + (be * nrhs + r0) * nce;
-                for (int r = 0; r < nr; ++r)
-                    for (int c = lane; c < nce; c += 64) Lslot[r * nce + c] = src[(int64_t)r * nce + c];
+                const int ntot = nr * nce;
+                for (int e0 = 0; e0 < ntot; e0 += 8 * 64) {
+                    cx<T> v[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int ee = e0 + k * 64 + lane;
+                        v[k] = ee < ntot ? src[ee] : mk<T>(0, 0);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int ee = e0 + k * 64 + lane;
+                        if (ee < ntot) Lslot[ee] = v[k];
+                    }
+                }
             }
         }
     }
