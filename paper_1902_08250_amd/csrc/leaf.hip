@@ -913,7 +913,15 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
     const size_t sh = (size_t)CH * per;
     int per_cu = (int)(device_shape().lds / (sh > 0 ? sh : 1));
     per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
-    const int G = leaves_per_block(nbox, ns, CH < P2M_THREADS ? CH : P2M_THREADS, per_cu);
+    int G = leaves_per_block(nbox, ns, CH < P2M_THREADS ? CH : P2M_THREADS, per_cu);
+    // in a merged launch of several instances the others fill the compute
+    // units too: take enough leaves for about 0.8 x 256 points per block
+    if (launch_batch_points() > ns) {
+        const double per_leaf = (double)ns / nbox;
+        const int64_t gf =
+            (int64_t)std::ceil(0.8 * (CH < P2M_THREADS ? CH : P2M_THREADS) / std::max(per_leaf, 1.0 / LEAF_GMAX));
+        G = (int)std::max<int64_t>(G, std::min<int64_t>(gf, LEAF_GMAX));
+    }
     cx<double> kd = k_src(med);
     cx<T> k1 = mk<T>((T)kd.re, (T)kd.im);
     T invR = (T)(M_SQRT2 / lv.w);
@@ -1016,6 +1024,15 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
             k = k < 1 ? 1 : (k > 2 ? 2 : k);
             const int64_t gd = ((int64_t)(nbox - n_if) + k * dv.cus - 1) / (k * dv.cus);
             G = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(gd, L2P_GMAX), gmax_deep));
+            // in a merged launch of several instances the others fill the
+            // compute units too: take enough leaves for about 0.8 x 512
+            // targets per block instead of spreading this instance's few
+            // targets over nearly empty blocks
+            if (launch_batch_points() > nt && nbox > n_if) {
+                const double per_leaf = (double)nt / nbox;
+                const int64_t gf = (int64_t)std::ceil(0.8 * L2P_THREADS / std::max(per_leaf, 1.0 / L2P_GMAX));
+                G = (int)std::max<int64_t>(G, std::min<int64_t>(std::min<int64_t>(gf, L2P_GMAX), gmax_deep));
+            }
         }
         const int nb_if = (n_if + G_if - 1) / G_if;
         const int nblk = nb_if + (nbox - n_if + G - 1) / G;
