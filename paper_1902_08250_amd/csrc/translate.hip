@@ -290,7 +290,11 @@ __global__ void __launch_bounds__(64 * M2L_DW) k_m2l_all_multi(MultiArgs m)
 // (l / 16 + 4 v, l % 16).
 // ---------------------------------------------------------------------------
 constexpr int MW = 4;       // waves per block
-constexpr int MW_TOP = 16;  // waves per block at the coarsest level (every non-adjacent pair: long slot lists)
+// waves per block at the coarsest level (every non-adjacent pair: long slot
+// lists): 16 in FP32; 8 in FP64, whose operand prefetch needs more registers
+// than a 16-wave block allows
+template <typename T>
+constexpr int mw_top() { return sizeof(T) == 8 ? 8 : 16; }
 constexpr int MKS = 8;      // k-steps (4 coefficients each) whose operands are loaded together
 template <typename T>
 struct M2LMK {
@@ -350,40 +354,56 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
     const int32_t *__restrict__ occ = a.occ[li];
     // a slot's source box for this lane's column, and whether it is in range
     // (adjacent parents at the levels below the coarsest); an empty source box
-    // has a zero expansion, so its flag is read too.  The next slot's entry and
-    // flag are read while the current slot computes.
-    auto probe = [&](int ss, int &rs_, int &csl_, int &flag_) {
+    // has a zero expansion, so its flag is read too and the slot skipped when
+    // no lane has a source.  The next slot's entry, flag and first MKS steps of
+    // operands are read while the current slot computes (operands of boxes in
+    // range; those of empty boxes are dropped when used).
+    auto probe = [&](int ss, int &rs_, int &csl_, bool &in_, int &flag_) {
         rs_ = cls3[3 * ss + 1];
         const int cs = col + cls3[3 * ss + 2];
         csl_ = cs - col_lo;
         const int dp = (cs >> 1) - (col >> 1);
-        const bool in = nvalid && rs_ < rows_s && csl_ >= 0 && csl_ < ncol && (top || (dp >= -1 && dp <= 1));
-        flag_ = in ? (occ ? occ[(int64_t)rs_ * ncol + csl_] : 1) : 0;
+        in_ = nvalid && rs_ < rows_s && csl_ >= 0 && csl_ < ncol && (top || (dp >= -1 && dp <= 1));
+        flag_ = in_ ? (occ ? occ[(int64_t)rs_ * ncol + csl_] : 1) : 0;
     };
-    int rsN = 0, cslN = 0, flagN = 0;
-    if (s0 + w < s1) probe(s0 + w, rsN, cslN, flagN);
-    for (int s = s0 + w; s < s1; s += NW) {
-        const int rs = rsN, csl = cslN;
-        const bool ok = flagN != 0;
-        if (s + NW < s1) probe(s + NW, rsN, cslN, flagN);
-        if (!__any(ok)) continue;
-        const cx<T> *__restrict__ As = At + (int64_t)s * nc * nc;
-        const cx<T> *__restrict__ xb = Ms + (((int64_t)rs * ncol + (ok ? csl : 0)) * k.nrhs + (ok ? r : 0)) * nc;
-        vx4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
-        for (int k0 = 0; k0 < nks; k0 += MKS) {
-            cx<T> av[MKS], bv[MKS];
+    auto load_steps = [&](int ss, int rs_, int csl_, bool in_, int k0, cx<T> (&av)[MKS], cx<T> (&bv)[MKS]) {
+        const cx<T> *__restrict__ As = At + (int64_t)ss * nc * nc;
+        const cx<T> *__restrict__ xb = Ms + (((int64_t)(in_ ? rs_ : 0) * ncol + (in_ ? csl_ : 0)) * k.nrhs + (in_ ? r : 0)) * nc;
 #pragma unroll
-            for (int u = 0; u < MKS; ++u) {
-                const int kq = 4 * (k0 + u) + kk;
-                const bool kin = kq < nc;
-                av[u] = (kin && p < nc) ? As[(int64_t)kq * nc + p] : mk<T>(0, 0);
-                bv[u] = (kin && ok) ? xb[kq] : mk<T>(0, 0);
-            }
-#pragma unroll
-            for (int u = 0; u < MKS; ++u)
-                if (k0 + u < nks) mfma_c(dr, di, av[u], bv[u]);
+        for (int u = 0; u < MKS; ++u) {
+            const int kq = 4 * (k0 + u) + kk;
+            const bool kin = kq < nc;
+            av[u] = (kin && p < nc) ? As[(int64_t)kq * nc + p] : mk<T>(0, 0);
+            bv[u] = (kin && in_) ? xb[kq] : mk<T>(0, 0);
         }
-        if (F32) {
+    };
+    if (F32) {
+        // FP32: the next slot's entry and flag only (a prefetch of operands was
+        // slower: more registers, fewer waves)
+        int rsN = 0, cslN = 0, flagN = 0;
+        bool inN = false;
+        if (s0 + w < s1) probe(s0 + w, rsN, cslN, inN, flagN);
+        for (int s = s0 + w; s < s1; s += NW) {
+            const int rs = rsN, csl = cslN;
+            const bool ok = flagN != 0;
+            if (s + NW < s1) probe(s + NW, rsN, cslN, inN, flagN);
+            if (!__any(ok)) continue;
+            const cx<T> *__restrict__ As = At + (int64_t)s * nc * nc;
+            const cx<T> *__restrict__ xb = Ms + (((int64_t)rs * ncol + (ok ? csl : 0)) * k.nrhs + (ok ? r : 0)) * nc;
+            vx4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+            for (int k0 = 0; k0 < nks; k0 += MKS) {
+                cx<T> av[MKS], bv[MKS];
+#pragma unroll
+                for (int u = 0; u < MKS; ++u) {
+                    const int kq = 4 * (k0 + u) + kk;
+                    const bool kin = kq < nc;
+                    av[u] = (kin && p < nc) ? As[(int64_t)kq * nc + p] : mk<T>(0, 0);
+                    bv[u] = (kin && ok) ? xb[kq] : mk<T>(0, 0);
+                }
+#pragma unroll
+                for (int u = 0; u < MKS; ++u)
+                    if (k0 + u < nks) mfma_c(dr, di, av[u], bv[u]);
+            }
             // compensated addition of the slot's product to the wave's sum
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -394,7 +414,40 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
                 sr[v] = tr;
                 si[v] = ti;
             }
-        } else {
+        }
+    } else {
+        int rsN = 0, cslN = 0, flagN = 0;
+        bool inN = false;
+        cx<T> avN[MKS], bvN[MKS];
+        if (s0 + w < s1) {
+            probe(s0 + w, rsN, cslN, inN, flagN);
+            load_steps(s0 + w, rsN, cslN, inN, 0, avN, bvN);
+        }
+        for (int s = s0 + w; s < s1; s += NW) {
+            const int rs = rsN, csl = cslN;
+            const bool in = inN, ok = flagN != 0;
+            cx<T> av0[MKS], bv0[MKS];
+#pragma unroll
+            for (int u = 0; u < MKS; ++u) {
+                av0[u] = avN[u];
+                bv0[u] = ok ? bvN[u] : mk<T>(0, 0);
+            }
+            if (s + NW < s1) {
+                probe(s + NW, rsN, cslN, inN, flagN);
+                load_steps(s + NW, rsN, cslN, inN, 0, avN, bvN);
+            }
+            if (!__any(ok)) continue;
+            vx4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < MKS; ++u)
+                if (u < nks) mfma_c(dr, di, av0[u], bv0[u]);
+            for (int k0 = MKS; k0 < nks; k0 += MKS) {
+                cx<T> av[MKS], bv[MKS];
+                load_steps(s, rs, csl, in, k0, av, bv);
+#pragma unroll
+                for (int u = 0; u < MKS; ++u)
+                    if (k0 + u < nks) mfma_c(dr, di, av[u], ok ? bv[u] : mk<T>(0, 0));
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 sr[v] += dr[v];
@@ -696,8 +749,8 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
             // product of about nc^2 / 4 steps
             const Level &lt = g.lev[g.ltop];
             launch_cost() = (double)lt.rows_s * lt.ncol * lt.nc * lt.nc;
-            emit((const void *)k_m2l_mfma<T, MW_TOP>, (const void *)k_m2l_mfma_multi<T, MW_TOP>, 0,
-                 dim3(a.blk0[a.n]), dim3(64 * MW_TOP), 0, st, k);
+            emit((const void *)k_m2l_mfma<T, mw_top<T>()>, (const void *)k_m2l_mfma_multi<T, mw_top<T>()>, 0,
+                 dim3(a.blk0[a.n]), dim3(64 * mw_top<T>()), 0, st, k);
             launch_cost() = 0;
         }
         if (part != 1 && levels(false, a) > 0) {
