@@ -206,6 +206,7 @@ struct M2LLevels {
     int n;
     int blk0[M2L_MAXLEV + 1];  // first block of each listed level; blk0[n] = total
     int nc[M2L_MAXLEV], ncol[M2L_MAXLEV], col_lo[M2L_MAXLEV], rows_s[M2L_MAXLEV], top[M2L_MAXLEV];
+    int nrow[M2L_MAXLEV];  // target rows of the launch at each level
     int64_t off_s[M2L_MAXLEV], off_t[M2L_MAXLEV];
     const int32_t *occ[M2L_MAXLEV];  // source-box occupancy flags (null: not used)
     const cx<T> *atab[M2L_MAXLEV];
@@ -333,11 +334,20 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
     int loc = bx - a.blk0[li];
     const int nc = a.nc[li], ncol = a.ncol[li], col_lo = a.col_lo[li];
     const int npt = (nc + 15) >> 4, ntile = (ncol + k.NB - 1) / k.NB, nrc = (k.nrhs + k.RC - 1) / k.RC;
-    const int pt = loc % npt;
-    loc /= npt;
-    const int rcn = loc % nrc;
-    loc /= nrc;
-    const int tile = loc % ntile, row = loc / ntile;
+    // Blocks come in runs of 8 x ntile: eight groups (row, right-hand-side
+    // chunk, coefficient tile), each with all its column tiles at indices
+    // eight apart.  Blocks are handed to the XCDs in turn, so a group's tiles,
+    // which read the same class tables, run on one XCD at about the same time
+    // and its L2 fetches those tables once.  Groups past the last are empty.
+    const int ngroup = a.nrow[li] * nrc * npt;
+    const int ghi = loc / (8 * ntile), rem = loc - ghi * 8 * ntile;
+    const int tile = rem >> 3;
+    int grp = ghi * 8 + (rem & 7);
+    if (grp >= ngroup) return;  // the whole block: no barrier has been reached
+    const int pt = grp % npt;
+    grp /= npt;
+    const int rcn = grp % nrc;
+    const int row = grp / nrc;
     const int n = l & 15, kk = l >> 4;
     const int j = n / k.RC, r = rcn * k.RC + n % k.RC;
     const int colL = tile * k.NB + j, col = col_lo + colL;
@@ -733,8 +743,9 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
             a.atab[i] = atab[l - l0];
             a.cls3[i] = cls3[l - l0];
             a.row_off[i] = row_off[l - l0];
+            a.nrow[i] = rows;
             if (mfma)
-                blk += rows * ((lv.ncol + NB - 1) / NB) * ((nrhs + RC - 1) / RC) * ((lv.nc + 15) / 16);
+                blk += (rows * ((nrhs + RC - 1) / RC) * ((lv.nc + 15) / 16) + 7) / 8 * 8 * ((lv.ncol + NB - 1) / NB);
             else
                 blk += rows * lv.ncol;
         }
