@@ -71,10 +71,10 @@ def parse():
     return ap.parse_args()
 
 
-def recorded_traffic(prefix, path=TRAFFIC_FILE):
-    """HBM bytes per launch of the kernels whose names start with `prefix`
-    (averaged over their dispatches) from a committed counter summary, if it
-    was taken on the current kernel sources (else None)."""
+def recorded_traffic(prefixes, path=TRAFFIC_FILE):
+    """HBM bytes per launch of the kernels whose names start with one of
+    `prefixes` (averaged over all their dispatches) from a committed counter
+    summary, if it was taken on the current kernel sources (else None)."""
     try:
         text = open(path).read()
     except OSError:
@@ -83,10 +83,11 @@ def recorded_traffic(prefix, path=TRAFFIC_FILE):
     if not m or m.group(1) != source_hash():
         return None
     tot, n = 0.0, 0
-    for m in re.finditer(r"^\|\s*%s[^|]*\|\s*(\d+)\s*\|[^\n]*?\|\s*bytes_per_launch=([0-9.eE+]+)" % re.escape(prefix),
-                         text, re.M):
-        tot += float(m.group(2)) * int(m.group(1))
-        n += int(m.group(1))
+    for prefix in prefixes:
+        for m in re.finditer(r"^\|\s*%s[^|]*\|\s*(\d+)\s*\|[^\n]*?\|\s*bytes_per_launch=([0-9.eE+]+)" % re.escape(prefix),
+                             text, re.M):
+            tot += float(m.group(2)) * int(m.group(1))
+            n += int(m.group(1))
     return tot / n if n else None
 
 
@@ -117,8 +118,8 @@ def roofline(st, peak_key, kernel_names, bound="alu", traffic_file=TRAFFIC_FILE)
     avg_s = cand[dom] / nap / launches * 1e-3
     flops_launch = st["kernel_flops"][dom] / launches
     achieved = flops_launch / avg_s
-    kname = kernel_names[dom]
-    traffic = recorded_traffic(kname, traffic_file)
+    kname = " + ".join(kernel_names[dom])
+    traffic = recorded_traffic(kernel_names[dom], traffic_file)
     return {"kernel": kname, "class": dom, "bound": bound, "achieved": achieved / 1e12,
             "peak": PEAK[peak_key] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[peak_key],
             "traffic": traffic, "flops_per_launch": flops_launch, "launches_per_apply": launches,
@@ -166,10 +167,14 @@ def time_batch(torch, b, items, outs, steps, warmup):
     return t, st
 
 
-# kernel class -> name prefix of its merged kernels (every template instance)
-BATCH_KERNELS = {"p2m": "k_p2m_multi<float", "m2m": "k_up_multi<float", "m2l": "k_m2l_mfma_multi<float",
-                 "l2l": "k_down_multi<float", "near_sweep": "k_near_sweep_multi<float",
-                 "l2p_near": "k_l2p_multi<float"}
+# kernel class -> name prefixes of its merged kernels (every template instance
+# and form the plans may choose)
+BATCH_KERNELS = {"p2m": ("k_p2m_multi<float", "k_p2m_series_multi<float"),
+                 "m2m": ("k_shift_mfma_multi<float, true", "k_up_multi<float"),
+                 "m2l": ("k_m2l_mfma_multi<float", "k_m2l_all_multi<float"),
+                 "l2l": ("k_shift_mfma_multi<float, false", "k_down_multi<float"),
+                 "near_sweep": ("k_near_sweep_multi<float",),
+                 "l2p_near": ("k_l2p_multi<float", "k_l2p_near_multi<float")}
 
 
 def batched_legs(torch, args):
@@ -241,8 +246,9 @@ def batched_legs(torch, args):
     return inst, out
 
 
-UNIFORM_KERNELS = {"p2m": "k_p2m<float", "m2m": "k_up<float", "m2l": "k_m2l_mfma<float", "l2l": "k_down<float",
-                   "l2p_near": "k_l2p<float"}
+UNIFORM_KERNELS = {"p2m": ("k_p2m<float", "k_p2m_series<float"), "m2m": ("k_shift_mfma<float, true", "k_up<float"),
+                   "m2l": ("k_m2l_mfma<float", "k_m2l_all<float"), "l2l": ("k_shift_mfma<float, false", "k_down<float"),
+                   "l2p_near": ("k_l2p<float", "k_l2p_near<float")}
 
 
 def run_plan(torch, Plan, w, precision, steps, warmup, timing=False, domain=None):

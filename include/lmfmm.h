@@ -118,9 +118,11 @@ int lmfmm_destroy(lmfmm_plan plan);
  *                 0): the total field u satisfies u_y + i k1 alpha u = 0 on
  *                 y = 0 (density (s1 + i k1 alpha) / (s1 - i k1 alpha)).
  *                 Setting it discards the plan's tables.
- *   "m2l_mfma"    "1" (default): multipole-to-local as products of the class
- *                 tables with tiles of boxes x right-hand sides on the matrix
- *                 cores; "0": one matrix-vector product per box pair list
+ *   "m2l_mfma"    "1": multipole-to-local as products of the class tables
+ *                 with tiles of boxes x right-hand sides on the matrix cores;
+ *                 "0": one matrix-vector product per box pair list; "auto"
+ *                 (default): the matrix cores from 4 right-hand sides on
+ *                 (FP32 expansions) or 3 (FP64), the vector form below
  *   "shift_mfma"  "1" (default): M2M and L2L as products of the shift tables
  *                 with tiles of boxes x right-hand sides on the matrix cores;
  *                 "0": one matrix-vector product per box

@@ -27,10 +27,10 @@ namespace {
 // points are contiguous in the grouped order (as are their densities, qs),
 // and walks those points in chunks of CH: a thread per point evaluates the
 // point's scaled basis into LDS, with the point's densities padded with zeros
-// to a multiple of four right-hand sides, then threads over (leaf, chunk of
-// four right-hand sides, coefficient) add the points of their leaf in the
-// chunk, in index order; the padding keeps that loop free of per-lane
-// branches.  The output block of the G leaves is contiguous, and so are the
+// to a multiple of R4 right-hand sides (1, 2 or 4, from nrhs), then threads
+// over (leaf, chunk of R4 right-hand sides, coefficient) add the points of
+// their leaf in the chunk, in index order; the padding keeps that loop free
+// of per-lane branches.  The output block of the G leaves is contiguous, and so are the
 // threads' stores.  Leaves without points get zeros.
 // ---------------------------------------------------------------------------
 constexpr int P2M_THREADS = 256;
@@ -50,7 +50,7 @@ struct P2MArgs {
     cx<T> *M;
     int32_t *occ;  // the leaves' occupancy flags
 };
-template <typename T>
+template <typename T, int R4>
 __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
 {
     const int32_t *__restrict__ start = A.start;
@@ -67,7 +67,7 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
     extern __shared__ unsigned char smem_raw[];
     __shared__ int bnd[LEAF_GMAX + 1];
     const int nc = 2 * P + 1;
-    const int nrc = (nrhs + 3) >> 2, nq = 4 * nrc;
+    const int nrc = (nrhs + R4 - 1) / R4, nq = R4 * nrc;
     cx<T> *B = reinterpret_cast<cx<T> *>(smem_raw);  // [CH][nc]
     cx<T> *Q = B + CH * nc;                          // [CH][nq]
     const int t = threadIdx.x;
@@ -112,7 +112,7 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
             const int it = glo * nout4 + it0;
             const int g = it / nout4, o = it - g * nout4;
             const int rc = o / nc, c = o - rc * nc;
-            const int r0 = rc * 4, nr = nrhs - r0 < 4 ? nrhs - r0 : 4;
+            const int r0 = rc * R4, nr = nrhs - r0 < R4 ? nrhs - r0 : R4;
             const int j0 = bnd[g] > c0 ? bnd[g] : c0, j1 = bnd[g + 1] < cend ? bnd[g + 1] : cend;
             // in increasing point order; four points' LDS reads issued together
             const cx<T> *bp = B + (j0 - c0) * nc + c, *qp = Q + (j0 - c0) * nq + r0;
@@ -120,20 +120,20 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
             // groups of four points summed plainly, the groups' sums added
             // with compensation (FP32: the error does not grow with the
             // leaf's point count)
-            CAcc<T> acc[4];
+            CAcc<T> acc[R4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[r].zero();
+            for (int r = 0; r < R4; ++r) acc[r].zero();
             int jj = 0;
             for (; jj + 4 <= np; jj += 4) {
-                cx<T> b[4], qv[4][4];
+                cx<T> b[4], qv[4][R4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     b[i] = bp[(jj + i) * nc];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) qv[i][r] = qp[(jj + i) * nq + r];
+                    for (int r = 0; r < R4; ++r) qv[i][r] = qp[(jj + i) * nq + r];
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < R4; ++r) {
                     cx<T> g4 = b[0] * qv[0][r];
                     cfma(g4, b[1], qv[1][r]);
                     cfma(g4, b[2], qv[2][r]);
@@ -141,16 +141,16 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
                     acc[r].add(g4);
                 }
             }
-            cx<T> g4[4];
+            cx<T> g4[R4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) g4[r] = mk<T>(0, 0);
+            for (int r = 0; r < R4; ++r) g4[r] = mk<T>(0, 0);
             for (; jj < np; ++jj) {
                 const cx<T> bj = bp[jj * nc];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cfma(g4[r], bj, qp[jj * nq + r]);
+                for (int r = 0; r < R4; ++r) cfma(g4[r], bj, qp[jj * nq + r]);
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < R4; ++r)
                 if (r < nr) {
                     acc[r].add(g4[r]);
                     cx<T> &dst = Mb[(int64_t)g * nout + (r0 + r) * nc + c];
@@ -164,14 +164,14 @@ __device__ __forceinline__ void p2m_body(const P2MArgs<T> &A, const int bx)
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(P2M_THREADS) k_p2m(P2MArgs<T> a) { p2m_body<T>(a, blockIdx.x); }
-template <typename T>
+template <typename T, int R4>
+__global__ void __launch_bounds__(P2M_THREADS) k_p2m(P2MArgs<T> a) { p2m_body<T, R4>(a, blockIdx.x); }
+template <typename T, int R4>
 __global__ void __launch_bounds__(P2M_THREADS) k_p2m_multi(MultiArgs m)
 {
     int i, bx, by, bz;
     multi_locate(m, i, bx, by, bz);
-    p2m_body<T>(static_cast<const P2MArgs<T> *>(m.args)[i], bx);
+    p2m_body<T, R4>(static_cast<const P2MArgs<T> *>(m.args)[i], bx);
 }
 
 // ---------------------------------------------------------------------------
@@ -905,7 +905,9 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
     // points per chunk: as many as the LDS share of a block holds, at most
     // P2M_CHMAX; the share is 78 KB (two blocks per compute unit) up to about
     // 0.8 x 256 points per block and compute unit, else 38 KB (four blocks)
-    const size_t per = (size_t)(lv.nc + 4 * ((nrhs + 3) / 4)) * sizeof(cx<T>);
+    // right-hand sides per item: the densities are padded to a multiple of it
+    const int R4 = nrhs == 1 ? 1 : (nrhs == 2 ? 2 : 4);
+    const size_t per = (size_t)(lv.nc + R4 * ((nrhs + R4 - 1) / R4)) * sizeof(cx<T>);
     const int64_t load = std::max<int64_t>(ns, launch_batch_points());
     const size_t share = load > (int64_t)(2 * 0.8 * P2M_THREADS * device_shape().cus) ? 38 * 1024 : 78 * 1024;
     int CH = (int)(share / per);
@@ -927,8 +929,15 @@ void p2m_dispatch(const int32_t *start, const int32_t *end, const double *xs, co
     T invR = (T)(M_SQRT2 / lv.w);
     const P2MArgs<T> a{start, end, xs, ys, reinterpret_cast<const cx<T> *>(qs), ns, nrhs, lv.P, nbox, lv.ncol,
                        lv.col_lo, g.x_lo, lv.w, k1, invR, G, CH, M + lv.off_s, occ + lv.off_occ};
-    emit((const void *)k_p2m<T>, (const void *)k_p2m_multi<T>, 0, dim3((nbox + G - 1) / G),
-         dim3(P2M_THREADS), sh, st, a);
+    if (R4 == 1)
+        emit((const void *)k_p2m<T, 1>, (const void *)k_p2m_multi<T, 1>, 0, dim3((nbox + G - 1) / G),
+             dim3(P2M_THREADS), sh, st, a);
+    else if (R4 == 2)
+        emit((const void *)k_p2m<T, 2>, (const void *)k_p2m_multi<T, 2>, 0, dim3((nbox + G - 1) / G),
+             dim3(P2M_THREADS), sh, st, a);
+    else
+        emit((const void *)k_p2m<T, 4>, (const void *)k_p2m_multi<T, 4>, 0, dim3((nbox + G - 1) / G),
+             dim3(P2M_THREADS), sh, st, a);
 }
 
 // Terms of the series P2M for the leaf level, or 0 where its k1 R is too

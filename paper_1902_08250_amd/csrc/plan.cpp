@@ -240,7 +240,7 @@ struct lmfmm_plan_s {
     double dom[4] = {0, 0, 0, 0};  // xmin, xmax, ys_max, yt_min
     bool do_near = true, do_far = true;
     bool near_sweep = true;  // near field by x-ordered sweeps (else pairwise)
-    bool m2l_mfma = true;    // M2L on the matrix cores (else vector matrix-vector products)
+    int m2l_mfma = -1;       // M2L on the matrix cores (1), as vector matrix-vector products (0), or chosen by nrhs (-1)
     bool eval_levels = true; // leaves evaluate the expansion of the level where their far field is complete
     bool shift_mfma = true;  // M2M and L2L on the matrix cores (else vector matrix-vector products)
     bool p2m_series = true;  // P2M by the ascending series where k1 R is small (else the recurrence form)
@@ -923,8 +923,8 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         return LMFMM_OK;
     }
     if (k == "m2l_mfma") {
-        if (v != "0" && v != "1") return fail(LMFMM_EINVAL, "m2l_mfma must be 0 or 1");
-        p->m2l_mfma = v == "1";
+        if (v != "0" && v != "1" && v != "auto") return fail(LMFMM_EINVAL, "m2l_mfma must be 0, 1 or auto");
+        p->m2l_mfma = v == "auto" ? -1 : (v == "1" ? 1 : 0);
         return LMFMM_OK;
     }
     if (k == "shift_mfma") {
@@ -1492,7 +1492,11 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
             for (int part = 1; part <= 2; ++part) {
                 timed(LMFMM_K_DOWN, 1);
                 set_stage(S_M2L, part);
-                launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, p->m2l_mfma, occ, part, sx);
+                // the matrix-core form pays from 4 right-hand sides (FP32) or 3
+                // (FP64) on; with fewer its 16-column tiles are mostly boxes
+                // whose tables differ little in cost from the vector form's
+                const bool mf = p->m2l_mfma < 0 ? nrhs >= (sizeof(T) == 8 ? 3 : 4) : p->m2l_mfma != 0;
+                launch_m2l_all<T>(g, ltop, L, atab, cls3, roff, nrt, M, Lc, nrhs, mf, occ, part, sx);
                 timed_done();
             }
             // the leaf level's shift is done by the leaf evaluation (forward apply)
