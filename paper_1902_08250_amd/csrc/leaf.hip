@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(256) k_p2m_series_multi(MultiArgs m)
 // decreasing p, so the sums are formed there by Horner's rule,
 // sum_{p >= 1} Lhat_p B_p = B_0 g_1 (Lhat_1 + g_2 (Lhat_2 + ...)), and no
 // table of ratios is kept (B_0 = J_0 is known only at the end).
-template <typename T, int PMAX, int RMAX>
+template <typename T, int RMAX>
 __device__ inline void eval_local(cx<T> k2, T X, T Y, T invR, int P, const cx<T> *Ls, int nr, cx<double> (&res)[RMAX])
 {
     const int nc = 2 * P + 1;
@@ -394,7 +394,7 @@ struct L2PArgs {
     cx<T> *u;
     EvalLevels ev;
 };
-template <typename T, int PMAX, int RMAX>
+template <typename T, int RMAX>
 __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, const int by)
 {
     const int32_t *__restrict__ start = A.start;
@@ -546,7 +546,7 @@ __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, cons
             const int s = s_slot[g], she = L - s_lev[s];
             const double we = ldexp(w, she);
             const double cxp = x_lo + ((col >> she) + 0.5) * we, cyp = -((row >> she) + 0.5) * we;
-            eval_local<T, PMAX, RMAX>(k2, (T)(px - cxp), (T)(py - cyp), invR / (T)(1 << she), s_P[s],
+            eval_local<T, RMAX>(k2, (T)(px - cxp), (T)(py - cyp), invR / (T)(1 << she), s_P[s],
                                       Ls + (int64_t)s * RMAX * ncmax, nr, res);
         }
         const int64_t o = pid - ns;
@@ -559,17 +559,17 @@ __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, cons
     }
 }
 
-template <typename T, int PMAX, int RMAX>
+template <typename T, int RMAX>
 __global__ void __launch_bounds__(L2P_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_l2p(L2PArgs<T> a)
 {
-    l2p_body<T, PMAX, RMAX>(a, blockIdx.x, blockIdx.y);
+    l2p_body<T, RMAX>(a, blockIdx.x, blockIdx.y);
 }
-template <typename T, int PMAX, int RMAX>
+template <typename T, int RMAX>
 __global__ void __launch_bounds__(L2P_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_l2p_multi(MultiArgs m)
 {
     int i, bx, by, bz;
     multi_locate(m, i, bx, by, bz);
-    l2p_body<T, PMAX, RMAX>(static_cast<const L2PArgs<T> *>(m.args)[i], bx, by);
+    l2p_body<T, RMAX>(static_cast<const L2PArgs<T> *>(m.args)[i], bx, by);
 }
 
 // ---------------------------------------------------------------------------
@@ -598,7 +598,7 @@ struct L2PNearArgs {
     int nparts;
     cx<T> *u;
 };
-template <typename T, int PMAX, int RMAX>
+template <typename T, int RMAX>
 __device__ __forceinline__ void l2p_near_body(const L2PNearArgs<T> &A, const int bx, const int by)
 {
     const int32_t *__restrict__ start = A.start;
@@ -671,7 +671,7 @@ __device__ __forceinline__ void l2p_near_body(const L2PNearArgs<T> &A, const int
         double x1 = xs[ii], y1 = ys[ii];
         cx<double> res[RMAX];
         for (int r = 0; r < RMAX; ++r) res[r] = {0.0, 0.0};
-        if (do_far) eval_local<T, PMAX, RMAX>(k2, (T)(x1 - cxp), (T)(y1 - cyp), invR, P, Ls, nr, res);
+        if (do_far) eval_local<T, RMAX>(k2, (T)(x1 - cxp), (T)(y1 - cyp), invR, P, Ls, nr, res);
         if (do_near && row == 0 && rows_s > 0) {
             if (unear) {
                 // near field computed by the sweep kernel: add its parts in order
@@ -707,14 +707,14 @@ __device__ __forceinline__ void l2p_near_body(const L2PNearArgs<T> &A, const int
     }
 }
 
-template <typename T, int PMAX, int RMAX>
-__global__ void __launch_bounds__(64) k_l2p_near(L2PNearArgs<T> a) { l2p_near_body<T, PMAX, RMAX>(a, blockIdx.x, blockIdx.y); }
-template <typename T, int PMAX, int RMAX>
+template <typename T, int RMAX>
+__global__ void __launch_bounds__(64) k_l2p_near(L2PNearArgs<T> a) { l2p_near_body<T, RMAX>(a, blockIdx.x, blockIdx.y); }
+template <typename T, int RMAX>
 __global__ void __launch_bounds__(64) k_l2p_near_multi(MultiArgs m)
 {
     int i, bx, by, bz;
     multi_locate(m, i, bx, by, bz);
-    l2p_near_body<T, PMAX, RMAX>(static_cast<const L2PNearArgs<T> *>(m.args)[i], bx, by);
+    l2p_near_body<T, RMAX>(static_cast<const L2PNearArgs<T> *>(m.args)[i], bx, by);
 }
 
 // Near-field derivative sums for the gradient: returns (sum D e^E lam, sum D e^E s_t)
@@ -1051,7 +1051,7 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
                      reinterpret_cast<cx<T> *>(u), ev};
         const size_t shmem = (size_t)std::max(G, G_if) * per_leaf;
 #define LMFMM_L2P_PACKED(RMC)                                                                              \
-    emit((const void *)k_l2p<T, PMAX, RMC>, (const void *)k_l2p_multi<T, PMAX, RMC>, 0, grid, dim3(L2P_THREADS), \
+    emit((const void *)k_l2p<T, RMC>, (const void *)k_l2p_multi<T, RMC>, 0, grid, dim3(L2P_THREADS), \
          shmem, st, a)
         if (RM == 1)
             LMFMM_L2P_PACKED(1);
@@ -1067,7 +1067,7 @@ void l2p_dispatch(const int32_t *start, const int32_t *end, const int32_t *idx, 
                            lv.ncol, lv.col_lo, lv.rows_s, g.x_lo, lv.w, k2, invR, Lc + lv.off_t, shift, nodes, nmid,
                            npan, t0, do_far, do_near, key_t0, unear, nparts, reinterpret_cast<cx<T> *>(u)};
 #define LMFMM_L2P_LAUNCH(RM)                                                                                 \
-    emit((const void *)k_l2p_near<T, PMAX, RM>, (const void *)k_l2p_near_multi<T, PMAX, RM>, 0,             \
+    emit((const void *)k_l2p_near<T, RM>, (const void *)k_l2p_near_multi<T, RM>, 0,             \
          dim3(nbox, (nrhs + RM - 1) / RM), dim3(64), sh, st, a)
     if (nrhs == 1)
         LMFMM_L2P_LAUNCH(1);
