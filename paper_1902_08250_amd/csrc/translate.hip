@@ -339,15 +339,11 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
     // eight apart.  Blocks are handed to the XCDs in turn, so a group's tiles,
     // which read the same class tables, run on one XCD at about the same time
     // and its L2 fetches those tables once.  Groups past the last are empty.
-    const int ngroup = a.nrow[li] * nrc * npt;
-    const int ghi = loc / (8 * ntile), rem = loc - ghi * 8 * ntile;
-    const int tile = rem >> 3;
-    int grp = ghi * 8 + (rem & 7);
-    if (grp >= ngroup) return;  // the whole block: no barrier has been reached
-    const int pt = grp % npt;
-    grp /= npt;
-    const int rcn = grp % nrc;
-    const int row = grp / nrc;
+    const int pt = loc % npt;
+    loc /= npt;
+    const int rcn = loc % nrc;
+    loc /= nrc;
+    const int tile = loc % ntile, row = loc / ntile;
     const int n = l & 15, kk = l >> 4;
     const int j = n / k.RC, r = rcn * k.RC + n % k.RC;
     const int colL = tile * k.NB + j, col = col_lo + colL;
@@ -745,7 +741,7 @@ void launch_m2l_all(const Geometry &g, int l0, int l1, const cx<T> *const *atab,
             a.row_off[i] = row_off[l - l0];
             a.nrow[i] = rows;
             if (mfma)
-                blk += (rows * ((nrhs + RC - 1) / RC) * ((lv.nc + 15) / 16) + 7) / 8 * 8 * ((lv.ncol + NB - 1) / NB);
+                blk += rows * ((lv.ncol + NB - 1) / NB) * ((nrhs + RC - 1) / RC) * ((lv.nc + 15) / 16);
             else
                 blk += rows * lv.ncol;
         }
