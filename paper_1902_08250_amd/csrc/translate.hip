@@ -292,10 +292,10 @@ __global__ void __launch_bounds__(64 * M2L_DW) k_m2l_all_multi(MultiArgs m)
 // ---------------------------------------------------------------------------
 constexpr int MW = 4;       // waves per block
 // waves per block at the coarsest level (every non-adjacent pair: long slot
-// lists): 16 in FP32; 8 in FP64, whose operand prefetch needs more registers
-// than a 16-wave block allows
+// lists); measured on the batched workload, 8 beat 4 and 16 in FP32, and the
+// FP64 operand prefetch needs more registers than a 16-wave block allows
 template <typename T>
-constexpr int mw_top() { return sizeof(T) == 8 ? 8 : 16; }
+constexpr int mw_top() { return 8; }
 constexpr int MKS = 8;      // k-steps (4 coefficients each) whose operands are loaded together
 template <typename T>
 struct M2LMK {
