@@ -183,6 +183,29 @@ def test_p2m_large_k1r_uses_recurrence_form(torch_cuda):
         check(u, ref, tol, f"{prec} k1=60 L=3 vs direct", say)
 
 
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 5])
+def test_rhs_counts_and_forms_match_direct(torch_cuda, nrhs):
+    """1, 2, 3 and 5 right-hand sides (densities padded to 1, 2, 4 and 2 x 4 in
+    the recurrence-form P2M; the M2L form chosen by their number: vector below
+    4 in FP32 and 3 in FP64), with M2L forced to either form and P2M in either
+    form, FP64 and mixed, 2500 x 2000 at 5 levels (about 3 sources per leaf),
+    against the GPU direct sum."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    rng = np.random.default_rng(90 + nrhs)
+    src, tgt, q, _ = workloads.draw_instance(rng, 2500, 2000, (0, 1), (0.05, 1), (-0.95, -0.05), nrhs)
+    k, d = workloads.MEDIUM_A
+    ref = host(Plan(k, d, order=20, tol=1e-10).direct(dev(src), dev(q), dev(tgt)))
+    say("nrhs", nrhs, "2500x2000 levels 5: m2l auto/1/0 x p2m series/recurrence")
+    for prec, tol in (("c128", 1e-10), ("c64", TOL["c64"])):
+        qq = q if prec == "c128" else q.astype(np.complex64)
+        for m2l, ser in (("auto", "1"), ("1", "0"), ("0", "0"), ("auto", "0")):
+            pl = Plan(k, d, order=20 if prec == "c128" else 16, tol=1e-10 if prec == "c128" else 1e-6, levels=5)
+            pl.set_option("m2l_mfma", m2l)
+            pl.set_option("p2m_series", ser)
+            u = host(pl.apply(dev(src), dev(qq), dev(tgt)))
+            check(u, ref, tol, f"{prec} nrhs={nrhs} m2l_mfma={m2l} p2m_series={ser} vs direct", say)
+
+
 @pytest.mark.parametrize("levels", [2, 5, 7])
 def test_eval_levels_match_leaf_evaluation(torch_cuda, mid, mid_direct, levels):
     """Leaves evaluating the expansion of the level where their far field is
