@@ -314,6 +314,16 @@ __device__ inline void mfma_c(mf32x4 &dr, mf32x4 &di, cx<float> x, cx<float> y)
     di = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, y.im, di, 0, 0, 0);
     di = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, y.re, di, 0, 0, 0);
 }
+// FP64 complex product as three real ones (Gauss): with t1 = (xr + xi) yr,
+// t2 = xr (yi - yr) and t3 = xi (yr + yi), the real part is t1 - t3 and the
+// imaginary part t1 + t2.  The extra rounding is a few units in the last
+// place of FP64.
+__device__ inline void mfma_c3(mf64x4 &t1, mf64x4 &t2, mf64x4 &t3, cx<double> x, cx<double> y)
+{
+    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re + x.im, y.re, t1, 0, 0, 0);
+    t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, y.im - y.re, t2, 0, 0, 0);
+    t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, y.re + y.im, t3, 0, 0, 0);
+}
 __device__ inline void mfma_c(mf64x4 &dr, mf64x4 &di, cx<double> x, cx<double> y)
 {
     dr = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, y.re, dr, 0, 0, 0);
@@ -383,7 +393,7 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
             bv[u] = (kin && in_) ? xb[kq] : mk<T>(0, 0);
         }
     };
-    if (F32) {
+    if constexpr (F32) {
         // FP32: the next slot's entry and flag only (a prefetch of operands was
         // slower: more registers, fewer waves)
         int rsN = 0, cslN = 0, flagN = 0;
@@ -443,17 +453,18 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
                 load_steps(s + NW, rsN, cslN, inN, 0, avN, bvN);
             }
             if (!__any(ok)) continue;
-            vx4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+            vx4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
 #pragma unroll
             for (int u = 0; u < MKS; ++u)
-                if (u < nks) mfma_c(dr, di, av0[u], bv0[u]);
+                if (u < nks) mfma_c3(t1, t2, t3, av0[u], bv0[u]);
             for (int k0 = MKS; k0 < nks; k0 += MKS) {
                 cx<T> av[MKS], bv[MKS];
                 load_steps(s, rs, csl, in, k0, av, bv);
 #pragma unroll
                 for (int u = 0; u < MKS; ++u)
-                    if (k0 + u < nks) mfma_c(dr, di, av[u], ok ? bv[u] : mk<T>(0, 0));
+                    if (k0 + u < nks) mfma_c3(t1, t2, t3, av[u], ok ? bv[u] : mk<T>(0, 0));
             }
+            const vx4 dr = t1 - t3, di = t1 + t2;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 sr[v] += dr[v];
