@@ -163,9 +163,10 @@ struct TreeCountArgs {
     uint32_t *key;
     int32_t *rank, *cnt, *err;
 };
+constexpr int TC_THREADS = 1024;  // threads per block of the count (1024 finished a few microseconds sooner than 256)
 __device__ __forceinline__ void tree_count_body(const TreeCountArgs &a, int bx)
 {
-    int64_t i = (int64_t)bx * 256 + threadIdx.x;
+    int64_t i = (int64_t)bx * TC_THREADS + threadIdx.x;
     if (i >= a.ns + a.nt) return;
     bool tg = i >= a.ns;
     double x = tg ? a.tgt[i - a.ns] : a.src[i];
@@ -184,8 +185,8 @@ __device__ __forceinline__ void tree_count_body(const TreeCountArgs &a, int bx)
     a.key[i] = k;
     a.rank[i] = atomicAdd(&a.cnt[k], 1);
 }
-__global__ void __launch_bounds__(256) k_tree_count(TreeCountArgs a) { tree_count_body(a, blockIdx.x); }
-__global__ void __launch_bounds__(256) k_tree_count_multi(MultiArgs m)
+__global__ void __launch_bounds__(TC_THREADS) k_tree_count(TreeCountArgs a) { tree_count_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(TC_THREADS) k_tree_count_multi(MultiArgs m)
 {
     int i, bx, by, bz;
     multi_locate(m, i, bx, by, bz);
@@ -479,7 +480,8 @@ void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, d
     if (n == 0 || nbox == 0) return;
     const unsigned g = (unsigned)((n + 255) / 256);
     const TreeCountArgs ca{src, ns, tgt, nt, x_lo, 1.0 / w, col_lo, ncol, rows_s, rows_t, ly, b.key, b.rank, b.cnt, err};
-    emit((const void *)k_tree_count, (const void *)k_tree_count_multi, 0, dim3(g), dim3(256), 0, st, ca);
+    emit((const void *)k_tree_count, (const void *)k_tree_count_multi, 0,
+         dim3((unsigned)((n + TC_THREADS - 1) / TC_THREADS)), dim3(TC_THREADS), 0, st, ca);
     const TreeScanArgs sa{b.cnt, nbox, n, b.start, b.end, err};
     emit((const void *)k_tree_scan, (const void *)k_tree_scan_multi, 1, dim3(1), dim3(SC_THREADS), 0, st, sa);
     const TreeScatterArgs xa{b.key, b.rank, n, b.start, b.perm};
