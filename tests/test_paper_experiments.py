@@ -13,7 +13,9 @@ with numpy/scipy quadrature (independent of the GPU library and the oracle):
     g_2^t (k = (1, 3, 1), x0 - x_c = 2, y0 - y_c = 3, r = 1.5): the ratio
     tends to r / rho = 1.5 / sqrt(13) = 0.416.  The printed rho = sqrt(2^2 + 3^3)
     is read as sqrt(2^2 + 3^2), the value the text states (0.416); d is not
-    given and the limit does not depend on it (d = 1 here).
+    given and the limit does not depend on it (d = 1 here);
+  * Remark after Theorem 1: with the modified distance the multipole
+    expansion also converges for a target in the source box itself.
 """
 import numpy as np
 import pytest
@@ -118,3 +120,27 @@ def test_fig5_three_layer_local_ratio():
         assert abs(R[p] - R_OVER_RHO) < 0.02
     # the printed rho = sqrt(2^2 + 3^3) would give 0.269
     assert abs(R[60] - 1.5 / np.sqrt(31.0)) > 0.1
+
+
+@pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
+def test_multipole_valid_in_own_box_under_modified_distance():
+    """Remark after Theorem 1: the scattered field's multipole expansion can
+    converge in the source box itself.  Source box centre and target both at
+    (0, 1.5), so the physical distance is 0, while the modified distance is
+    y + y_c = 3: the term ratio of the impedance half-space's expansion
+    tends to r / 3 = 0.5 < 1.  The imaged tree places such a target at
+    (0, -1.5), at twice the radius r from the source centre, so the pair is a far
+    pair there."""
+    k, alpha, y, yc, r = 0.1, 1.0, 1.5, 1.5, 1.5
+
+    def phi(p):
+        def f(lam):
+            s = sroot(lam, k)
+            sig = (s + 1j * k * alpha) / (s - 1j * k * alpha)
+            return ((lam + s) / k) ** p * np.exp(-s * (y + yc)) * sig / (4 * np.pi * s)
+        return cquad(f, k, k + 200 + 5 * p)
+
+    R = ratio_sequence(phi, k, r, [40, 50, 60])
+    print("own-box term ratios", R, "r/(y+yc)", r / (y + yc))
+    for p in (40, 50, 60):
+        assert abs(R[p] - r / (y + yc)) < 0.02
