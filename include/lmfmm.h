@@ -118,6 +118,14 @@ int lmfmm_destroy(lmfmm_plan plan);
  *                 0): the total field u satisfies u_y + i k1 alpha u = 0 on
  *                 y = 0 (density (s1 + i k1 alpha) / (s1 - i k1 alpha)).
  *                 Setting it discards the plan's tables.
+ *   "tree_sort"   grouping of the points by leaf (Algorithm 1, Step 1):
+ *                 "radix": a stable radix sort of the leaf keys (no atomics
+ *                 per point); "count": a counting sort with one atomic per
+ *                 point and a per-leaf sort of the original indices; "auto"
+ *                 (default): radix from 3e5 points on (counted over all
+ *                 instances of a batched apply).  Both give every leaf its
+ *                 points in increasing original index, so the results are
+ *                 the same bit for bit.
  *   "m2l_mfma"    "1": multipole-to-local as products of the class tables
  *                 with tiles of boxes x right-hand sides on the matrix cores;
  *                 "0": one matrix-vector product per box pair list; "auto"

@@ -94,6 +94,12 @@ inline int64_t &launch_batch_points()
     static thread_local int64_t n = 0;
     return n;
 }
+// While a batch is recorded: the sources and targets of all its instances.
+inline int64_t &launch_batch_all_points()
+{
+    static thread_local int64_t n = 0;
+    return n;
+}
 
 // Argument of a multi-instance launch: instance i takes the blocks
 // [blk0[i], blk0[i + 1]) of the flat grid, its own grid is grid[3i .. 3i + 2]
@@ -519,16 +525,23 @@ int bbox_blocks(int64_t n);
 // order to qs (same layout), unless q is null.
 struct TreeBufs {
     uint32_t *key;
-    int32_t *rank, *cnt, *start, *end, *perm, *scratch, *idx;
+    int32_t *rank, *cnt, *tab, *start, *end, *perm, *scratch, *idx;  // scratch: 2n; tab: tree_table_len(n)
     double *xs, *ys;
     const uint64_t *q = nullptr;
     uint64_t *qs = nullptr;
     int nrhs = 0, qw = 0;
 };
 void launch_tree(const double *src, int64_t ns, const double *tgt, int64_t nt, double x_lo, double w, int col_lo,
-                 int ncol, int rows_s, int rows_t, const Layers &ly, const TreeBufs &b, int32_t *err,
+                 int ncol, int rows_s, int rows_t, const Layers &ly, const TreeBufs &b, int32_t *err, bool radix,
                  hipStream_t st);
 void launch_zero_bytes(void *p, size_t nbytes, hipStream_t st);
+// Grouping form of a tree of n points (form: -1 by size, 0 counting sort, 1
+// radix sort; a recorded batch decides by all its points), the kernels
+// launch_tree issues for nbox leaves, and the ints of TreeBufs::tab.
+constexpr int64_t TREE_RADIX_MIN_POINTS = 300000;
+bool tree_radix(int64_t n, int form);
+int tree_launch_count(int64_t nbox, bool radix);
+int64_t tree_table_len(int64_t n);
 
 
 // leaf.hip and translate.hip (T = double or float)

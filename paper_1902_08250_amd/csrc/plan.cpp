@@ -240,6 +240,7 @@ struct lmfmm_plan_s {
     double dom[4] = {0, 0, 0, 0};  // xmin, xmax, ys_max, yt_min
     bool do_near = true, do_far = true;
     bool near_sweep = true;  // near field by x-ordered sweeps (else pairwise)
+    int tree_sort = -1;      // grouping by radix sort (1), by counting sort (0), or chosen by the point count (-1)
     int m2l_mfma = -1;       // M2L on the matrix cores (1), as vector matrix-vector products (0), or chosen by nrhs (-1)
     bool eval_levels = true; // leaves evaluate the expansion of the level where their far field is complete
     bool shift_mfma = true;  // M2M and L2L on the matrix cores (else vector matrix-vector products)
@@ -922,6 +923,12 @@ int lmfmm_set_option(lmfmm_plan p, const char *key, const char *value)
         p->g_prekey.clear();
         return LMFMM_OK;
     }
+    if (k == "tree_sort") {
+        if (v != "radix" && v != "count" && v != "auto")
+            return fail(LMFMM_EINVAL, "tree_sort must be radix, count or auto");
+        p->tree_sort = v == "auto" ? -1 : (v == "radix" ? 1 : 0);
+        return LMFMM_OK;
+    }
     if (k == "m2l_mfma") {
         if (v != "0" && v != "1" && v != "auto") return fail(LMFMM_EINVAL, "m2l_mfma must be 0, 1 or auto");
         p->m2l_mfma = v == "auto" ? -1 : (v == "1" ? 1 : 0);
@@ -1371,7 +1378,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     int64_t n = ns + nt;
     int64_t nbox = (int64_t)(lv.rows_s + lv.rows_t) * lv.ncol;
     size_t need = 0;
-    need += 6 * (size_t)n * 4 + 3 * (size_t)nbox * 4 + 2 * (size_t)n * 8;
+    need += 6 * (size_t)n * 4 + (size_t)tree_table_len(n) * 4 + 3 * (size_t)nbox * 4 + 2 * (size_t)n * 8 + 2 * 256;
     need += (size_t)ns * nrhs * sizeof(cx<T>) + 256;  // densities in grouped order
     need += ((size_t)g.ncoef_s + (size_t)g.ncoef_t) * sizeof(cx<T>) + 64 + 20 * 256;
     need += (size_t)g.nocc_s * 4 + 256;
@@ -1392,11 +1399,12 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     }
     Carve cv{fixed_ws ? (char *)fixed_ws : (char *)p->ws.p};
     TreeBufs tb;
-    // error flags and leaf counters first: this prefix must hold zeros when a
-    // tree build starts
+    // error flags and the counting sort's leaf counters first: this prefix
+    // must hold zeros when a tree build starts (every build leaves it so)
     int32_t *err = cv.take<int32_t>(2);
     tb.cnt = cv.take<int32_t>(nbox);
     const size_t zero_bytes = cv.off;
+    tb.tab = cv.take<int32_t>(tree_table_len(n));
     tb.key = cv.take<uint32_t>(n);
     tb.rank = cv.take<int32_t>(n);
     tb.perm = cv.take<int32_t>(n);
@@ -1418,7 +1426,8 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
     p->d_err = err;
     p->err_valid = n > 0 && nbox > 0;
     cx<double> *unear = sweep ? cv.take<cx<double>>(nun) : nullptr;
-    int tree_launches = (have_bb ? 0 : 2) + 4;
+    const bool radix = tree_radix(n, p->tree_sort);
+    int tree_launches = (have_bb ? 0 : 2) + tree_launch_count(nbox, radix);
     if (fixed_ws) {
         // the fixed array is shared by every plan on this device: clear the
         // counters every time
@@ -1443,7 +1452,7 @@ static int apply_impl(lmfmm_plan p, int adj, int64_t ns, const double *src, cons
         if (with_bbox) bbox_launch(p, med, ns, src, nt, tgt, sx);
         set_stage(S_TREE);
         launch_tree(src, ns, tgt, nt, g.x_lo, lv.w, lv.col_lo, lv.ncol, lv.rows_s, lv.rows_t, layers_of(med), tb,
-                    err, sx);
+                    err, radix, sx);
         group_end(tree_launches, sx);
 
         // Step 2: upward pass
@@ -1802,7 +1811,7 @@ int lmfmm_sync_status(lmfmm_plan p, void *stream)
         HIPCHK(hipStreamSynchronize(st));
         int32_t e;
         std::memcpy(&e, p->h_bbox + 12, sizeof e);
-        if (e & 2) return fail(LMFMM_EHIP, "inconsistent leaf counts in the tree build (results invalid)");
+        if (e & 2) return fail(LMFMM_EHIP, "inconsistent grouping in the tree build (results invalid)");
         if (e) return fail(LMFMM_EDOMAIN, "a point lies outside the domain or its layer");
         return LMFMM_OK;
     }
@@ -2003,9 +2012,13 @@ static int batch_record_merge(lmfmm_batch_s *b, const lmfmm_instance *inst, int 
         RecLaunch L;
     };
     std::vector<Rec> all;
-    int64_t tot_src = 0;
-    for (int i = 0; i < b->n; ++i) tot_src += inst[i].n_src;
+    int64_t tot_src = 0, tot_all = 0;
+    for (int i = 0; i < b->n; ++i) {
+        tot_src += inst[i].n_src;
+        tot_all += inst[i].n_src + inst[i].n_tgt;
+    }
     launch_batch_points() = tot_src;
+    launch_batch_all_points() = tot_all;
     for (int i = 0; i < b->n; ++i) {
         lmfmm_plan_s *p = b->plans[i];
         if (inst[i].n_tgt == 0 || inst[i].n_src == 0) continue;  // (no sources: zeroed by the apply)
@@ -2019,11 +2032,13 @@ static int batch_record_merge(lmfmm_batch_s *b, const lmfmm_instance *inst, int 
         p->timing = timing;
         if (rc) {
             launch_batch_points() = 0;
+            launch_batch_all_points() = 0;
             return rc;
         }
         for (auto &L : rec.v) all.push_back(Rec{i, std::move(L)});
     }
     launch_batch_points() = 0;
+    launch_batch_all_points() = 0;
     std::stable_sort(all.begin(), all.end(), [](const Rec &a, const Rec &c) {
         if (a.L.key != c.L.key) return a.L.key < c.L.key;
         return std::less<const void *>()(a.L.multi, c.L.multi);

@@ -51,6 +51,13 @@ def test_batched_instances():
     b64 = Batch([(d["k"], d["d"]) for d in inst], order_set=(20,), tol=1e-10, tune=False)
     items64 = [(s, dev(d["q"].astype(np.complex128)), t) for (s, _, t), d in zip(items, inst)]
     outs64 = [o.cpu().numpy() for o in b64.apply(items64)]
+    # the batch's 1.1e6 points take the radix-sort grouping; the counting
+    # sort gives the same grouped order, hence the same results bit for bit
+    say("fp64 batch with tree_sort=count")
+    b64c = Batch([(d["k"], d["d"]) for d in inst], order_set=(20,), tol=1e-10, tune=False)
+    b64c.set_option("tree_sort", "count")
+    for a, o in zip(outs64, b64c.apply(items64)):
+        assert np.array_equal(a, o.cpu().numpy())
     for i, d in enumerate(inst):
         g = np.load(os.path.join(GOLD, f"oracle_batched_inst{i}.npz"))
         sel, ref = g["sel"], g["u"]

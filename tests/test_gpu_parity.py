@@ -234,6 +234,26 @@ def test_mid_mixed_vs_fp64(torch_cuda, mid, mid_direct):
     check(u, mid_direct, TOL["c64"], "mixed 4000x3000 nrhs=11 vs direct", say)
 
 
+@pytest.mark.parametrize("levels", [2, 5, 8, 9])
+def test_tree_sort_forms(torch_cuda, mid, mid_direct, levels):
+    """Both groupings of the points by leaf, the radix sort and the counting
+    sort (option tree_sort), list every leaf's points in increasing original
+    index, so the results agree bit for bit.  Level 2 has 32 leaves (one
+    5-bit digit pass of the radix sort); levels 8 and 9 have about 3e4 and
+    1.3e5 leaves for 7000 points (15- and 17-bit keys: two and three passes),
+    so most leaf ranges are empty runs between occupied leaves.  FP64 against
+    the GPU direct sum."""
+    from paper_1902_08250_amd.lmfmm import Plan
+    out = {}
+    for form in ("radix", "count"):
+        say("tree_sort", form, "4000x3000 nrhs=11 levels", levels)
+        pl = Plan(mid["k"], mid["d"], order=20, tol=1e-10, levels=levels)
+        pl.set_option("tree_sort", form)
+        out[form] = host(pl.apply(dev(mid["src"]), dev(mid["q"]), dev(mid["tgt"])))
+        check(out[form], mid_direct, 1e-10, f"c128 L={levels} tree_sort={form} vs direct", say)
+    assert np.array_equal(out["radix"], out["count"])
+
+
 def test_deterministic(torch_cuda, mid):
     from paper_1902_08250_amd.lmfmm import Plan
     say("determinism 4000x3000")
