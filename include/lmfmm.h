@@ -272,8 +272,12 @@ int lmfmm_sync_status(lmfmm_plan plan, void *stream);
  *     holds the instance's key (medium, size buckets, tol, nrhs, precision,
  *     order set), else an autotuner times every candidate with HIP events and
  *     keeps the fastest, then times the other near-field form (sweep or
- *     pairwise sum, plan option "near_sweep") at that choice, and the choice
- *     is added to the cache;
+ *     pairwise sum, plan option "near_sweep") at that choice; then the
+ *     depth of the instances tuned now is capped at one and two levels below
+ *     the deepest, the merged launch sequence is timed for each cap, and the
+ *     fastest is kept (merged launches of one stage run together, so the
+ *     deepest instance sets the number of per-level launches); the choices
+ *     are added to the cache;
  *   - every instance's launch sequence is recorded and the launches of each
  *     stage (tree passes, P2M, M2M per level, M2L, L2L per level, near field,
  *     local evaluation) are merged into one launch over all instances, captured

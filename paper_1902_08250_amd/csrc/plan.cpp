@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -2125,6 +2126,11 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
     } guard{e0, e1};
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // every timed (order, levels, us) of the instances tuned here, and their
+    // cache keys and near-field forms
+    std::vector<std::vector<std::array<double, 3>>> cands(b->n);
+    std::vector<std::string> keys(b->n);
+    std::vector<int> sweeps(b->n, 1);
     for (int i = 0; i < b->n; ++i) {
         lmfmm_plan_s *p = b->plans[i];
         const lmfmm_instance &in = inst[i];
@@ -2151,20 +2157,24 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
             b->from_cache[i] = 1;
         } else if (b->tune) {
             // time one candidate: a first apply builds its tables, a second
-            // captures its launch sequence, then the replays are timed
+            // captures its launch sequence, then the replays are timed in
+            // three windows of three, of which the fastest counts
             auto time_candidate = [&](double &us) -> int {
                 int r = plan_apply_any(p, in, nrhs, prec, st);
                 if (r) return r;
                 if ((r = plan_apply_any(p, in, nrhs, prec, st))) return r;
                 const int reps = 3;
-                HIPCHK(hipEventRecord(e0, st));
-                for (int k = 0; k < reps && r == LMFMM_OK; ++k) r = plan_apply_any(p, in, nrhs, prec, st);
-                if (r) return r;
-                HIPCHK(hipEventRecord(e1, st));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                us = 1e3 * ms / reps;
+                us = 1e300;
+                for (int win = 0; win < 3; ++win) {
+                    HIPCHK(hipEventRecord(e0, st));
+                    for (int k = 0; k < reps && r == LMFMM_OK; ++k) r = plan_apply_any(p, in, nrhs, prec, st);
+                    if (r) return r;
+                    HIPCHK(hipEventRecord(e1, st));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    us = std::min(us, 1e3 * ms / reps);
+                }
                 return LMFMM_OK;
             };
             // per order floor, the depth by descent from the automatic one:
@@ -2205,6 +2215,8 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
                     bo = o;
                     bl = Lb;
                 }
+                for (const auto &kv : seen)
+                    if (kv.second < 1e300) cands[i].push_back({(double)o, (double)kv.first, kv.second});
             }
             if (best >= 1e300) return fail(LMFMM_ETOL, "no candidate order meets the tolerance");
             if (b->tune_near) {
@@ -2221,6 +2233,8 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
             }
             cache[key] = TuneEntry{bo, bl, bs, best};
             cache_dirty = true;
+            keys[i] = key;
+            sweeps[i] = bs;
         }
         p->order = bo;
         p->levels_opt = b->tune ? bl : 0;
@@ -2231,6 +2245,88 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
         // 3. warm the chosen configuration (tables, workspace)
         if ((rc = plan_apply_any(p, in, nrhs, prec, st))) return rc;
         b->chosen_levels[i] = p->geo.L;
+    }
+    // 4. The merged launches of one stage run together, so the deepest
+    // instance sets how many per-level launches the batch has.  Cap the depth
+    // of the instances tuned here at one and two levels below the deepest
+    // (each deeper one takes its fastest timed candidate within the cap, else
+    // its order at the cap's depth), time the merged sequence, and keep the
+    // cap that saves most (by more than 1 %).  A cap some instance cannot
+    // meet (its order or tolerance out of reach at that depth) is skipped.
+    // Deeper cuts were slow to prepare: a tree much shallower than an
+    // instance's own choice leaves most of its work to the near field.
+    int deepest = 0;
+    for (int i = 0; i < b->n; ++i)
+        if (!cands[i].empty()) deepest = std::max(deepest, b->chosen_levels[i]);
+    if (deepest > 2 && b->n > 1) {
+        auto time_merged = [&](double &us) -> int {
+            int r = batch_record_merge(b, inst, nrhs, prec, st);
+            if (r || (r = batch_launch_seq(b, st, false))) return r;
+            us = 1e300;
+            for (int win = 0; win < 3; ++win) {
+                HIPCHK(hipEventRecord(e0, st));
+                for (int k = 0; k < 3; ++k)
+                    if ((r = batch_launch_seq(b, st, false))) return r;
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                us = std::min(us, 1e3 * ms / 3);
+            }
+            return LMFMM_OK;
+        };
+        auto set_choice = [&](const std::vector<int> &o, const std::vector<int> &l) -> int {
+            for (int i = 0; i < b->n; ++i) {
+                lmfmm_plan_s *p = b->plans[i];
+                if (cands[i].empty() || (p->order == o[i] && p->levels_opt == l[i] && p->geo.L == l[i])) continue;
+                p->order = o[i];
+                p->levels_opt = l[i];
+                int r = plan_apply_any(p, inst[i], nrhs, prec, st);
+                if (r) return r;
+            }
+            return LMFMM_OK;
+        };
+        const std::vector<int> o0 = b->chosen_order, l0 = b->chosen_levels;
+        std::vector<int> bo = o0, bl = l0;
+        double best_us = 0.0;
+        if ((rc = time_merged(best_us))) return rc;
+        for (int cap = deepest - 1; cap >= std::max(2, deepest - 2); --cap) {
+            std::vector<int> o = o0, l = l0;
+            bool changed = false;
+            for (int i = 0; i < b->n; ++i) {
+                if (cands[i].empty() || l0[i] <= cap) continue;
+                double bu = 1e300;
+                for (const auto &c : cands[i])
+                    if ((int)c[1] <= cap && c[2] < bu) {
+                        bu = c[2];
+                        o[i] = (int)c[0];
+                        l[i] = (int)c[1];
+                    }
+                if (bu >= 1e300) l[i] = cap;  // not timed alone: the merged timing decides
+                changed = true;
+            }
+            if (!changed) break;
+            double us = 0.0;
+            rc = set_choice(o, l);
+            if (rc == LMFMM_ETOL || rc == LMFMM_EINVAL) continue;
+            if (rc || (rc = time_merged(us))) return rc;
+            if (us < 0.99 * best_us) {
+                best_us = us;
+                bo = o;
+                bl = l;
+            }
+        }
+        if ((rc = set_choice(bo, bl))) return rc;
+        for (int i = 0; i < b->n; ++i) {
+            if (cands[i].empty()) continue;
+            if (bo[i] != o0[i] || bl[i] != l0[i]) {
+                for (const auto &c : cands[i])
+                    if ((int)c[0] == bo[i] && (int)c[1] == bl[i]) b->chosen_us[i] = c[2];
+                cache[keys[i]] = TuneEntry{bo[i], bl[i], sweeps[i], b->chosen_us[i]};
+            }
+            b->chosen_order[i] = bo[i];
+            b->chosen_levels[i] = b->plans[i]->geo.L;
+        }
     }
     if (cache_dirty && !b->cache_path.empty()) write_tune_cache(b->cache_path, cache);
     HIPCHK(hipStreamSynchronize(st));
