@@ -2250,11 +2250,10 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
     // instance sets how many per-level launches the batch has.  Cap the depth
     // of the instances tuned here at one and two levels below the deepest
     // (each deeper one takes its fastest timed candidate within the cap, else
-    // its order at the cap's depth), time the merged sequence, and keep the
-    // cap that saves most (by more than 1 %).  A cap some instance cannot
-    // meet (its order or tolerance out of reach at that depth) is skipped.
-    // Deeper cuts were slow to prepare: a tree much shallower than an
-    // instance's own choice leaves most of its work to the near field.
+    // its order at the cap's depth if the near field stays empty there), time
+    // the merged sequence, and keep the cap that saves most (by more than
+    // 1 %).  A cap some instance cannot meet (its order or tolerance out of
+    // reach at that depth) is skipped.
     int deepest = 0;
     for (int i = 0; i < b->n; ++i)
         if (!cands[i].empty()) deepest = std::max(deepest, b->chosen_levels[i]);
@@ -2302,7 +2301,19 @@ static int batch_prepare(lmfmm_batch_s *b, const lmfmm_instance *inst, int nrhs,
                         o[i] = (int)c[0];
                         l[i] = (int)c[1];
                     }
-                if (bu >= 1e300) l[i] = cap;  // not timed alone: the merged timing decides
+                if (bu >= 1e300) {
+                    // not timed alone: allowed where the cap's leaves leave the
+                    // near field empty (else its cost can grow many times over)
+                    lmfmm_plan_s *p = b->plans[i];
+                    const int keep = p->levels_opt;
+                    Geometry gc;
+                    p->levels_opt = cap;
+                    const int grc = make_geometry(p, p->box, inst[i].n_src, nrhs, gc);
+                    p->levels_opt = keep;
+                    const double wl = gc.lev[gc.L].w;
+                    if (grc || gc.L != cap || !(p->box[2] >= wl || p->box[5] <= -wl)) continue;
+                    l[i] = cap;
+                }
                 changed = true;
             }
             if (!changed) break;
