@@ -1112,7 +1112,10 @@ void launch_p2m(const int32_t *start, const int32_t *end, const double *xs, cons
     // repeated for every pair of orders
     const Level &lv = g.lev[g.L];
     const int64_t nbox = (int64_t)lv.rows_s * lv.ncol;
-    const bool few = sizeof(T) == 4 && nbox > 0 && ns < P2M_SERIES_MIN_PER_LEAF * nbox;
+    // (in a recorded batch the series launch runs for the other instances
+    // anyway, and one merged launch fewer saves more than the form costs)
+    const bool few =
+        sizeof(T) == 4 && nbox > 0 && ns < P2M_SERIES_MIN_PER_LEAF * nbox && launch_batch_points() <= ns;
     const int nterm = series && !few ? p2m_series_terms(g, med, sizeof(T) == 8) : 0;
     if (nterm > 0)
         p2m_series_dispatch<T>(start, end, xs, ys, qs, ns, nrhs, g, med, M, occ, nterm, st);
