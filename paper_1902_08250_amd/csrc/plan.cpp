@@ -2026,7 +2026,9 @@ static int batch_record_merge(lmfmm_batch_s *b, const lmfmm_instance *inst, int 
         Recorder rec;
         const bool timing = p->timing;
         p->timing = false;
-        p->tz_bytes = 0;  // the recorded sequence clears its own leaf counters
+        // (no clearing launch is recorded while the plan's counters are known to
+        // be zero: the warm apply of the preparation left them so, and every
+        // tree build, replays included, leaves them zero)
         launch_recorder() = &rec;
         int rc = plan_apply_any(p, inst[i], nrhs, prec, st);
         launch_recorder() = nullptr;
