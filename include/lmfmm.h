@@ -186,6 +186,8 @@ int lmfmm_apply(lmfmm_plan plan, int64_t n_src, const double *src_xy, const void
  *   - The plan's device must be current.  Kernels are launched one by one (no
  *     graph); without the "domain" option the call waits for the bounding box
  *     as lmfmm_apply does.  The plan's statistics are not updated.
+ *   - With "tree_sort" at "auto" the points are grouped by the counting sort,
+ *     which needs the least workspace; "radix" is honoured.
  *   - Every call on one GPU shares that GPU's array: calls that overlap on a
  *     GPU (other streams, other host threads, other plans) race and give wrong
  *     results.  lmfmm_sync_status reports the error flag of the last such call
