@@ -238,11 +238,11 @@ def test_mid_mixed_vs_fp64(torch_cuda, mid, mid_direct):
 def test_tree_sort_forms(torch_cuda, mid, mid_direct, levels):
     """Both groupings of the points by leaf, the radix sort and the counting
     sort (option tree_sort), list every leaf's points in increasing original
-    index, so the results agree bit for bit.  Level 2 has 32 leaves (one
-    5-bit digit pass of the radix sort); levels 8 and 9 have about 3e4 and
-    1.3e5 leaves for 7000 points (15- and 17-bit keys: two and three passes),
-    so most leaf ranges are empty runs between occupied leaves.  FP64 against
-    the GPU direct sum."""
+    index, so the results agree bit for bit.  Level 2 has 12 leaves (one
+    4-bit digit pass of the radix sort), level 5 about 540 (two passes);
+    levels 8 and 9 have about 3e4 and 1.3e5 leaves for 7000 points (15- and
+    17-bit keys: two and three passes), so most leaf ranges are empty runs
+    between occupied leaves.  FP64 against the GPU direct sum."""
     from paper_1902_08250_amd.lmfmm import Plan
     out = {}
     for form in ("radix", "count"):
