@@ -247,18 +247,29 @@ __device__ __forceinline__ void p2ms_body(const P2MSArgs<T> &A, const int bx, co
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i][r] = mk<double>(0, 0);
+    // FP32 densities: the next point's coordinates and densities are loaded
+    // while the current one is summed (with FP64 densities the extra
+    // registers cost a wave per SIMD, and the prefetch then loses)
+    constexpr bool PF = sizeof(T) == 4;
+    double xn = 0.0, yn = 0.0;
+    cx<T> qn[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) qn[r] = mk<T>(0, 0);
+    auto load = [&](int j) {
+        xn = A.xs[j];
+        yn = A.ys[j];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (r < nr) qn[r] = A.qs[(int64_t)(r0 + r) * A.ns + j];
+    };
+    if (PF && j0 + s < j1) load(j0 + s);
     for (int j = j0 + s; j < j1; j += S) {
-        const double X = A.xs[j] - cxp, Y = A.ys[j] - cyp;
+        if (!PF) load(j);
+        const double X = xn - cxp, Y = yn - cyp;
         cx<double> qv[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (r < nr) {
-                const cx<T> q = A.qs[(int64_t)(r0 + r) * A.ns + j];
-                qv[r] = mk<double>(q.re, q.im);
-            } else {
-                qv[r] = mk<double>(0, 0);
-            }
-        }
+        for (int r = 0; r < 4; ++r) qv[r] = mk<double>(qn[r].re, qn[r].im);
+        if (PF && j + S < j1) load(j + S);
         const cx<double> zeta = kappa * (X * X + Y * Y);
         const cx<double> up = mk<double>(X * invR, -Y * invR);
         cx<double> pa = mk<double>(1, 0), bb = up;
@@ -532,10 +543,12 @@ __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, cons
     for (int c0 = S; c0 < E; c0 += L2P_THREADS) {
         const int i = c0 + t;
         if (i >= E) break;
-        if (c0 != S) {
-            px = xs[i];
-            py = ys[i];
-            pid = idx[i];
+        const double px0 = px, py0 = py;
+        const int32_t pid0 = pid;
+        if (i + L2P_THREADS < E) {  // the next chunk's point, loaded during this one
+            px = xs[i + L2P_THREADS];
+            py = ys[i + L2P_THREADS];
+            pid = idx[i + L2P_THREADS];
         }
         int g = 0;
         while (i >= bnd[g + 1]) ++g;
@@ -546,10 +559,10 @@ __device__ __forceinline__ void l2p_body(const L2PArgs<T> &A, const int bx, cons
             const int s = s_slot[g], she = L - s_lev[s];
             const double we = ldexp(w, she);
             const double cxp = x_lo + ((col >> she) + 0.5) * we, cyp = -((row >> she) + 0.5) * we;
-            eval_local<T, RMAX>(k2, (T)(px - cxp), (T)(py - cyp), invR / (T)(1 << she), s_P[s],
+            eval_local<T, RMAX>(k2, (T)(px0 - cxp), (T)(py0 - cyp), invR / (T)(1 << she), s_P[s],
                                       Ls + (int64_t)s * RMAX * ncmax, nr, res);
         }
-        const int64_t o = pid - ns;
+        const int64_t o = pid0 - ns;
         if (unear && row == 0)
             for (int pp = 0; pp < nparts; ++pp)
                 for (int r = 0; r < RMAX; ++r)
