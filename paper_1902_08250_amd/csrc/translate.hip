@@ -344,11 +344,8 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
     int loc = bx - a.blk0[li];
     const int nc = a.nc[li], ncol = a.ncol[li], col_lo = a.col_lo[li];
     const int npt = (nc + 15) >> 4, ntile = (ncol + k.NB - 1) / k.NB, nrc = (k.nrhs + k.RC - 1) / k.RC;
-    // Blocks come in runs of 8 x ntile: eight groups (row, right-hand-side
-    // chunk, coefficient tile), each with all its column tiles at indices
-    // eight apart.  Blocks are handed to the XCDs in turn, so a group's tiles,
-    // which read the same class tables, run on one XCD at about the same time
-    // and its L2 fetches those tables once.  Groups past the last are empty.
+    // block index within the level: coefficient tile fastest, then the
+    // right-hand-side chunk, the column tile and the target row
     const int pt = loc % npt;
     loc /= npt;
     const int rcn = loc % nrc;
