@@ -1965,12 +1965,17 @@ static void read_tune_cache(const std::string &path, std::map<std::string, TuneE
         const char *k1 = std::strchr(k0, '"');
         if (!k1) continue;
         TuneEntry e;
-        const char *o = std::strstr(k1, "\"order\": "), *l = std::strstr(k1, "\"levels\": "), *u = std::strstr(k1, "\"us\": ");
+        // the text after a field's name (null if the field is absent)
+        auto field = [&](const char *name) -> const char * {
+            const char *f = std::strstr(k1, name);
+            return f ? f + std::strlen(name) : nullptr;
+        };
+        const char *o = field("\"order\": "), *l = field("\"levels\": "), *u = field("\"us\": ");
         if (!o || !l || !u) continue;
-        e.order = std::atoi(o + 9);
-        e.levels = std::atoi(l + 10);
-        e.us = std::atof(u + 6);
-        if (const char *sw = std::strstr(k1, "\"sweep\": ")) e.sweep = std::atoi(sw + 10) != 0;
+        e.order = std::atoi(o);
+        e.levels = std::atoi(l);
+        e.us = std::atof(u);
+        if (const char *sw = field("\"sweep\": ")) e.sweep = std::atoi(sw) != 0;
         if (e.order < 1 || e.order > 256 || e.levels < 1 || e.levels > MAXLEV) continue;
         out[std::string(k0, k1)] = e;
     }

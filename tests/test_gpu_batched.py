@@ -114,3 +114,30 @@ def test_batched_points_leave_box():
     d = inst[1]
     ref = Plan(d["k"], d["d"], order=12, tol=1e-6).apply(items[1][0], items[1][1], items[1][2]).cpu().numpy()
     check(outs[1].cpu().numpy(), ref, TOL["c64"], "moved instance vs plan", say)
+
+
+def test_batched_tune_cache_round_trip(tmp_path):
+    """A second batch over the same instances takes every choice from the
+    tuning cache the first one wrote (after the depth cap on the merged
+    sequence), makes the same choices and gives bit-identical results."""
+    import torch
+    from paper_1902_08250_amd.lmfmm import Batch
+    inst = workloads.make_batched(seed=11, n_inst=6, n_hi=60_000)
+    say("batched tuning cache round trip, sizes", [d["n"] for d in inst])
+    cache = str(tmp_path / "tune.jsonl")
+    items = [(dev(d["src"]), dev(d["q"]), dev(d["tgt"])) for d in inst]
+    media = [(d["k"], d["d"]) for d in inst]
+    b1 = Batch(media, order_set=(12, 16, 20), tol=1e-6, tune_cache=cache)
+    first = [o.cpu().numpy() for o in b1.apply(items)]
+    c1 = b1.choices()
+    say("tuned", c1)
+    assert b1.stats()["tuned_from_cache"] == 0
+    b2 = Batch(media, order_set=(12, 16, 20), tol=1e-6, tune_cache=cache)
+    second = [o.cpu().numpy() for o in b2.apply(items)]
+    torch.cuda.synchronize()
+    c2 = b2.choices()
+    assert b2.stats()["tuned_from_cache"] == len(inst)
+    for a, c in zip(c1, c2):
+        assert (a["order"], a["levels"], a["near_sweep"]) == (c["order"], c["levels"], c["near_sweep"])
+    for a, c in zip(first, second):
+        assert np.array_equal(a, c)
