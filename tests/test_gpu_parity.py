@@ -252,6 +252,9 @@ def test_tree_sort_forms(torch_cuda, mid, mid_direct, levels):
         out[form] = host(pl.apply(dev(mid["src"]), dev(mid["q"]), dev(mid["tgt"])))
         check(out[form], mid_direct, 1e-10, f"c128 L={levels} tree_sort={form} vs direct", say)
     assert np.array_equal(out["radix"], out["count"])
+    from paper_1902_08250_amd.lmfmm import LMFMMError
+    with pytest.raises(LMFMMError, match="tree_sort"):
+        pl.set_option("tree_sort", "bucket")
 
 
 def test_deterministic(torch_cuda, mid):

@@ -24,17 +24,21 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+@pytest.mark.parametrize("tree_sort", ["auto", "radix"])
 @pytest.mark.parametrize("precision", ["c64", "c128"])
-def test_noalloc_matches_apply(precision):
+def test_noalloc_matches_apply(precision, tree_sort):
+    """tree_sort "auto" groups these 5.5e4 points by the counting sort,
+    "radix" by the radix sort (its digit table is in the fixed array too)."""
     import torch
     from paper_1902_08250_amd.lmfmm import Plan
-    say("apply_noalloc vs apply,", precision)
+    say("apply_noalloc vs apply,", precision, "tree_sort", tree_sort)
     w = workloads.make(1, n_src=30000, n_tgt=25000, nrhs=2)
     dt = np.complex64 if precision == "c64" else np.complex128
     tol = 1e-6 if precision == "c64" else 1e-10
     k, d = w["k"], w["d"]
     src, tgt, q = dev(w["src"]), dev(w["tgt"]), dev(w["q"].astype(dt))
     pl = Plan(k, d, order=16, tol=tol, levels=6, domain=DOMAIN)
+    pl.set_option("tree_sort", tree_sort)
     ref = pl.apply(src, q, tgt)  # builds the plan's tables for this geometry
     out = torch.empty_like(ref)
     pl.apply_noalloc(src, q, tgt, out)
