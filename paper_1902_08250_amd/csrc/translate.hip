@@ -545,6 +545,9 @@ struct ShiftMK {
 template <typename T, bool UP>
 __device__ __forceinline__ void shift_mfma_body(const ShiftMK<T> &k, const int bx)
 {
+    // operand steps in flight: with FP32, a whole column up to order 23 at
+    // once (with FP64 the registers would cost a wave per SIMD)
+    constexpr int MKS_SH = sizeof(T) == 4 ? 12 : MKS;
     typedef typename std::conditional<sizeof(T) == 4, mf32x4, mf64x4>::type vx4;
     constexpr bool F32 = sizeof(T) == 4;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
@@ -598,17 +601,17 @@ __device__ __forceinline__ void shift_mfma_body(const ShiftMK<T> &k, const int b
         const cx<T> *__restrict__ xb =
             k.X + (((int64_t)(ok ? irow : 0) * k.ncol_in + (ok ? icl : 0)) * k.nrhs + (ok ? r : 0)) * nin;
         const int nks = (nin + 3) >> 2;
-        for (int k0 = 0; k0 < nks; k0 += MKS) {
-            cx<T> av[MKS], bv[MKS];
+        for (int k0 = 0; k0 < nks; k0 += MKS_SH) {
+            cx<T> av[MKS_SH], bv[MKS_SH];
 #pragma unroll
-            for (int u = 0; u < MKS; ++u) {
+            for (int u = 0; u < MKS_SH; ++u) {
                 const int kq = 4 * (k0 + u) + kk;
                 const bool kin = kq < nin;
                 av[u] = (kin && p < nout) ? A[(int64_t)kq * nout + p] : mk<T>(0, 0);
                 bv[u] = (kin && ok) ? xb[kq] : mk<T>(0, 0);
             }
 #pragma unroll
-            for (int u = 0; u < MKS; ++u)
+            for (int u = 0; u < MKS_SH; ++u)
                 if (k0 + u < nks) mfma_c(dr, di, av[u], bv[u]);
         }
     }
