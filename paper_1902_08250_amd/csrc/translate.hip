@@ -404,17 +404,20 @@ __device__ __forceinline__ void m2l_mfma_body(const M2LMK<T> &k, const int bx)
             const cx<T> *__restrict__ As = At + (int64_t)s * nc * nc;
             const cx<T> *__restrict__ xb = Ms + (((int64_t)rs * ncol + (ok ? csl : 0)) * k.nrhs + (ok ? r : 0)) * nc;
             vx4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
-            for (int k0 = 0; k0 < nks; k0 += MKS) {
-                cx<T> av[MKS], bv[MKS];
+            // the 4-wave launch (levels below the coarsest) has registers for
+            // ten steps in flight, a whole column up to order 19
+            constexpr int MK = NW == 4 ? 10 : MKS;
+            for (int k0 = 0; k0 < nks; k0 += MK) {
+                cx<T> av[MK], bv[MK];
 #pragma unroll
-                for (int u = 0; u < MKS; ++u) {
+                for (int u = 0; u < MK; ++u) {
                     const int kq = 4 * (k0 + u) + kk;
                     const bool kin = kq < nc;
                     av[u] = (kin && p < nc) ? As[(int64_t)kq * nc + p] : mk<T>(0, 0);
                     bv[u] = (kin && ok) ? xb[kq] : mk<T>(0, 0);
                 }
 #pragma unroll
-                for (int u = 0; u < MKS; ++u)
+                for (int u = 0; u < MK; ++u)
                     if (k0 + u < nks) mfma_c(dr, di, av[u], bv[u]);
             }
             // compensated addition of the slot's product to the wave's sum
