@@ -126,9 +126,10 @@ def roofline(st, peak_key, kernel_names, bound="alu", traffic_file=TRAFFIC_FILE)
             "avg_launch_us": avg_s * 1e6, "hbm_GBps_if_traffic": (traffic / avg_s / 1e9) if traffic else None}
 
 
-# algorithmic HBM bytes of the tree build per point (count: coordinates in,
-# leaf key and slot out; scatter: key and slot in, index out; leaf order:
-# index and coordinates in, grouped coordinates and index out), plus the
+# algorithmic HBM bytes of the tree build per point, those of a counting
+# sort by leaf (count: coordinates in, leaf key and slot out; scatter: key and
+# slot in, index out; leaf order: index and coordinates in, grouped
+# coordinates and index out), the yardstick for both grouping forms, plus the
 # bounding box (coordinates in) when it is computed, plus each source's
 # densities read and written in grouped order
 TREE_BYTES_PER_POINT = (16 + 8) + (8 + 4) + (4 + 16 + 16 + 4)
